@@ -1,0 +1,399 @@
+/*
+ * Plain FP64 CPU oracle for the finite-difference TDSE of arXiv:1308.1856.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg to check the GPU library; never by the product
+ * path.  Deliberately slow and literal: loops over l then r, no blocking, no
+ * fusion, no SIMD, built with -ffp-contract=off.  Every function follows the
+ * passage of the paper named in its comment.
+ */
+#include "tdse_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Sec. 2, grid definition: uniform points, the first one a spacing away from
+ * the origin ("Start = 1"), optionally displaced by the "Offset" setting. */
+double orc_radius(const orc_grid* g, int i) { return (double)(i + 1) * g->dr + g->r_shift; }
+
+/* Sec. 2, angular coupling k_{l,l'}(m) for m = 0 and l_> = l:
+ * kappa_l = sqrt(l^2 / (4 l^2 - 1)). */
+double orc_kappa(int l)
+{
+    if (l <= 0) return 0.0;
+    double ll = (double)l;
+    return sqrt(ll * ll / (4.0 * ll * ll - 1.0));
+}
+
+/* Sec. 3, field with the Hann (sine-squared) envelope: E0 f(tau) cos(w tau +
+ * phi), f = sin^2(pi tau / T), T = 2 pi n_c / w, zero outside the pulse. */
+double orc_field(const orc_pulse* p, double t)
+{
+    double tau = t - p->t_on;
+    double period = 2.0 * M_PI * p->n_cycles / p->omega;
+    if (!(tau >= 0.0 && tau <= period)) return 0.0;
+    double s = sin(M_PI * tau / period);
+    return p->e0 * s * s * cos(p->omega * tau + p->cep);
+}
+
+static double complex value_at(const orc_grid* g, const double complex* row, int i)
+{
+    /* Sec. 2.1: the finite-difference terms beyond the box edges are zero */
+    if (i < 0 || i >= g->n) return 0.0;
+    return row[i];
+}
+
+/* H(t) f for the length gauge (Sec. 2, radial TDSE in the L gauge, with the
+ * field-free block h_l and the matrix layout of eq. h_matrix):
+ *   (H f)_l = -1/2 D2 f_l + [l(l+1)/(2 r^2) - z/r] f_l
+ *             + E r [kappa_l f_{l-1} + kappa_{l+1} f_{l+1}]
+ * D2 is the 3-point second difference or the 5-point fourth-order formula of
+ * Sec. 2. */
+void orc_apply_h(const orc_grid* g, double efield, const double complex* f, double complex* hf)
+{
+    const int n = g->n;
+    const double h2 = g->dr * g->dr;
+    for (int l = 0; l <= g->lmax; ++l) {
+        const double complex* fl = f + (size_t)l * n;
+        const double complex* flm = (l > 0) ? f + (size_t)(l - 1) * n : NULL;
+        const double complex* flp = (l < g->lmax) ? f + (size_t)(l + 1) * n : NULL;
+        const double kl = orc_kappa(l);
+        const double klp = orc_kappa(l + 1);
+        const double centrifugal = 0.5 * (double)l * (double)(l + 1);
+        for (int i = 0; i < n; ++i) {
+            double complex d2;
+            if (g->stencil == 3) {
+                d2 = (value_at(g, fl, i + 1) - 2.0 * fl[i] + value_at(g, fl, i - 1)) / h2;
+            } else {
+                d2 = (-value_at(g, fl, i + 2) + 16.0 * value_at(g, fl, i + 1) - 30.0 * fl[i]
+                      + 16.0 * value_at(g, fl, i - 1) - value_at(g, fl, i - 2))
+                     / (12.0 * h2);
+            }
+            const double r = orc_radius(g, i);
+            const double v = centrifugal / (r * r) - g->z / r;
+            double complex coupling = 0.0;
+            if (flm) coupling += kl * flm[i];
+            if (flp) coupling += klp * flp[i];
+            hf[(size_t)l * n + i] = -0.5 * d2 + v * fl[i] + efield * r * coupling;
+        }
+    }
+}
+
+/* Gershgorin bound on the spectral radius of H(E): the largest absolute
+ * row sum of the matrix of eq. h_matrix.  Used as the scale of the Lanczos
+ * breakdown test and of the explicit-step stability limit. */
+double orc_h_bound(const orc_grid* g, double efield)
+{
+    const double h2 = g->dr * g->dr;
+    const double diag_kin = (g->stencil == 3) ? 1.0 / h2 : 30.0 / (24.0 * h2);
+    const double off_kin = (g->stencil == 3) ? 1.0 / h2 : (32.0 + 2.0) / (24.0 * h2);
+    double bound = 0.0;
+    for (int l = 0; l <= g->lmax; ++l) {
+        const double coup = orc_kappa(l) + ((l < g->lmax) ? orc_kappa(l + 1) : 0.0);
+        for (int i = 0; i < g->n; ++i) {
+            const double r = orc_radius(g, i);
+            const double d = diag_kin + 0.5 * (double)l * (double)(l + 1) / (r * r) - g->z / r;
+            const double row = fabs(d) + off_kin + fabs(efield) * r * coup;
+            if (row > bound) bound = row;
+        }
+    }
+    return bound;
+}
+
+static size_t state_len(const orc_grid* g) { return (size_t)(g->lmax + 1) * (size_t)g->n; }
+
+/* Sec. 5.2 (Taylor.c), eq. Taylor with the recurrence divisor read as p+1:
+ *   F_{n+1} = sum_{p=0..P} F^(p),  F^(0) = F_n,  F^(p+1) = (-i dt/(p+1)) H F^(p)
+ * H is frozen at the field value passed in (the step midpoint). */
+void orc_taylor_step(const orc_grid* g, double efield, double dt, int order, double complex* psi)
+{
+    const size_t len = state_len(g);
+    double complex* term = malloc(len * sizeof *term);
+    double complex* next = malloc(len * sizeof *next);
+    memcpy(term, psi, len * sizeof *term);
+    for (int p = 0; p < order; ++p) {
+        orc_apply_h(g, efield, term, next);
+        const double complex factor = -I * dt / (double)(p + 1);
+        for (size_t k = 0; k < len; ++k) {
+            term[k] = factor * next[k];
+            psi[k] += term[k];
+        }
+    }
+    free(term);
+    free(next);
+}
+
+/* Sec. 5.2 (RungeKutta.c), eq. RKDeriv with the classic fourth-order tableau
+ * (c = 0, 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6) applied to dF/dt = -i H(t) F
+ * (eq. tdse_matrix).  The field values at the stage times are passed in. */
+static void rk4_step_fields(const orc_grid* g, double e_start, double e_mid, double e_end,
+                            double dt, double complex* psi)
+{
+    const size_t len = state_len(g);
+    double complex* k = malloc(len * sizeof *k);
+    double complex* y = malloc(len * sizeof *y);
+    double complex* acc = malloc(len * sizeof *acc);
+    const double a[4] = {0.0, 0.5, 0.5, 1.0};
+    const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double e[4] = {e_start, e_mid, e_mid, e_end};
+    memcpy(acc, psi, len * sizeof *acc);
+    memcpy(y, psi, len * sizeof *y);
+    for (int s = 0; s < 4; ++s) {
+        if (s > 0)
+            for (size_t j = 0; j < len; ++j) y[j] = psi[j] + a[s] * dt * k[j];
+        orc_apply_h(g, e[s], y, k);
+        for (size_t j = 0; j < len; ++j) k[j] = -I * k[j];
+        for (size_t j = 0; j < len; ++j) acc[j] += b[s] * dt * k[j];
+    }
+    memcpy(psi, acc, len * sizeof *acc);
+    free(k);
+    free(y);
+    free(acc);
+}
+
+void orc_rk4_step(const orc_grid* g, const orc_pulse* p, double t, double dt, double complex* psi)
+{
+    rk4_step_fields(g, orc_field(p, t), orc_field(p, t + 0.5 * dt), orc_field(p, t + dt), dt, psi);
+}
+
+/* Cyclic-by-row Jacobi method for a dense symmetric matrix (the rotation of
+ * Golub & Van Loan, Matrix Computations, Sec. 8.5).  Each rotation zeroes one
+ * off-diagonal pair; sweeps repeat until the off-diagonal part vanishes. */
+void orc_jacobi_eig(int m, double* a, double* v)
+{
+#define A(i, j) a[(size_t)(i) * m + (j)]
+#define V(i, j) v[(size_t)(i) * m + (j)]
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) V(i, j) = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < m; ++i) {
+            diag += A(i, i) * A(i, i);
+            for (int j = i + 1; j < m; ++j) off += A(i, j) * A(i, j);
+        }
+        if (off == 0.0 || off <= 1e-36 * diag) break;
+        for (int p = 0; p < m - 1; ++p) {
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = A(p, q);
+                if (apq == 0.0) continue;
+                const double tau = (A(q, q) - A(p, p)) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = t * c;
+                for (int k = 0; k < m; ++k) { /* A <- A J */
+                    const double akp = A(k, p), akq = A(k, q);
+                    A(k, p) = c * akp - s * akq;
+                    A(k, q) = s * akp + c * akq;
+                }
+                for (int k = 0; k < m; ++k) { /* A <- J^T A */
+                    const double apk = A(p, k), aqk = A(q, k);
+                    A(p, k) = c * apk - s * aqk;
+                    A(q, k) = s * apk + c * aqk;
+                }
+                for (int k = 0; k < m; ++k) { /* V <- V J */
+                    const double vkp = V(k, p), vkq = V(k, q);
+                    V(k, p) = c * vkp - s * vkq;
+                    V(k, q) = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+#undef A
+#undef V
+}
+
+/* Appendix "Lanczos methods" and Sec. 5.2 (Lanczos.c): the Hermitian Lanczos
+ * process builds an orthonormal Krylov basis q_1..q_m of H (frozen at the
+ * field passed in) from q_1 = F/||F|| together with the tridiagonal matrix
+ * T (alpha on the diagonal, beta beside it).  Each new direction w = H q_j is
+ * orthogonalised against every earlier basis vector in one classical
+ * Gram-Schmidt pass (this contains the three-term recurrence of the
+ * listing); alpha_j = <q_j, H q_j>, beta_j = ||w||.  The process stops early
+ * (the listing's "beta = 0" exit) when beta_j is below 1e-12 times the
+ * Gershgorin bound of H, i.e. at round-off level for this operator.  The subspace propagator
+ * exp(-i T dt) e_1 is formed from the eigen-decomposition of T, and the
+ * state is expanded back: F_{n+1} = ||F|| sum_k c_k q_k. */
+int orc_lanczos_step(const orc_grid* g, double efield, double dt, int m, double complex* psi)
+{
+    const size_t len = state_len(g);
+    double complex* q = malloc((size_t)m * len * sizeof *q);
+    double complex* w = malloc(len * sizeof *w);
+    double complex* h = malloc((size_t)m * sizeof *h);
+    double* alpha = calloc((size_t)m, sizeof *alpha);
+    double* beta = calloc((size_t)m, sizeof *beta);
+
+    double norm2 = 0.0;
+    for (size_t k = 0; k < len; ++k) norm2 += creal(psi[k]) * creal(psi[k]) + cimag(psi[k]) * cimag(psi[k]);
+    const double norm = sqrt(norm2);
+    for (size_t k = 0; k < len; ++k) q[k] = psi[k] / norm;
+
+    const double breakdown = 1e-12 * orc_h_bound(g, efield);
+    int meff = 0;
+    for (int j = 0; j < m; ++j) {
+        double complex* qj = q + (size_t)j * len;
+        orc_apply_h(g, efield, qj, w);
+        for (int i = 0; i <= j; ++i) {
+            const double complex* qi = q + (size_t)i * len;
+            double complex dot = 0.0;
+            for (size_t k = 0; k < len; ++k) dot += conj(qi[k]) * w[k];
+            h[i] = dot;
+        }
+        for (int i = 0; i <= j; ++i) {
+            const double complex* qi = q + (size_t)i * len;
+            for (size_t k = 0; k < len; ++k) w[k] -= h[i] * qi[k];
+        }
+        alpha[j] = creal(h[j]);
+        double b2 = 0.0;
+        for (size_t k = 0; k < len; ++k) b2 += creal(w[k]) * creal(w[k]) + cimag(w[k]) * cimag(w[k]);
+        beta[j] = sqrt(b2);
+        meff = j + 1;
+        if (j == m - 1) break;
+        if (beta[j] <= breakdown) break; /* invariant subspace found */
+        double complex* qn = q + (size_t)(j + 1) * len;
+        for (size_t k = 0; k < len; ++k) qn[k] = w[k] / beta[j];
+    }
+
+    double* tmat = calloc((size_t)meff * meff, sizeof *tmat);
+    double* s = malloc((size_t)meff * meff * sizeof *s);
+    for (int j = 0; j < meff; ++j) {
+        tmat[(size_t)j * meff + j] = alpha[j];
+        if (j + 1 < meff) {
+            tmat[(size_t)j * meff + j + 1] = beta[j];
+            tmat[(size_t)(j + 1) * meff + j] = beta[j];
+        }
+    }
+    orc_jacobi_eig(meff, tmat, s);
+    /* c = S exp(-i Lambda dt) S^T e_1 */
+    double complex* c = calloc((size_t)meff, sizeof *c);
+    for (int k = 0; k < meff; ++k) {
+        double complex acc = 0.0;
+        for (int j = 0; j < meff; ++j) {
+            const double lam = tmat[(size_t)j * meff + j];
+            acc += s[(size_t)k * meff + j] * cexp(-I * lam * dt) * s[(size_t)0 * meff + j];
+        }
+        c[k] = acc;
+    }
+    for (size_t k = 0; k < len; ++k) {
+        double complex acc = 0.0;
+        for (int j = 0; j < meff; ++j) acc += c[j] * q[(size_t)j * len + k];
+        psi[k] = norm * acc;
+    }
+    free(c);
+    free(s);
+    free(tmat);
+    free(q);
+    free(w);
+    free(h);
+    free(alpha);
+    free(beta);
+    return meff;
+}
+
+/* Initial state: the hydrogenic 1s radial function u(r) ~ r exp(-z r)
+ * (Fig. "1sHydroRad": density 4 r^2 exp(-2r) for z = 1), normalised on the
+ * grid, placed in the l = 0 partial wave.  u0 receives the normalised l = 0
+ * row (the reference state of eq. p_g). */
+void orc_initial_state(const orc_grid* g, double complex* psi, double* u0)
+{
+    double sum = 0.0;
+    for (int i = 0; i < g->n; ++i) {
+        const double r = orc_radius(g, i);
+        u0[i] = r * exp(-g->z * r);
+        sum += u0[i] * u0[i];
+    }
+    const double scale = 1.0 / sqrt(g->dr * sum);
+    for (int i = 0; i < g->n; ++i) u0[i] *= scale;
+    memset(psi, 0, state_len(g) * sizeof *psi);
+    for (int i = 0; i < g->n; ++i) psi[i] = u0[i];
+}
+
+/* Sec. 4 observables, radial integrals by the rectangle rule dr * sum:
+ *   norm  = sum_l int |f_l|^2
+ *   p_g   = |<psi(0)|psi(t)>|^2 with psi(0) the l = 0 row u0 (eq. p_g)
+ *   P_nl  = |<phi_nl|f_l>|^2 for the bound eigenvectors supplied by the caller
+ *   p_ion = sum_l int_{r > r_b} |f_l|^2   (eq. yield_1)
+ *   <z>   = 2 sum_l kappa_{l+1} Re int r f_l^* f_{l+1}           (eq. Dipole)
+ *   <z''> = -E(t) - 2 z sum_l kappa_{l+1} Re int f_l^* f_{l+1} / r^2
+ *                                                           (eq. DipoleAccel) */
+void orc_observables(const orc_grid* g, const orc_pulse* p, double t, double r_ion,
+                     const double* u0, int n_states, const int32_t* state_l, const double* phi,
+                     const double complex* psi, double* out)
+{
+    const int n = g->n;
+    const double dr = g->dr;
+    double norm = 0.0, outer = 0.0, dip = 0.0, acc = 0.0;
+    for (int l = 0; l <= g->lmax; ++l) {
+        const double complex* fl = psi + (size_t)l * n;
+        for (int i = 0; i < n; ++i) {
+            const double a2 = creal(fl[i]) * creal(fl[i]) + cimag(fl[i]) * cimag(fl[i]);
+            norm += a2;
+            if (orc_radius(g, i) > r_ion) outer += a2;
+        }
+        if (l < g->lmax) {
+            const double complex* fn = psi + (size_t)(l + 1) * n;
+            double sd = 0.0, sa = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double r = orc_radius(g, i);
+                const double re = creal(conj(fl[i]) * fn[i]);
+                sd += r * re;
+                sa += re / (r * r);
+            }
+            dip += orc_kappa(l + 1) * sd;
+            acc += orc_kappa(l + 1) * sa;
+        }
+    }
+    double complex proj0 = 0.0;
+    for (int i = 0; i < n; ++i) proj0 += u0[i] * psi[i];
+    proj0 *= dr;
+    const double efield = orc_field(p, t);
+
+    out[0] = t;
+    out[1] = efield;
+    out[2] = dr * norm;
+    out[3] = creal(proj0) * creal(proj0) + cimag(proj0) * cimag(proj0);
+    double pbound = 0.0;
+    for (int k = 0; k < n_states; ++k) {
+        const double complex* fl = psi + (size_t)state_l[k] * n;
+        const double* ph = phi + (size_t)k * n;
+        double complex proj = 0.0;
+        for (int i = 0; i < n; ++i) proj += ph[i] * fl[i];
+        proj *= dr;
+        const double pop = creal(proj) * creal(proj) + cimag(proj) * cimag(proj);
+        out[ORC_OBS_FIXED + k] = pop;
+        pbound += pop;
+    }
+    out[4] = pbound;
+    out[5] = dr * outer;
+    out[6] = 2.0 * dr * dip;
+    out[7] = -efield - 2.0 * g->z * dr * acc;
+}
+
+int orc_propagate(const orc_grid* g, const orc_pulse* p, int method, int order_or_m, double t0,
+                  double dt, int64_t nsteps, int64_t obs_every, double r_ion, const double* u0,
+                  int n_states, const int32_t* state_l, const double* phi, double complex* psi,
+                  double* obs_out)
+{
+    const int rec = ORC_OBS_FIXED + n_states;
+    int64_t n_obs = 0;
+    int min_m = (method == ORC_LANCZOS) ? order_or_m : 0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const double t_start = t0 + (double)s * dt;
+        const double t_mid = t0 + ((double)s + 0.5) * dt;
+        const double t_end = t0 + (double)(s + 1) * dt;
+        if (method == ORC_TAYLOR) {
+            orc_taylor_step(g, orc_field(p, t_mid), dt, order_or_m, psi);
+        } else if (method == ORC_RK4) {
+            rk4_step_fields(g, orc_field(p, t_start), orc_field(p, t_mid), orc_field(p, t_end), dt, psi);
+        } else {
+            const int used = orc_lanczos_step(g, orc_field(p, t_mid), dt, order_or_m, psi);
+            if (used < min_m) min_m = used;
+        }
+        if (obs_every > 0 && (s + 1) % obs_every == 0 && obs_out) {
+            orc_observables(g, p, t_end, r_ion, u0, n_states, state_l, phi, psi,
+                            obs_out + (size_t)n_obs * rec);
+            ++n_obs;
+        }
+    }
+    return min_m;
+}

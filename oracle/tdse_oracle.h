@@ -1,0 +1,94 @@
+/*
+ * Plain FP64 CPU oracle for the finite-difference, length-gauge, partial-wave
+ * TDSE of hydrogen-like atoms (O Broin & Nikolopoulos, arXiv:1308.1856).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library; it is
+ * never called by the product path.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark load it.  It shares no source with the
+ * GPU library.
+ *
+ * Conventions (each a reading of the paper, listed in the design doc):
+ *   state      psi[l*n + i] = f_l(r_i), l = 0..lmax, i = 0..n-1, complex128
+ *   grid       r_i = (i+1)*dr + r_shift   (Sec. 2 grid, "Start"/"Offset" of
+ *              the FD settings group); f = 0 outside [0, n)  (Sec. 2.1: the FD
+ *              terms beyond the fixed boundary are zero)
+ *   inner prod <u|v> = dr * sum conj(u) v   (rectangle rule)
+ */
+#ifndef TDSE_ORACLE_H
+#define TDSE_ORACLE_H
+
+#include <complex.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t n;        /* radial points per partial wave                    */
+    int32_t lmax;     /* highest partial wave                              */
+    int32_t stencil;  /* 3 (2nd order) or 5 (4th order, Sec. 2)            */
+    int32_t pad_;
+    double dr;        /* grid spacing (au)                                 */
+    double z;         /* nuclear charge, V(r) = -z/r                       */
+    double r_shift;   /* grid offset added to every radius (normally 0)    */
+} orc_grid;
+
+typedef struct {
+    double e0;        /* peak field (au)                                   */
+    double omega;     /* carrier angular frequency (au)                    */
+    double n_cycles;  /* number of carrier cycles under the envelope       */
+    double cep;       /* carrier-envelope phase                            */
+    double t_on;      /* pulse start time (au)                             */
+} orc_pulse;
+
+/* Observable record, in this order (all FP64):
+ *   0 t, 1 E(t), 2 norm, 3 p_g, 4 p_bound (sum of P_nl), 5 p_ion(r_b),
+ *   6 <z>, 7 <z''>, 8.. the populations P_nl (n_states of them)          */
+#define ORC_OBS_FIXED 8
+
+enum { ORC_TAYLOR = 0, ORC_RK4 = 1, ORC_LANCZOS = 2 };
+
+double orc_radius(const orc_grid* g, int i);
+double orc_kappa(int l);
+double orc_field(const orc_pulse* p, double t);
+
+double orc_h_bound(const orc_grid* g, double efield);
+
+void orc_apply_h(const orc_grid* g, double efield,
+                 const double complex* f, double complex* hf);
+
+void orc_taylor_step(const orc_grid* g, double efield, double dt, int order,
+                     double complex* psi);
+void orc_rk4_step(const orc_grid* g, const orc_pulse* p, double t, double dt,
+                  double complex* psi);
+/* returns the Krylov dimension actually used (smaller than m on breakdown) */
+int orc_lanczos_step(const orc_grid* g, double efield, double dt, int m,
+                     double complex* psi);
+
+/* Eigen-decomposition of a dense real symmetric m x m matrix (row-major) by
+ * cyclic Jacobi rotations: on return a holds the eigenvalues on its diagonal
+ * and v (row-major) the eigenvectors as columns. */
+void orc_jacobi_eig(int m, double* a, double* v);
+
+void orc_initial_state(const orc_grid* g, double complex* psi, double* u0);
+
+void orc_observables(const orc_grid* g, const orc_pulse* p, double t,
+                     double r_ion, const double* u0, int n_states,
+                     const int32_t* state_l, const double* phi,
+                     const double complex* psi, double* out);
+
+/* Runs nsteps steps of the chosen method from t0.  After every obs_every-th
+ * step the observables are appended to obs_out (record length
+ * ORC_OBS_FIXED + n_states).  Returns the smallest Krylov dimension used
+ * (Lanczos) or 0. */
+int orc_propagate(const orc_grid* g, const orc_pulse* p, int method,
+                  int order_or_m, double t0, double dt, int64_t nsteps,
+                  int64_t obs_every, double r_ion, const double* u0,
+                  int n_states, const int32_t* state_l, const double* phi,
+                  double complex* psi, double* obs_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
