@@ -211,7 +211,8 @@ void orc_jacobi_eig(int m, double* a, double* v)
  * Gram-Schmidt pass (this contains the three-term recurrence of the
  * listing); alpha_j = <q_j, H q_j>, beta_j = ||w||.  The process stops early
  * (the listing's "beta = 0" exit) when beta_j is below 1e-12 times the
- * Gershgorin bound of H, i.e. at round-off level for this operator.  The subspace propagator
+ * Gershgorin bound of the field-free H, i.e. at round-off level for this
+ * operator.  The subspace propagator
  * exp(-i T dt) e_1 is formed from the eigen-decomposition of T, and the
  * state is expanded back: F_{n+1} = ||F|| sum_k c_k q_k. */
 int orc_lanczos_step(const orc_grid* g, double efield, double dt, int m, double complex* psi)
@@ -228,7 +229,7 @@ int orc_lanczos_step(const orc_grid* g, double efield, double dt, int m, double 
     const double norm = sqrt(norm2);
     for (size_t k = 0; k < len; ++k) q[k] = psi[k] / norm;
 
-    const double breakdown = 1e-12 * orc_h_bound(g, efield);
+    const double breakdown = 1e-12 * orc_h_bound(g, 0.0);
     int meff = 0;
     for (int j = 0; j < m; ++j) {
         double complex* qj = q + (size_t)j * len;
