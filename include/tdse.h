@@ -1,0 +1,205 @@
+/*
+ * tdse.h -- C ABI of the MI355X (gfx950) finite-difference TDSE library.
+ *
+ * What it computes (arXiv:1308.1856, O Broin & Nikolopoulos):
+ *   the length-gauge, m = 0 partial-wave TDSE of a hydrogen-like atom,
+ *     i d/dt F = H(t) F              (Sec. 2, eq. tdse_matrix)
+ *   with F = [f_0(r_1..r_N), ..., f_lmax(r_1..r_N)] and H(t) the block-
+ *   tridiagonal matrix of eq. h_matrix:
+ *     (H F)_l = -1/2 D2 f_l + [l(l+1)/(2r^2) - Z/r] f_l
+ *               + E(t) r [kappa_l f_{l-1} + kappa_{l+1} f_{l+1}]
+ *   D2 is the 3-point or the 5-point (4th-order, Sec. 2) second difference
+ *   with zero values beyond the box (Sec. 2.1); kappa_l = l / sqrt(4l^2 - 1);
+ *   r_i = (i+1) dr, i = 0..N-1.  The field is the Hann-envelope pulse of
+ *   Sec. 3 (eq. EField):  E(t) = E0 sin^2(pi tau/T) cos(w tau + cep),
+ *   tau = t - t_on in [0, T], T = 2 pi n_cycles / w, zero outside.
+ *
+ * Memory and ownership
+ *   The library never allocates device memory.  The caller owns the state
+ *   buffer, the workspace, the observable buffers and the HIP stream; the
+ *   library owns only its opaque host context (and small pinned host
+ *   staging buffers).  All device work is enqueued on the stream given to
+ *   tdse_bind and is asynchronous unless a function says it synchronises.
+ *
+ * State layout (device)
+ *   Instances are concatenated; instance k starts at element offset
+ *   tdse_state_offset(ctx, k) (a multiple of 64 elements).  Within an
+ *   instance, element (l, i) sits at offset + l*N + i.  An element is an
+ *   interleaved complex number: 16 bytes (re, im as double) for
+ *   TDSE_FP64, 8 bytes (re, im as float) for TDSE_FP32.  In TDSE_FP32 mode
+ *   every sweep reads and writes FP32 values but computes in FP64, and all
+ *   reductions (norms, inner products, observables, Lanczos coefficients,
+ *   the tridiagonal eigen-decomposition) are FP64.
+ *
+ * Errors
+ *   Every function returning tdse_status returns TDSE_OK (0) or a negative
+ *   code; nothing throws across the ABI.  tdse_last_error() gives a message
+ *   for the last failing call on a context.  On an error nothing has been
+ *   enqueued unless the code is TDSE_E_HIP.
+ */
+#ifndef TDSE_H
+#define TDSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tdse_status;
+enum {
+    TDSE_OK = 0,
+    TDSE_E_INVALID = -1,    /* bad argument (null pointer, size, range)            */
+    TDSE_E_NOMEM = -2,      /* host allocation failed                              */
+    TDSE_E_HIP = -3,        /* a HIP runtime call failed                           */
+    TDSE_E_UNSTABLE = -4,   /* explicit step would exceed its stability limit      */
+    TDSE_E_NONFINITE = -6,  /* a norm came out NaN or Inf                          */
+    TDSE_E_WORKSPACE = -7,  /* bound workspace smaller than the method needs       */
+    TDSE_E_UNBOUND = -8     /* no device memory bound yet (tdse_bind)              */
+};
+
+typedef enum { TDSE_FP64 = 0, TDSE_FP32 = 1 } tdse_precision;
+typedef enum { TDSE_METHOD_TAYLOR = 0, TDSE_METHOD_RK4 = 1, TDSE_METHOD_LANCZOS = 2 } tdse_method;
+
+/* One instance (one radial grid and partial-wave set).  All instances of a
+ * context must share stencil and precision. */
+typedef struct {
+    int32_t n_r;        /* radial points N, >= 8                                  */
+    int32_t lmax;       /* highest partial wave, 0..1023                          */
+    int32_t stencil;    /* 3 or 5                                                 */
+    int32_t precision;  /* tdse_precision                                         */
+    double dr;          /* grid spacing (au), > 0                                 */
+    double z_nuc;       /* nuclear charge Z (> 0)                                 */
+    double r_ion;       /* ionisation radius r_b (au) for p_ion                   */
+} tdse_grid_desc;
+
+/* Sec. 3 pulse (eq. EField with the Hann envelope). */
+typedef struct {
+    double e0;          /* peak field (au)                                        */
+    double omega;       /* carrier angular frequency (au), > 0                    */
+    double n_cycles;    /* carrier cycles under the envelope, > 0                 */
+    double cep;         /* carrier-envelope phase (a sine carrier is -pi/2)       */
+    double t_on;        /* start of the pulse (au)                                */
+} tdse_pulse;
+
+#define TDSE_MAX_STATES 15
+/* Observables at one time (Sec. 4), all FP64 with radial integrals dr*sum:
+ *   norm    = sum_l int |f_l|^2
+ *   p_g     = |<u0|f_0>|^2, u0 the normalised analytic 1s (eq. p_g, read as
+ *             a probability)
+ *   pop[k]  = |<phi_k|f_l(k)>|^2, phi_k the k-th bound eigenvector of the
+ *             field-free block h_l, states ordered 1s 2s 3s 4s 5s 2p 3p 4p
+ *             5p 3d 4d 5d 4f 5f 5g (fewer if lmax < 4; unused entries are 0)
+ *   p_bound = sum_k pop[k]
+ *   p_ion   = sum_l int_{r > r_ion} |f_l|^2                  (eq. yield_1)
+ *   dipole  = 2 sum_l kappa_{l+1} Re int r f_l^* f_{l+1}      (eq. Dipole)
+ *   accel   = -E(t) - 2 Z sum_l kappa_{l+1} Re int f_l^* f_{l+1} / r^2
+ *                                                        (eq. DipoleAccel) */
+typedef struct {
+    double t, e_field, norm, p_g, p_bound, p_ion, dipole, accel;
+    double pop[TDSE_MAX_STATES];
+} tdse_obs;
+
+typedef struct tdse_ctx tdse_ctx;
+
+/* Creates a context for n_inst instances (n_inst = 1 for a single run; every
+ * other call takes per-instance arrays of length n_inst).  Computes on the
+ * host, in FP64: the instance and tile tables, kappa_l, the normalised 1s
+ * row u0 and the bound eigenvectors phi_nl (n <= 5) of each h_l.  Touches no
+ * device memory.  *out receives the context (NULL on error). */
+tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_inst, tdse_ctx** out);
+
+/* Frees the host context (never the caller's device memory). */
+void tdse_destroy(tdse_ctx* ctx);
+
+const char* tdse_last_error(const tdse_ctx* ctx);
+
+int32_t tdse_num_instances(const tdse_ctx* ctx);
+/* Element offset of instance k in the state (and in any state-shaped vector). */
+int64_t tdse_state_offset(const tdse_ctx* ctx, int32_t inst);
+/* Bytes of one state-shaped device vector (all instances). */
+size_t tdse_state_bytes(const tdse_ctx* ctx);
+/* Workspace bytes needed by a method (order_or_m: Taylor order, ignored for
+ * RK4, Krylov dimension for Lanczos).  The largest of the methods a caller
+ * uses is enough for all of them. */
+size_t tdse_workspace_bytes(const tdse_ctx* ctx, int32_t method, int32_t order_or_m);
+
+/* Binds caller-owned device memory and a HIP stream (hipStream_t, may be
+ * NULL for the null stream).  d_state: tdse_state_bytes bytes, 256-byte
+ * aligned.  d_work: work_bytes >= tdse_workspace_bytes for every method used,
+ * 256-byte aligned.  Uploads the tables into the workspace and synchronises
+ * the stream.  May be called again to rebind. */
+tdse_status tdse_bind(tdse_ctx* ctx, void* d_state, void* d_work, size_t work_bytes,
+                      void* hip_stream);
+
+/* Host <-> device copies of one instance's state as complex128 (interleaved
+ * re, im doubles, (lmax+1)*N of them).  host_c128 == NULL in set_state puts
+ * the normalised 1s state u0 in l = 0 and zeros elsewhere.  Both synchronise
+ * the stream. */
+tdse_status tdse_set_state(tdse_ctx* ctx, int32_t inst, const double* host_c128);
+tdse_status tdse_get_state(tdse_ctx* ctx, int32_t inst, double* host_c128);
+
+/* d_out = H(E) d_in for every instance, with e_field[k] the field of
+ * instance k (Sec. 2, eq. h_matrix).  d_in and d_out are caller-owned
+ * state-shaped device vectors in the context's precision; they must not
+ * overlap.  Asynchronous. */
+tdse_status tdse_apply_H(tdse_ctx* ctx, const double* e_field, const void* d_in, void* d_out);
+
+/* Taylor propagator of order `order` (1..16), Sec. 5.2 eq. Taylor:
+ *   F <- sum_{p=0..P} (-i dt H(t_s + dt/2))^p / p! F
+ * evaluated in Horner form, one fused sweep per term.  For each instance k
+ * advances the bound state by nsteps steps of dt[k] from t0[k]; step s
+ * spans [t0 + s dt, t0 + (s+1) dt].  If obs_every > 0 and d_obs != NULL the
+ * observables after every obs_every-th step are written to d_obs (device
+ * memory, [n_inst][nsteps / obs_every] records).  Returns TDSE_E_UNSTABLE
+ * (and enqueues nothing) if dt[k] times tdse_lambda_max_bound(k, |e0|)
+ * exceeds the imaginary-axis stability limit of the order-P polynomial.
+ * Asynchronous. */
+tdse_status tdse_step_taylor(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0,
+                             const double* dt, int32_t order, int32_t nsteps, int32_t obs_every,
+                             tdse_obs* d_obs);
+
+/* Classic fourth-order Runge-Kutta (Sec. 5.2 eq. RKDeriv, tableau c = 0, 1/2,
+ * 1/2, 1; b = 1/6, 1/3, 1/3, 1/6) on dF/dt = -i H(t) F.  Arguments,
+ * stability check and observables as tdse_step_taylor (limit of order 4). */
+tdse_status tdse_step_rk4(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0,
+                          const double* dt, int32_t nsteps, int32_t obs_every, tdse_obs* d_obs);
+
+/* Lanczos propagator (Sec. 5.2 Lanczos.c, appendix "Lanczos methods"): an
+ * m-dimensional Krylov basis of H(t_s + dt/2) from F/||F|| with full
+ * re-orthogonalisation (FP64 coefficients), the exponential of the m x m
+ * tridiagonal from its eigen-decomposition, and F <- ||F|| Q exp(-i T dt) e1.
+ * The process stops early at breakdown (beta_j <= 1e-12 times the
+ * Gershgorin bound of H).  m in 1..64.  No stability limit.  Asynchronous. */
+tdse_status tdse_step_lanczos(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0,
+                              const double* dt, int32_t m, int32_t nsteps, int32_t obs_every,
+                              tdse_obs* d_obs);
+
+/* Observables of the bound state at time t[k] (E(t) from pulses[k]) for
+ * every instance, copied to host_out[n_inst].  Synchronises the stream.
+ * Returns TDSE_E_NONFINITE if any norm is not finite. */
+tdse_status tdse_observables(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t,
+                             tdse_obs* host_out);
+
+/* Gershgorin bound on the spectral radius of H for instance k when
+ * |E| <= e_max: the largest absolute row sum of eq. h_matrix. */
+double tdse_lambda_max_bound(const tdse_ctx* ctx, int32_t inst, double e_max);
+
+/* Imaginary-axis stability limit y_P of the degree-P Taylor polynomial: the
+ * largest y with |sum_{k<=P} (i y')^k / k!| <= 1 + 1e-12 for all y' <= y. */
+double tdse_taylor_stability_limit(int32_t order);
+
+/* Kernel timing with HIP events recorded around every launch of the named
+ * kernel family on the bound stream ("taylor_term", "rk4_stage",
+ * "observables", "lanczos_sweep_a", "apply_h").  tdse_timing_enable(ctx, 1)
+ * clears the counters; tdse_timing_read synchronises the stream and returns
+ * the number of launches and their summed duration in milliseconds. */
+tdse_status tdse_timing_enable(tdse_ctx* ctx, int32_t enable);
+tdse_status tdse_timing_read(tdse_ctx* ctx, const char* kernel, int64_t* launches,
+                             double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDSE_H */

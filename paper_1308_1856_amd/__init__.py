@@ -1,0 +1,308 @@
+"""Python binding of libtdse (MI355X finite-difference TDSE library).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libtdse.so`` (built by ``paper_1308_1856_amd/build.py``).
+PyTorch provides device memory and the stream.  The functions mirror the C
+ABI of ``include/tdse.h`` one to one; ``Propagator`` bundles a context with
+its torch-owned buffers.  There is no CPU fallback: if the library is not
+built, importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdse.so")
+
+TDSE_OK = 0
+STATUS = {0: "TDSE_OK", -1: "TDSE_E_INVALID", -2: "TDSE_E_NOMEM", -3: "TDSE_E_HIP",
+          -4: "TDSE_E_UNSTABLE", -6: "TDSE_E_NONFINITE", -7: "TDSE_E_WORKSPACE",
+          -8: "TDSE_E_UNBOUND"}
+FP64, FP32 = 0, 1
+METHOD_TAYLOR, METHOD_RK4, METHOD_LANCZOS = 0, 1, 2
+MAX_STATES = 15
+OBS_FIELDS = ("t", "e_field", "norm", "p_g", "p_bound", "p_ion", "dipole", "accel")
+OBS_DOUBLES = len(OBS_FIELDS) + MAX_STATES
+
+EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_instances",
+            "tdse_state_offset", "tdse_state_bytes", "tdse_workspace_bytes", "tdse_bind",
+            "tdse_set_state", "tdse_get_state", "tdse_apply_H", "tdse_step_taylor",
+            "tdse_step_rk4", "tdse_step_lanczos", "tdse_observables", "tdse_lambda_max_bound",
+            "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read")
+
+
+class TdseError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("n_r", ctypes.c_int32), ("lmax", ctypes.c_int32), ("stencil", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("dr", ctypes.c_double), ("z_nuc", ctypes.c_double),
+                ("r_ion", ctypes.c_double)]
+
+
+class Pulse(ctypes.Structure):
+    _fields_ = [("e0", ctypes.c_double), ("omega", ctypes.c_double), ("n_cycles", ctypes.c_double),
+                ("cep", ctypes.c_double), ("t_on", ctypes.c_double)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in OBS_FIELDS] + [("pop", ctypes.c_double * MAX_STATES)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i32, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int64
+    ctxp = ctypes.c_void_p
+    sig = {
+        "tdse_init_grid": ([ctypes.POINTER(GridDesc), i32, ctypes.POINTER(ctxp)], i32),
+        "tdse_destroy": ([ctxp], None),
+        "tdse_last_error": ([ctxp], ctypes.c_char_p),
+        "tdse_num_instances": ([ctxp], i32),
+        "tdse_state_offset": ([ctxp, i32], i64),
+        "tdse_state_bytes": ([ctxp], ctypes.c_size_t),
+        "tdse_workspace_bytes": ([ctxp, i32, i32], ctypes.c_size_t),
+        "tdse_bind": ([ctxp, vp, vp, ctypes.c_size_t, vp], i32),
+        "tdse_set_state": ([ctxp, i32, dp], i32),
+        "tdse_get_state": ([ctxp, i32, dp], i32),
+        "tdse_apply_H": ([ctxp, dp, vp, vp], i32),
+        "tdse_step_taylor": ([ctxp, ctypes.POINTER(Pulse), dp, dp, i32, i32, i32, vp], i32),
+        "tdse_step_rk4": ([ctxp, ctypes.POINTER(Pulse), dp, dp, i32, i32, vp], i32),
+        "tdse_step_lanczos": ([ctxp, ctypes.POINTER(Pulse), dp, dp, i32, i32, i32, vp], i32),
+        "tdse_observables": ([ctxp, ctypes.POINTER(Pulse), dp, ctypes.POINTER(Obs)], i32),
+        "tdse_lambda_max_bound": ([ctxp, i32, ctypes.c_double], ctypes.c_double),
+        "tdse_taylor_stability_limit": ([i32], ctypes.c_double),
+        "tdse_timing_enable": ([ctxp, i32], i32),
+        "tdse_timing_read": ([ctxp, ctypes.c_char_p, ctypes.POINTER(i64), dp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes, f.restype = args, res
+    return L
+
+
+lib = _load()
+
+
+def _check(ctx, code: int):
+    if code != TDSE_OK:
+        msg = lib.tdse_last_error(ctx).decode() if ctx else ""
+        raise TdseError(code, msg)
+
+
+def _dvec(values, n: int):
+    arr = (ctypes.c_double * n)(*[float(v) for v in values])
+    return arr
+
+
+def _pulses(pulses: Sequence) -> ctypes.Array:
+    arr = (Pulse * len(pulses))()
+    for k, p in enumerate(pulses):
+        arr[k] = Pulse(float(p.e0), float(p.omega), float(p.n_cycles), float(p.cep), float(p.t_on))
+    return arr
+
+
+# ------------------------------------------------------------------------
+# thin wrappers with the C names
+# ------------------------------------------------------------------------
+
+def tdse_init_grid(grids: Sequence[GridDesc]) -> ctypes.c_void_p:
+    arr = (GridDesc * len(grids))(*grids)
+    ctx = ctypes.c_void_p()
+    code = lib.tdse_init_grid(arr, len(grids), ctypes.byref(ctx))
+    if code != TDSE_OK:
+        raise TdseError(code, "tdse_init_grid rejected the grid description")
+    return ctx
+
+
+def tdse_destroy(ctx):
+    lib.tdse_destroy(ctx)
+
+
+def tdse_bind(ctx, d_state: int, d_work: int, work_bytes: int, stream: int):
+    _check(ctx, lib.tdse_bind(ctx, d_state, d_work, work_bytes, stream))
+
+
+def tdse_set_state(ctx, inst: int, host: Optional[np.ndarray]):
+    if host is None:
+        _check(ctx, lib.tdse_set_state(ctx, inst, None))
+        return
+    h = np.ascontiguousarray(host, dtype=np.complex128)
+    _check(ctx, lib.tdse_set_state(ctx, inst, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+
+def tdse_get_state(ctx, inst: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.complex128)
+    _check(ctx, lib.tdse_get_state(ctx, inst, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def tdse_apply_H(ctx, e_field: Sequence[float], d_in: int, d_out: int):
+    n = lib.tdse_num_instances(ctx)
+    _check(ctx, lib.tdse_apply_H(ctx, _dvec(e_field, n), d_in, d_out))
+
+
+def tdse_step_taylor(ctx, pulses, t0, dt, order, nsteps, obs_every, d_obs):
+    n = lib.tdse_num_instances(ctx)
+    _check(ctx, lib.tdse_step_taylor(ctx, _pulses(pulses), _dvec(t0, n), _dvec(dt, n), order,
+                                     nsteps, obs_every, d_obs))
+
+
+def tdse_step_rk4(ctx, pulses, t0, dt, nsteps, obs_every, d_obs):
+    n = lib.tdse_num_instances(ctx)
+    _check(ctx, lib.tdse_step_rk4(ctx, _pulses(pulses), _dvec(t0, n), _dvec(dt, n), nsteps,
+                                  obs_every, d_obs))
+
+
+def tdse_step_lanczos(ctx, pulses, t0, dt, m, nsteps, obs_every, d_obs):
+    n = lib.tdse_num_instances(ctx)
+    _check(ctx, lib.tdse_step_lanczos(ctx, _pulses(pulses), _dvec(t0, n), _dvec(dt, n), m,
+                                      nsteps, obs_every, d_obs))
+
+
+def tdse_observables(ctx, pulses, t) -> np.ndarray:
+    n = lib.tdse_num_instances(ctx)
+    out = (Obs * n)()
+    _check(ctx, lib.tdse_observables(ctx, _pulses(pulses), _dvec(t, n), out))
+    return np.frombuffer(out, dtype=np.float64).reshape(n, OBS_DOUBLES).copy()
+
+
+def tdse_lambda_max_bound(ctx, inst: int, e_max: float) -> float:
+    return lib.tdse_lambda_max_bound(ctx, inst, float(e_max))
+
+
+def tdse_taylor_stability_limit(order: int) -> float:
+    return lib.tdse_taylor_stability_limit(int(order))
+
+
+def tdse_timing_enable(ctx, enable: bool):
+    _check(ctx, lib.tdse_timing_enable(ctx, 1 if enable else 0))
+
+
+def tdse_timing_read(ctx, kernel: str):
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(ctx, lib.tdse_timing_read(ctx, kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+# ------------------------------------------------------------------------
+# convenience: a context with torch-owned device buffers
+# ------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Grid:
+    n: int
+    lmax: int
+    dr: float
+    stencil: int = 3
+    precision: int = FP64
+    z: float = 1.0
+    r_ion: float = 50.0
+
+    def desc(self) -> GridDesc:
+        return GridDesc(self.n, self.lmax, self.stencil, self.precision, self.dr, self.z, self.r_ion)
+
+
+class Propagator:
+    """One context (n_inst instances) plus its state and workspace on a GPU.
+
+    `methods` lists (method, order_or_m) pairs the workspace must serve.
+    """
+
+    def __init__(self, grids: Sequence[Grid], methods=((METHOD_TAYLOR, 8),), device="cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.grids = list(grids)
+        self.ctx = tdse_init_grid([g.desc() for g in self.grids])
+        self.n_inst = len(self.grids)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        sbytes = lib.tdse_state_bytes(self.ctx)
+        wbytes = max(lib.tdse_workspace_bytes(self.ctx, m, o) for m, o in methods)
+        # byte buffers (torch's caching allocator aligns to >= 512 B)
+        self.state = torch.zeros(sbytes, dtype=torch.uint8, device=self.device)
+        self.work = torch.zeros(wbytes, dtype=torch.uint8, device=self.device)
+        self.work_bytes = wbytes
+        tdse_bind(self.ctx, self.state.data_ptr(), self.work.data_ptr(), wbytes,
+                  self.stream.cuda_stream)
+        self.offsets = [lib.tdse_state_offset(self.ctx, k) for k in range(self.n_inst)]
+        self.elem = 16 if self.grids[0].precision == FP64 else 8
+
+    def close(self):
+        if self.ctx:
+            self.torch.cuda.synchronize(self.device)
+            tdse_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # state
+    def set_state(self, inst: int, psi: Optional[np.ndarray] = None):
+        tdse_set_state(self.ctx, inst, psi)
+
+    def get_state(self, inst: int) -> np.ndarray:
+        g = self.grids[inst]
+        return tdse_get_state(self.ctx, inst, (g.lmax + 1) * g.n)
+
+    def new_vector(self):
+        """A zeroed device vector shaped like the state (for apply_H)."""
+        return self.torch.zeros_like(self.state)
+
+    def obs_buffer(self, nsteps: int, obs_every: int):
+        n_rec = nsteps // obs_every if obs_every > 0 else 0
+        return self.torch.zeros((self.n_inst, max(n_rec, 1), OBS_DOUBLES), dtype=self.torch.float64,
+                                device=self.device)
+
+    def _per_inst(self, v):
+        return [v] * self.n_inst if np.isscalar(v) else list(v)
+
+    def apply_H(self, e_field, d_in, d_out):
+        tdse_apply_H(self.ctx, self._per_inst(e_field), d_in.data_ptr(), d_out.data_ptr())
+
+    def step_taylor(self, pulses, t0, dt, order, nsteps, obs_every=0, obs=None):
+        ptr = obs.data_ptr() if obs is not None else None
+        tdse_step_taylor(self.ctx, self._pulse_list(pulses), self._per_inst(t0),
+                         self._per_inst(dt), order, nsteps, obs_every, ptr)
+
+    def step_rk4(self, pulses, t0, dt, nsteps, obs_every=0, obs=None):
+        ptr = obs.data_ptr() if obs is not None else None
+        tdse_step_rk4(self.ctx, self._pulse_list(pulses), self._per_inst(t0), self._per_inst(dt),
+                      nsteps, obs_every, ptr)
+
+    def step_lanczos(self, pulses, t0, dt, m, nsteps, obs_every=0, obs=None):
+        ptr = obs.data_ptr() if obs is not None else None
+        tdse_step_lanczos(self.ctx, self._pulse_list(pulses), self._per_inst(t0),
+                          self._per_inst(dt), m, nsteps, obs_every, ptr)
+
+    def observables(self, pulses, t) -> np.ndarray:
+        return tdse_observables(self.ctx, self._pulse_list(pulses), self._per_inst(t))
+
+    def _pulse_list(self, pulses):
+        if isinstance(pulses, (list, tuple)):
+            return list(pulses)
+        return [pulses] * self.n_inst
+
+    def lambda_max_bound(self, inst: int, e_max: float) -> float:
+        return tdse_lambda_max_bound(self.ctx, inst, e_max)
+
+    def timing(self, enable: bool):
+        tdse_timing_enable(self.ctx, enable)
+
+    def timing_read(self, kernel: str):
+        return tdse_timing_read(self.ctx, kernel)

@@ -1,0 +1,124 @@
+// Device helpers: complex loads/stores with FP64 registers, wave64/block
+// reductions in FP64 with a fixed (timing-independent) order.
+#pragma once
+
+#include "tdse_internal.hpp"
+
+namespace tdse {
+
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = double2; };
+template <> struct Cplx<float> { using type = float2; };
+
+__device__ __forceinline__ double2 ldc(const double2* p, int64_t k) { return p[k]; }
+__device__ __forceinline__ double2 ldc(const float2* p, int64_t k)
+{
+    const float2 v = p[k];
+    return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ void stc(double2* p, int64_t k, double2 v) { p[k] = v; }
+__device__ __forceinline__ void stc(float2* p, int64_t k, double2 v)
+{
+    p[k] = make_float2((float)v.x, (float)v.y);
+}
+
+__device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
+
+// Sum over the 64 lanes of a wave; every lane gets the total.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide sums of NQ values for a kBlock-thread block.  Thread q < NQ of
+// the block receives the sum of value q in `out_q` (others get 0).  The
+// summation tree depends only on thread indices, so results are bitwise
+// reproducible.  Must be reached by every thread of the block.
+template <int NQ>
+__device__ __forceinline__ double block_sum(double (&v)[NQ], double* lds /* [kBlock/64][NQ] */)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) lds[wave * NQ + q] = s;
+    }
+    __syncthreads();
+    double out = 0.0;
+    if (threadIdx.x < NQ) {
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) out += lds[w * NQ + threadIdx.x];
+    }
+    __syncthreads();
+    return out;
+}
+
+// The tile handled by this workgroup.
+__device__ __forceinline__ Tile my_tile(const SweepGeom& g) { return g.tiles[g.order[blockIdx.x]]; }
+__device__ __forceinline__ int my_tile_index(const SweepGeom& g) { return g.order[blockIdx.x]; }
+
+// Stencil weights of -1/2 D2 (zero-padded 3- or 5-point second difference).
+template <int S> struct Kin;
+template <> struct Kin<1> {
+    static constexpr double c0 = 1.0, c1 = -0.5, c2 = 0.0;
+};
+template <> struct Kin<2> {
+    static constexpr double c0 = 30.0 / 24.0, c1 = -16.0 / 24.0, c2 = 1.0 / 24.0;
+};
+
+// Per-thread radial constants.
+struct RadialPoint {
+    double r, inv_r2, z_over_r;
+};
+__device__ __forceinline__ RadialPoint radial_point(const Inst& I, int i)
+{
+    RadialPoint p;
+    p.r = (double)(i + 1) * I.dr;
+    const double inv_r = 1.0 / p.r;
+    p.inv_r2 = inv_r * inv_r;
+    p.z_over_r = I.z * inv_r;
+    return p;
+}
+
+// (H f)_{l,i} from the centre value, its radial neighbours (already zero
+// outside the box) and the values of rows l-1, l+1 at the same radius.
+template <int S>
+__device__ __forceinline__ double2 h_point(double2 cur, double2 m1, double2 p1, double2 m2, double2 p2,
+                                           double2 lm, double2 lp, double kin_scale, double v,
+                                           double er, double kl, double klp)
+{
+    const double d0 = Kin<S>::c0 * kin_scale + v;
+    const double d1 = Kin<S>::c1 * kin_scale;
+    const double d2 = Kin<S>::c2 * kin_scale;
+    const double ekl = er * kl, eklp = er * klp;
+    double2 h;
+    h.x = d0 * cur.x + d1 * (m1.x + p1.x) + ekl * lm.x + eklp * lp.x;
+    h.y = d0 * cur.y + d1 * (m1.y + p1.y) + ekl * lm.y + eklp * lp.y;
+    if (S == 2) {
+        h.x += d2 * (m2.x + p2.x);
+        h.y += d2 * (m2.y + p2.y);
+    }
+    return h;
+}
+
+// Radial neighbours of element i of a row (zero outside [0, n)).
+template <int S, typename C>
+struct Neighbours {
+    double2 m1, p1, m2, p2;
+    __device__ __forceinline__ void load(const C* row, int i, int n)
+    {
+        m1 = (i >= 1) ? ldc(row, i - 1) : zero2();
+        p1 = (i + 1 < n) ? ldc(row, i + 1) : zero2();
+        if (S == 2) {
+            m2 = (i >= 2) ? ldc(row, i - 2) : zero2();
+            p2 = (i + 2 < n) ? ldc(row, i + 2) : zero2();
+        } else {
+            m2 = p2 = zero2();
+        }
+    }
+};
+
+}  // namespace tdse

@@ -1,0 +1,445 @@
+// Lanczos propagator (Sec. 5.2 Lanczos.c; appendix "Lanczos methods").
+//
+// Per step and instance: q_0 = F/||F||; for j = 0..m-1:
+//   sweep A:  w = H(t_mid) q_j, partial sums of h_i = <q_i, w>, i <= j
+//   finish A: h_i, alpha_j = Re h_j
+//   sweep B:  q_{j+1} <- w - sum_i h_i q_i  (one classical Gram-Schmidt pass
+//             against every earlier vector: three-term recurrence plus full
+//             re-orthogonalisation), partial sums of ||.||^2
+//   finish B: beta_j, scale of q_{j+1} = 1/beta_j, breakdown test
+// then the eigen-decomposition of the tridiagonal T (one wave per instance,
+// implicit QR with Wilkinson shifts) gives c = S exp(-i Lambda dt) S^T e_1 and
+// F <- ||F|| sum_k c_k q_k.
+//
+// Basis vectors are stored unnormalised (FP64 or FP32) and scaled on load by
+// FP64 factors; q_0 is the state buffer itself.  All inner products, norms
+// and coefficients are FP64.
+#include "device_common.hpp"
+
+namespace tdse {
+
+template <typename C>
+__device__ __forceinline__ const C* basis_vec(const C* psi, const C* basis, int64_t stride, int j)
+{
+    return (j == 0) ? psi : basis + (int64_t)(j - 1) * stride;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_lz_norm(SweepGeom g, const typename Cplx<T>::type* __restrict__ psi, double* __restrict__ partial)
+{
+    __shared__ double lds[kBlock / 64];
+    const int t = my_tile_index(g);
+    const Tile tile = g.tiles[t];
+    const Inst& I = g.inst[tile.inst];
+    const int i = tile.r0 + (int)threadIdx.x;
+    double acc[1] = {0.0};
+    if (i < I.n) {
+        for (int l = tile.l0; l < tile.l1; ++l) {
+            const double2 v = ldc(psi, I.off + (int64_t)l * I.n + i);
+            acc[0] += v.x * v.x + v.y * v.y;
+        }
+    }
+    const double s = block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partial[t] = s;
+}
+
+// One workgroup per instance: sum nq partials of stride `stride` over the
+// instance's tiles in a fixed order; thread q < nq receives sum q.
+template <int NQ>
+__device__ __forceinline__ double instance_sum(const Inst& I, const double* partial, int stride,
+                                               int nq, double* lds)
+{
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int t = I.tile_begin + (int)threadIdx.x; t < I.tile_end; t += kBlock) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q < nq) acc[q] += partial[(int64_t)t * stride + q];
+    }
+    return block_sum<NQ>(acc, lds);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_lz_norm_finish(SweepGeom g, const double* __restrict__ partial, LanczosScalars* __restrict__ scs)
+{
+    __shared__ double lds[kBlock / 64];
+    const int k = blockIdx.x;
+    const double s = instance_sum<1>(g.inst[k], partial, 1, 1, lds);
+    if (threadIdx.x == 0) {
+        LanczosScalars& sc = scs[k];
+        const double nrm = sqrt(s);
+        sc.norm0 = nrm;
+        sc.meff = 0;
+        sc.done = (nrm > 0.0) ? 0 : 1;
+        sc.scale[0] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+    }
+}
+
+// Sweep A for iteration j: w = H q_j over the tile rows, then the partial
+// sums of <q_i, w> for i <= j (w re-read from the lines this thread just
+// wrote, eight basis vectors at a time).
+template <int S, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
+             const typename Cplx<T>::type* basis, int64_t stride, typename Cplx<T>::type* w,
+             const double* __restrict__ step, const LanczosScalars* __restrict__ scs,
+             double* __restrict__ partial)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int JB = 8;
+    __shared__ double lds[(kBlock / 64) * 2 * JB];
+    const int t = my_tile_index(g);
+    const Tile tile = g.tiles[t];
+    const Inst& I = g.inst[tile.inst];
+    const LanczosScalars& sc = scs[tile.inst];
+    if (sc.done) return;  // uniform over the workgroup
+    const int n = I.n;
+    const int i = tile.r0 + (int)threadIdx.x;
+    const bool active = i < n;
+    const C* qj = basis_vec(psi, basis, stride, j);
+    const double sj = sc.scale[j];
+
+    if (active) {
+        const RadialPoint rp = radial_point(I, i);
+        const double er = step_value(step, g.n_inst, kEMid, tile.inst) * rp.r;
+        const int64_t base = I.off;
+        double2 prev = (tile.l0 > 0) ? ldc(qj, base + (int64_t)(tile.l0 - 1) * n + i) : zero2();
+        double2 cur = ldc(qj, base + (int64_t)tile.l0 * n + i);
+        for (int l = tile.l0; l < tile.l1; ++l) {
+            const int64_t row = base + (int64_t)l * n;
+            const double2 next = (l < I.lmax) ? ldc(qj, row + n + i) : zero2();
+            Neighbours<S, C> nb;
+            nb.load(qj + row, i, n);
+            const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
+            double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
+                                   g.kappa[l], g.kappa[l + 1]);
+            h.x *= sj;
+            h.y *= sj;
+            stc(w, row + i, h);
+            prev = cur;
+            cur = next;
+        }
+    }
+    const int stride_p = 2 * m;
+    for (int i0 = 0; i0 <= j; i0 += JB) {
+        double acc[2 * JB];
+#pragma unroll
+        for (int q = 0; q < 2 * JB; ++q) acc[q] = 0.0;
+        if (active) {
+            for (int l = tile.l0; l < tile.l1; ++l) {
+                const int64_t k = I.off + (int64_t)l * n + i;
+                const double2 wv = ldc(w, k);
+#pragma unroll
+                for (int u = 0; u < JB; ++u) {
+                    if (i0 + u <= j) {
+                        const double s = sc.scale[i0 + u];
+                        const double2 q = ldc(basis_vec(psi, basis, stride, i0 + u), k);
+                        // conj(s q) w
+                        acc[2 * u] += s * (q.x * wv.x + q.y * wv.y);
+                        acc[2 * u + 1] += s * (q.x * wv.y - q.y * wv.x);
+                    }
+                }
+            }
+        }
+        const double s = block_sum<2 * JB>(acc, lds);
+        if ((int)threadIdx.x < 2 * JB && i0 + (int)threadIdx.x / 2 <= j)
+            partial[(int64_t)t * stride_p + 2 * i0 + threadIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_lz_finish_a(SweepGeom g, int j, int m, const double* __restrict__ partial,
+              LanczosScalars* __restrict__ scs)
+{
+    constexpr int JB = 8;
+    __shared__ double lds[(kBlock / 64) * 2 * JB];
+    const int k = blockIdx.x;
+    LanczosScalars& sc = scs[k];
+    if (sc.done) return;
+    const Inst& I = g.inst[k];
+    for (int i0 = 0; i0 <= j; i0 += JB) {
+        const int nq = min(2 * JB, 2 * (j + 1 - i0));
+        const double s = instance_sum<2 * JB>(I, partial + 2 * i0, 2 * m, nq, lds);
+        if ((int)threadIdx.x < nq) sc.h[2 * i0 + threadIdx.x] = s;
+        if ((int)threadIdx.x == 2 * (j - i0)) sc.alpha[j] = s;  // Re <q_j, H q_j>
+    }
+    if (threadIdx.x == 0) sc.meff = j + 1;
+}
+
+// q_{j+1} (stored unnormalised) = w - sum_{i<=j} h_i q_i, and ||.||^2 partials.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_lz_sweep_b(SweepGeom g, int j, const typename Cplx<T>::type* psi, typename Cplx<T>::type* basis,
+             int64_t stride, const typename Cplx<T>::type* __restrict__ w,
+             const LanczosScalars* __restrict__ scs, double* __restrict__ partial)
+{
+    __shared__ double lds[kBlock / 64];
+    const int t = my_tile_index(g);
+    const Tile tile = g.tiles[t];
+    const Inst& I = g.inst[tile.inst];
+    const LanczosScalars& sc = scs[tile.inst];
+    if (sc.done) return;
+    const int i = tile.r0 + (int)threadIdx.x;
+    typename Cplx<T>::type* out = basis + (int64_t)j * stride;  // vector j+1
+    double acc[1] = {0.0};
+    if (i < I.n) {
+        for (int l = tile.l0; l < tile.l1; ++l) {
+            const int64_t k = I.off + (int64_t)l * I.n + i;
+            double2 v = ldc(w, k);
+            for (int q = 0; q <= j; ++q) {
+                const double s = sc.scale[q];
+                const double hr = s * sc.h[2 * q], hi = s * sc.h[2 * q + 1];
+                const double2 b = ldc(basis_vec(psi, (const typename Cplx<T>::type*)basis, stride, q), k);
+                v.x -= hr * b.x - hi * b.y;
+                v.y -= hr * b.y + hi * b.x;
+            }
+            stc(out, k, v);
+            // the norm is taken of the stored (possibly rounded) vector
+            const double2 vs = ldc(out, k);
+            acc[0] += vs.x * vs.x + vs.y * vs.y;
+        }
+    }
+    const double s = block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partial[t] = s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_lz_finish_b(SweepGeom g, int j, const double* __restrict__ partial, LanczosScalars* __restrict__ scs)
+{
+    __shared__ double lds[kBlock / 64];
+    const int k = blockIdx.x;
+    LanczosScalars& sc = scs[k];
+    if (sc.done) return;
+    const double s = instance_sum<1>(g.inst[k], partial, 1, 1, lds);
+    if (threadIdx.x == 0) {
+        const double b = sqrt(s);
+        sc.beta[j] = b;
+        if (!(b > g.inst[k].breakdown)) {
+            sc.done = 1;  // invariant subspace: keep meff = j + 1
+        } else {
+            sc.scale[j + 1] = 1.0 / b;
+        }
+    }
+}
+
+// Givens pair (c, s) with [c s; -s c]^T [x; z] = [r; 0] (Golub & Van Loan).
+__device__ __forceinline__ void givens(double x, double z, double& c, double& s)
+{
+    if (z == 0.0) {
+        c = 1.0;
+        s = 0.0;
+    } else if (fabs(z) > fabs(x)) {
+        const double tau = -x / z;
+        s = 1.0 / sqrt(1.0 + tau * tau);
+        c = s * tau;
+    } else {
+        const double tau = -z / x;
+        c = 1.0 / sqrt(1.0 + tau * tau);
+        s = c * tau;
+    }
+}
+
+// One wave per instance.  Every lane runs the same scalar QR iteration on
+// (a, b) (so no lane waits for another) and applies each rotation to its own
+// row of the eigenvector matrix S held in LDS.
+__global__ void __launch_bounds__(64)
+k_lz_expm(SweepGeom g, const double* __restrict__ step, LanczosScalars* __restrict__ scs)
+{
+    constexpr int LD = kMaxKrylov + 1;
+    __shared__ double sm[kMaxKrylov * LD];
+    const int inst = blockIdx.x;
+    LanczosScalars& sc = scs[inst];
+    const int m = sc.meff;
+    const int lane = threadIdx.x;
+    const double dt = step_value(step, g.n_inst, kDt, inst);
+    double a[kMaxKrylov], b[kMaxKrylov];
+    for (int k = 0; k < m; ++k) {
+        a[k] = sc.alpha[k];
+        b[k] = (k + 1 < m) ? sc.beta[k] : 0.0;
+    }
+    double* srow = sm + lane * LD;
+    if (lane < m)
+        for (int k = 0; k < m; ++k) srow[k] = (k == lane) ? 1.0 : 0.0;
+
+    const double eps = 2.220446049250313e-16;
+    int hi = m - 1;
+    int iter = 0;
+    while (hi > 0 && iter < 40 * m) {
+        if (fabs(b[hi - 1]) <= eps * (fabs(a[hi - 1]) + fabs(a[hi]))) {
+            b[hi - 1] = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && fabs(b[lo - 1]) > eps * (fabs(a[lo - 1]) + fabs(a[lo]))) --lo;
+        if (lo > 0) b[lo - 1] = 0.0;
+        // Wilkinson shift: eigenvalue of the trailing 2x2 closer to a[hi]
+        const double d = 0.5 * (a[hi - 1] - a[hi]);
+        const double bb = b[hi - 1];
+        const double den = d + copysign(sqrt(d * d + bb * bb), d);
+        const double mu = a[hi] - bb * bb / den;
+        double x = a[lo] - mu, z = b[lo], bulge = 0.0;
+        for (int k = lo; k < hi; ++k) {
+            double c, s;
+            givens(x, z, c, s);
+            if (k > lo) b[k - 1] = c * b[k - 1] - s * bulge;
+            const double ap = a[k], aq = a[k + 1], bp = b[k];
+            a[k] = c * c * ap - 2.0 * c * s * bp + s * s * aq;
+            a[k + 1] = s * s * ap + 2.0 * c * s * bp + c * c * aq;
+            b[k] = c * s * (ap - aq) + (c * c - s * s) * bp;
+            if (k + 1 < hi) {
+                bulge = -s * b[k + 1];
+                b[k + 1] = c * b[k + 1];
+                x = b[k];
+                z = bulge;
+            }
+            if (lane < m) {
+                const double sp = srow[k], sq = srow[k + 1];
+                srow[k] = c * sp - s * sq;
+                srow[k + 1] = s * sp + c * sq;
+            }
+        }
+        ++iter;
+    }
+    __syncthreads();
+    // c_k = sum_j S[k][j] exp(-i lambda_j dt) S[0][j], weighted by ||F|| and
+    // the storage scale of basis vector k
+    if (lane < m) {
+        double cr = 0.0, ci = 0.0;
+        for (int jj = 0; jj < m; ++jj) {
+            double sn, cs;
+            sincos(a[jj] * dt, &sn, &cs);
+            const double w = srow[jj] * sm[jj];  // S[k][j] * S[0][j]
+            cr += w * cs;
+            ci -= w * sn;
+        }
+        const double f = sc.norm0 * sc.scale[lane];
+        sc.coef[2 * lane] = f * cr;
+        sc.coef[2 * lane + 1] = f * ci;
+    }
+}
+
+// F <- sum_k coef_k stored_k  (stored_0 is F itself: read before written).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_lz_recombine(SweepGeom g, typename Cplx<T>::type* psi, const typename Cplx<T>::type* __restrict__ basis,
+               int64_t stride, const LanczosScalars* __restrict__ scs)
+{
+    const Tile tile = my_tile(g);
+    const Inst& I = g.inst[tile.inst];
+    const LanczosScalars& sc = scs[tile.inst];
+    const int i = tile.r0 + (int)threadIdx.x;
+    if (i >= I.n) return;
+    const int m = sc.meff;
+    for (int l = tile.l0; l < tile.l1; ++l) {
+        const int64_t k = I.off + (int64_t)l * I.n + i;
+        double2 v = zero2();
+        for (int q = 0; q < m; ++q) {
+            const double cr = sc.coef[2 * q], ci = sc.coef[2 * q + 1];
+            const double2 b = ldc(basis_vec((const typename Cplx<T>::type*)psi, basis, stride, q), k);
+            v.x += cr * b.x - ci * b.y;
+            v.y += cr * b.y + ci * b.x;
+        }
+        stc(psi, k, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_lz_norm(int prec, const SweepGeom& g, const void* psi, double* partial,
+                          hipStream_t st)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL((k_lz_norm<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const double2*>(psi), partial);
+    else
+        hipLaunchKernelGGL((k_lz_norm<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const float2*>(psi), partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_lz_norm_finish(const SweepGeom& g, const double* partial, LanczosScalars* sc,
+                                 hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lz_norm_finish, dim3(g.n_inst), dim3(kBlock), 0, st, g, partial, sc);
+    return hipGetLastError();
+}
+
+template <int S, typename T>
+static hipError_t sweep_a_t(const SweepGeom& g, int j, int m, const void* psi, const void* basis,
+                            int64_t stride, void* w, const double* step, const LanczosScalars* sc,
+                            double* partial, hipStream_t st)
+{
+    using C = typename Cplx<T>::type;
+    hipLaunchKernelGGL((k_lz_sweep_a<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j, m,
+                       static_cast<const C*>(psi), static_cast<const C*>(basis), stride,
+                       static_cast<C*>(w), step, sc, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_lz_sweep_a(int prec, int S, const SweepGeom& g, int j, int m, const void* psi,
+                             const void* basis, int64_t vec_stride, void* w, const double* step,
+                             const LanczosScalars* sc, double* partial, hipStream_t st)
+{
+    if (prec == 0)
+        return S == 1 ? sweep_a_t<1, double>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st)
+                      : sweep_a_t<2, double>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st);
+    return S == 1 ? sweep_a_t<1, float>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st)
+                  : sweep_a_t<2, float>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st);
+}
+
+hipError_t launch_lz_finish_a(const SweepGeom& g, int j, int m, const double* partial,
+                              LanczosScalars* sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lz_finish_a, dim3(g.n_inst), dim3(kBlock), 0, st, g, j, m, partial, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_lz_sweep_b(int prec, const SweepGeom& g, int j, const void* psi,
+                             const void* basis, int64_t vec_stride, const void* w,
+                             const LanczosScalars* sc, double* partial, hipStream_t st)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL((k_lz_sweep_b<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j,
+                           static_cast<const double2*>(psi),
+                           static_cast<double2*>(const_cast<void*>(basis)), vec_stride,
+                           static_cast<const double2*>(w), sc, partial);
+    else
+        hipLaunchKernelGGL((k_lz_sweep_b<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j,
+                           static_cast<const float2*>(psi),
+                           static_cast<float2*>(const_cast<void*>(basis)), vec_stride,
+                           static_cast<const float2*>(w), sc, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_lz_finish_b(const SweepGeom& g, int j, const double* partial,
+                              LanczosScalars* sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lz_finish_b, dim3(g.n_inst), dim3(kBlock), 0, st, g, j, partial, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_lz_expm(const SweepGeom& g, const double* step, LanczosScalars* sc,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lz_expm, dim3(g.n_inst), dim3(64), 0, st, g, step, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_lz_recombine(int prec, const SweepGeom& g, int m, void* psi, const void* basis,
+                               int64_t vec_stride, const LanczosScalars* sc, hipStream_t st)
+{
+    (void)m;
+    if (prec == 0)
+        hipLaunchKernelGGL((k_lz_recombine<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<double2*>(psi), static_cast<const double2*>(basis),
+                           vec_stride, sc);
+    else
+        hipLaunchKernelGGL((k_lz_recombine<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<float2*>(psi), static_cast<const float2*>(basis), vec_stride,
+                           sc);
+    return hipGetLastError();
+}
+
+}  // namespace tdse

@@ -1,0 +1,191 @@
+// Sweep kernels: H.psi (Sec. 2, eq. h_matrix), one fused Horner term of the
+// Taylor step (Sec. 5.2, eq. Taylor) and the fused classic RK4 stage
+// (Sec. 5.2, eq. RKDeriv).
+//
+// Work decomposition: a workgroup of 256 threads owns 256 consecutive radial
+// points of rows [l0, l1) of one instance.  Each thread walks down its rows
+// keeping f_{l-1}, f_l, f_{l+1} at its radius in registers, so the l +- 1
+// coupling costs one new load per row; the radial neighbours come from the
+// same row through the L1/L2 caches.  All arithmetic is FP64; storage is FP64
+// or FP32.  HBM traffic per unknown and term: read `in` once, read psi once,
+// write out once.
+#include "device_common.hpp"
+
+namespace tdse {
+
+template <int S, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_hsweep(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
+         const typename Cplx<T>::type* psi, typename Cplx<T>::type* out,
+         const double* __restrict__ step, int term)
+{
+    using C = typename Cplx<T>::type;
+    const Tile tile = my_tile(g);
+    const Inst& I = g.inst[tile.inst];
+    const int n = I.n;
+    const int i = tile.r0 + (int)threadIdx.x;
+    if (i >= n) return;
+    const RadialPoint rp = radial_point(I, i);
+    const double e = step_value(step, g.n_inst, kEMid, tile.inst);
+    const double er = e * rp.r;
+    // Horner term: out = psi + (-i dt/term) h;  (-i c)(x + i y) = c y - i c x
+    const double c = (term > 0) ? step_value(step, g.n_inst, kDt, tile.inst) / (double)term : 0.0;
+    const int64_t base = I.off;
+
+    double2 prev = (tile.l0 > 0) ? ldc(in, base + (int64_t)(tile.l0 - 1) * n + i) : zero2();
+    double2 cur = ldc(in, base + (int64_t)tile.l0 * n + i);
+    for (int l = tile.l0; l < tile.l1; ++l) {
+        const int64_t row = base + (int64_t)l * n;
+        const double2 next = (l < I.lmax) ? ldc(in, row + n + i) : zero2();
+        Neighbours<S, C> nb;
+        nb.load(in + row, i, n);
+        const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
+        const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
+                                     g.kappa[l], g.kappa[l + 1]);
+        if (term > 0) {
+            const double2 p = ldc(psi, row + i);
+            stc(out, row + i, make_double2(p.x + c * h.y, p.y - c * h.x));
+        } else {
+            stc(out, row + i, h);
+        }
+        prev = cur;
+        cur = next;
+    }
+}
+
+// Classic RK4 with k_s = -i H(t_s) g_s:
+//   stage 0: g = psi                 acc  = psi + dt/6 k, gout = psi + dt/2 k
+//   stage 1: g = gin                 acc += dt/3 k,       gout = psi + dt/2 k
+//   stage 2: g = gin                 acc += dt/3 k,       gout = psi + dt k
+//   stage 3: g = gin                 psi  = acc + dt/6 k
+// H is taken at t_n (stage 0), t_n + dt/2 (stages 1, 2) and t_n + dt (stage 3).
+template <int S, typename T, int STAGE>
+__global__ void __launch_bounds__(kBlock)
+k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
+            typename Cplx<T>::type* psi, typename Cplx<T>::type* acc,
+            typename Cplx<T>::type* __restrict__ gout, const double* __restrict__ step)
+{
+    using C = typename Cplx<T>::type;
+    const Tile tile = my_tile(g);
+    const Inst& I = g.inst[tile.inst];
+    const int n = I.n;
+    const int i = tile.r0 + (int)threadIdx.x;
+    if (i >= n) return;
+    const RadialPoint rp = radial_point(I, i);
+    const int slot = (STAGE == 0) ? kEStart : (STAGE == 3 ? kEEnd : kEMid);
+    const double er = step_value(step, g.n_inst, slot, tile.inst) * rp.r;
+    const double dt = step_value(step, g.n_inst, kDt, tile.inst);
+    const double bw = (STAGE == 0 || STAGE == 3) ? dt / 6.0 : dt / 3.0;
+    const double aw = (STAGE == 2) ? dt : 0.5 * dt;
+    const int64_t base = I.off;
+
+    double2 prev = (tile.l0 > 0) ? ldc(gin, base + (int64_t)(tile.l0 - 1) * n + i) : zero2();
+    double2 cur = ldc(gin, base + (int64_t)tile.l0 * n + i);
+    for (int l = tile.l0; l < tile.l1; ++l) {
+        const int64_t row = base + (int64_t)l * n;
+        const double2 next = (l < I.lmax) ? ldc(gin, row + n + i) : zero2();
+        Neighbours<S, C> nb;
+        nb.load(gin + row, i, n);
+        const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
+        const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
+                                     g.kappa[l], g.kappa[l + 1]);
+        const double2 k = make_double2(h.y, -h.x);  // -i h
+        if (STAGE == 0) {
+            stc(acc, row + i, make_double2(cur.x + bw * k.x, cur.y + bw * k.y));
+            stc(gout, row + i, make_double2(cur.x + aw * k.x, cur.y + aw * k.y));
+        } else if (STAGE < 3) {
+            const double2 a = ldc(acc, row + i);
+            const double2 p = ldc(psi, row + i);
+            stc(acc, row + i, make_double2(a.x + bw * k.x, a.y + bw * k.y));
+            stc(gout, row + i, make_double2(p.x + aw * k.x, p.y + aw * k.y));
+        } else {
+            const double2 a = ldc(acc, row + i);
+            stc(psi, row + i, make_double2(a.x + bw * k.x, a.y + bw * k.y));
+        }
+        prev = cur;
+        cur = next;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_copy(SweepGeom g, const typename Cplx<T>::type* __restrict__ src, typename Cplx<T>::type* __restrict__ dst)
+{
+    const Tile tile = my_tile(g);
+    const Inst& I = g.inst[tile.inst];
+    const int i = tile.r0 + (int)threadIdx.x;
+    if (i >= I.n) return;
+    for (int l = tile.l0; l < tile.l1; ++l) {
+        const int64_t k = I.off + (int64_t)l * I.n + i;
+        dst[k] = src[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int S, typename T>
+static hipError_t hsweep_t(const SweepGeom& g, const void* in, const void* psi, void* out,
+                           const double* step, int term, hipStream_t st)
+{
+    using C = typename Cplx<T>::type;
+    hipLaunchKernelGGL((k_hsweep<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                       static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                       step, term);
+    return hipGetLastError();
+}
+
+hipError_t launch_hsweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi,
+                         void* out, const double* step, int term, hipStream_t st)
+{
+    if (prec == 0) return S == 1 ? hsweep_t<1, double>(g, in, psi, out, step, term, st)
+                                 : hsweep_t<2, double>(g, in, psi, out, step, term, st);
+    return S == 1 ? hsweep_t<1, float>(g, in, psi, out, step, term, st)
+                  : hsweep_t<2, float>(g, in, psi, out, step, term, st);
+}
+
+template <int S, typename T, int STAGE>
+static hipError_t rk4_t(const SweepGeom& g, const void* gin, const void* psi, void* acc, void* gout,
+                        const double* step, hipStream_t st)
+{
+    using C = typename Cplx<T>::type;
+    hipLaunchKernelGGL((k_rk4_stage<S, T, STAGE>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                       static_cast<const C*>(gin), static_cast<C*>(const_cast<void*>(psi)),
+                       static_cast<C*>(acc), static_cast<C*>(gout), step);
+    return hipGetLastError();
+}
+
+template <int S, typename T>
+static hipError_t rk4_s(const SweepGeom& g, int stage, const void* gin, const void* psi, void* acc,
+                        void* gout, const double* step, hipStream_t st)
+{
+    switch (stage) {
+        case 0: return rk4_t<S, T, 0>(g, gin, psi, acc, gout, step, st);
+        case 1: return rk4_t<S, T, 1>(g, gin, psi, acc, gout, step, st);
+        case 2: return rk4_t<S, T, 2>(g, gin, psi, acc, gout, step, st);
+        default: return rk4_t<S, T, 3>(g, gin, psi, acc, gout, step, st);
+    }
+}
+
+hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, const void* gin,
+                            const void* psi, void* acc, void* gout, const double* step,
+                            hipStream_t st)
+{
+    if (prec == 0) return S == 1 ? rk4_s<1, double>(g, stage, gin, psi, acc, gout, step, st)
+                                 : rk4_s<2, double>(g, stage, gin, psi, acc, gout, step, st);
+    return S == 1 ? rk4_s<1, float>(g, stage, gin, psi, acc, gout, step, st)
+                  : rk4_s<2, float>(g, stage, gin, psi, acc, gout, step, st);
+}
+
+hipError_t launch_copy(int prec, const SweepGeom& g, const void* src, void* dst, hipStream_t st)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL((k_copy<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const double2*>(src), static_cast<double2*>(dst));
+    else
+        hipLaunchKernelGGL((k_copy<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const float2*>(src), static_cast<float2*>(dst));
+    return hipGetLastError();
+}
+
+}  // namespace tdse

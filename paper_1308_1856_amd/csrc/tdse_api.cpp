@@ -1,0 +1,788 @@
+// C ABI of the TDSE library: context, tables, workspace layout, launches.
+// The declarations and their documentation are in include/tdse.h.
+#include "tdse.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "host_eigen.hpp"
+#include "tdse_internal.hpp"
+
+using namespace tdse;
+
+namespace {
+
+constexpr int kEtabSteps = 256;          // steps per uploaded chunk of per-step scalars
+constexpr size_t kAlign = 256;
+constexpr int kTileRows = 32;            // largest number of rows per tile
+constexpr int kTargetTiles = 2048;       // aim for >= 8 workgroups per CU on 256 CUs
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+const char* kTimedNames[] = {"taylor_term", "rk4_stage", "observables", "lanczos_sweep_a", "apply_h"};
+constexpr int kNumTimed = 5;
+
+}  // namespace
+
+struct tdse_ctx {
+    std::string err;
+    int n_inst = 0, stencil = 3, prec = 0;
+    size_t elem = 16;
+    std::vector<tdse_grid_desc> grids;
+    std::vector<Inst> inst;
+    std::vector<Tile> tiles;
+    std::vector<int32_t> order;
+    std::vector<double> kappa;
+    std::vector<double> radial;            // per instance: u0 row then n_states phi rows
+    std::vector<int> lmax_max;
+    int64_t state_elems = 0;
+    // device binding
+    bool bound = false;
+    char* d_state = nullptr;
+    char* d_work = nullptr;
+    size_t work_bytes = 0;
+    hipStream_t stream = nullptr;
+    // workspace layout (bytes from d_work)
+    size_t off_inst = 0, off_tiles = 0, off_order = 0, off_kappa = 0, off_radial = 0, off_step = 0,
+           off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0;
+    size_t partial_doubles = 0;
+    // pinned staging for the per-step scalars (double buffered)
+    double* h_step[2] = {nullptr, nullptr};
+    hipEvent_t step_ev[2] = {nullptr, nullptr};
+    bool step_ev_used[2] = {false, false};
+    int step_buf = 0;
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> ev_kind;
+
+    tdse_status fail(tdse_status code, const std::string& msg)
+    {
+        err = msg;
+        return code;
+    }
+    tdse_status hip_fail(hipError_t e, const char* what)
+    {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return TDSE_E_HIP;
+    }
+    SweepGeom geom() const
+    {
+        SweepGeom g;
+        g.inst = reinterpret_cast<const Inst*>(d_work + off_inst);
+        g.tiles = reinterpret_cast<const Tile*>(d_work + off_tiles);
+        g.order = reinterpret_cast<const int32_t*>(d_work + off_order);
+        g.kappa = reinterpret_cast<const double*>(d_work + off_kappa);
+        g.n_tiles = (int32_t)tiles.size();
+        g.n_inst = n_inst;
+        return g;
+    }
+    double* d_step() const { return reinterpret_cast<double*>(d_work + off_step); }
+    double* d_partial() const { return reinterpret_cast<double*>(d_work + off_partial); }
+    double* d_radial() const { return reinterpret_cast<double*>(d_work + off_radial); }
+    LanczosScalars* d_lz() const { return reinterpret_cast<LanczosScalars*>(d_work + off_lz); }
+    char* d_vec(int k) const { return d_work + off_vecs + (size_t)k * state_bytes(); }
+    size_t state_bytes() const { return align_up((size_t)state_elems * elem, kAlign); }
+    size_t vecs_needed(int method, int order_or_m) const
+    {
+        if (method == TDSE_METHOD_TAYLOR) return 2;
+        if (method == TDSE_METHOD_RK4) return 3;
+        if (method == TDSE_METHOD_LANCZOS) return (size_t)std::max(1, order_or_m);
+        return 0;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// timing helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+int timed_kind(const char* name)
+{
+    for (int k = 0; k < kNumTimed; ++k)
+        if (std::strcmp(name, kTimedNames[k]) == 0) return k;
+    return -1;
+}
+
+struct TimedLaunch {
+    tdse_ctx* c;
+    int kind;
+    size_t slot = (size_t)-1;
+    TimedLaunch(tdse_ctx* ctx, int k) : c(ctx), kind(k)
+    {
+        if (!c->timing) return;
+        if (c->ev_used == c->ev_pool.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+            c->ev_pool.emplace_back(a, b);
+            c->ev_kind.push_back(-1);
+        }
+        slot = c->ev_used++;
+        c->ev_kind[slot] = kind;
+        (void)hipEventRecord(c->ev_pool[slot].first, c->stream);
+    }
+    ~TimedLaunch()
+    {
+        if (slot != (size_t)-1) (void)hipEventRecord(c->ev_pool[slot].second, c->stream);
+    }
+};
+
+double taylor_poly_abs(int order, double y)
+{
+    std::complex<double> term(1.0, 0.0), sum(1.0, 0.0);
+    const std::complex<double> iy(0.0, y);
+    for (int k = 1; k <= order; ++k) {
+        term *= iy / (double)k;
+        sum += term;
+    }
+    return std::abs(sum);
+}
+
+}  // namespace
+
+extern "C" double tdse_taylor_stability_limit(int32_t order)
+{
+    static std::mutex mu;
+    static std::map<int, double> cache;
+    if (order < 1 || order > 16) return 0.0;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(order);
+    if (it != cache.end()) return it->second;
+    // scan upward in small steps, then bisect the first crossing of 1 + 1e-12
+    const double tol = 1.0 + 1e-12;
+    double y = 0.0;
+    const double h = 1e-4;
+    while (y < 10.0 && taylor_poly_abs(order, y + h) <= tol) y += h;
+    double a = y, b = y + h;
+    for (int i = 0; i < 60; ++i) {
+        const double mid = 0.5 * (a + b);
+        if (taylor_poly_abs(order, mid) <= tol) a = mid; else b = mid;
+    }
+    cache[order] = a;
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// context creation
+// ---------------------------------------------------------------------------
+static double gershgorin_bound(const tdse_grid_desc& g, double e_max)
+{
+    const double h2 = g.dr * g.dr;
+    const double dk = (g.stencil == 3) ? 1.0 / h2 : 30.0 / (24.0 * h2);
+    const double ok = (g.stencil == 3) ? 1.0 / h2 : 34.0 / (24.0 * h2);
+    double best = 0.0;
+    for (int l = 0; l <= g.lmax; ++l) {
+        const double kl = (l > 0) ? std::sqrt((double)l * l / (4.0 * l * l - 1.0)) : 0.0;
+        const double kp = (l < g.lmax) ? std::sqrt((double)(l + 1) * (l + 1) / (4.0 * (l + 1) * (l + 1) - 1.0)) : 0.0;
+        for (int i = 0; i < g.n_r; ++i) {
+            const double r = (double)(i + 1) * g.dr;
+            const double d = dk + 0.5 * (double)l * (l + 1) / (r * r) - g.z_nuc / r;
+            best = std::max(best, std::fabs(d) + ok + std::fabs(e_max) * r * (kl + kp));
+        }
+    }
+    return best;
+}
+
+static int states_for(int lmax)
+{
+    int s = 0;
+    for (int l = 0; l <= std::min(lmax, 4); ++l) s += 5 - l;
+    return s;
+}
+
+extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_inst, tdse_ctx** out)
+{
+    if (!out) return TDSE_E_INVALID;
+    *out = nullptr;
+    if (!grids || n_inst < 1 || n_inst > (1 << 20)) return TDSE_E_INVALID;
+    tdse_ctx* c = new (std::nothrow) tdse_ctx;
+    if (!c) return TDSE_E_NOMEM;
+    c->n_inst = n_inst;
+    c->grids.assign(grids, grids + n_inst);
+    c->stencil = grids[0].stencil;
+    c->prec = grids[0].precision;
+    for (int k = 0; k < n_inst; ++k) {
+        const tdse_grid_desc& g = grids[k];
+        if (g.n_r < 8 || g.n_r > (1 << 26) || g.lmax < 0 || g.lmax > 1023 ||
+            (g.stencil != 3 && g.stencil != 5) || (g.precision != TDSE_FP64 && g.precision != TDSE_FP32) ||
+            !(g.dr > 0.0) || !(g.z_nuc > 0.0) || !std::isfinite(g.r_ion) || g.stencil != c->stencil ||
+            g.precision != c->prec) {
+            delete c;
+            return TDSE_E_INVALID;
+        }
+    }
+    c->elem = (c->prec == TDSE_FP64) ? 16 : 8;
+    // instance table, offsets aligned to 64 elements
+    int lmax_all = 0;
+    int64_t off = 0, tab = 0;
+    c->inst.resize(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        const tdse_grid_desc& g = grids[k];
+        Inst& I = c->inst[k];
+        std::memset(&I, 0, sizeof I);
+        I.off = off;
+        I.n = g.n_r;
+        I.lmax = g.lmax;
+        I.n_states = states_for(g.lmax);
+        I.dr = g.dr;
+        I.inv_dr2 = 1.0 / (g.dr * g.dr);
+        I.z = g.z_nuc;
+        int i_ion = 0;
+        while (i_ion < g.n_r && (double)(i_ion + 1) * g.dr <= g.r_ion) ++i_ion;
+        I.i_ion = i_ion;
+        I.tab_off = tab;
+        I.breakdown = 1e-12 * gershgorin_bound(g, 0.0);
+        tab += (int64_t)(1 + I.n_states) * g.n_r;
+        off += ((int64_t)(g.lmax + 1) * g.n_r + 63) / 64 * 64;
+        lmax_all = std::max(lmax_all, g.lmax);
+    }
+    c->state_elems = off;
+    c->kappa.resize(lmax_all + 2);
+    for (int l = 0; l < lmax_all + 2; ++l)
+        c->kappa[l] = (l > 0) ? std::sqrt((double)l * l / (4.0 * l * l - 1.0)) : 0.0;
+    // tiles: rows per tile chosen so the whole launch has >= kTargetTiles workgroups
+    int64_t total_cols = 0;
+    for (int k = 0; k < n_inst; ++k)
+        total_cols += (int64_t)((grids[k].n_r + kBlock - 1) / kBlock) * (grids[k].lmax + 1);
+    int rows = kTileRows;
+    while (rows > 1 && total_cols / rows < kTargetTiles) rows /= 2;
+    for (int k = 0; k < n_inst; ++k) {
+        Inst& I = c->inst[k];
+        I.tile_begin = (int32_t)c->tiles.size();
+        for (int l0 = 0; l0 <= I.lmax; l0 += rows)
+            for (int r0 = 0; r0 < I.n; r0 += kBlock)
+                c->tiles.push_back(Tile{k, r0, l0, std::min(l0 + rows, I.lmax + 1)});
+        I.tile_end = (int32_t)c->tiles.size();
+    }
+    // XCD-aware block order: the hardware deals workgroup b to XCD b mod 8; give
+    // each XCD a contiguous run of tiles so radial and l halos stay in its L2.
+    const int nt = (int)c->tiles.size();
+    c->order.resize(nt);
+    const int q = nt / 8, rem = nt % 8;
+    for (int b = 0; b < nt; ++b) {
+        const int x = b % 8, j = b / 8;
+        const int start = x * q + std::min(x, rem);
+        c->order[b] = start + j;
+    }
+    // radial tables: u0 (normalised r exp(-z r)) and the bound eigenvectors
+    c->radial.assign(tab, 0.0);
+    std::vector<std::thread> pool;
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<int> next(1, 0);
+    std::mutex mu;
+    auto worker = [&]() {
+        for (;;) {
+            int k;
+            {
+                std::lock_guard<std::mutex> lock(mu);
+                if (next[0] >= n_inst) return;
+                k = next[0]++;
+            }
+            const tdse_grid_desc& g = grids[k];
+            const Inst& I = c->inst[k];
+            double* t = c->radial.data() + I.tab_off;
+            double s = 0.0;
+            for (int i = 0; i < g.n_r; ++i) {
+                const double r = (double)(i + 1) * g.dr;
+                t[i] = r * std::exp(-g.z_nuc * r);
+                s += t[i] * t[i];
+            }
+            const double nrm = 1.0 / std::sqrt(g.dr * s);
+            for (int i = 0; i < g.n_r; ++i) t[i] *= nrm;
+            int row = 1;
+            for (int l = 0; l <= std::min(g.lmax, 4); ++l) {
+                std::vector<double> e, v;
+                lowest_radial_states(g.n_r, g.stencil, g.dr, g.z_nuc, l, 5 - l, e, v);
+                std::memcpy(t + (size_t)row * g.n_r, v.data(), v.size() * sizeof(double));
+                row += 5 - l;
+            }
+        }
+    };
+    for (unsigned w = 0; w < std::min<unsigned>(hw, (unsigned)n_inst); ++w) pool.emplace_back(worker);
+    for (auto& th : pool) th.join();
+
+    // workspace layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, kAlign);
+        return at;
+    };
+    c->off_inst = take(sizeof(Inst) * n_inst);
+    c->off_tiles = take(sizeof(Tile) * nt);
+    c->off_order = take(sizeof(int32_t) * nt);
+    c->off_kappa = take(sizeof(double) * c->kappa.size());
+    c->off_radial = take(sizeof(double) * c->radial.size());
+    c->off_step = take(sizeof(double) * kSlots * (size_t)n_inst * kEtabSteps);
+    c->off_obs_tmp = take(sizeof(tdse_obs) * n_inst);
+    c->off_lz = take(sizeof(LanczosScalars) * n_inst);
+    c->partial_doubles = (size_t)nt * std::max(kObsQ, 2 * kMaxKrylov);
+    c->off_partial = take(sizeof(double) * c->partial_doubles);
+    c->off_vecs = o;
+    c->fixed_bytes = o;
+    *out = c;
+    return TDSE_OK;
+}
+
+extern "C" void tdse_destroy(tdse_ctx* c)
+{
+    if (!c) return;
+    for (auto& e : c->ev_pool) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    for (int b = 0; b < 2; ++b) {
+        if (c->step_ev[b]) {
+            (void)hipEventSynchronize(c->step_ev[b]);
+            (void)hipEventDestroy(c->step_ev[b]);
+        }
+        if (c->h_step[b]) (void)hipHostFree(c->h_step[b]);
+    }
+    delete c;
+}
+
+extern "C" const char* tdse_last_error(const tdse_ctx* c) { return c ? c->err.c_str() : "null context"; }
+extern "C" int32_t tdse_num_instances(const tdse_ctx* c) { return c ? c->n_inst : 0; }
+extern "C" int64_t tdse_state_offset(const tdse_ctx* c, int32_t k)
+{
+    return (c && k >= 0 && k < c->n_inst) ? c->inst[k].off : -1;
+}
+extern "C" size_t tdse_state_bytes(const tdse_ctx* c) { return c ? c->state_bytes() : 0; }
+extern "C" size_t tdse_workspace_bytes(const tdse_ctx* c, int32_t method, int32_t order_or_m)
+{
+    if (!c) return 0;
+    return c->fixed_bytes + c->vecs_needed(method, order_or_m) * c->state_bytes();
+}
+
+extern "C" double tdse_lambda_max_bound(const tdse_ctx* c, int32_t k, double e_max)
+{
+    if (!c || k < 0 || k >= c->n_inst) return -1.0;
+    return gershgorin_bound(c->grids[k], e_max);
+}
+
+// ---------------------------------------------------------------------------
+// binding and state transfer
+// ---------------------------------------------------------------------------
+extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_t work_bytes,
+                                 void* hip_stream)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!d_state || !d_work) return c->fail(TDSE_E_INVALID, "tdse_bind: null device pointer");
+    if ((reinterpret_cast<uintptr_t>(d_state) | reinterpret_cast<uintptr_t>(d_work)) % kAlign)
+        return c->fail(TDSE_E_INVALID, "tdse_bind: device buffers must be 256-byte aligned");
+    if (work_bytes < c->fixed_bytes)
+        return c->fail(TDSE_E_WORKSPACE, "tdse_bind: workspace smaller than the fixed tables");
+    c->d_state = static_cast<char*>(d_state);
+    c->d_work = static_cast<char*>(d_work);
+    c->work_bytes = work_bytes;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    for (int b = 0; b < 2; ++b) {
+        if (!c->h_step[b]) {
+            hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->h_step[b]),
+                                         sizeof(double) * kSlots * (size_t)c->n_inst * kEtabSteps);
+            if (e != hipSuccess) return c->hip_fail(e, "hipHostMalloc");
+            e = hipEventCreateWithFlags(&c->step_ev[b], hipEventDisableTiming);
+            if (e != hipSuccess) return c->hip_fail(e, "hipEventCreate");
+        }
+    }
+    struct Up {
+        size_t off;
+        const void* src;
+        size_t bytes;
+    } ups[] = {
+        {c->off_inst, c->inst.data(), sizeof(Inst) * c->inst.size()},
+        {c->off_tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size()},
+        {c->off_order, c->order.data(), sizeof(int32_t) * c->order.size()},
+        {c->off_kappa, c->kappa.data(), sizeof(double) * c->kappa.size()},
+        {c->off_radial, c->radial.data(), sizeof(double) * c->radial.size()},
+    };
+    for (const Up& u : ups) {
+        hipError_t e = hipMemcpyAsync(c->d_work + u.off, u.src, u.bytes, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_bind upload");
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_bind sync");
+    c->bound = true;
+    return TDSE_OK;
+}
+
+extern "C" tdse_status tdse_set_state(tdse_ctx* c, int32_t k, const double* host)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_set_state: not bound");
+    if (k < 0 || k >= c->n_inst) return c->fail(TDSE_E_INVALID, "tdse_set_state: bad instance");
+    const Inst& I = c->inst[k];
+    const size_t cnt = (size_t)(I.lmax + 1) * I.n;
+    std::vector<double> tmp;
+    if (!host) {
+        tmp.assign(2 * cnt, 0.0);
+        for (int i = 0; i < I.n; ++i) tmp[2 * i] = c->radial[I.tab_off + i];
+        host = tmp.data();
+    }
+    hipError_t e;
+    char* dst = c->d_state + (size_t)I.off * c->elem;
+    if (c->prec == TDSE_FP64) {
+        e = hipMemcpyAsync(dst, host, cnt * 16, hipMemcpyHostToDevice, c->stream);
+    } else {
+        std::vector<float> f(2 * cnt);
+        for (size_t j = 0; j < 2 * cnt; ++j) f[j] = (float)host[j];
+        e = hipMemcpyAsync(dst, f.data(), cnt * 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return (e == hipSuccess) ? TDSE_OK : c->hip_fail(e, "tdse_set_state");
+}
+
+extern "C" tdse_status tdse_get_state(tdse_ctx* c, int32_t k, double* host)
+{
+    if (!c || !host) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_get_state: not bound");
+    if (k < 0 || k >= c->n_inst) return c->fail(TDSE_E_INVALID, "tdse_get_state: bad instance");
+    const Inst& I = c->inst[k];
+    const size_t cnt = (size_t)(I.lmax + 1) * I.n;
+    const char* src = c->d_state + (size_t)I.off * c->elem;
+    hipError_t e;
+    if (c->prec == TDSE_FP64) {
+        e = hipMemcpyAsync(host, src, cnt * 16, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    } else {
+        std::vector<float> f(2 * cnt);
+        e = hipMemcpyAsync(f.data(), src, cnt * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        for (size_t j = 0; j < 2 * cnt; ++j) host[j] = (double)f[j];
+    }
+    return (e == hipSuccess) ? TDSE_OK : c->hip_fail(e, "tdse_get_state");
+}
+
+// ---------------------------------------------------------------------------
+// per-step scalars
+// ---------------------------------------------------------------------------
+namespace {
+
+double field_at(const tdse_pulse& p, double t)
+{
+    const double tau = t - p.t_on;
+    const double period = 2.0 * M_PI * p.n_cycles / p.omega;
+    if (!(tau >= 0.0 && tau <= period)) return 0.0;
+    const double s = std::sin(M_PI * tau / period);
+    return p.e0 * s * s * std::cos(p.omega * tau + p.cep);
+}
+
+// Fills and uploads the scalars of steps [s0, s0 + count) (count <= kEtabSteps)
+// for every instance; returns the device base of the chunk.
+tdse_status upload_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, const double* dt,
+                         int64_t s0, int count)
+{
+    const int b = c->step_buf;
+    c->step_buf ^= 1;
+    if (c->step_ev_used[b]) {
+        hipError_t e = hipEventSynchronize(c->step_ev[b]);
+        if (e != hipSuccess) return c->hip_fail(e, "step staging wait");
+    }
+    double* h = c->h_step[b];
+    const int n = c->n_inst;
+    for (int s = 0; s < count; ++s) {
+        double* row = h + (size_t)s * kSlots * n;
+        for (int k = 0; k < n; ++k) {
+            const double step = (double)(s0 + s);
+            const double ts = t0[k] + step * dt[k];
+            const double tm = t0[k] + (step + 0.5) * dt[k];
+            const double te = t0[k] + (step + 1.0) * dt[k];
+            row[kEStart * n + k] = pulses ? field_at(pulses[k], ts) : 0.0;
+            row[kEMid * n + k] = pulses ? field_at(pulses[k], tm) : 0.0;
+            row[kEEnd * n + k] = pulses ? field_at(pulses[k], te) : 0.0;
+            row[kTEnd * n + k] = te;
+            row[kDt * n + k] = dt[k];
+        }
+    }
+    hipError_t e = hipMemcpyAsync(c->d_step(), h, sizeof(double) * kSlots * n * (size_t)count,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "step upload");
+    e = hipEventRecord(c->step_ev[b], c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "step event");
+    c->step_ev_used[b] = true;
+    return TDSE_OK;
+}
+
+tdse_status check_common(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, const double* dt,
+                         int32_t nsteps, int32_t obs_every, tdse_obs* d_obs, int method, int order)
+{
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "step: no device memory bound");
+    if (!pulses || !t0 || !dt) return c->fail(TDSE_E_INVALID, "step: null argument");
+    if (nsteps < 0) return c->fail(TDSE_E_INVALID, "step: nsteps < 0");
+    if (obs_every < 0) return c->fail(TDSE_E_INVALID, "step: obs_every < 0");
+    if (obs_every > 0 && !d_obs) return c->fail(TDSE_E_INVALID, "step: observables requested, d_obs is null");
+    for (int k = 0; k < c->n_inst; ++k) {
+        if (!std::isfinite(t0[k]) || !(dt[k] > 0.0) || !std::isfinite(dt[k]))
+            return c->fail(TDSE_E_INVALID, "step: t0 must be finite and dt > 0");
+        if (!(pulses[k].omega > 0.0) || !(pulses[k].n_cycles > 0.0) || !std::isfinite(pulses[k].e0))
+            return c->fail(TDSE_E_INVALID, "step: pulse needs omega > 0, n_cycles > 0, finite e0");
+    }
+    const size_t need = tdse_workspace_bytes(c, method, order);
+    if (c->work_bytes < need)
+        return c->fail(TDSE_E_WORKSPACE, "step: workspace too small for this method (" +
+                                             std::to_string(need) + " bytes needed)");
+    return TDSE_OK;
+}
+
+tdse_status check_stable(tdse_ctx* c, const tdse_pulse* pulses, const double* dt, int order)
+{
+    const double y = tdse_taylor_stability_limit(order);
+    for (int k = 0; k < c->n_inst; ++k) {
+        const double lam = gershgorin_bound(c->grids[k], std::fabs(pulses[k].e0));
+        if (dt[k] * lam > y) {
+            char buf[256];
+            std::snprintf(buf, sizeof buf,
+                          "instance %d: dt*lambda_max = %.4g exceeds the order-%d stability limit %.4g "
+                          "(dt must be <= %.4g)", k, dt[k] * lam, order, y, y / lam);
+            return c->fail(TDSE_E_UNSTABLE, buf);
+        }
+    }
+    return TDSE_OK;
+}
+
+// observables of the state after step s (within the uploaded chunk at `step`)
+hipError_t launch_obs(tdse_ctx* c, const void* psi, const double* step, double* rec_base,
+                      int64_t rec_stride)
+{
+    TimedLaunch tl(c, 2);
+    const SweepGeom g = c->geom();
+    hipError_t e = launch_obs_partial(c->prec, g, c->d_radial(), psi, c->d_partial(), c->stream);
+    if (e != hipSuccess) return e;
+    return launch_obs_finish(g, c->d_partial(), step, rec_stride, rec_base, c->stream);
+}
+
+template <typename StepFn>
+tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, const double* dt,
+                      int32_t nsteps, int32_t obs_every, tdse_obs* d_obs, StepFn&& step_fn)
+{
+    const int64_t n_rec = (obs_every > 0) ? nsteps / obs_every : 0;
+    const int64_t rec_stride = n_rec * (int64_t)(sizeof(tdse_obs) / sizeof(double));
+    for (int64_t s0 = 0; s0 < nsteps; s0 += kEtabSteps) {
+        const int count = (int)std::min<int64_t>(kEtabSteps, nsteps - s0);
+        tdse_status st = upload_steps(c, pulses, t0, dt, s0, count);
+        if (st != TDSE_OK) return st;
+        for (int s = 0; s < count; ++s) {
+            const double* step = c->d_step() + (size_t)s * kSlots * c->n_inst;
+            hipError_t e = step_fn(step);
+            if (e != hipSuccess) return c->hip_fail(e, "step launch");
+            const int64_t done = s0 + s + 1;
+            if (obs_every > 0 && done % obs_every == 0) {
+                double* rec = reinterpret_cast<double*>(d_obs + (done / obs_every - 1));
+                e = launch_obs(c, c->d_state, step, rec, rec_stride);
+                if (e != hipSuccess) return c->hip_fail(e, "observables launch");
+            }
+        }
+    }
+    return TDSE_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the hot path
+// ---------------------------------------------------------------------------
+extern "C" tdse_status tdse_apply_H(tdse_ctx* c, const double* e_field, const void* d_in, void* d_out)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_apply_H: not bound");
+    if (!e_field || !d_in || !d_out) return c->fail(TDSE_E_INVALID, "tdse_apply_H: null argument");
+    const char* a = static_cast<const char*>(d_in);
+    const char* b = static_cast<const char*>(d_out);
+    const size_t nb = (size_t)c->state_elems * c->elem;
+    if (a < b + nb && b < a + nb) return c->fail(TDSE_E_INVALID, "tdse_apply_H: in and out overlap");
+    std::vector<tdse_pulse> none(c->n_inst);
+    std::vector<double> zero(c->n_inst, 0.0), one(c->n_inst, 1.0);
+    // slot kEMid carries the caller's field values
+    tdse_status st = upload_steps(c, nullptr, zero.data(), one.data(), 0, 1);
+    if (st != TDSE_OK) return st;
+    hipError_t e = hipMemcpyAsync(c->d_step() + kEMid * c->n_inst, e_field, sizeof(double) * c->n_inst,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_apply_H field upload");
+    e = hipStreamSynchronize(c->stream);  // e_field is pageable caller memory
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_apply_H sync");
+    TimedLaunch tl(c, 4);
+    e = launch_hsweep(c->prec, c->stencil == 3 ? 1 : 2, c->geom(), d_in, nullptr, d_out, c->d_step(), 0,
+                      c->stream);
+    return (e == hipSuccess) ? TDSE_OK : c->hip_fail(e, "tdse_apply_H launch");
+}
+
+extern "C" tdse_status tdse_step_taylor(tdse_ctx* c, const tdse_pulse* pulses, const double* t0,
+                                        const double* dt, int32_t order, int32_t nsteps,
+                                        int32_t obs_every, tdse_obs* d_obs)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (order < 1 || order > 16) return c->fail(TDSE_E_INVALID, "tdse_step_taylor: order must be 1..16");
+    tdse_status st = check_common(c, pulses, t0, dt, nsteps, obs_every, d_obs, TDSE_METHOD_TAYLOR, order);
+    if (st != TDSE_OK) return st;
+    st = check_stable(c, pulses, dt, order);
+    if (st != TDSE_OK) return st;
+    const int S = c->stencil == 3 ? 1 : 2;
+    const SweepGeom g = c->geom();
+    void* psi = c->d_state;
+    void* wa = c->d_vec(0);
+    void* wb = c->d_vec(1);
+    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, [&](const double* step) {
+        // Horner: w = psi + (-i dt/P) H psi; w = psi + (-i dt/k) H w, k = P-1..1
+        const void* in = psi;
+        void* bufs[2] = {wa, wb};
+        int which = 0;
+        for (int k = order; k >= 1; --k) {
+            void* out = (k == 1 && order > 1) ? psi : bufs[which];
+            hipError_t e;
+            {
+                TimedLaunch tl(c, 0);
+                e = launch_hsweep(c->prec, S, g, in, psi, out, step, k, c->stream);
+            }
+            if (e != hipSuccess) return e;
+            in = out;
+            which ^= 1;
+        }
+        if (order == 1) return launch_copy(c->prec, g, wa, psi, c->stream);
+        return hipSuccess;
+    });
+}
+
+extern "C" tdse_status tdse_step_rk4(tdse_ctx* c, const tdse_pulse* pulses, const double* t0,
+                                     const double* dt, int32_t nsteps, int32_t obs_every,
+                                     tdse_obs* d_obs)
+{
+    if (!c) return TDSE_E_INVALID;
+    tdse_status st = check_common(c, pulses, t0, dt, nsteps, obs_every, d_obs, TDSE_METHOD_RK4, 4);
+    if (st != TDSE_OK) return st;
+    st = check_stable(c, pulses, dt, 4);
+    if (st != TDSE_OK) return st;
+    const int S = c->stencil == 3 ? 1 : 2;
+    const SweepGeom g = c->geom();
+    void* psi = c->d_state;
+    void* ga = c->d_vec(0);
+    void* gb = c->d_vec(1);
+    void* acc = c->d_vec(2);
+    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, [&](const double* step) {
+        const void* gin[4] = {psi, ga, gb, ga};
+        void* gout[4] = {ga, gb, ga, nullptr};
+        for (int s = 0; s < 4; ++s) {
+            TimedLaunch tl(c, 1);
+            hipError_t e = launch_rk4_stage(c->prec, S, g, s, gin[s], psi, acc, gout[s], step, c->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    });
+}
+
+extern "C" tdse_status tdse_step_lanczos(tdse_ctx* c, const tdse_pulse* pulses, const double* t0,
+                                         const double* dt, int32_t m, int32_t nsteps,
+                                         int32_t obs_every, tdse_obs* d_obs)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (m < 1 || m > kMaxKrylov) return c->fail(TDSE_E_INVALID, "tdse_step_lanczos: m must be 1..64");
+    tdse_status st = check_common(c, pulses, t0, dt, nsteps, obs_every, d_obs, TDSE_METHOD_LANCZOS, m);
+    if (st != TDSE_OK) return st;
+    const int S = c->stencil == 3 ? 1 : 2;
+    const SweepGeom g = c->geom();
+    void* psi = c->d_state;
+    void* w = c->d_vec(0);
+    void* basis = c->d_vec(1);  // vectors 1..m-1
+    const int64_t stride = (int64_t)(c->state_bytes() / c->elem);
+    LanczosScalars* sc = c->d_lz();
+    double* part = c->d_partial();
+    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, [&](const double* step) {
+        hipError_t e = launch_lz_norm(c->prec, g, psi, part, c->stream);
+        if (e == hipSuccess) e = launch_lz_norm_finish(g, part, sc, c->stream);
+        for (int j = 0; j < m && e == hipSuccess; ++j) {
+            {
+                TimedLaunch tl(c, 3);
+                e = launch_lz_sweep_a(c->prec, S, g, j, m, psi, basis, stride, w, step, sc, part, c->stream);
+            }
+            if (e == hipSuccess) e = launch_lz_finish_a(g, j, m, part, sc, c->stream);
+            if (j + 1 < m) {
+                if (e == hipSuccess) e = launch_lz_sweep_b(c->prec, g, j, psi, basis, stride, w, sc, part, c->stream);
+                if (e == hipSuccess) e = launch_lz_finish_b(g, j, part, sc, c->stream);
+            }
+        }
+        if (e == hipSuccess) e = launch_lz_expm(g, step, sc, c->stream);
+        if (e == hipSuccess) e = launch_lz_recombine(c->prec, g, m, psi, basis, stride, sc, c->stream);
+        return e;
+    });
+}
+
+extern "C" tdse_status tdse_observables(tdse_ctx* c, const tdse_pulse* pulses, const double* t,
+                                        tdse_obs* host_out)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_observables: not bound");
+    if (!pulses || !t || !host_out) return c->fail(TDSE_E_INVALID, "tdse_observables: null argument");
+    // one pseudo-step whose end is t: t0 = t - dt with dt = 1 gives t_end = t
+    std::vector<double> t0(c->n_inst), one(c->n_inst, 1.0);
+    for (int k = 0; k < c->n_inst; ++k) t0[k] = t[k] - 1.0;
+    tdse_status st = upload_steps(c, pulses, t0.data(), one.data(), 0, 1);
+    if (st != TDSE_OK) return st;
+    // the exact time t (not (t - 1) + 1) goes into the record
+    double* tmp = reinterpret_cast<double*>(c->d_work + c->off_obs_tmp);
+    hipError_t e = hipMemcpyAsync(c->d_step() + kTEnd * c->n_inst, t, sizeof(double) * c->n_inst,
+                                  hipMemcpyHostToDevice, c->stream);
+    std::vector<double> ee(c->n_inst);
+    for (int k = 0; k < c->n_inst; ++k) ee[k] = field_at(pulses[k], t[k]);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_step() + kEEnd * c->n_inst, ee.data(), sizeof(double) * c->n_inst,
+                           hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_obs(c, c->d_state, c->d_step(), tmp, sizeof(tdse_obs) / sizeof(double));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_out, tmp, sizeof(tdse_obs) * c->n_inst, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_observables");
+    for (int k = 0; k < c->n_inst; ++k)
+        if (!std::isfinite(host_out[k].norm)) return c->fail(TDSE_E_NONFINITE, "tdse_observables: norm is not finite");
+    return TDSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+extern "C" tdse_status tdse_timing_enable(tdse_ctx* c, int32_t enable)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (c->bound) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_timing_enable sync");
+    }
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    return TDSE_OK;
+}
+
+extern "C" tdse_status tdse_timing_read(tdse_ctx* c, const char* kernel, int64_t* launches, double* total_ms)
+{
+    if (!c || !kernel || !launches || !total_ms) return TDSE_E_INVALID;
+    const int kind = timed_kind(kernel);
+    if (kind < 0) return c->fail(TDSE_E_INVALID, "tdse_timing_read: unknown kernel family");
+    if (c->bound) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_timing_read sync");
+    }
+    int64_t cnt = 0;
+    double tot = 0.0;
+    for (size_t s = 0; s < c->ev_used; ++s) {
+        if (c->ev_kind[s] != kind) continue;
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, c->ev_pool[s].first, c->ev_pool[s].second);
+        if (e != hipSuccess) return c->hip_fail(e, "hipEventElapsedTime");
+        ++cnt;
+        tot += ms;
+    }
+    *launches = cnt;
+    *total_ms = tot;
+    return TDSE_OK;
+}

@@ -1,0 +1,237 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle.
+
+FP64 path: relative state error <= 1e-12 (||psi_gpu - psi_orc|| / ||psi_orc||)
+and, per observable time series, max_t |x_gpu - x_orc| <= 1e-12 * max_t
+|x_orc| with an absolute floor of 1e-13 (sums of O(1) terms over 1e4-1e6
+points carry ~sqrt(n)*eps ~ 1e-14 of round-off that depends on summation
+order, which differs between the two sides).
+
+FP32 path (FP32 storage, FP64 arithmetic and reductions): every sweep rounds
+its output to FP32 (relative 6e-8 per element), so single applications agree
+to ~1e-7; propagation targets are populations and p_ion within 1e-5 relative
+and norm drift below 1e-6.
+
+Sizes span several 256-point radial tiles with a ragged tail and several
+row tiles.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_helpers import (lib, obs_columns, orc_grid, orc_pulse, read_vector, rel_err, say,
+                         series_err, to_fp32)
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+FLOOR64 = 1e-13
+
+
+def make(grids, methods, prec=0):
+    t = lib()
+    gs = [t.Grid(n, lm, dr, st, prec, 1.0, rion) for (n, lm, dr, st, rion) in grids]
+    return t.Propagator(gs, methods=methods)
+
+
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_h(stencil, prec):
+    t = lib()
+    n, lmax, dr, e = 700, 9, 0.1, 0.071
+    say(f"apply_H stencil={stencil} prec={prec} N={n} lmax={lmax} seed=11")
+    prop = make([(n, lmax, dr, stencil, 20.0)], [(t.METHOD_TAYLOR, 2)], prec)
+    psi = workloads.random_state(11, n, lmax)
+    if prec == 1:
+        psi = to_fp32(psi)
+    prop.set_state(0, psi)
+    out = prop.new_vector()
+    prop.apply_H(e, prop.state, out)
+    got = read_vector(prop, out, 0)
+    ref = oracle.apply_h(orc_grid(prop.grids[0]), e, psi)
+    err = rel_err(got, ref)
+    say(f"  rel err {err:.3e}")
+    assert err < (2e-15 if prec == 0 else 1.2e-7)
+    if prec == 0:
+        # element by element, against the size of the terms that built each element
+        assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+    prop.close()
+
+
+def _propagate_pair(method, order, n=520, lmax=7, dr=0.1, stencil=5, dt=4e-4, steps=40,
+                    obs_every=10, prec=0, pulse=None, psi=None, t0=0.0, r_ion=12.0):
+    t = lib()
+    pulse = pulse or t.Pulse(0.06, 0.35, 2.0, 0.2, 0.0)
+    grid = (n, lmax, dr, stencil, r_ion)
+    mcode = {"taylor": t.METHOD_TAYLOR, "rk4": t.METHOD_RK4, "lanczos": t.METHOD_LANCZOS}[method]
+    prop = make([grid], [(mcode, order)], prec)
+    g = orc_grid(prop.grids[0])
+    setup = oracle.obs_setup(g, r_ion=r_ion)
+    if psi is None:
+        psi, _ = oracle.initial_state(g)
+    if prec == 1:
+        psi = to_fp32(psi)
+    prop.set_state(0, psi)
+    obs = prop.obs_buffer(steps, obs_every)
+    if method == "taylor":
+        prop.step_taylor(pulse, t0, dt, order, steps, obs_every, obs)
+    elif method == "rk4":
+        prop.step_rk4(pulse, t0, dt, steps, obs_every, obs)
+    else:
+        prop.step_lanczos(pulse, t0, dt, order, steps, obs_every, obs)
+    got = prop.get_state(0)
+    gobs = obs.cpu().numpy()[0][:, :obs_columns(setup)]
+    prop.close()
+    ocode = {"taylor": oracle.TAYLOR, "rk4": oracle.RK4, "lanczos": oracle.LANCZOS}[method]
+    ref, robs, _ = oracle.propagate(g, orc_pulse(pulse), ocode, order, t0, dt, steps, obs_every,
+                                    setup, psi)
+    return got, ref, gobs, robs
+
+
+@pytest.mark.parametrize("method,order,stencil", [("taylor", 8, 5), ("taylor", 4, 3), ("taylor", 1, 3),
+                                                  ("taylor", 3, 5), ("rk4", 4, 3), ("rk4", 4, 5)])
+def test_explicit_steps_fp64(method, order, stencil):
+    say(f"{method}-{order} stencil={stencil} FP64 vs oracle")
+    # below each order's imaginary-axis limit (lambda_max ~ 3.1e3 here); an
+    # order-1 step has no stable interval, so it gets a vanishing dt
+    dt = 4e-4 if order > 1 else 1e-10
+    got, ref, gobs, robs = _propagate_pair(method, order, stencil=stencil, dt=dt)
+    err = rel_err(got, ref)
+    oerr = series_err(gobs, robs, FLOOR64)
+    say(f"  state {err:.2e}  observables max {oerr.max():.2e}")
+    assert err < TOL64
+    assert np.all(oerr < TOL64), oerr
+    assert np.all(gobs[:, 0] == robs[:, 0])          # times identical
+    assert np.all(gobs[:, 1] == robs[:, 1])          # fields identical (same libm on the host)
+
+
+@pytest.mark.parametrize("m,stencil,dt", [(12, 5, 0.05), (20, 3, 0.02), (1, 3, 1e-3)])
+def test_lanczos_fp64(m, stencil, dt):
+    say(f"lanczos m={m} stencil={stencil} dt={dt} FP64 vs oracle")
+    got, ref, gobs, robs = _propagate_pair("lanczos", m, stencil=stencil, dt=dt, steps=30)
+    err = rel_err(got, ref)
+    oerr = series_err(gobs, robs, FLOOR64)
+    say(f"  state {err:.2e}  observables max {oerr.max():.2e}")
+    assert err < TOL64
+    assert np.all(oerr < TOL64), oerr
+
+
+def test_lanczos_breakdown_on_eigenstate():
+    # a field-free eigenvector: the Krylov space is invariant after one vector
+    t = lib()
+    n, lmax, dr = 600, 3, 0.1
+    g = oracle.Grid(n=n, lmax=lmax, dr=dr, stencil=3)
+    e, phi, states = oracle.bound_states(g, 3)
+    k = states.index((3, 2))
+    psi = np.zeros(g.size, dtype=np.complex128)
+    psi[2 * n:3 * n] = phi[k]
+    say("lanczos breakdown on the 3d eigenvector")
+    got, ref, _, _ = _propagate_pair("lanczos", 20, n=n, lmax=lmax, dr=dr, stencil=3, dt=0.5,
+                                     steps=4, pulse=t.Pulse(0.0, 1.0, 1.0, 0.0, 0.0), psi=psi,
+                                     obs_every=2)
+    assert rel_err(got, np.exp(-1j * e[k] * 2.0) * psi) < 1e-12
+    assert rel_err(got, ref) < 1e-12
+
+
+def test_batch_matches_single_instances():
+    t = lib()
+    grids = [(300, 3, 0.1, 5, 8.0), (777, 10, 0.05, 5, 20.0), (257, 0, 0.2, 5, 10.0)]
+    pulses = [t.Pulse(0.05, 0.3, 2.0, 0.0, 0.0), t.Pulse(-0.03, 0.5, 3.0, 1.0, 0.5),
+              t.Pulse(0.08, 0.2, 1.0, -0.5, 0.0)]
+    dts = [1e-3, 4e-4, 2e-3]
+    t0s = [0.0, 0.3, 1.0]
+    steps, every = 30, 10
+    say("batched Taylor-6 over 3 uneven grids vs the oracle per grid")
+    prop = make(grids, [(t.METHOD_TAYLOR, 6)])
+    for k in range(3):
+        prop.set_state(k, None)
+    obs = prop.obs_buffer(steps, every)
+    prop.step_taylor(pulses, t0s, dts, 6, steps, every, obs)
+    gobs_all = obs.cpu().numpy()
+    for k, (n, lm, dr, st, rion) in enumerate(grids):
+        got = prop.get_state(k)
+        g = oracle.Grid(n=n, lmax=lm, dr=dr, stencil=st)
+        setup = oracle.obs_setup(g, r_ion=rion)
+        psi0, _ = oracle.initial_state(g)
+        ref, robs, _ = oracle.propagate(g, orc_pulse(pulses[k]), oracle.TAYLOR, 6, t0s[k], dts[k],
+                                        steps, every, setup, psi0)
+        err = rel_err(got, ref)
+        oerr = series_err(gobs_all[k][:, :obs_columns(setup)], robs, FLOOR64)
+        say(f"  instance {k}: state {err:.2e} observables {oerr.max():.2e}")
+        assert err < TOL64 and np.all(oerr < TOL64)
+        assert np.all(gobs_all[k][:, obs_columns(setup):] == 0.0)   # unused population slots
+    prop.close()
+
+
+def test_observables_entry_point():
+    t = lib()
+    n, lmax, dr = 900, 6, 0.1
+    say("tdse_observables on a random state vs the oracle")
+    prop = make([(n, lmax, dr, 3, 30.0)], [(t.METHOD_TAYLOR, 2)])
+    psi = workloads.random_state(5, n, lmax)
+    psi /= np.sqrt(dr * np.vdot(psi, psi).real)
+    prop.set_state(0, psi)
+    p = t.Pulse(0.05, 0.057, 2.0, -math.pi / 2, 0.0)
+    got = prop.observables(p, 37.25)[0]
+    g = orc_grid(prop.grids[0])
+    setup = oracle.obs_setup(g, r_ion=30.0)
+    ref = oracle.observables(g, orc_pulse(p), 37.25, setup, psi)
+    prop.close()
+    k = len(ref)
+    d = np.abs(got[:k] - ref) / np.maximum(np.abs(ref), FLOOR64)
+    say(f"  max rel diff {d.max():.2e}")
+    assert np.all(d < 1e-12), d
+
+
+def test_unstable_dt_is_rejected_and_state_untouched():
+    t = lib()
+    prop = make([(400, 8, 0.1, 3, 20.0)], [(t.METHOD_TAYLOR, 4)])
+    prop.set_state(0, None)
+    before = prop.get_state(0)
+    lam = prop.lambda_max_bound(0, 0.05)
+    dt = 1.01 * t.tdse_taylor_stability_limit(4) / lam
+    say(f"unstable dt {dt:.3e} (limit {t.tdse_taylor_stability_limit(4) / lam:.3e})")
+    with pytest.raises(t.TdseError) as e:
+        prop.step_taylor(t.Pulse(0.05, 0.3, 2.0, 0.0, 0.0), 0.0, dt, 4, 10)
+    assert e.value.code == -4
+    with pytest.raises(t.TdseError):
+        prop.step_rk4(t.Pulse(0.05, 0.3, 2.0, 0.0, 0.0), 0.0, dt, 10)
+    assert np.array_equal(prop.get_state(0), before)
+    prop.close()
+
+
+def test_fp32_taylor_tracks_fp64_oracle():
+    # 5000 Taylor-8 steps with FP32 storage against the FP64 oracle.  Every
+    # sweep rounds its output to FP32 (unit round-off u = 6e-8); the errors
+    # random-walk, so the comparison is on a window of 5000 steps.
+    t = lib()
+    say("FP32-state Taylor-8, 5000 steps vs the FP64 oracle")
+    pulse = t.Pulse(0.1, 0.5, 2.0, 0.0, 0.0)
+    steps, every = 5000, 1000
+    got, ref, gobs, robs = _propagate_pair("taylor", 8, n=600, lmax=8, dr=0.1, stencil=3,
+                                           dt=8e-4, steps=steps, obs_every=every, prec=1,
+                                           pulse=pulse, r_ion=5.0)
+    pops_g, pops_r = gobs[:, 8:], robs[:, 8:]
+    big = pops_r > 1e-3
+    rel = np.abs(pops_g[big] - pops_r[big]) / pops_r[big]
+    ion = np.abs(gobs[:, 5] - robs[:, 5]) / robs[:, 5]
+    pb = np.abs(gobs[:, 4] - robs[:, 4]) / robs[:, 4]
+    drift = np.max(np.abs(gobs[:, 2] - robs[:, 2]))
+    say(f"  P_nl>1e-3 rel {rel.max():.2e}  p_bound rel {pb.max():.2e}  p_ion rel {ion.max():.2e} "
+        f"(p_ion {robs[-1, 5]:.3e})  norm drift {drift:.2e}  |N-1| {np.max(np.abs(gobs[:, 2] - 1)):.2e}"
+        f"  state {rel_err(got, ref):.2e}")
+    assert robs[-1, 5] > 1e-3                                   # not a vacuous p_ion check
+    assert ion.max() < 1e-5 and pb.max() < 1e-5 and drift < 1e-6
+    assert rel.max() < 1e-4
+
+
+def test_minimum_grid_and_single_partial_wave():
+    # N = 8 (one partial tile), lmax = 0 (no coupling): all three methods
+    for method, order in (("taylor", 4), ("rk4", 4), ("lanczos", 5)):
+        say(f"{method} on N=8, lmax=0")
+        got, ref, gobs, robs = _propagate_pair(method, order, n=8, lmax=0, dr=0.5, stencil=5,
+                                               dt=2e-3, steps=10, obs_every=5)
+        assert rel_err(got, ref) < TOL64
+        assert np.all(series_err(gobs, robs, FLOOR64) < TOL64)
