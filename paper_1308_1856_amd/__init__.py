@@ -58,6 +58,11 @@ class Obs(ctypes.Structure):
 
 
 def _load():
+    # torch ships its own HIP runtime with the same SONAME (libamdhip64.so.7).
+    # Importing torch first makes libtdse bind to that already-loaded runtime,
+    # so there is one HIP runtime in the process and torch's streams and
+    # allocations are valid handles for the library.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950)")

@@ -58,3 +58,37 @@ def series_err(gpu: np.ndarray, ref: np.ndarray, floor: float) -> np.ndarray:
 
 def obs_columns(setup) -> int:
     return OBS_N + len(setup.state_l)
+
+
+EPS = np.finfo(np.float64).eps
+
+
+def obs_abs_tol(g: oracle.Grid, setup, ref: np.ndarray, floor: float = 1e-13,
+                c: float = 10.0) -> np.ndarray:
+    """Absolute tolerance per observable column for the reference series `ref`.
+
+    Fixed columns get `floor` (summation-order round-off).  A population
+    P = |<phi_nl|f_l>|^2 also inherits the difference between two
+    independently computed eigenvectors, |d phi| <= delta = c eps ||h_l|| /
+    gap_nl (eigenvector conditioning), so |dP| <= 2 sqrt(P_max) delta +
+    delta^2 (||f_l|| <= 1); p_bound sums these."""
+    e6, _, states6 = oracle.bound_states(g, 6)
+    energy = {st: e for st, e in zip(states6, e6)}
+    tol = [floor] * oracle.OBS_FIXED
+    pb = 0.0
+    for k, (n, l) in enumerate(zip(setup.state_n, setup.state_l)):
+        hl = oracle.h_bound(oracle.Grid(n=g.n, lmax=int(l), dr=g.dr, stencil=g.stencil, z=g.z), 0.0)
+        nb = [energy[(j, l)] for j in (n - 1, n + 1) if (j, l) in energy]
+        gap = min(abs(energy[(n, l)] - x) for x in nb)
+        delta = c * EPS * hl / gap
+        pmax = float(np.max(np.abs(ref[..., oracle.OBS_FIXED + k])))
+        t = 2 * np.sqrt(pmax) * delta + delta * delta + floor
+        tol.append(t)
+        pb += t
+    tol[4] = pb + floor
+    return np.array(tol)
+
+
+def series_ratio(gpu: np.ndarray, ref: np.ndarray, rel: float, abs_tol) -> np.ndarray:
+    """Per column: max_t |gpu - ref| / (rel * max_t |ref| + abs_tol); <= 1 passes."""
+    return np.max(np.abs(gpu - ref), axis=0) / (rel * np.max(np.abs(ref), axis=0) + abs_tol)

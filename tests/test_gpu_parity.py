@@ -2,9 +2,17 @@
 
 FP64 path: relative state error <= 1e-12 (||psi_gpu - psi_orc|| / ||psi_orc||)
 and, per observable time series, max_t |x_gpu - x_orc| <= 1e-12 * max_t
-|x_orc| with an absolute floor of 1e-13 (sums of O(1) terms over 1e4-1e6
-points carry ~sqrt(n)*eps ~ 1e-14 of round-off that depends on summation
-order, which differs between the two sides).
+|x_orc| + a, with a = 1e-13 for the fixed observables (sums of O(1) terms over
+1e4-1e6 points carry ~sqrt(n)*eps ~ 1e-14 of round-off that depends on the
+summation order, which differs between the two sides) and, for a population
+P_nl, a = 2 delta + delta^2 with delta = 10 eps ||h_l|| / gap_nl: the two
+sides compute the bound eigenvectors with different eigensolvers, and an
+eigenvector is only defined to ~eps ||h_l|| / gap_nl.
+
+Lanczos parity at 1e-12 needs a converged Krylov space (lambda_max dt of a
+few units for m = 12-20); where it is far from converged (stiff grids, large
+dt) the result amplifies round-off, and the tolerance is measured from the
+oracle's own response to an eps-level perturbation of its input.
 
 FP32 path (FP32 storage, FP64 arithmetic and reductions): every sweep rounds
 its output to FP32 (relative 6e-8 per element), so single applications agree
@@ -21,8 +29,8 @@ import pytest
 
 import oracle
 import workloads
-from gpu_helpers import (lib, obs_columns, orc_grid, orc_pulse, read_vector, rel_err, say,
-                         series_err, to_fp32)
+from gpu_helpers import (lib, obs_abs_tol, obs_columns, orc_grid, orc_pulse, read_vector, rel_err,
+                         say, series_ratio, to_fp32)
 
 pytestmark = pytest.mark.gpu
 
@@ -87,7 +95,13 @@ def _propagate_pair(method, order, n=520, lmax=7, dr=0.1, stencil=5, dt=4e-4, st
     ocode = {"taylor": oracle.TAYLOR, "rk4": oracle.RK4, "lanczos": oracle.LANCZOS}[method]
     ref, robs, _ = oracle.propagate(g, orc_pulse(pulse), ocode, order, t0, dt, steps, obs_every,
                                     setup, psi)
+    _propagate_pair.last = (g, setup, psi, orc_pulse(pulse), ocode)
     return got, ref, gobs, robs
+
+
+def _obs_ratio(gobs, robs):
+    g, setup = _propagate_pair.last[:2]
+    return series_ratio(gobs, robs, TOL64, obs_abs_tol(g, setup, robs))
 
 
 @pytest.mark.parametrize("method,order,stencil", [("taylor", 8, 5), ("taylor", 4, 3), ("taylor", 1, 3),
@@ -99,23 +113,41 @@ def test_explicit_steps_fp64(method, order, stencil):
     dt = 4e-4 if order > 1 else 1e-10
     got, ref, gobs, robs = _propagate_pair(method, order, stencil=stencil, dt=dt)
     err = rel_err(got, ref)
-    oerr = series_err(gobs, robs, FLOOR64)
-    say(f"  state {err:.2e}  observables max {oerr.max():.2e}")
+    ratio = _obs_ratio(gobs, robs)
+    say(f"  state {err:.2e}  observables worst ratio to tolerance {ratio.max():.2e}")
     assert err < TOL64
-    assert np.all(oerr < TOL64), oerr
+    assert np.all(ratio <= 1.0), ratio
     assert np.all(gobs[:, 0] == robs[:, 0])          # times identical
     assert np.all(gobs[:, 1] == robs[:, 1])          # fields identical (same libm on the host)
 
 
-@pytest.mark.parametrize("m,stencil,dt", [(12, 5, 0.05), (20, 3, 0.02), (1, 3, 1e-3)])
+@pytest.mark.parametrize("m,stencil,dt", [(12, 5, 1e-3), (20, 3, 2e-3), (1, 3, 1e-3)])
 def test_lanczos_fp64(m, stencil, dt):
-    say(f"lanczos m={m} stencil={stencil} dt={dt} FP64 vs oracle")
+    say(f"lanczos m={m} stencil={stencil} dt={dt} FP64 vs oracle (converged Krylov space)")
     got, ref, gobs, robs = _propagate_pair("lanczos", m, stencil=stencil, dt=dt, steps=30)
     err = rel_err(got, ref)
-    oerr = series_err(gobs, robs, FLOOR64)
-    say(f"  state {err:.2e}  observables max {oerr.max():.2e}")
+    ratio = _obs_ratio(gobs, robs)
+    say(f"  state {err:.2e}  observables worst ratio to tolerance {ratio.max():.2e}")
     assert err < TOL64
-    assert np.all(oerr < TOL64), oerr
+    assert np.all(ratio <= 1.0), ratio
+
+
+@pytest.mark.parametrize("m,dt", [(12, 0.05), (20, 0.02)])
+def test_lanczos_fp64_stiff(m, dt):
+    # lambda_max dt ~ 60-150: the Krylov space is far from converged in the
+    # upper spectrum and the result amplifies round-off.  Tolerance: 10x the
+    # oracle's own spread under a relative 1e-15 perturbation of its input.
+    say(f"lanczos m={m} dt={dt} FP64 vs oracle, unconverged regime")
+    got, ref, _, _ = _propagate_pair("lanczos", m, stencil=5, dt=dt, steps=30)
+    g, setup, psi, pulse, ocode = _propagate_pair.last
+    rng = np.random.default_rng(99)
+    pert = psi * (1 + 1e-15 * (rng.standard_normal(psi.size) + 1j * rng.standard_normal(psi.size)))
+    ref2, _, _ = oracle.propagate(g, pulse, ocode, m, 0.0, dt, 30, 10, setup, pert)
+    spread = rel_err(ref2, ref)
+    err = rel_err(got, ref)
+    say(f"  gpu vs oracle {err:.2e}; oracle vs perturbed oracle {spread:.2e}")
+    assert err <= 10 * max(spread, 1e-15)
+    assert abs(np.vdot(got, got).real / np.vdot(ref, ref).real - 1) < 1e-12   # unitary either way
 
 
 def test_lanczos_breakdown_on_eigenstate():
@@ -140,27 +172,27 @@ def test_batch_matches_single_instances():
     grids = [(300, 3, 0.1, 5, 8.0), (777, 10, 0.05, 5, 20.0), (257, 0, 0.2, 5, 10.0)]
     pulses = [t.Pulse(0.05, 0.3, 2.0, 0.0, 0.0), t.Pulse(-0.03, 0.5, 3.0, 1.0, 0.5),
               t.Pulse(0.08, 0.2, 1.0, -0.5, 0.0)]
-    dts = [1e-3, 4e-4, 2e-3]
+    dts = [1e-3, 5e-5, 2e-3]            # each below its grid's order-7 stability limit
     t0s = [0.0, 0.3, 1.0]
     steps, every = 30, 10
-    say("batched Taylor-6 over 3 uneven grids vs the oracle per grid")
-    prop = make(grids, [(t.METHOD_TAYLOR, 6)])
+    say("batched Taylor-7 over 3 uneven grids vs the oracle per grid")
+    prop = make(grids, [(t.METHOD_TAYLOR, 7)])
     for k in range(3):
         prop.set_state(k, None)
     obs = prop.obs_buffer(steps, every)
-    prop.step_taylor(pulses, t0s, dts, 6, steps, every, obs)
+    prop.step_taylor(pulses, t0s, dts, 7, steps, every, obs)
     gobs_all = obs.cpu().numpy()
     for k, (n, lm, dr, st, rion) in enumerate(grids):
         got = prop.get_state(k)
         g = oracle.Grid(n=n, lmax=lm, dr=dr, stencil=st)
         setup = oracle.obs_setup(g, r_ion=rion)
         psi0, _ = oracle.initial_state(g)
-        ref, robs, _ = oracle.propagate(g, orc_pulse(pulses[k]), oracle.TAYLOR, 6, t0s[k], dts[k],
+        ref, robs, _ = oracle.propagate(g, orc_pulse(pulses[k]), oracle.TAYLOR, 7, t0s[k], dts[k],
                                         steps, every, setup, psi0)
         err = rel_err(got, ref)
-        oerr = series_err(gobs_all[k][:, :obs_columns(setup)], robs, FLOOR64)
-        say(f"  instance {k}: state {err:.2e} observables {oerr.max():.2e}")
-        assert err < TOL64 and np.all(oerr < TOL64)
+        ratio = series_ratio(gobs_all[k][:, :obs_columns(setup)], robs, TOL64, obs_abs_tol(g, setup, robs))
+        say(f"  instance {k}: state {err:.2e} observables worst ratio {ratio.max():.2e}")
+        assert err < TOL64 and np.all(ratio <= 1.0)
         assert np.all(gobs_all[k][:, obs_columns(setup):] == 0.0)   # unused population slots
     prop.close()
 
@@ -180,9 +212,9 @@ def test_observables_entry_point():
     ref = oracle.observables(g, orc_pulse(p), 37.25, setup, psi)
     prop.close()
     k = len(ref)
-    d = np.abs(got[:k] - ref) / np.maximum(np.abs(ref), FLOOR64)
-    say(f"  max rel diff {d.max():.2e}")
-    assert np.all(d < 1e-12), d
+    ratio = series_ratio(got[None, :k], ref[None, :], TOL64, obs_abs_tol(g, setup, ref[None, :]))
+    say(f"  worst ratio to tolerance {ratio.max():.2e}")
+    assert np.all(ratio <= 1.0), ratio
 
 
 def test_unstable_dt_is_rejected_and_state_untouched():
@@ -234,4 +266,4 @@ def test_minimum_grid_and_single_partial_wave():
         got, ref, gobs, robs = _propagate_pair(method, order, n=8, lmax=0, dr=0.5, stencil=5,
                                                dt=2e-3, steps=10, obs_every=5)
         assert rel_err(got, ref) < TOL64
-        assert np.all(series_err(gobs, robs, FLOOR64) < TOL64)
+        assert np.all(_obs_ratio(gobs, robs) <= 1.0)

@@ -41,6 +41,13 @@ def test_exports_every_declared_symbol(tdse):
     assert sorted(tdse.EXPORTED) == names
 
 
+def test_single_hip_runtime(tdse):
+    # libtdse must share torch's HIP runtime: exactly one libamdhip64 mapped
+    maps = open("/proc/self/maps").read().splitlines()
+    hip = {l.split()[-1] for l in maps if "libamdhip64" in l}
+    assert len(hip) == 1, hip
+
+
 def test_stability_limits(tdse):
     assert tdse.tdse_taylor_stability_limit(4) == pytest.approx(2 * math.sqrt(2), abs=1e-9)
     assert tdse.tdse_taylor_stability_limit(3) == pytest.approx(math.sqrt(3), abs=1e-9)
