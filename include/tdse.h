@@ -190,6 +190,14 @@ double tdse_lambda_max_bound(const tdse_ctx* ctx, int32_t inst, double e_max);
  * largest y with |sum_{k<=P} (i y')^k / k!| <= 1 + 1e-12 for all y' <= y. */
 double tdse_taylor_stability_limit(int32_t order);
 
+/* Step-loop replay through HIP graphs (default off).  When on, and timing is
+ * off, and the bound stream is not the null stream, each step call captures
+ * the launches of a 256-step chunk once into a hipGraph and replays it for
+ * every chunk with the same launch pattern; results are bitwise identical to
+ * direct launches.  Graphs are cached per (method, order, chunk length,
+ * observable spacing, d_obs) and dropped on rebind.  Synchronises the stream. */
+tdse_status tdse_use_graphs(tdse_ctx* ctx, int32_t enable);
+
 /* Kernel timing with HIP events recorded around every launch of the named
  * kernel family on the bound stream ("taylor_term", "rk4_stage",
  * "observables", "lanczos_sweep_a", "apply_h").  tdse_timing_enable(ctx, 1)

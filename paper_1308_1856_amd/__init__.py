@@ -33,7 +33,8 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_state_offset", "tdse_state_bytes", "tdse_workspace_bytes", "tdse_bind",
             "tdse_set_state", "tdse_get_state", "tdse_apply_H", "tdse_step_taylor",
             "tdse_step_rk4", "tdse_step_lanczos", "tdse_observables", "tdse_lambda_max_bound",
-            "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read")
+            "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read",
+            "tdse_use_graphs")
 
 
 class TdseError(RuntimeError):
@@ -89,6 +90,7 @@ def _load():
         "tdse_taylor_stability_limit": ([i32], ctypes.c_double),
         "tdse_timing_enable": ([ctxp, i32], i32),
         "tdse_timing_read": ([ctxp, ctypes.c_char_p, ctypes.POINTER(i64), dp], i32),
+        "tdse_use_graphs": ([ctxp, i32], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -194,6 +196,10 @@ def tdse_timing_enable(ctx, enable: bool):
     _check(ctx, lib.tdse_timing_enable(ctx, 1 if enable else 0))
 
 
+def tdse_use_graphs(ctx, enable: bool):
+    _check(ctx, lib.tdse_use_graphs(ctx, 1 if enable else 0))
+
+
 def tdse_timing_read(ctx, kernel: str):
     n = ctypes.c_int64()
     ms = ctypes.c_double()
@@ -222,28 +228,41 @@ class Grid:
 class Propagator:
     """One context (n_inst instances) plus its state and workspace on a GPU.
 
-    `methods` lists (method, order_or_m) pairs the workspace must serve.
+    `methods` lists (method, order_or_m) pairs the workspace must serve.  The
+    library works on its own stream (default priority); every call first
+    orders that stream after torch's current stream and afterwards orders
+    torch's current stream after it, so torch code may use the buffers
+    directly.  `graphs` turns on hipGraph replay of the step loop.
     """
 
     def __init__(self, grids: Sequence[Grid], methods=((METHOD_TAYLOR, 8),), device="cuda:0",
-                 stream=None):
+                 stream=None, graphs: bool = False):
         import torch
         self.torch = torch
         self.grids = list(grids)
         self.ctx = tdse_init_grid([g.desc() for g in self.grids])
         self.n_inst = len(self.grids)
         self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         sbytes = lib.tdse_state_bytes(self.ctx)
         wbytes = max(lib.tdse_workspace_bytes(self.ctx, m, o) for m, o in methods)
         # byte buffers (torch's caching allocator aligns to >= 512 B)
         self.state = torch.zeros(sbytes, dtype=torch.uint8, device=self.device)
         self.work = torch.zeros(wbytes, dtype=torch.uint8, device=self.device)
         self.work_bytes = wbytes
+        torch.cuda.synchronize(self.device)
         tdse_bind(self.ctx, self.state.data_ptr(), self.work.data_ptr(), wbytes,
                   self.stream.cuda_stream)
         self.offsets = [lib.tdse_state_offset(self.ctx, k) for k in range(self.n_inst)]
         self.elem = 16 if self.grids[0].precision == FP64 else 8
+        if graphs:
+            tdse_use_graphs(self.ctx, True)
+
+    def _enter(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
     def close(self):
         if self.ctx:
@@ -259,10 +278,13 @@ class Propagator:
 
     # state
     def set_state(self, inst: int, psi: Optional[np.ndarray] = None):
+        self._enter()
         tdse_set_state(self.ctx, inst, psi)
+        self._leave()
 
     def get_state(self, inst: int) -> np.ndarray:
         g = self.grids[inst]
+        self._enter()
         return tdse_get_state(self.ctx, inst, (g.lmax + 1) * g.n)
 
     def new_vector(self):
@@ -278,25 +300,37 @@ class Propagator:
         return [v] * self.n_inst if np.isscalar(v) else list(v)
 
     def apply_H(self, e_field, d_in, d_out):
+        self._enter()
         tdse_apply_H(self.ctx, self._per_inst(e_field), d_in.data_ptr(), d_out.data_ptr())
+        self._leave()
 
     def step_taylor(self, pulses, t0, dt, order, nsteps, obs_every=0, obs=None):
         ptr = obs.data_ptr() if obs is not None else None
+        self._enter()
         tdse_step_taylor(self.ctx, self._pulse_list(pulses), self._per_inst(t0),
                          self._per_inst(dt), order, nsteps, obs_every, ptr)
+        self._leave()
 
     def step_rk4(self, pulses, t0, dt, nsteps, obs_every=0, obs=None):
         ptr = obs.data_ptr() if obs is not None else None
+        self._enter()
         tdse_step_rk4(self.ctx, self._pulse_list(pulses), self._per_inst(t0), self._per_inst(dt),
                       nsteps, obs_every, ptr)
+        self._leave()
 
     def step_lanczos(self, pulses, t0, dt, m, nsteps, obs_every=0, obs=None):
         ptr = obs.data_ptr() if obs is not None else None
+        self._enter()
         tdse_step_lanczos(self.ctx, self._pulse_list(pulses), self._per_inst(t0),
                           self._per_inst(dt), m, nsteps, obs_every, ptr)
+        self._leave()
 
     def observables(self, pulses, t) -> np.ndarray:
+        self._enter()
         return tdse_observables(self.ctx, self._pulse_list(pulses), self._per_inst(t))
+
+    def use_graphs(self, enable: bool):
+        tdse_use_graphs(self.ctx, enable)
 
     def _pulse_list(self, pulses):
         if isinstance(pulses, (list, tuple)):

@@ -56,9 +56,17 @@ __device__ __forceinline__ double block_sum(double (&v)[NQ], double* lds /* [kBl
     return out;
 }
 
-// The tile handled by this workgroup.
-__device__ __forceinline__ Tile my_tile(const SweepGeom& g) { return g.tiles[g.order[blockIdx.x]]; }
-__device__ __forceinline__ int my_tile_index(const SweepGeom& g) { return g.order[blockIdx.x]; }
+// The tile handled by this workgroup.  The hardware deals workgroup b to XCD
+// b mod 8; each XCD gets a contiguous run of tiles (so the radial and l halos
+// of neighbouring tiles meet in that XCD's L2).  A bijection of [0, n_tiles).
+__device__ __forceinline__ int my_tile_index(const SweepGeom& g)
+{
+    const int b = (int)blockIdx.x;
+    const int q = g.n_tiles >> 3, rem = g.n_tiles & 7;
+    const int x = b & 7, j = b >> 3;
+    return x * q + min(x, rem) + j;
+}
+__device__ __forceinline__ Tile my_tile(const SweepGeom& g) { return g.tiles[my_tile_index(g)]; }
 
 // Stencil weights of -1/2 D2 (zero-padded 3- or 5-point second difference).
 template <int S> struct Kin;
@@ -73,7 +81,7 @@ template <> struct Kin<2> {
 struct RadialPoint {
     double r, inv_r2, z_over_r;
 };
-__device__ __forceinline__ RadialPoint radial_point(const Inst& I, int i)
+__device__ __forceinline__ RadialPoint radial_point(const Tile& I, int i)
 {
     RadialPoint p;
     p.r = (double)(i + 1) * I.dr;

@@ -30,8 +30,8 @@ k_lz_norm(SweepGeom g, const typename Cplx<T>::type* __restrict__ psi, double* _
 {
     __shared__ double lds[kBlock / 64];
     const int t = my_tile_index(g);
-    const Tile tile = g.tiles[t];
-    const Inst& I = g.inst[tile.inst];
+    const Tile I = g.tiles[t];
+    const Tile& tile = I;
     const int i = tile.r0 + (int)threadIdx.x;
     double acc[1] = {0.0};
     if (i < I.n) {
@@ -53,7 +53,7 @@ __device__ __forceinline__ double instance_sum(const Inst& I, const double* part
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-    for (int t = I.tile_begin + (int)threadIdx.x; t < I.tile_end; t += kBlock) {
+    for (int t = I.tbegin[kSweepTiles] + (int)threadIdx.x; t < I.tend[kSweepTiles]; t += kBlock) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
             if (q < nq) acc[q] += partial[(int64_t)t * stride + q];
@@ -91,8 +91,8 @@ k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
     constexpr int JB = 8;
     __shared__ double lds[(kBlock / 64) * 2 * JB];
     const int t = my_tile_index(g);
-    const Tile tile = g.tiles[t];
-    const Inst& I = g.inst[tile.inst];
+    const Tile I = g.tiles[t];
+    const Tile& tile = I;
     const LanczosScalars& sc = scs[tile.inst];
     if (sc.done) return;  // uniform over the workgroup
     const int n = I.n;
@@ -177,8 +177,8 @@ k_lz_sweep_b(SweepGeom g, int j, const typename Cplx<T>::type* psi, typename Cpl
 {
     __shared__ double lds[kBlock / 64];
     const int t = my_tile_index(g);
-    const Tile tile = g.tiles[t];
-    const Inst& I = g.inst[tile.inst];
+    const Tile I = g.tiles[t];
+    const Tile& tile = I;
     const LanczosScalars& sc = scs[tile.inst];
     if (sc.done) return;
     const int i = tile.r0 + (int)threadIdx.x;
@@ -327,8 +327,8 @@ __global__ void __launch_bounds__(kBlock)
 k_lz_recombine(SweepGeom g, typename Cplx<T>::type* psi, const typename Cplx<T>::type* __restrict__ basis,
                int64_t stride, const LanczosScalars* __restrict__ scs)
 {
-    const Tile tile = my_tile(g);
-    const Inst& I = g.inst[tile.inst];
+    const Tile I = my_tile(g);
+    const Tile& tile = I;
     const LanczosScalars& sc = scs[tile.inst];
     const int i = tile.r0 + (int)threadIdx.x;
     if (i >= I.n) return;

@@ -1,104 +1,135 @@
 // Observables of Sec. 4 as FP64 reductions in a fixed order:
 //   norm, p_ion (eq. yield_1), <z> (eq. Dipole), <z''> (eq. DipoleAccel),
 //   p_g (eq. p_g) and the bound-state projections P_nl.
-// Pass 1 writes kObsQ partial sums per tile; pass 2 (one workgroup per
-// instance) adds the partials of the instance's tiles in tile order and
-// forms the record, so results do not depend on scheduling.
+// Pass 1 has two roles in one launch: workgroups [0, n_reduce) stream every
+// row of their reduce tile and sum 4 values; the remaining workgroups each
+// take one population tile (rows l <= 4 of 256 radial points) and sum the 32
+// projection values.  Partials are stored [q][tile] so that pass 2 (one
+// workgroup per instance, adding its tiles in tile order) reads them
+// coalesced.  Results do not depend on scheduling.
 #include "device_common.hpp"
 
 namespace tdse {
 
-// partial layout per tile: 0 sum|f|^2, 1 sum_{r>r_b}|f|^2, 2 sum kappa r Re(f_l* f_l+1),
-// 3 sum kappa Re(f_l* f_l+1)/r^2, 4/5 sum u0 f_0 (re, im), 6+2k/7+2k sum phi_k f_l(k)
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_obs_partial(SweepGeom g, const double* __restrict__ radial, const typename Cplx<T>::type* __restrict__ psi,
-              double* __restrict__ partial)
+__device__ __forceinline__ void obs_main(const SweepGeom& g, const typename Cplx<T>::type* __restrict__ psi,
+                                         double* __restrict__ partial, double* lds)
 {
-    __shared__ double lds[(kBlock / 64) * kObsQ];
     const int t = my_tile_index(g);
-    const Tile tile = g.tiles[t];
-    const Inst& I = g.inst[tile.inst];
+    const Tile I = g.tiles[t];
     const int n = I.n;
-    const int i = tile.r0 + (int)threadIdx.x;
-    double acc[kObsQ];
-#pragma unroll
-    for (int q = 0; q < kObsQ; ++q) acc[q] = 0.0;
+    const int i = I.r0 + (int)threadIdx.x;
+    double acc[kObsMainQ] = {0.0, 0.0, 0.0, 0.0};
     if (i < n) {
         const RadialPoint rp = radial_point(I, i);
-        const double* tab = radial + I.tab_off;
         const bool outer = i >= I.i_ion;
-        double2 cur = ldc(psi, I.off + (int64_t)tile.l0 * n + i);
-        for (int l = tile.l0; l < tile.l1; ++l) {
+        double2 cur = ldc(psi, I.off + (int64_t)I.l0 * n + i);
+        for (int l = I.l0; l < I.l1; ++l) {
             const int64_t row = I.off + (int64_t)l * n;
             const double2 next = (l < I.lmax) ? ldc(psi, row + n + i) : zero2();
             const double a2 = cur.x * cur.x + cur.y * cur.y;
             acc[0] += a2;
             if (outer) acc[1] += a2;
-            const double re = cur.x * next.x + cur.y * next.y;
-            const double kp = g.kappa[l + 1];
-            acc[2] += kp * rp.r * re;
-            acc[3] += kp * re * rp.inv_r2;
-            if (l == 0) {
-                const double u = tab[i];
-                acc[4] += u * cur.x;
-                acc[5] += u * cur.y;
-            }
-            if (l <= 4) {
-                // states ordered l-major: l = 0 -> 0..4, 1 -> 5..8, 2 -> 9..11, 3 -> 12..13, 4 -> 14
-#pragma unroll
-                for (int k = 0; k < kMaxStates; ++k) {
-                    const int kl = (k < 5) ? 0 : (k < 9) ? 1 : (k < 12) ? 2 : (k < 14) ? 3 : 4;
-                    if (kl == l && k < I.n_states) {
-                        const double ph = tab[(int64_t)(1 + k) * n + i];
-                        acc[6 + 2 * k] += ph * cur.x;
-                        acc[7 + 2 * k] += ph * cur.y;
-                    }
-                }
-            }
+            const double re = (cur.x * next.x + cur.y * next.y) * g.kappa[l + 1];
+            acc[2] += rp.r * re;
+            acc[3] += re * rp.inv_r2;
             cur = next;
         }
     }
-    const double s = block_sum<kObsQ>(acc, lds);
-    if (threadIdx.x < kObsQ) partial[(int64_t)t * kObsQ + threadIdx.x] = s;
+    const double s = block_sum<kObsMainQ>(acc, lds);
+    if (threadIdx.x < kObsMainQ) partial[(int64_t)threadIdx.x * g.n_tiles + t] = s;
+}
+
+template <typename T>
+__device__ __forceinline__ void obs_pop(const SweepGeom& g, int t, const double* __restrict__ radial,
+                                        const typename Cplx<T>::type* __restrict__ psi,
+                                        double* __restrict__ partial, double* lds)
+{
+    const Tile I = g.tiles[t];
+    const int n = I.n;
+    const int i = I.r0 + (int)threadIdx.x;
+    double acc[kObsPopQ];
+#pragma unroll
+    for (int q = 0; q < kObsPopQ; ++q) acc[q] = 0.0;
+    if (i < n) {
+        const double* tab = radial + I.tab_off;
+        const double2 f0 = ldc(psi, I.off + i);
+        const double u = tab[i];
+        acc[0] = u * f0.x;
+        acc[1] = u * f0.y;
+        // states ordered l-major: l = 0 -> 0..4, 1 -> 5..8, 2 -> 9..11, 3 -> 12..13, 4 -> 14
+#pragma unroll
+        for (int k = 0; k < kMaxStates; ++k) {
+            const int kl = (k < 5) ? 0 : (k < 9) ? 1 : (k < 12) ? 2 : (k < 14) ? 3 : 4;
+            if (k < I.n_states) {
+                const double2 f = ldc(psi, I.off + (int64_t)kl * n + i);
+                const double ph = tab[(int64_t)(1 + k) * n + i];
+                acc[2 + 2 * k] = ph * f.x;
+                acc[3 + 2 * k] = ph * f.y;
+            }
+        }
+    }
+    const double s = block_sum<kObsPopQ>(acc, lds);
+    if (threadIdx.x < kObsPopQ) partial[(int64_t)threadIdx.x * g.n_tiles + t] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_obs_partial(SweepGeom red, SweepGeom pop, const double* __restrict__ radial,
+              const typename Cplx<T>::type* __restrict__ psi, double* __restrict__ partial_main,
+              double* __restrict__ partial_pop)
+{
+    __shared__ double lds[(kBlock / 64) * kObsPopQ];
+    if ((int)blockIdx.x < red.n_tiles)
+        obs_main<T>(red, psi, partial_main, lds);
+    else
+        obs_pop<T>(pop, (int)blockIdx.x - red.n_tiles, radial, psi, partial_pop, lds);
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_obs_finish(SweepGeom g, const double* __restrict__ partial, const double* __restrict__ step,
-             int64_t rec_stride, double* __restrict__ records)
+k_obs_finish(SweepGeom red, SweepGeom pop, const double* __restrict__ pmain,
+             const double* __restrict__ ppop, const double* __restrict__ step, int64_t rec_stride,
+             double* __restrict__ records)
 {
-    __shared__ double lds[(kBlock / 64) * kObsQ];
-    __shared__ double tot[kObsQ];
+    constexpr int Q = kObsMainQ + kObsPopQ;
+    __shared__ double lds[(kBlock / 64) * Q];
+    __shared__ double tot[Q];
     const int k = blockIdx.x;
-    const Inst& I = g.inst[k];
-    double acc[kObsQ];
+    const Inst& I = red.inst[k];
+    double acc[Q];
 #pragma unroll
-    for (int q = 0; q < kObsQ; ++q) acc[q] = 0.0;
-    for (int t = I.tile_begin + (int)threadIdx.x; t < I.tile_end; t += kBlock) {
+    for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+    for (int t = I.tbegin[kReduceTiles] + (int)threadIdx.x; t < I.tend[kReduceTiles]; t += kBlock) {
 #pragma unroll
-        for (int q = 0; q < kObsQ; ++q) acc[q] += partial[(int64_t)t * kObsQ + q];
+        for (int q = 0; q < kObsMainQ; ++q) acc[q] += pmain[(int64_t)q * red.n_tiles + t];
     }
-    const double s = block_sum<kObsQ>(acc, lds);
-    if (threadIdx.x < kObsQ) tot[threadIdx.x] = s;
+    for (int t = I.tbegin[kPopTiles] + (int)threadIdx.x; t < I.tend[kPopTiles]; t += kBlock) {
+#pragma unroll
+        for (int q = 0; q < kObsPopQ; ++q) acc[kObsMainQ + q] += ppop[(int64_t)q * pop.n_tiles + t];
+    }
+    const double s = block_sum<Q>(acc, lds);
+    if (threadIdx.x < Q) tot[threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         const double dr = I.dr;
-        const double e = step_value(step, g.n_inst, kEEnd, k);
-        double* rec = records + (int64_t)k * rec_stride;
-        rec[0] = step_value(step, g.n_inst, kTEnd, k);
+        const double e = step_value(step, red.n_inst, kEEnd, k);
+        const int64_t ridx = (int64_t)step_value(step, red.n_inst, kRec, k);
+        double* rec = records + (int64_t)k * rec_stride + ridx * kObsRecord;
+        const double* pp = tot + kObsMainQ;
+        rec[0] = step_value(step, red.n_inst, kTEnd, k);
         rec[1] = e;
         rec[2] = dr * tot[0];
-        const double pgr = dr * tot[4], pgi = dr * tot[5];
+        const double pgr = dr * pp[0], pgi = dr * pp[1];
         rec[3] = pgr * pgr + pgi * pgi;
         double pb = 0.0;
         for (int q = 0; q < kMaxStates; ++q) {
-            double pop = 0.0;
+            double popq = 0.0;
             if (q < I.n_states) {
-                const double a = dr * tot[6 + 2 * q], b = dr * tot[7 + 2 * q];
-                pop = a * a + b * b;
+                const double a = dr * pp[2 + 2 * q], b = dr * pp[3 + 2 * q];
+                popq = a * a + b * b;
             }
-            rec[8 + q] = pop;
-            pb += pop;
+            rec[8 + q] = popq;
+            pb += popq;
         }
         rec[4] = pb;
         rec[5] = dr * tot[1];
@@ -107,23 +138,26 @@ k_obs_finish(SweepGeom g, const double* __restrict__ partial, const double* __re
     }
 }
 
-hipError_t launch_obs_partial(int prec, const SweepGeom& g, const double* radial_tab,
-                              const void* psi, double* partial, hipStream_t st)
+hipError_t launch_obs_partial(int prec, const SweepGeom& red, const SweepGeom& pop,
+                              const double* radial_tab, const void* psi, double* partial_main,
+                              double* partial_pop, hipStream_t st)
 {
+    const dim3 grid(red.n_tiles + pop.n_tiles);
     if (prec == 0)
-        hipLaunchKernelGGL((k_obs_partial<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           radial_tab, static_cast<const double2*>(psi), partial);
+        hipLaunchKernelGGL((k_obs_partial<double>), grid, dim3(kBlock), 0, st, red, pop, radial_tab,
+                           static_cast<const double2*>(psi), partial_main, partial_pop);
     else
-        hipLaunchKernelGGL((k_obs_partial<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           radial_tab, static_cast<const float2*>(psi), partial);
+        hipLaunchKernelGGL((k_obs_partial<float>), grid, dim3(kBlock), 0, st, red, pop, radial_tab,
+                           static_cast<const float2*>(psi), partial_main, partial_pop);
     return hipGetLastError();
 }
 
-hipError_t launch_obs_finish(const SweepGeom& g, const double* partial, const double* step,
-                             int64_t rec_stride, double* out_records, hipStream_t st)
+hipError_t launch_obs_finish(const SweepGeom& red, const SweepGeom& pop, const double* partial_main,
+                             const double* partial_pop, const double* step, int64_t rec_stride,
+                             double* out_records, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_obs_finish, dim3(g.n_inst), dim3(kBlock), 0, st, g, partial, step,
-                       rec_stride, out_records);
+    hipLaunchKernelGGL(k_obs_finish, dim3(red.n_inst), dim3(kBlock), 0, st, red, pop, partial_main,
+                       partial_pop, step, rec_stride, out_records);
     return hipGetLastError();
 }
 

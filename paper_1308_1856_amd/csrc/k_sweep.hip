@@ -20,8 +20,8 @@ k_hsweep(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
          const double* __restrict__ step, int term)
 {
     using C = typename Cplx<T>::type;
-    const Tile tile = my_tile(g);
-    const Inst& I = g.inst[tile.inst];
+    const Tile I = my_tile(g);
+    const Tile& tile = I;
     const int n = I.n;
     const int i = tile.r0 + (int)threadIdx.x;
     if (i >= n) return;
@@ -66,8 +66,8 @@ k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
             typename Cplx<T>::type* __restrict__ gout, const double* __restrict__ step)
 {
     using C = typename Cplx<T>::type;
-    const Tile tile = my_tile(g);
-    const Inst& I = g.inst[tile.inst];
+    const Tile I = my_tile(g);
+    const Tile& tile = I;
     const int n = I.n;
     const int i = tile.r0 + (int)threadIdx.x;
     if (i >= n) return;
@@ -111,11 +111,10 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_copy(SweepGeom g, const typename Cplx<T>::type* __restrict__ src, typename Cplx<T>::type* __restrict__ dst)
 {
-    const Tile tile = my_tile(g);
-    const Inst& I = g.inst[tile.inst];
-    const int i = tile.r0 + (int)threadIdx.x;
+    const Tile I = my_tile(g);
+    const int i = I.r0 + (int)threadIdx.x;
     if (i >= I.n) return;
-    for (int l = tile.l0; l < tile.l1; ++l) {
+    for (int l = I.l0; l < I.l1; ++l) {
         const int64_t k = I.off + (int64_t)l * I.n + i;
         dst[k] = src[k];
     }

@@ -41,8 +41,8 @@ struct tdse_ctx {
     size_t elem = 16;
     std::vector<tdse_grid_desc> grids;
     std::vector<Inst> inst;
-    std::vector<Tile> tiles;
-    std::vector<int32_t> order;
+    std::vector<Tile> tiles[kNumTileSets];
+    int rows_sweep = 1, rows_reduce = 1;
     std::vector<double> kappa;
     std::vector<double> radial;            // per instance: u0 row then n_states phi rows
     std::vector<int> lmax_max;
@@ -54,14 +54,22 @@ struct tdse_ctx {
     size_t work_bytes = 0;
     hipStream_t stream = nullptr;
     // workspace layout (bytes from d_work)
-    size_t off_inst = 0, off_tiles = 0, off_order = 0, off_kappa = 0, off_radial = 0, off_step = 0,
-           off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0;
+    size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0}, off_kappa = 0, off_radial = 0,
+           off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0;
     size_t partial_doubles = 0;
     // pinned staging for the per-step scalars (double buffered)
     double* h_step[2] = {nullptr, nullptr};
     hipEvent_t step_ev[2] = {nullptr, nullptr};
     bool step_ev_used[2] = {false, false};
     int step_buf = 0;
+    // captured step graphs, keyed by the launch pattern of a chunk
+    bool use_graphs = false;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    void drop_graphs()
+    {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        graphs.clear();
+    }
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -78,15 +86,16 @@ struct tdse_ctx {
         err = std::string(what) + ": " + hipGetErrorString(e);
         return TDSE_E_HIP;
     }
-    SweepGeom geom() const
+    SweepGeom geom(int set = kSweepTiles) const
     {
         SweepGeom g;
         g.inst = reinterpret_cast<const Inst*>(d_work + off_inst);
-        g.tiles = reinterpret_cast<const Tile*>(d_work + off_tiles);
-        g.order = reinterpret_cast<const int32_t*>(d_work + off_order);
+        g.tiles = reinterpret_cast<const Tile*>(d_work + off_tiles[set]);
         g.kappa = reinterpret_cast<const double*>(d_work + off_kappa);
-        g.n_tiles = (int32_t)tiles.size();
+        g.n_tiles = (int32_t)tiles[set].size();
         g.n_inst = n_inst;
+        g.set = set;
+        g.pad_ = 0;
         return g;
     }
     double* d_step() const { return reinterpret_cast<double*>(d_work + off_step); }
@@ -252,29 +261,45 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->kappa.resize(lmax_all + 2);
     for (int l = 0; l < lmax_all + 2; ++l)
         c->kappa[l] = (l > 0) ? std::sqrt((double)l * l / (4.0 * l * l - 1.0)) : 0.0;
-    // tiles: rows per tile chosen so the whole launch has >= kTargetTiles workgroups
+    // Tile sets.  Sweeps: rows per tile chosen so the launch has >= kTargetTiles
+    // workgroups.  Reductions: taller tiles (fewer partial sums).  Populations:
+    // one tile per 256 radial points covering rows 0..min(lmax, 4).
     int64_t total_cols = 0;
     for (int k = 0; k < n_inst; ++k)
         total_cols += (int64_t)((grids[k].n_r + kBlock - 1) / kBlock) * (grids[k].lmax + 1);
     int rows = kTileRows;
     while (rows > 1 && total_cols / rows < kTargetTiles) rows /= 2;
-    for (int k = 0; k < n_inst; ++k) {
-        Inst& I = c->inst[k];
-        I.tile_begin = (int32_t)c->tiles.size();
-        for (int l0 = 0; l0 <= I.lmax; l0 += rows)
-            for (int r0 = 0; r0 < I.n; r0 += kBlock)
-                c->tiles.push_back(Tile{k, r0, l0, std::min(l0 + rows, I.lmax + 1)});
-        I.tile_end = (int32_t)c->tiles.size();
-    }
-    // XCD-aware block order: the hardware deals workgroup b to XCD b mod 8; give
-    // each XCD a contiguous run of tiles so radial and l halos stay in its L2.
-    const int nt = (int)c->tiles.size();
-    c->order.resize(nt);
-    const int q = nt / 8, rem = nt % 8;
-    for (int b = 0; b < nt; ++b) {
-        const int x = b % 8, j = b / 8;
-        const int start = x * q + std::min(x, rem);
-        c->order[b] = start + j;
+    c->rows_sweep = rows;
+    c->rows_reduce = std::max(rows, 16);
+    for (int set = 0; set < kNumTileSets; ++set) {
+        const int rset = (set == kSweepTiles) ? c->rows_sweep : c->rows_reduce;
+        for (int k = 0; k < n_inst; ++k) {
+            Inst& I = c->inst[k];
+            I.tbegin[set] = (int32_t)c->tiles[set].size();
+            const int lhi = (set == kPopTiles) ? std::min(I.lmax, 4) + 1 : I.lmax + 1;
+            const int step = (set == kPopTiles) ? lhi : rset;
+            for (int l0 = 0; l0 < lhi; l0 += step) {
+                for (int r0 = 0; r0 < I.n; r0 += kBlock) {
+                    Tile t;
+                    std::memset(&t, 0, sizeof t);
+                    t.off = I.off;
+                    t.tab_off = I.tab_off;
+                    t.inst = k;
+                    t.r0 = r0;
+                    t.l0 = l0;
+                    t.l1 = std::min(l0 + step, lhi);
+                    t.n = I.n;
+                    t.lmax = I.lmax;
+                    t.i_ion = I.i_ion;
+                    t.n_states = I.n_states;
+                    t.dr = I.dr;
+                    t.inv_dr2 = I.inv_dr2;
+                    t.z = I.z;
+                    c->tiles[set].push_back(t);
+                }
+            }
+            I.tend[set] = (int32_t)c->tiles[set].size();
+        }
     }
     // radial tables: u0 (normalised r exp(-z r)) and the bound eigenvectors
     c->radial.assign(tab, 0.0);
@@ -321,14 +346,15 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         return at;
     };
     c->off_inst = take(sizeof(Inst) * n_inst);
-    c->off_tiles = take(sizeof(Tile) * nt);
-    c->off_order = take(sizeof(int32_t) * nt);
+    for (int set = 0; set < kNumTileSets; ++set) c->off_tiles[set] = take(sizeof(Tile) * c->tiles[set].size());
     c->off_kappa = take(sizeof(double) * c->kappa.size());
     c->off_radial = take(sizeof(double) * c->radial.size());
     c->off_step = take(sizeof(double) * kSlots * (size_t)n_inst * kEtabSteps);
     c->off_obs_tmp = take(sizeof(tdse_obs) * n_inst);
     c->off_lz = take(sizeof(LanczosScalars) * n_inst);
-    c->partial_doubles = (size_t)nt * std::max(kObsQ, 2 * kMaxKrylov);
+    c->partial_doubles = std::max((size_t)c->tiles[kSweepTiles].size() * 2 * kMaxKrylov,
+                                  (size_t)c->tiles[kReduceTiles].size() * kObsMainQ +
+                                      (size_t)c->tiles[kPopTiles].size() * kObsPopQ);
     c->off_partial = take(sizeof(double) * c->partial_doubles);
     c->off_vecs = o;
     c->fixed_bytes = o;
@@ -339,6 +365,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
 extern "C" void tdse_destroy(tdse_ctx* c)
 {
     if (!c) return;
+    c->drop_graphs();
     for (auto& e : c->ev_pool) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -384,6 +411,7 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         return c->fail(TDSE_E_INVALID, "tdse_bind: device buffers must be 256-byte aligned");
     if (work_bytes < c->fixed_bytes)
         return c->fail(TDSE_E_WORKSPACE, "tdse_bind: workspace smaller than the fixed tables");
+    c->drop_graphs();
     c->d_state = static_cast<char*>(d_state);
     c->d_work = static_cast<char*>(d_work);
     c->work_bytes = work_bytes;
@@ -403,8 +431,9 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         size_t bytes;
     } ups[] = {
         {c->off_inst, c->inst.data(), sizeof(Inst) * c->inst.size()},
-        {c->off_tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size()},
-        {c->off_order, c->order.data(), sizeof(int32_t) * c->order.size()},
+        {c->off_tiles[kSweepTiles], c->tiles[kSweepTiles].data(), sizeof(Tile) * c->tiles[kSweepTiles].size()},
+        {c->off_tiles[kReduceTiles], c->tiles[kReduceTiles].data(), sizeof(Tile) * c->tiles[kReduceTiles].size()},
+        {c->off_tiles[kPopTiles], c->tiles[kPopTiles].data(), sizeof(Tile) * c->tiles[kPopTiles].size()},
         {c->off_kappa, c->kappa.data(), sizeof(double) * c->kappa.size()},
         {c->off_radial, c->radial.data(), sizeof(double) * c->radial.size()},
     };
@@ -483,7 +512,7 @@ double field_at(const tdse_pulse& p, double t)
 // Fills and uploads the scalars of steps [s0, s0 + count) (count <= kEtabSteps)
 // for every instance; returns the device base of the chunk.
 tdse_status upload_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, const double* dt,
-                         int64_t s0, int count)
+                         int64_t s0, int count, int obs_every)
 {
     const int b = c->step_buf;
     c->step_buf ^= 1;
@@ -505,6 +534,8 @@ tdse_status upload_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0
             row[kEEnd * n + k] = pulses ? field_at(pulses[k], te) : 0.0;
             row[kTEnd * n + k] = te;
             row[kDt * n + k] = dt[k];
+            const int64_t done = s0 + s + 1;
+            row[kRec * n + k] = (obs_every > 0 && done % obs_every == 0) ? (double)(done / obs_every - 1) : -1.0;
         }
     }
     hipError_t e = hipMemcpyAsync(c->d_step(), h, sizeof(double) * kSlots * n * (size_t)count,
@@ -554,37 +585,80 @@ tdse_status check_stable(tdse_ctx* c, const tdse_pulse* pulses, const double* dt
 }
 
 // observables of the state after step s (within the uploaded chunk at `step`)
-hipError_t launch_obs(tdse_ctx* c, const void* psi, const double* step, double* rec_base,
+hipError_t launch_obs(tdse_ctx* c, const void* psi, const double* step, double* records,
                       int64_t rec_stride)
 {
     TimedLaunch tl(c, 2);
-    const SweepGeom g = c->geom();
-    hipError_t e = launch_obs_partial(c->prec, g, c->d_radial(), psi, c->d_partial(), c->stream);
+    const SweepGeom red = c->geom(kReduceTiles), pop = c->geom(kPopTiles);
+    double* pmain = c->d_partial();
+    double* ppop = pmain + (size_t)red.n_tiles * kObsMainQ;
+    hipError_t e = launch_obs_partial(c->prec, red, pop, c->d_radial(), psi, pmain, ppop, c->stream);
     if (e != hipSuccess) return e;
-    return launch_obs_finish(g, c->d_partial(), step, rec_stride, rec_base, c->stream);
+    return launch_obs_finish(red, pop, pmain, ppop, step, rec_stride, records, c->stream);
 }
 
+// Enqueues the launches of steps [s0, s0 + count) of the current chunk.
+template <typename StepFn>
+hipError_t enqueue_chunk(tdse_ctx* c, int64_t s0, int count, int32_t obs_every, tdse_obs* d_obs,
+                         int64_t rec_stride, StepFn& step_fn)
+{
+    for (int s = 0; s < count; ++s) {
+        const double* step = c->d_step() + (size_t)s * kSlots * c->n_inst;
+        hipError_t e = step_fn(step);
+        if (e != hipSuccess) return e;
+        if (obs_every > 0 && (s0 + s + 1) % obs_every == 0) {
+            e = launch_obs(c, c->d_state, step, reinterpret_cast<double*>(d_obs), rec_stride);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// Runs nsteps steps in chunks of kEtabSteps.  With graphs on (and timing
+// off), the launches of a chunk are captured once into a hipGraph and the
+// executable graph is replayed for every chunk with the same pattern; the
+// per-step scalars (fields, times, record indices) are uploaded before each
+// chunk, so the graph itself never changes.
 template <typename StepFn>
 tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, const double* dt,
-                      int32_t nsteps, int32_t obs_every, tdse_obs* d_obs, StepFn&& step_fn)
+                      int32_t nsteps, int32_t obs_every, tdse_obs* d_obs, int64_t method_key,
+                      StepFn&& step_fn)
 {
     const int64_t n_rec = (obs_every > 0) ? nsteps / obs_every : 0;
-    const int64_t rec_stride = n_rec * (int64_t)(sizeof(tdse_obs) / sizeof(double));
+    const int64_t rec_stride = n_rec * (int64_t)kObsRecord;
+    const bool graphs = c->use_graphs && !c->timing && c->stream != nullptr;
     for (int64_t s0 = 0; s0 < nsteps; s0 += kEtabSteps) {
         const int count = (int)std::min<int64_t>(kEtabSteps, nsteps - s0);
-        tdse_status st = upload_steps(c, pulses, t0, dt, s0, count);
+        tdse_status st = upload_steps(c, pulses, t0, dt, s0, count, obs_every);
         if (st != TDSE_OK) return st;
-        for (int s = 0; s < count; ++s) {
-            const double* step = c->d_step() + (size_t)s * kSlots * c->n_inst;
-            hipError_t e = step_fn(step);
+        if (!graphs) {
+            hipError_t e = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, step_fn);
             if (e != hipSuccess) return c->hip_fail(e, "step launch");
-            const int64_t done = s0 + s + 1;
-            if (obs_every > 0 && done % obs_every == 0) {
-                double* rec = reinterpret_cast<double*>(d_obs + (done / obs_every - 1));
-                e = launch_obs(c, c->d_state, step, rec, rec_stride);
-                if (e != hipSuccess) return c->hip_fail(e, "observables launch");
-            }
+            continue;
         }
+        const std::vector<int64_t> key = {method_key, count, obs_every,
+                                          obs_every > 0 ? s0 % obs_every : 0,
+                                          (int64_t)reinterpret_cast<uintptr_t>(d_obs), rec_stride};
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return c->hip_fail(e, "hipStreamBeginCapture");
+            hipError_t el = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, step_fn);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(c->stream, &graph);
+            if (el != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return c->hip_fail(el, "step launch during capture");
+            }
+            if (e != hipSuccess) return c->hip_fail(e, "hipStreamEndCapture");
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return c->hip_fail(e, "hipGraphInstantiate");
+            it = c->graphs.emplace(key, exec).first;
+        }
+        hipError_t e = hipGraphLaunch(it->second, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "hipGraphLaunch");
     }
     return TDSE_OK;
 }
@@ -606,7 +680,7 @@ extern "C" tdse_status tdse_apply_H(tdse_ctx* c, const double* e_field, const vo
     std::vector<tdse_pulse> none(c->n_inst);
     std::vector<double> zero(c->n_inst, 0.0), one(c->n_inst, 1.0);
     // slot kEMid carries the caller's field values
-    tdse_status st = upload_steps(c, nullptr, zero.data(), one.data(), 0, 1);
+    tdse_status st = upload_steps(c, nullptr, zero.data(), one.data(), 0, 1, 0);
     if (st != TDSE_OK) return st;
     hipError_t e = hipMemcpyAsync(c->d_step() + kEMid * c->n_inst, e_field, sizeof(double) * c->n_inst,
                                   hipMemcpyHostToDevice, c->stream);
@@ -634,7 +708,7 @@ extern "C" tdse_status tdse_step_taylor(tdse_ctx* c, const tdse_pulse* pulses, c
     void* psi = c->d_state;
     void* wa = c->d_vec(0);
     void* wb = c->d_vec(1);
-    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, [&](const double* step) {
+    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 1000 + order, [&](const double* step) {
         // Horner: w = psi + (-i dt/P) H psi; w = psi + (-i dt/k) H w, k = P-1..1
         const void* in = psi;
         void* bufs[2] = {wa, wb};
@@ -670,7 +744,7 @@ extern "C" tdse_status tdse_step_rk4(tdse_ctx* c, const tdse_pulse* pulses, cons
     void* ga = c->d_vec(0);
     void* gb = c->d_vec(1);
     void* acc = c->d_vec(2);
-    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, [&](const double* step) {
+    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 2000, [&](const double* step) {
         const void* gin[4] = {psi, ga, gb, ga};
         void* gout[4] = {ga, gb, ga, nullptr};
         for (int s = 0; s < 4; ++s) {
@@ -698,7 +772,7 @@ extern "C" tdse_status tdse_step_lanczos(tdse_ctx* c, const tdse_pulse* pulses, 
     const int64_t stride = (int64_t)(c->state_bytes() / c->elem);
     LanczosScalars* sc = c->d_lz();
     double* part = c->d_partial();
-    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, [&](const double* step) {
+    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 3000 + m, [&](const double* step) {
         hipError_t e = launch_lz_norm(c->prec, g, psi, part, c->stream);
         if (e == hipSuccess) e = launch_lz_norm_finish(g, part, sc, c->stream);
         for (int j = 0; j < m && e == hipSuccess; ++j) {
@@ -727,7 +801,7 @@ extern "C" tdse_status tdse_observables(tdse_ctx* c, const tdse_pulse* pulses, c
     // one pseudo-step whose end is t: t0 = t - dt with dt = 1 gives t_end = t
     std::vector<double> t0(c->n_inst), one(c->n_inst, 1.0);
     for (int k = 0; k < c->n_inst; ++k) t0[k] = t[k] - 1.0;
-    tdse_status st = upload_steps(c, pulses, t0.data(), one.data(), 0, 1);
+    tdse_status st = upload_steps(c, pulses, t0.data(), one.data(), 0, 1, 1);
     if (st != TDSE_OK) return st;
     // the exact time t (not (t - 1) + 1) goes into the record
     double* tmp = reinterpret_cast<double*>(c->d_work + c->off_obs_tmp);
@@ -738,13 +812,25 @@ extern "C" tdse_status tdse_observables(tdse_ctx* c, const tdse_pulse* pulses, c
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_step() + kEEnd * c->n_inst, ee.data(), sizeof(double) * c->n_inst,
                            hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = launch_obs(c, c->d_state, c->d_step(), tmp, sizeof(tdse_obs) / sizeof(double));
+    if (e == hipSuccess) e = launch_obs(c, c->d_state, c->d_step(), tmp, kObsRecord);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host_out, tmp, sizeof(tdse_obs) * c->n_inst, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "tdse_observables");
     for (int k = 0; k < c->n_inst; ++k)
         if (!std::isfinite(host_out[k].norm)) return c->fail(TDSE_E_NONFINITE, "tdse_observables: norm is not finite");
+    return TDSE_OK;
+}
+
+extern "C" tdse_status tdse_use_graphs(tdse_ctx* c, int32_t enable)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (c->bound) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_use_graphs sync");
+    }
+    c->use_graphs = enable != 0;
+    if (!c->use_graphs) c->drop_graphs();
     return TDSE_OK;
 }
 

@@ -11,9 +11,12 @@ namespace tdse {
 constexpr int kBlock = 256;         // threads per workgroup of the sweep kernels (4 wave64)
 constexpr int kMaxStates = 15;      // bound states n <= 5
 constexpr int kMaxKrylov = 64;      // largest Lanczos dimension
-constexpr int kObsQ = 6 + 2 * kMaxStates;  // per-tile partial sums of the observables
 
-// One instance (grid) as the kernels see it.
+// Tile sets: the sweeps (H applications), the streaming reductions, and the
+// population projections (rows l <= 4 only).
+enum TileSetId { kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kNumTileSets = 3 };
+
+// One instance (grid) as the per-instance kernels see it.
 struct Inst {
     int64_t off;        // element offset of (l = 0, i = 0) in every state-shaped vector
     int64_t tab_off;    // offset (doubles) of this instance's u0 row in the radial table
@@ -21,20 +24,23 @@ struct Inst {
     int32_t lmax;
     int32_t n_states;   // bound states tracked (<= 15)
     int32_t i_ion;      // first radial index with r_i > r_ion
-    int32_t tile_begin; // tiles [tile_begin, tile_end) of the sweep tile table
-    int32_t tile_end;
+    int32_t tbegin[kNumTileSets];  // tiles [tbegin, tend) of each tile set
+    int32_t tend[kNumTileSets];
     double dr;
     double inv_dr2;     // 1 / dr^2
     double z;
     double breakdown;   // Lanczos breakdown threshold: 1e-12 * Gershgorin bound of H
 };
 
-// A workgroup's share of a sweep: radial points [r0, r0 + kBlock) of rows [l0, l1).
+// A workgroup's share of a sweep: radial points [r0, r0 + kBlock) of rows
+// [l0, l1) of one instance, with the instance fields the kernels need, so a
+// workgroup starts with one uniform (scalar) load.
 struct Tile {
-    int32_t inst;
-    int32_t r0;
-    int32_t l0;
-    int32_t l1;
+    int64_t off;
+    int64_t tab_off;
+    int32_t inst, r0, l0, l1;
+    int32_t n, lmax, i_ion, n_states;
+    double dr, inv_dr2, z, pad_;
 };
 
 // Lanczos scalars per instance (FP64, device).
@@ -56,15 +62,17 @@ struct LanczosScalars {
 // ----------------------------------------------------------------------------
 struct SweepGeom {
     const Inst* inst;      // device instance table
-    const Tile* tiles;     // device tile table
-    const int32_t* order;  // device block -> tile permutation (XCD-aware)
+    const Tile* tiles;     // device tile table of the tile set used by the launch
     const double* kappa;   // device kappa_l table (lmax_max + 2 entries)
     int32_t n_tiles;
     int32_t n_inst;
+    int32_t set;           // TileSetId of `tiles`
+    int32_t pad_;
 };
 
 // Per-step scalars, FP64, laid out [slot][instance] with these slots:
-enum StepSlot { kEStart = 0, kEMid = 1, kEEnd = 2, kTEnd = 3, kDt = 4, kSlots = 5 };
+// kRec: index of the observable record written after this step (-1: none).
+enum StepSlot { kEStart = 0, kEMid = 1, kEEnd = 2, kTEnd = 3, kDt = 4, kRec = 5, kSlots = 6 };
 __host__ __device__ inline double step_value(const double* st, int n_inst, int slot, int inst)
 {
     return st[slot * n_inst + inst];
@@ -81,13 +89,21 @@ hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, cons
                             const void* psi, void* acc, void* gout, const double* step,
                             hipStream_t st);
 
-// Per-tile partial sums of the observables of `psi` (kObsQ per tile).
-hipError_t launch_obs_partial(int prec, const SweepGeom& g, const double* radial_tab,
-                              const void* psi, double* partial, hipStream_t st);
+// Observables: per-tile partial sums of norm, p_ion, dipole and acceleration
+// over the reduce tiles (kObsMainQ per tile, stored [q][tile]) and of p_g and
+// the projections over the population tiles (kObsPopQ per tile, [q][tile]).
+constexpr int kObsMainQ = 4;
+constexpr int kObsRecord = 8 + kMaxStates;   // doubles per tdse_obs record
+constexpr int kObsPopQ = 2 + 2 * kMaxStates;
+hipError_t launch_obs_partial(int prec, const SweepGeom& red, const SweepGeom& pop,
+                              const double* radial_tab, const void* psi, double* partial_main,
+                              double* partial_pop, hipStream_t st);
 // One block per instance: sums the partials in tile order and writes the
-// record of instance k at out_records + k * rec_stride (doubles).
-hipError_t launch_obs_finish(const SweepGeom& g, const double* partial, const double* step,
-                             int64_t rec_stride, double* out_records, hipStream_t st);
+// record of instance k at records + k * rec_stride + 23 * rec, with rec the
+// record index of the step (kRec slot).
+hipError_t launch_obs_finish(const SweepGeom& red, const SweepGeom& pop, const double* partial_main,
+                             const double* partial_pop, const double* step, int64_t rec_stride,
+                             double* out_records, hipStream_t st);
 
 // Lanczos pieces (basis vector j >= 1 lives at basis + (j-1)*vec_stride
 // elements; vector 0 is the state itself).

@@ -267,3 +267,39 @@ def test_minimum_grid_and_single_partial_wave():
                                                dt=2e-3, steps=10, obs_every=5)
         assert rel_err(got, ref) < TOL64
         assert np.all(_obs_ratio(gobs, robs) <= 1.0)
+
+
+@pytest.mark.parametrize("method", ["taylor", "rk4", "lanczos"])
+def test_graph_replay_matches_direct_launches(method):
+    # 700 steps = chunks of 256, 256, 188 steps; observables every 64 steps,
+    # so the first two chunks replay one graph.  The call is made twice and
+    # each graph replay is compared bit for bit with direct launches.
+    t = lib()
+    grid = t.Grid(300, 5, 0.1, 5, t.FP64, 1.0, 10.0)
+    mcode = {"taylor": t.METHOD_TAYLOR, "rk4": t.METHOD_RK4, "lanczos": t.METHOD_LANCZOS}[method]
+    order = {"taylor": 8, "rk4": 4, "lanczos": 10}[method]
+    pulse = t.Pulse(0.05, 0.4, 2.0, 0.0, 0.0)
+    dt = 5e-4 if method != "lanczos" else 5e-3
+    say(f"graph replay vs direct launches: {method}")
+    results = []
+    for graphs in (False, True):
+        prop = t.Propagator([grid], methods=((mcode, order),), graphs=graphs)
+        prop.set_state(0, None)
+        states, records = [], []
+        for call in range(2):
+            obs = prop.obs_buffer(700, 64)
+            t0 = call * 700 * dt
+            if method == "taylor":
+                prop.step_taylor(pulse, t0, dt, order, 700, 64, obs)
+            elif method == "rk4":
+                prop.step_rk4(pulse, t0, dt, 700, 64, obs)
+            else:
+                prop.step_lanczos(pulse, t0, dt, order, 700, 64, obs)
+            states.append(prop.get_state(0))
+            records.append(obs.cpu().numpy())
+            _ = prop.observables(pulse, t0)        # eager work between replays
+        prop.close()
+        results.append((states, records))
+    for call in range(2):
+        assert np.array_equal(results[0][0][call], results[1][0][call])
+        assert np.array_equal(results[0][1][call], results[1][1][call])

@@ -141,15 +141,21 @@ def batch_members(count: int = 256, seed: int = BATCH_SEED):
 BATCH_DR = 0.1
 BATCH_STENCIL = 3
 BATCH_ORDER = 8
+BATCH_R_ION_FRACTION = 0.25      # r_b = 0.25 * R for each member
+BATCH_DT_SAFETY = 0.8            # dt = 0.8 * y_8 / lambda_bound(member)
 
 
 def random_state(seed: int, n: int, lmax: int, smooth: bool = False) -> np.ndarray:
-    """Seeded complex128 test vector of shape [(lmax+1)*n] (unnormalised)."""
+    """Seeded complex128 test vector of shape [(lmax+1)*n] (unnormalised).
+    smooth=True: per partial wave a random complex amplitude times
+    sin^2(pi r/R) plus 0.1 times another random amplitude times sin(6 pi r/R)."""
     rng = np.random.default_rng(seed)
-    v = rng.standard_normal((lmax + 1, n)) + 1j * rng.standard_normal((lmax + 1, n))
     if smooth:
-        # a random superposition of smooth bumps per partial wave
+        c = rng.standard_normal((lmax + 1, 4))
+        a = (c[:, 0] + 1j * c[:, 1])[:, None]
+        b = (c[:, 2] + 1j * c[:, 3])[:, None]
         r = np.arange(1, n + 1) / n
-        env = np.sin(np.pi * r) ** 2
-        v = v[:, :1] * env[None, :] + 0.1 * v[:, 1:2] * np.sin(6 * np.pi * r)[None, :]
+        v = a * (np.sin(np.pi * r) ** 2)[None, :] + 0.1 * b * np.sin(6 * np.pi * r)[None, :]
+    else:
+        v = rng.standard_normal((lmax + 1, n)) + 1j * rng.standard_normal((lmax + 1, n))
     return np.ascontiguousarray(v.reshape(-1))
