@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 METRIC = "H·ψ applies/s & HBM GB/s fraction; steps/s FP32-mixed vs FP64 at stated error"
+BATCH_NAME = "batch256_fp32_taylor8"
 HBM_PEAK_GBS = 8000.0
 
 
@@ -44,10 +45,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="hydrogen_n20000_l64_fp64_taylor8",
-                    choices=sorted(workloads.WORKLOADS))
+                    choices=sorted(workloads.WORKLOADS) + [BATCH_NAME])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--graphs", type=int, default=1, help="replay step chunks as HIP graphs")
+    ap.add_argument("--autotune", type=int, default=1, help="autotune the sweep tile shape first")
     return ap.parse_args()
 
 
@@ -55,9 +58,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_prop(tdse, wl, precision, method_code):
+def make_prop(tdse, wl, precision, method_code, graphs=True, autotune=True):
     g = tdse.Grid(wl.n, wl.lmax, wl.dr, wl.stencil, precision, wl.z, wl.r_ion)
-    prop = tdse.Propagator([g], methods=((method_code, wl.order),))
+    methods = ((method_code, wl.order), (tdse.METHOD_TAYLOR, 2))
+    prop = tdse.Propagator([g], methods=methods, graphs=bool(graphs))
+    if autotune:
+        prop.autotune()
     prop.set_state(0, None)
     return prop
 
@@ -72,24 +78,133 @@ def run_steps(prop, tdse, wl, t0, nsteps, obs):
         prop.step_lanczos(p, t0, wl.dt, wl.order, nsteps, wl.obs_every, obs)
 
 
-def timed(prop, tdse, wl, torch, steps, warmup, kernel):
+def timed(prop, tdse, wl, torch, steps, warmup, kernel, graphs):
     obs_w = prop.obs_buffer(max(warmup, 1), wl.obs_every)
     obs = prop.obs_buffer(steps, wl.obs_every)
-    run_steps(prop, tdse, wl, wl.t0, warmup, obs_w)
+    t = wl.t0
+    run_steps(prop, tdse, wl, t, warmup, obs_w)
+    t += warmup * wl.dt
+    if graphs:
+        # capture and instantiate the chunk graphs of a K-step call outside the
+        # timed region (replays of the same pattern reuse them)
+        run_steps(prop, tdse, wl, t, steps, obs)
+        t += steps * wl.dt
     torch.cuda.synchronize()
-    t_start = wl.t0 + warmup * wl.dt
     t0 = time.perf_counter()
-    run_steps(prop, tdse, wl, t_start, steps, obs)
+    run_steps(prop, tdse, wl, t, steps, obs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    t += steps * wl.dt
     # second pass of the same length with HIP events around each launch of the
-    # dominant kernel (kept out of the wall-clock pass above)
+    # dominant kernel (direct launches; kept out of the wall-clock pass above)
     prop.timing(True)
-    run_steps(prop, tdse, wl, t_start + steps * wl.dt, steps, obs)
+    run_steps(prop, tdse, wl, t, steps, obs)
     launches, kms = prop.timing_read(kernel)
     prop.timing(False)
     torch.cuda.synchronize()
     return wall, launches, kms, obs
+
+
+def batch_setup(tdse, precision):
+    members = workloads.batch_members()
+    grids, pulses = [], []
+    for m in members:
+        R = m.n * workloads.BATCH_DR
+        grids.append(tdse.Grid(m.n, m.lmax, workloads.BATCH_DR, workloads.BATCH_STENCIL, precision,
+                               1.0, workloads.BATCH_R_ION_FRACTION * R))
+        pp = m.pulse
+        pulses.append(tdse.Pulse(pp.e0, pp.omega, pp.n_cycles, pp.cep, pp.t_on))
+    return members, grids, pulses
+
+
+def run_batch_prec(tdse, torch, precision, args):
+    members, grids, pulses = batch_setup(tdse, precision)
+    order = workloads.BATCH_ORDER
+    prop = tdse.Propagator(grids, methods=((tdse.METHOD_TAYLOR, order),), graphs=bool(args.graphs))
+    if args.autotune:
+        prop.autotune()
+    y = tdse.tdse_taylor_stability_limit(order)
+    dts = [workloads.BATCH_DT_SAFETY * y / prop.lambda_max_bound(k, abs(p.e0)) for k, p in enumerate(pulses)]
+    for k in range(len(grids)):
+        prop.set_state(k, None)
+    t = [0.0] * len(grids)
+
+    def run(n, obs):
+        nonlocal t
+        prop.step_taylor(pulses, t, dts, order, n, 1, obs)
+        t = [tk + n * d for tk, d in zip(t, dts)]
+
+    obs_w = prop.obs_buffer(max(args.warmup, 1), 1)
+    obs = prop.obs_buffer(args.steps, 1)
+    run(args.warmup, obs_w)
+    if args.graphs:
+        run(args.steps, obs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps, obs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prop.timing(True)
+    run(args.steps, obs)
+    launches, kms = prop.timing_read("taylor_term")
+    prop.timing(False)
+    rows = (prop.tile_rows, prop.sweep_variant)
+    o = obs.cpu().numpy()[:, -1, :]
+    prop.close()
+    del prop
+    torch.cuda.empty_cache()
+    U = sum((g.lmax + 1) * g.n for g in grids)
+    return dict(wall=wall, launches=launches, kms=kms, rows=rows, obs=o, U=U, dts=dts, n=len(grids))
+
+
+def run_batch(args, tdse, torch):
+    log(f"bench: batch of 256 members, FP32 storage, Taylor-8, steps={args.steps} warmup={args.warmup}")
+    r32 = run_batch_prec(tdse, torch, tdse.FP32, args)
+    log(f"bench: batch FP32 {args.steps / r32['wall']:.1f} steps/s")
+    r64 = run_batch_prec(tdse, torch, tdse.FP64, args)
+    log(f"bench: batch FP64 {args.steps / r64['wall']:.1f} steps/s")
+    sps = args.steps / r32["wall"]
+    U = r32["U"]
+    avg_ms = r32["kms"] / max(r32["launches"], 1)
+    achieved = 3 * 8 * U / (avg_ms * 1e-3) / 1e9
+    avg64 = r64["kms"] / max(r64["launches"], 1)
+    drift = float(np.max(np.abs(r32["obs"][:, 2] - r64["obs"][:, 2])))
+    pb = float(np.max(np.abs(r32["obs"][:, 4] - r64["obs"][:, 4]) / np.abs(r64["obs"][:, 4])))
+    out = {
+        "metric": METRIC, "value": workloads.BATCH_ORDER * r32["n"] * sps, "unit": "H·ψ applies/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * r32["wall"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-storage/f64-arith", "data": "synthetic",
+        "config": {"workload": BATCH_NAME, "members": r32["n"], "unknowns": U,
+                   "seed": workloads.BATCH_SEED, "dr": workloads.BATCH_DR, "stencil": workloads.BATCH_STENCIL,
+                   "method": "taylor", "order": workloads.BATCH_ORDER, "obs_every": 1,
+                   "dt_range": [min(r32["dts"]), max(r32["dts"])], "parallelism": "single GPU",
+                   "tile_rows": r32["rows"], "graphs": bool(args.graphs)},
+        "steps_per_s": sps,
+        "roofline": {"bound": "hbm", "kernel": "taylor_term", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": 3 * 8 * U, "mean_launch_us": avg_ms * 1e3,
+                     "launches_timed": r32["launches"]},
+        "fp64_batched": {"steps_per_s": args.steps / r64["wall"],
+                         "fp32_speedup_vs_fp64": sps / (args.steps / r64["wall"]),
+                         "kernel_mean_us": avg64 * 1e3,
+                         "kernel_gbs": 3 * 16 * U / (avg64 * 1e-3) / 1e9,
+                         "max_norm_diff_fp32_vs_fp64": drift,
+                         "max_p_bound_rel_diff_fp32_vs_fp64": pb,
+                         "steps_compared": (3 if args.graphs else 2) * args.steps + args.warmup},
+    }
+    if not args.no_cpu_baseline:
+        members = workloads.batch_members()
+        import oracle
+        m = members[0]
+        wl = workloads.Workload("batch_member0", m.n, m.lmax, workloads.BATCH_DR, workloads.BATCH_STENCIL,
+                                "fp64", "taylor", workloads.BATCH_ORDER, m.pulse, dt=r32["dts"][0],
+                                dt_nominal=float("nan"), nsteps=0, obs_every=1,
+                                r_ion=workloads.BATCH_R_ION_FRACTION * m.n * workloads.BATCH_DR)
+        cb = cpu_baseline(wl, args.cpu_seconds, workloads.BATCH_ORDER)
+        cb["sample"] = "member 0 of the batch (N=%d, lmax=%d): %s" % (m.n, m.lmax, cb["sample"])
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -100,6 +215,8 @@ def main():
         sys.exit(2)
     import torch
     import paper_1308_1856_amd as tdse
+    if args.workload == BATCH_NAME:
+        return run_batch(args, tdse, torch)
 
     wl = workloads.WORKLOADS[args.workload]
     prec = tdse.FP64 if wl.precision == "fp64" else tdse.FP32
@@ -113,8 +230,10 @@ def main():
 
     log(f"bench: workload {wl.name} U={U} method={wl.method}-{wl.order} dt={wl.dt} "
         f"steps={args.steps} warmup={args.warmup}")
-    prop = make_prop(tdse, wl, prec, mcode)
-    wall, launches, kms, obs = timed(prop, tdse, wl, torch, args.steps, args.warmup, kernel)
+    prop = make_prop(tdse, wl, prec, mcode, args.graphs, args.autotune)
+    tile_rows = prop.tile_rows
+    variant = prop.sweep_variant
+    wall, launches, kms, obs = timed(prop, tdse, wl, torch, args.steps, args.warmup, kernel, args.graphs)
     psi_main = prop.get_state(0)
     steps_per_s = args.steps / wall
     value = applies_per_step * steps_per_s
@@ -145,7 +264,8 @@ def main():
         "config": {"workload": wl.name, "n_r": wl.n, "lmax": wl.lmax, "dr": wl.dr,
                    "stencil": wl.stencil, "method": wl.method, "order": wl.order,
                    "dt": wl.dt, "dt_nominal": wl.dt_nominal, "unknowns": U,
-                   "obs_every": wl.obs_every, "parallelism": "single GPU"},
+                   "obs_every": wl.obs_every, "parallelism": "single GPU",
+                   "tile_rows": tile_rows, "sweep_variant": variant, "graphs": bool(args.graphs)},
         "steps_per_s": steps_per_s,
         "roofline": {
             "bound": "hbm",
@@ -165,8 +285,8 @@ def main():
 
     if not args.no_fp32 and prec == tdse.FP64:
         wl32 = wl.with_(precision="fp32")
-        prop = make_prop(tdse, wl32, tdse.FP32, mcode)
-        wall32, l32, k32, obs32 = timed(prop, tdse, wl32, torch, args.steps, args.warmup, kernel)
+        prop = make_prop(tdse, wl32, tdse.FP32, mcode, args.graphs, args.autotune)
+        wall32, l32, k32, obs32 = timed(prop, tdse, wl32, torch, args.steps, args.warmup, kernel, args.graphs)
         psi32 = prop.get_state(0)
         o32 = obs32.cpu().numpy()[0, -1]
         prop.close()
@@ -183,7 +303,7 @@ def main():
             "rel_state_error_vs_fp64": rel_state,
             "norm_drift_vs_fp64": float(abs(o32[2] - obs_last[2])),
             "p_bound_rel_error_vs_fp64": float(abs(o32[4] - obs_last[4]) / abs(obs_last[4])),
-            "steps_compared": 2 * args.steps + args.warmup,
+            "steps_compared": (3 if args.graphs else 2) * args.steps + args.warmup,
         }
         log(f"bench: fp32 {sps32:.1f} steps/s ({sps32 / steps_per_s:.2f}x), state diff {rel_state:.2e}")
 

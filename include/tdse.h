@@ -190,6 +190,22 @@ double tdse_lambda_max_bound(const tdse_ctx* ctx, int32_t inst, double e_max);
  * largest y with |sum_{k<=P} (i y')^k / k!| <= 1 + 1e-12 for all y' <= y. */
 double tdse_taylor_stability_limit(int32_t order);
 
+/* Autotuner for the sweep kernels (H.psi, Horner terms, RK4 stages): times a
+ * Horner-term sweep of the bound state for each tile shape (256 radii x 1, 2,
+ * 4, 8, 16 or 32 rows per workgroup) and each loop variant (one row at a
+ * time, or software-pipelined one row ahead), checks that every choice produces
+ * bit-identical results to the current one (a sweep's arithmetic does not
+ * depend on the tile shape), keeps the fastest and appends it to the tuning
+ * cache named by the environment variable TDSE_TUNE_CACHE (if set; read by
+ * tdse_init_grid for grids of the same shape class).  Needs the Taylor
+ * workspace (two state-shaped vectors, overwritten); leaves the state
+ * untouched.  *rows_out (may be NULL) receives the choice.  Synchronises. */
+tdse_status tdse_autotune(tdse_ctx* ctx, int32_t* rows_out);
+/* Rows per workgroup of the sweep tile set in use, and the loop variant
+ * (0 one row at a time, 1 software-pipelined). */
+int32_t tdse_tile_rows(const tdse_ctx* ctx);
+int32_t tdse_sweep_variant(const tdse_ctx* ctx);
+
 /* Step-loop replay through HIP graphs (default off).  When on, and timing is
  * off, and the bound stream is not the null stream, each step call captures
  * the launches of a 256-step chunk once into a hipGraph and replays it for

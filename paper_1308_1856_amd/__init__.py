@@ -34,7 +34,7 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_set_state", "tdse_get_state", "tdse_apply_H", "tdse_step_taylor",
             "tdse_step_rk4", "tdse_step_lanczos", "tdse_observables", "tdse_lambda_max_bound",
             "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read",
-            "tdse_use_graphs")
+            "tdse_use_graphs", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant")
 
 
 class TdseError(RuntimeError):
@@ -91,6 +91,9 @@ def _load():
         "tdse_timing_enable": ([ctxp, i32], i32),
         "tdse_timing_read": ([ctxp, ctypes.c_char_p, ctypes.POINTER(i64), dp], i32),
         "tdse_use_graphs": ([ctxp, i32], i32),
+        "tdse_autotune": ([ctxp, ctypes.POINTER(i32)], i32),
+        "tdse_tile_rows": ([ctxp], i32),
+        "tdse_sweep_variant": ([ctxp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -194,6 +197,16 @@ def tdse_taylor_stability_limit(order: int) -> float:
 
 def tdse_timing_enable(ctx, enable: bool):
     _check(ctx, lib.tdse_timing_enable(ctx, 1 if enable else 0))
+
+
+def tdse_autotune(ctx) -> int:
+    rows = ctypes.c_int32()
+    _check(ctx, lib.tdse_autotune(ctx, ctypes.byref(rows)))
+    return rows.value
+
+
+def tdse_tile_rows(ctx) -> int:
+    return lib.tdse_tile_rows(ctx)
 
 
 def tdse_use_graphs(ctx, enable: bool):
@@ -331,6 +344,20 @@ class Propagator:
 
     def use_graphs(self, enable: bool):
         tdse_use_graphs(self.ctx, enable)
+
+    def autotune(self) -> int:
+        self._enter()
+        rows = tdse_autotune(self.ctx)
+        self._leave()
+        return rows
+
+    @property
+    def tile_rows(self) -> int:
+        return tdse_tile_rows(self.ctx)
+
+    @property
+    def sweep_variant(self) -> int:
+        return lib.tdse_sweep_variant(self.ctx)
 
     def _pulse_list(self, pulses):
         if isinstance(pulses, (list, tuple)):

@@ -1,4 +1,6 @@
 // Lanczos propagator (Sec. 5.2 Lanczos.c; appendix "Lanczos methods").
+// All its kernels run over the reduce tile set (at most 16 rows per tile), so
+// the per-tile partial sums of the 2m dot products stay small.
 //
 // Per step and instance: q_0 = F/||F||; for j = 0..m-1:
 //   sweep A:  w = H(t_mid) q_j, partial sums of h_i = <q_i, w>, i <= j
@@ -53,7 +55,7 @@ __device__ __forceinline__ double instance_sum(const Inst& I, const double* part
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-    for (int t = I.tbegin[kSweepTiles] + (int)threadIdx.x; t < I.tend[kSweepTiles]; t += kBlock) {
+    for (int t = I.tbegin[kReduceTiles] + (int)threadIdx.x; t < I.tend[kReduceTiles]; t += kBlock) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
             if (q < nq) acc[q] += partial[(int64_t)t * stride + q];

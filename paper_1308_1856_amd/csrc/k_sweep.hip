@@ -13,7 +13,7 @@
 
 namespace tdse {
 
-template <int S, typename T>
+template <int S, typename T, bool PIPE>
 __global__ void __launch_bounds__(kBlock)
 k_hsweep(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
          const typename Cplx<T>::type* psi, typename Cplx<T>::type* out,
@@ -21,35 +21,70 @@ k_hsweep(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
 {
     using C = typename Cplx<T>::type;
     const Tile I = my_tile(g);
-    const Tile& tile = I;
     const int n = I.n;
-    const int i = tile.r0 + (int)threadIdx.x;
+    const int i = I.r0 + (int)threadIdx.x;
     if (i >= n) return;
     const RadialPoint rp = radial_point(I, i);
-    const double e = step_value(step, g.n_inst, kEMid, tile.inst);
+    const double e = step_value(step, g.n_inst, kEMid, I.inst);
     const double er = e * rp.r;
     // Horner term: out = psi + (-i dt/term) h;  (-i c)(x + i y) = c y - i c x
-    const double c = (term > 0) ? step_value(step, g.n_inst, kDt, tile.inst) / (double)term : 0.0;
+    const double c = (term > 0) ? step_value(step, g.n_inst, kDt, I.inst) / (double)term : 0.0;
     const int64_t base = I.off;
 
-    double2 prev = (tile.l0 > 0) ? ldc(in, base + (int64_t)(tile.l0 - 1) * n + i) : zero2();
-    double2 cur = ldc(in, base + (int64_t)tile.l0 * n + i);
-    for (int l = tile.l0; l < tile.l1; ++l) {
+    if (!PIPE) {
+        // plain loop: one row at a time (fewer registers, more waves)
+        double2 prev = (I.l0 > 0) ? ldc(in, base + (int64_t)(I.l0 - 1) * n + i) : zero2();
+        double2 cur = ldc(in, base + (int64_t)I.l0 * n + i);
+        for (int l = I.l0; l < I.l1; ++l) {
+            const int64_t row = base + (int64_t)l * n;
+            const double2 next = (l < I.lmax) ? ldc(in, row + n + i) : zero2();
+            Neighbours<S, C> nb;
+            nb.load(in + row, i, n);
+            const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
+            const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v,
+                                         er, g.kappa[l], g.kappa[l + 1]);
+            if (term > 0) {
+                const double2 p = ldc(psi, row + i);
+                stc(out, row + i, make_double2(p.x + c * h.y, p.y - c * h.x));
+            } else {
+                stc(out, row + i, h);
+            }
+            prev = cur;
+            cur = next;
+        }
+        return;
+    }
+    // Software pipeline: the loads row l + 1 needs (the input two rows ahead,
+    // the radial neighbours of row l + 1, psi of row l + 1) are issued before
+    // row l is computed and stored.  Safe when out == psi: a thread reads
+    // psi(l + 1, i) and writes out(l, i), never the same element.
+    const C* row0 = in + base + (int64_t)I.l0 * n;
+    double2 prev = (I.l0 > 0) ? ldc(row0 - n, i) : zero2();
+    double2 cur = ldc(row0, i);
+    double2 next = (I.l0 < I.lmax) ? ldc(row0 + n, i) : zero2();
+    Neighbours<S, C> nb;
+    nb.load(row0, i, n);
+    double2 p = (term > 0) ? ldc(psi + base + (int64_t)I.l0 * n, i) : zero2();
+    for (int l = I.l0; l < I.l1; ++l) {
         const int64_t row = base + (int64_t)l * n;
-        const double2 next = (l < I.lmax) ? ldc(in, row + n + i) : zero2();
-        Neighbours<S, C> nb;
-        nb.load(in + row, i, n);
+        const bool more = l + 1 < I.l1;
+        const double2 next2 = (l + 2 <= I.lmax) ? ldc(in, row + 2 * n + i) : zero2();
+        Neighbours<S, C> nb_next;
+        if (more) nb_next.load(in + row + n, i, n);
+        const double2 p_next = (more && term > 0) ? ldc(psi, row + n + i) : zero2();
+
         const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
         const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
                                      g.kappa[l], g.kappa[l + 1]);
-        if (term > 0) {
-            const double2 p = ldc(psi, row + i);
+        if (term > 0)
             stc(out, row + i, make_double2(p.x + c * h.y, p.y - c * h.x));
-        } else {
+        else
             stc(out, row + i, h);
-        }
         prev = cur;
         cur = next;
+        next = next2;
+        if (more) nb = nb_next;
+        p = p_next;
     }
 }
 
@@ -67,25 +102,39 @@ k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
 {
     using C = typename Cplx<T>::type;
     const Tile I = my_tile(g);
-    const Tile& tile = I;
     const int n = I.n;
-    const int i = tile.r0 + (int)threadIdx.x;
+    const int i = I.r0 + (int)threadIdx.x;
     if (i >= n) return;
     const RadialPoint rp = radial_point(I, i);
     const int slot = (STAGE == 0) ? kEStart : (STAGE == 3 ? kEEnd : kEMid);
-    const double er = step_value(step, g.n_inst, slot, tile.inst) * rp.r;
-    const double dt = step_value(step, g.n_inst, kDt, tile.inst);
+    const double er = step_value(step, g.n_inst, slot, I.inst) * rp.r;
+    const double dt = step_value(step, g.n_inst, kDt, I.inst);
     const double bw = (STAGE == 0 || STAGE == 3) ? dt / 6.0 : dt / 3.0;
     const double aw = (STAGE == 2) ? dt : 0.5 * dt;
     const int64_t base = I.off;
+    constexpr bool kReadAcc = STAGE > 0;
+    constexpr bool kReadPsi = STAGE == 1 || STAGE == 2;
 
-    double2 prev = (tile.l0 > 0) ? ldc(gin, base + (int64_t)(tile.l0 - 1) * n + i) : zero2();
-    double2 cur = ldc(gin, base + (int64_t)tile.l0 * n + i);
-    for (int l = tile.l0; l < tile.l1; ++l) {
+    // software pipeline as in k_hsweep: row l + 1's loads go out before row l
+    // is stored (acc and psi are read and written only at a thread's own
+    // elements, one row apart)
+    const C* row0 = gin + base + (int64_t)I.l0 * n;
+    double2 prev = (I.l0 > 0) ? ldc(row0 - n, i) : zero2();
+    double2 cur = ldc(row0, i);
+    double2 next = (I.l0 < I.lmax) ? ldc(row0 + n, i) : zero2();
+    Neighbours<S, C> nb;
+    nb.load(row0, i, n);
+    double2 a = kReadAcc ? ldc(acc, base + (int64_t)I.l0 * n + i) : zero2();
+    double2 p = kReadPsi ? ldc(psi, base + (int64_t)I.l0 * n + i) : zero2();
+    for (int l = I.l0; l < I.l1; ++l) {
         const int64_t row = base + (int64_t)l * n;
-        const double2 next = (l < I.lmax) ? ldc(gin, row + n + i) : zero2();
-        Neighbours<S, C> nb;
-        nb.load(gin + row, i, n);
+        const bool more = l + 1 < I.l1;
+        const double2 next2 = (l + 2 <= I.lmax) ? ldc(gin, row + 2 * n + i) : zero2();
+        Neighbours<S, C> nb_next;
+        if (more) nb_next.load(gin + row + n, i, n);
+        const double2 a_next = (kReadAcc && more) ? ldc(acc, row + n + i) : zero2();
+        const double2 p_next = (kReadPsi && more) ? ldc(psi, row + n + i) : zero2();
+
         const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
         const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
                                      g.kappa[l], g.kappa[l + 1]);
@@ -94,16 +143,17 @@ k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
             stc(acc, row + i, make_double2(cur.x + bw * k.x, cur.y + bw * k.y));
             stc(gout, row + i, make_double2(cur.x + aw * k.x, cur.y + aw * k.y));
         } else if (STAGE < 3) {
-            const double2 a = ldc(acc, row + i);
-            const double2 p = ldc(psi, row + i);
             stc(acc, row + i, make_double2(a.x + bw * k.x, a.y + bw * k.y));
             stc(gout, row + i, make_double2(p.x + aw * k.x, p.y + aw * k.y));
         } else {
-            const double2 a = ldc(acc, row + i);
             stc(psi, row + i, make_double2(a.x + bw * k.x, a.y + bw * k.y));
         }
         prev = cur;
         cur = next;
+        next = next2;
+        if (more) nb = nb_next;
+        a = a_next;
+        p = p_next;
     }
 }
 
@@ -120,6 +170,33 @@ k_copy(SweepGeom g, const typename Cplx<T>::type* __restrict__ src, typename Cpl
     }
 }
 
+__device__ __forceinline__ bool bits_differ(double2 a, double2 b)
+{
+    return __double_as_longlong(a.x) != __double_as_longlong(b.x) ||
+           __double_as_longlong(a.y) != __double_as_longlong(b.y);
+}
+__device__ __forceinline__ bool bits_differ(float2 a, float2 b)
+{
+    return __float_as_uint(a.x) != __float_as_uint(b.x) || __float_as_uint(a.y) != __float_as_uint(b.y);
+}
+
+// Counts elements (over the tiles of g) whose stored values differ bit for bit.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_count_diff(SweepGeom g, const typename Cplx<T>::type* __restrict__ a,
+             const typename Cplx<T>::type* __restrict__ b, unsigned int* __restrict__ count)
+{
+    const Tile I = my_tile(g);
+    const int i = I.r0 + (int)threadIdx.x;
+    if (i >= I.n) return;
+    unsigned int d = 0;
+    for (int l = I.l0; l < I.l1; ++l) {
+        const int64_t k = I.off + (int64_t)l * I.n + i;
+        d += bits_differ(a[k], b[k]) ? 1u : 0u;
+    }
+    if (d) atomicAdd(count, d);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -128,9 +205,14 @@ static hipError_t hsweep_t(const SweepGeom& g, const void* in, const void* psi, 
                            const double* step, int term, hipStream_t st)
 {
     using C = typename Cplx<T>::type;
-    hipLaunchKernelGGL((k_hsweep<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                       static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
-                       step, term);
+    if (g.variant == 1)
+        hipLaunchKernelGGL((k_hsweep<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                           step, term);
+    else
+        hipLaunchKernelGGL((k_hsweep<S, T, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                           step, term);
     return hipGetLastError();
 }
 
@@ -174,6 +256,18 @@ hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, cons
                                  : rk4_s<2, double>(g, stage, gin, psi, acc, gout, step, st);
     return S == 1 ? rk4_s<1, float>(g, stage, gin, psi, acc, gout, step, st)
                   : rk4_s<2, float>(g, stage, gin, psi, acc, gout, step, st);
+}
+
+hipError_t launch_count_diff(int prec, const SweepGeom& g, const void* a, const void* b,
+                             unsigned int* count, hipStream_t st)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL((k_count_diff<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const double2*>(a), static_cast<const double2*>(b), count);
+    else
+        hipLaunchKernelGGL((k_count_diff<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const float2*>(a), static_cast<const float2*>(b), count);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy(int prec, const SweepGeom& g, const void* src, void* dst, hipStream_t st)

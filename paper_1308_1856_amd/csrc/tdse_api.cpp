@@ -43,6 +43,8 @@ struct tdse_ctx {
     std::vector<Inst> inst;
     std::vector<Tile> tiles[kNumTileSets];
     int rows_sweep = 1, rows_reduce = 1;
+    int sweep_variant = 0;              // 0 plain loop, 1 software-pipelined (autotuned)
+    int64_t total_cols = 0;             // sum over instances of ceil(N/256) * (lmax+1)
     std::vector<double> kappa;
     std::vector<double> radial;            // per instance: u0 row then n_states phi rows
     std::vector<int> lmax_max;
@@ -95,7 +97,7 @@ struct tdse_ctx {
         g.n_tiles = (int32_t)tiles[set].size();
         g.n_inst = n_inst;
         g.set = set;
-        g.pad_ = 0;
+        g.variant = (set == kSweepTiles) ? sweep_variant : 0;
         return g;
     }
     double* d_step() const { return reinterpret_cast<double*>(d_work + off_step); }
@@ -211,6 +213,83 @@ static int states_for(int lmax)
     return s;
 }
 
+// (Re)builds one tile set.  rows = 0 for the population set.
+static void build_tiles(tdse_ctx* c, int set, int rows)
+{
+    c->tiles[set].clear();
+    for (int k = 0; k < c->n_inst; ++k) {
+        Inst& I = c->inst[k];
+        I.tbegin[set] = (int32_t)c->tiles[set].size();
+        const int lhi = (set == kPopTiles) ? std::min(I.lmax, 4) + 1 : I.lmax + 1;
+        const int step = (set == kPopTiles) ? lhi : rows;
+        for (int l0 = 0; l0 < lhi; l0 += step) {
+            for (int r0 = 0; r0 < I.n; r0 += kBlock) {
+                Tile t;
+                std::memset(&t, 0, sizeof t);
+                t.off = I.off;
+                t.tab_off = I.tab_off;
+                t.inst = k;
+                t.r0 = r0;
+                t.l0 = l0;
+                t.l1 = std::min(l0 + step, lhi);
+                t.n = I.n;
+                t.lmax = I.lmax;
+                t.i_ion = I.i_ion;
+                t.n_states = I.n_states;
+                t.dr = I.dr;
+                t.inv_dr2 = I.inv_dr2;
+                t.z = I.z;
+                c->tiles[set].push_back(t);
+            }
+        }
+        I.tend[set] = (int32_t)c->tiles[set].size();
+    }
+}
+
+// Tuning cache: a text file (path in TDSE_TUNE_CACHE) with one line per
+// shape, "<key> <rows> <variant>", key = stencil.precision.log2(unknowns).log2(mean rows).
+static std::string tune_key(const tdse_ctx* c)
+{
+    int64_t unknowns = 0, rows = 0;
+    for (const tdse_grid_desc& g : c->grids) {
+        unknowns += (int64_t)(g.lmax + 1) * g.n_r;
+        rows += g.lmax + 1;
+    }
+    const int ub = (int)std::ceil(std::log2((double)std::max<int64_t>(unknowns, 1)));
+    const int rb = (int)std::ceil(std::log2((double)std::max<int64_t>(rows / c->n_inst, 1)));
+    return "s" + std::to_string(c->stencil) + ".p" + std::to_string(c->prec) + ".u" + std::to_string(ub) +
+           ".l" + std::to_string(rb);
+}
+
+static int tune_cache_lookup(const tdse_ctx* c, int* variant)
+{
+    const char* path = std::getenv("TDSE_TUNE_CACHE");
+    if (!path) return 0;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return 0;
+    const std::string key = tune_key(c);
+    char kbuf[128];
+    int rows = 0, var = 0, found = 0;
+    while (std::fscanf(f, "%127s %d %d", kbuf, &rows, &var) == 3) {
+        if (key == kbuf && rows >= 1 && rows <= kTileRows && (var == 0 || var == 1)) {
+            found = rows;  // last entry wins
+            *variant = var;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_cache_store(const tdse_ctx* c, int rows, int variant)
+{
+    const char* path = std::getenv("TDSE_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d\n", tune_key(c).c_str(), rows, variant);
+    std::fclose(f);
+}
+
 extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_inst, tdse_ctx** out)
 {
     if (!out) return TDSE_E_INVALID;
@@ -261,46 +340,26 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->kappa.resize(lmax_all + 2);
     for (int l = 0; l < lmax_all + 2; ++l)
         c->kappa[l] = (l > 0) ? std::sqrt((double)l * l / (4.0 * l * l - 1.0)) : 0.0;
-    // Tile sets.  Sweeps: rows per tile chosen so the launch has >= kTargetTiles
-    // workgroups.  Reductions: taller tiles (fewer partial sums).  Populations:
-    // one tile per 256 radial points covering rows 0..min(lmax, 4).
+    // Tile sets.  Sweeps: rows per tile from the tuning cache if it has this
+    // shape, else chosen so the launch has >= kTargetTiles workgroups.
+    // Reductions (observables, Lanczos): up to 16 rows, >= 1024 workgroups.
+    // Populations: one tile per 256 radial points covering rows 0..min(lmax, 4).
     int64_t total_cols = 0;
     for (int k = 0; k < n_inst; ++k)
         total_cols += (int64_t)((grids[k].n_r + kBlock - 1) / kBlock) * (grids[k].lmax + 1);
+    c->total_cols = total_cols;
     int rows = kTileRows;
     while (rows > 1 && total_cols / rows < kTargetTiles) rows /= 2;
-    c->rows_sweep = rows;
-    c->rows_reduce = std::max(rows, 16);
-    for (int set = 0; set < kNumTileSets; ++set) {
-        const int rset = (set == kSweepTiles) ? c->rows_sweep : c->rows_reduce;
-        for (int k = 0; k < n_inst; ++k) {
-            Inst& I = c->inst[k];
-            I.tbegin[set] = (int32_t)c->tiles[set].size();
-            const int lhi = (set == kPopTiles) ? std::min(I.lmax, 4) + 1 : I.lmax + 1;
-            const int step = (set == kPopTiles) ? lhi : rset;
-            for (int l0 = 0; l0 < lhi; l0 += step) {
-                for (int r0 = 0; r0 < I.n; r0 += kBlock) {
-                    Tile t;
-                    std::memset(&t, 0, sizeof t);
-                    t.off = I.off;
-                    t.tab_off = I.tab_off;
-                    t.inst = k;
-                    t.r0 = r0;
-                    t.l0 = l0;
-                    t.l1 = std::min(l0 + step, lhi);
-                    t.n = I.n;
-                    t.lmax = I.lmax;
-                    t.i_ion = I.i_ion;
-                    t.n_states = I.n_states;
-                    t.dr = I.dr;
-                    t.inv_dr2 = I.inv_dr2;
-                    t.z = I.z;
-                    c->tiles[set].push_back(t);
-                }
-            }
-            I.tend[set] = (int32_t)c->tiles[set].size();
-        }
-    }
+    int cached_variant = 0;
+    const int cached = tune_cache_lookup(c, &cached_variant);
+    c->rows_sweep = cached > 0 ? cached : rows;
+    c->sweep_variant = cached > 0 ? cached_variant : 0;
+    int rr = 16;
+    while (rr > 1 && total_cols / rr < 1024) rr /= 2;
+    c->rows_reduce = rr;
+    build_tiles(c, kSweepTiles, c->rows_sweep);
+    build_tiles(c, kReduceTiles, c->rows_reduce);
+    build_tiles(c, kPopTiles, 0);
     // radial tables: u0 (normalised r exp(-z r)) and the bound eigenvectors
     c->radial.assign(tab, 0.0);
     std::vector<std::thread> pool;
@@ -346,13 +405,17 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         return at;
     };
     c->off_inst = take(sizeof(Inst) * n_inst);
-    for (int set = 0; set < kNumTileSets; ++set) c->off_tiles[set] = take(sizeof(Tile) * c->tiles[set].size());
+    for (int set = 0; set < kNumTileSets; ++set) {
+        // the sweep set may be rebuilt by the autotuner: room for one row per tile
+        const size_t cap = (set == kSweepTiles) ? (size_t)c->total_cols : c->tiles[set].size();
+        c->off_tiles[set] = take(sizeof(Tile) * cap);
+    }
     c->off_kappa = take(sizeof(double) * c->kappa.size());
     c->off_radial = take(sizeof(double) * c->radial.size());
     c->off_step = take(sizeof(double) * kSlots * (size_t)n_inst * kEtabSteps);
     c->off_obs_tmp = take(sizeof(tdse_obs) * n_inst);
     c->off_lz = take(sizeof(LanczosScalars) * n_inst);
-    c->partial_doubles = std::max((size_t)c->tiles[kSweepTiles].size() * 2 * kMaxKrylov,
+    c->partial_doubles = std::max((size_t)c->tiles[kReduceTiles].size() * 2 * kMaxKrylov,
                                   (size_t)c->tiles[kReduceTiles].size() * kObsMainQ +
                                       (size_t)c->tiles[kPopTiles].size() * kObsPopQ);
     c->off_partial = take(sizeof(double) * c->partial_doubles);
@@ -765,7 +828,7 @@ extern "C" tdse_status tdse_step_lanczos(tdse_ctx* c, const tdse_pulse* pulses, 
     tdse_status st = check_common(c, pulses, t0, dt, nsteps, obs_every, d_obs, TDSE_METHOD_LANCZOS, m);
     if (st != TDSE_OK) return st;
     const int S = c->stencil == 3 ? 1 : 2;
-    const SweepGeom g = c->geom();
+    const SweepGeom g = c->geom(kReduceTiles);
     void* psi = c->d_state;
     void* w = c->d_vec(0);
     void* basis = c->d_vec(1);  // vectors 1..m-1
@@ -821,6 +884,95 @@ extern "C" tdse_status tdse_observables(tdse_ctx* c, const tdse_pulse* pulses, c
         if (!std::isfinite(host_out[k].norm)) return c->fail(TDSE_E_NONFINITE, "tdse_observables: norm is not finite");
     return TDSE_OK;
 }
+
+static hipError_t upload_tiles(tdse_ctx* c, int set)
+{
+    return hipMemcpyAsync(c->d_work + c->off_tiles[set], c->tiles[set].data(),
+                          sizeof(Tile) * c->tiles[set].size(), hipMemcpyHostToDevice, c->stream);
+}
+
+extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_autotune: not bound");
+    if (c->work_bytes < tdse_workspace_bytes(c, TDSE_METHOD_TAYLOR, 2))
+        return c->fail(TDSE_E_WORKSPACE, "tdse_autotune: needs the Taylor workspace (two vectors)");
+    std::vector<double> zero(c->n_inst, 0.0), one(c->n_inst, 1.0);
+    tdse_status st = upload_steps(c, nullptr, zero.data(), one.data(), 0, 1, 0);
+    if (st != TDSE_OK) return st;
+    const int S = c->stencil == 3 ? 1 : 2;
+    void* psi = c->d_state;
+    void* out = c->d_vec(0);
+    void* ref = c->d_vec(1);
+    unsigned int* counter = reinterpret_cast<unsigned int*>(c->d_work + c->off_obs_tmp);
+    const int start_rows = c->rows_sweep;
+    const int start_variant = c->sweep_variant;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // reference sweep with the current tiles
+    if (e == hipSuccess) e = launch_hsweep(c->prec, S, c->geom(), psi, psi, ref, c->d_step(), 1, c->stream);
+    double best_ms = 1e300;
+    int best = start_rows, best_variant = start_variant;
+    const int cands[] = {1, 2, 4, 8, 16, 32};
+    for (int cand = 0; cand < 12; ++cand) {
+        const int rows = cands[cand % 6];
+        const int variant = cand / 6;
+        if (e != hipSuccess) break;
+        if (rows != 1 && c->total_cols / rows < 64) continue;
+        c->sweep_variant = variant;
+        build_tiles(c, kSweepTiles, rows);
+        e = upload_tiles(c, kSweepTiles);
+        const SweepGeom g = c->geom();
+        for (int w = 0; w < 2 && e == hipSuccess; ++w)
+            e = launch_hsweep(c->prec, S, g, psi, psi, out, c->d_step(), 1, c->stream);
+        const int reps = 20;
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_hsweep(c->prec, S, g, psi, psi, out, c->d_step(), 1, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(counter, 0, sizeof(unsigned int), c->stream);
+        if (e == hipSuccess) e = launch_count_diff(c->prec, c->geom(kReduceTiles), out, ref, counter, c->stream);
+        unsigned int diff = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&diff, counter, sizeof diff, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (diff != 0) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            build_tiles(c, kSweepTiles, start_rows);
+            c->sweep_variant = start_variant;
+            (void)upload_tiles(c, kSweepTiles);
+            (void)hipStreamSynchronize(c->stream);
+            return c->fail(TDSE_E_HIP, "tdse_autotune: a tile shape changed the result of a sweep (" +
+                                           std::to_string(diff) + " elements, rows " + std::to_string(rows) +
+                                           ", variant " + std::to_string(variant) + ")");
+        }
+        if (ms / reps < best_ms) {
+            best_ms = ms / reps;
+            best = rows;
+            best_variant = variant;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    build_tiles(c, kSweepTiles, (e == hipSuccess) ? best : start_rows);
+    c->sweep_variant = (e == hipSuccess) ? best_variant : start_variant;
+    hipError_t e2 = upload_tiles(c, kSweepTiles);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_autotune");
+    if (e2 != hipSuccess) return c->hip_fail(e2, "tdse_autotune upload");
+    c->rows_sweep = best;
+    c->drop_graphs();
+    tune_cache_store(c, best, best_variant);
+    if (rows_out) *rows_out = best;
+    return TDSE_OK;
+}
+
+extern "C" int32_t tdse_tile_rows(const tdse_ctx* c) { return c ? c->rows_sweep : 0; }
+extern "C" int32_t tdse_sweep_variant(const tdse_ctx* c) { return c ? c->sweep_variant : 0; }
 
 extern "C" tdse_status tdse_use_graphs(tdse_ctx* c, int32_t enable)
 {

@@ -67,7 +67,7 @@ struct SweepGeom {
     int32_t n_tiles;
     int32_t n_inst;
     int32_t set;           // TileSetId of `tiles`
-    int32_t pad_;
+    int32_t variant;       // sweep loop: 0 one row at a time, 1 software-pipelined
 };
 
 // Per-step scalars, FP64, laid out [slot][instance] with these slots:
@@ -125,6 +125,10 @@ hipError_t launch_lz_expm(const SweepGeom& g, const double* step, LanczosScalars
                           hipStream_t st);
 hipError_t launch_lz_recombine(int prec, const SweepGeom& g, int m, void* psi, const void* basis,
                                int64_t vec_stride, const LanczosScalars* sc, hipStream_t st);
+
+// Number of elements whose stored values differ bit for bit, added to *count.
+hipError_t launch_count_diff(int prec, const SweepGeom& g, const void* a, const void* b,
+                             unsigned int* count, hipStream_t st);
 
 // dst = src over every tile (state-shaped vectors).
 hipError_t launch_copy(int prec, const SweepGeom& g, const void* src, void* dst, hipStream_t st);

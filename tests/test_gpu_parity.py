@@ -303,3 +303,31 @@ def test_graph_replay_matches_direct_launches(method):
     for call in range(2):
         assert np.array_equal(results[0][0][call], results[1][0][call])
         assert np.array_equal(results[0][1][call], results[1][1][call])
+
+
+def test_autotune_keeps_results_bitwise(tmp_path, monkeypatch):
+    t = lib()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("TDSE_TUNE_CACHE", str(cache))
+    grid = t.Grid(5000, 20, 0.1, 3, t.FP64, 1.0, 50.0)
+    pulse = t.Pulse(0.05, 0.1, 2.0, 0.0, 0.0)
+    say("autotune: Taylor-8 results before and after re-tiling")
+    prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),))
+    dt = 0.8 * t.tdse_taylor_stability_limit(8) / prop.lambda_max_bound(0, 0.05)
+    start_rows = prop.tile_rows
+    out = []
+    for tune in (False, True):
+        prop.set_state(0, None)
+        if tune:
+            rows = prop.autotune()
+            say(f"  rows {start_rows} -> {rows}")
+            assert rows in (1, 2, 4, 8, 16, 32) and prop.tile_rows == rows
+        prop.step_taylor(pulse, 10.0, dt, 8, 20)
+        out.append(prop.get_state(0))
+    prop.close()
+    assert np.array_equal(out[0], out[1])
+    assert cache.read_text().split()[-2] == str(rows)
+    # a new context of the same shape class starts from the cached choice
+    prop2 = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),))
+    assert prop2.tile_rows == rows
+    prop2.close()
