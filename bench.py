@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", type=int, default=1, help="replay step chunks as HIP graphs")
-    ap.add_argument("--autotune", type=int, default=1, help="autotune the sweep tile shape first")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: autotune the sweep tiles; 2: also choose the Taylor fusion depth")
     return ap.parse_args()
 
 
@@ -60,10 +61,12 @@ def log(msg):
 
 def make_prop(tdse, wl, precision, method_code, graphs=True, autotune=True):
     g = tdse.Grid(wl.n, wl.lmax, wl.dr, wl.stencil, precision, wl.z, wl.r_ion)
-    methods = ((method_code, wl.order), (tdse.METHOD_TAYLOR, 2))
+    methods = ((method_code, wl.order), (tdse.METHOD_TAYLOR, 2), (tdse.METHOD_TUNE, 0))
     prop = tdse.Propagator([g], methods=methods, graphs=bool(graphs))
     if autotune:
         prop.autotune()
+        if wl.method == "taylor" and autotune > 1:
+            prop.autotune_taylor(wl.order)
     prop.set_state(0, None)
     return prop
 

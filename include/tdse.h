@@ -60,7 +60,10 @@ enum {
 };
 
 typedef enum { TDSE_FP64 = 0, TDSE_FP32 = 1 } tdse_precision;
-typedef enum { TDSE_METHOD_TAYLOR = 0, TDSE_METHOD_RK4 = 1, TDSE_METHOD_LANCZOS = 2 } tdse_method;
+/* TDSE_METHOD_TUNE only sizes the workspace the autotuners need (four
+ * state-shaped vectors). */
+typedef enum { TDSE_METHOD_TAYLOR = 0, TDSE_METHOD_RK4 = 1, TDSE_METHOD_LANCZOS = 2,
+               TDSE_METHOD_TUNE = 3 } tdse_method;
 
 /* One instance (one radial grid and partial-wave set).  All instances of a
  * context must share stencil and precision. */
@@ -201,6 +204,25 @@ double tdse_taylor_stability_limit(int32_t order);
  * workspace (two state-shaped vectors, overwritten); leaves the state
  * untouched.  *rows_out (may be NULL) receives the choice.  Synchronises. */
 tdse_status tdse_autotune(tdse_ctx* ctx, int32_t* rows_out);
+/* Autotuner for the Taylor step of order `order` (1..16): times whole steps
+ * of the bound state (field-free, stable dt) with one launch per Horner term
+ * (the sweep tiles in use) and with K = ceil(order/2)..min(order, 8) terms
+ * fused per launch on 256-radius tiles of 8, 16 or 32 rows, verifies each
+ * candidate's step against the one-launch-per-term step (bit for bit in
+ * FP64; relative 2-norm difference <= 1e-6 with FP32 storage, where the
+ * fused launches keep their intermediates in FP64), and keeps the fastest for
+ * later tdse_step_taylor calls.  Needs the TDSE_METHOD_TUNE workspace; the
+ * state is restored.  *fuse_k_out (0: one launch per term) and *rows_out (may
+ * be NULL) receive the choice.  Synchronises. */
+tdse_status tdse_autotune_taylor(tdse_ctx* ctx, int32_t order, int32_t* fuse_k_out, int32_t* rows_out);
+/* Horner terms per fused Taylor launch in use (0: one launch per term), and
+ * an explicit choice: k = 0 (one launch per term) or 1..8 terms per fused
+ * launch on tiles of `rows` rows (1..64).  The fused path is used by
+ * tdse_step_taylor when 2k >= order (at most two launches per step).
+ * Synchronises. */
+int32_t tdse_taylor_fusion(const tdse_ctx* ctx);
+tdse_status tdse_set_taylor_fusion(tdse_ctx* ctx, int32_t k, int32_t rows);
+
 /* Rows per workgroup of the sweep tile set in use, and the loop variant
  * (0 one row at a time, 1 software-pipelined). */
 int32_t tdse_tile_rows(const tdse_ctx* ctx);
@@ -216,7 +238,7 @@ tdse_status tdse_use_graphs(tdse_ctx* ctx, int32_t enable);
 
 /* Kernel timing with HIP events recorded around every launch of the named
  * kernel family on the bound stream ("taylor_term", "rk4_stage",
- * "observables", "lanczos_sweep_a", "apply_h").  tdse_timing_enable(ctx, 1)
+ * "observables", "lanczos_sweep_a", "apply_h", "taylor_fused").  tdse_timing_enable(ctx, 1)
  * clears the counters; tdse_timing_read synchronises the stream and returns
  * the number of launches and their summed duration in milliseconds. */
 tdse_status tdse_timing_enable(tdse_ctx* ctx, int32_t enable);

@@ -24,7 +24,7 @@ STATUS = {0: "TDSE_OK", -1: "TDSE_E_INVALID", -2: "TDSE_E_NOMEM", -3: "TDSE_E_HI
           -4: "TDSE_E_UNSTABLE", -6: "TDSE_E_NONFINITE", -7: "TDSE_E_WORKSPACE",
           -8: "TDSE_E_UNBOUND"}
 FP64, FP32 = 0, 1
-METHOD_TAYLOR, METHOD_RK4, METHOD_LANCZOS = 0, 1, 2
+METHOD_TAYLOR, METHOD_RK4, METHOD_LANCZOS, METHOD_TUNE = 0, 1, 2, 3
 MAX_STATES = 15
 OBS_FIELDS = ("t", "e_field", "norm", "p_g", "p_bound", "p_ion", "dipole", "accel")
 OBS_DOUBLES = len(OBS_FIELDS) + MAX_STATES
@@ -34,7 +34,8 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_set_state", "tdse_get_state", "tdse_apply_H", "tdse_step_taylor",
             "tdse_step_rk4", "tdse_step_lanczos", "tdse_observables", "tdse_lambda_max_bound",
             "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read",
-            "tdse_use_graphs", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant")
+            "tdse_use_graphs", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
+            "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_set_taylor_fusion")
 
 
 class TdseError(RuntimeError):
@@ -94,6 +95,9 @@ def _load():
         "tdse_autotune": ([ctxp, ctypes.POINTER(i32)], i32),
         "tdse_tile_rows": ([ctxp], i32),
         "tdse_sweep_variant": ([ctxp], i32),
+        "tdse_autotune_taylor": ([ctxp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "tdse_taylor_fusion": ([ctxp], i32),
+        "tdse_set_taylor_fusion": ([ctxp, i32, i32], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -203,6 +207,12 @@ def tdse_autotune(ctx) -> int:
     rows = ctypes.c_int32()
     _check(ctx, lib.tdse_autotune(ctx, ctypes.byref(rows)))
     return rows.value
+
+
+def tdse_autotune_taylor(ctx, order: int):
+    k, rows = ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, lib.tdse_autotune_taylor(ctx, int(order), ctypes.byref(k), ctypes.byref(rows)))
+    return k.value, rows.value
 
 
 def tdse_tile_rows(ctx) -> int:
@@ -358,6 +368,20 @@ class Propagator:
     @property
     def sweep_variant(self) -> int:
         return lib.tdse_sweep_variant(self.ctx)
+
+    def autotune_taylor(self, order: int):
+        """(fused terms per launch or 0, rows per fused tile) chosen for `order`."""
+        self._enter()
+        out = tdse_autotune_taylor(self.ctx, order)
+        self._leave()
+        return out
+
+    @property
+    def taylor_fusion(self) -> int:
+        return lib.tdse_taylor_fusion(self.ctx)
+
+    def set_taylor_fusion(self, k: int, rows: int = 16):
+        _check(self.ctx, lib.tdse_set_taylor_fusion(self.ctx, int(k), int(rows)))
 
     def _pulse_list(self, pulses):
         if isinstance(pulses, (list, tuple)):

@@ -197,6 +197,29 @@ k_count_diff(SweepGeom g, const typename Cplx<T>::type* __restrict__ a,
     if (d) atomicAdd(count, d);
 }
 
+// out[0] += sum |a - b|^2, out[1] += sum |b|^2 over the tiles of g (FP64).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_diff_norm(SweepGeom g, const typename Cplx<T>::type* __restrict__ a,
+            const typename Cplx<T>::type* __restrict__ b, double* __restrict__ out)
+{
+    __shared__ double lds[(kBlock / 64) * 2];
+    const Tile I = my_tile(g);
+    const int i = I.r0 + (int)threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    if (i < I.n) {
+        for (int l = I.l0; l < I.l1; ++l) {
+            const int64_t k = I.off + (int64_t)l * I.n + i;
+            const double2 x = ldc(a, k), y = ldc(b, k);
+            const double dx = x.x - y.x, dy = x.y - y.y;
+            acc[0] += dx * dx + dy * dy;
+            acc[1] += y.x * y.x + y.y * y.y;
+        }
+    }
+    const double s = block_sum<2>(acc, lds);
+    if (threadIdx.x < 2) atomicAdd(&out[threadIdx.x], s);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -267,6 +290,18 @@ hipError_t launch_count_diff(int prec, const SweepGeom& g, const void* a, const 
     else
         hipLaunchKernelGGL((k_count_diff<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
                            static_cast<const float2*>(a), static_cast<const float2*>(b), count);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_norm(int prec, const SweepGeom& g, const void* a, const void* b, double* out,
+                            hipStream_t st)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL((k_diff_norm<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const double2*>(a), static_cast<const double2*>(b), out);
+    else
+        hipLaunchKernelGGL((k_diff_norm<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const float2*>(a), static_cast<const float2*>(b), out);
     return hipGetLastError();
 }
 

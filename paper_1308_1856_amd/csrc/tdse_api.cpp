@@ -30,8 +30,9 @@ constexpr int kTargetTiles = 2048;       // aim for >= 8 workgroups per CU on 25
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-const char* kTimedNames[] = {"taylor_term", "rk4_stage", "observables", "lanczos_sweep_a", "apply_h"};
-constexpr int kNumTimed = 5;
+const char* kTimedNames[] = {"taylor_term", "rk4_stage", "observables", "lanczos_sweep_a", "apply_h",
+                             "taylor_fused"};
+constexpr int kNumTimed = 6;
 
 }  // namespace
 
@@ -44,6 +45,8 @@ struct tdse_ctx {
     std::vector<Tile> tiles[kNumTileSets];
     int rows_sweep = 1, rows_reduce = 1;
     int sweep_variant = 0;              // 0 plain loop, 1 software-pipelined (autotuned)
+    int fuse_k = 0;                     // Horner terms per fused launch (0: one launch per term)
+    int rows_fused = 16;
     int64_t total_cols = 0;             // sum over instances of ceil(N/256) * (lmax+1)
     std::vector<double> kappa;
     std::vector<double> radial;            // per instance: u0 row then n_states phi rows
@@ -56,7 +59,7 @@ struct tdse_ctx {
     size_t work_bytes = 0;
     hipStream_t stream = nullptr;
     // workspace layout (bytes from d_work)
-    size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0}, off_kappa = 0, off_radial = 0,
+    size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0, 0}, off_kappa = 0, off_radial = 0,
            off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0;
     size_t partial_doubles = 0;
     // pinned staging for the per-step scalars (double buffered)
@@ -67,10 +70,12 @@ struct tdse_ctx {
     // captured step graphs, keyed by the launch pattern of a chunk
     bool use_graphs = false;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    std::map<std::vector<int64_t>, void*> graph_end_psi;   // psi buffer after a graph's chunk
     void drop_graphs()
     {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
+        graph_end_psi.clear();
     }
     // timing
     bool timing = false;
@@ -111,6 +116,7 @@ struct tdse_ctx {
         if (method == TDSE_METHOD_TAYLOR) return 2;
         if (method == TDSE_METHOD_RK4) return 3;
         if (method == TDSE_METHOD_LANCZOS) return (size_t)std::max(1, order_or_m);
+        if (method == TDSE_METHOD_TUNE) return 4;
         return 0;
     }
 };
@@ -213,10 +219,46 @@ static int states_for(int lmax)
     return s;
 }
 
-// (Re)builds one tile set.  rows = 0 for the population set.
+static int fused_width(int K, int stencil) { return kBlock - 2 * (K - 1) * (stencil == 3 ? 1 : 2); }
+
+// (Re)builds one tile set.  rows = 0 for the population set.  The fused set
+// (K = c->fuse_k terms per launch) uses radially overlapping tiles: tile t
+// starts at radius t*W - (K-1)s and writes the W = 256 - 2(K-1)s radii
+// [t*W, (t+1)*W).
 static void build_tiles(tdse_ctx* c, int set, int rows)
 {
     c->tiles[set].clear();
+    if (set == kFusedTiles) {
+        const int K = std::max(1, c->fuse_k);
+        const int s = (c->stencil == 3) ? 1 : 2;
+        const int W = fused_width(K, c->stencil);
+        for (int k = 0; k < c->n_inst; ++k) {
+            Inst& I = c->inst[k];
+            I.tbegin[set] = (int32_t)c->tiles[set].size();
+            for (int l0 = 0; l0 <= I.lmax; l0 += rows) {
+                for (int o0 = 0; o0 < I.n; o0 += W) {
+                    Tile t;
+                    std::memset(&t, 0, sizeof t);
+                    t.off = I.off;
+                    t.tab_off = I.tab_off;
+                    t.inst = k;
+                    t.r0 = o0 - (K - 1) * s;
+                    t.l0 = l0;
+                    t.l1 = std::min(l0 + rows, I.lmax + 1);
+                    t.n = I.n;
+                    t.lmax = I.lmax;
+                    t.i_ion = I.i_ion;
+                    t.n_states = I.n_states;
+                    t.dr = I.dr;
+                    t.inv_dr2 = I.inv_dr2;
+                    t.z = I.z;
+                    c->tiles[set].push_back(t);
+                }
+            }
+            I.tend[set] = (int32_t)c->tiles[set].size();
+        }
+        return;
+    }
     for (int k = 0; k < c->n_inst; ++k) {
         Inst& I = c->inst[k];
         I.tbegin[set] = (int32_t)c->tiles[set].size();
@@ -360,6 +402,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     build_tiles(c, kSweepTiles, c->rows_sweep);
     build_tiles(c, kReduceTiles, c->rows_reduce);
     build_tiles(c, kPopTiles, 0);
+    build_tiles(c, kFusedTiles, c->rows_fused);
     // radial tables: u0 (normalised r exp(-z r)) and the bound eigenvectors
     c->radial.assign(tab, 0.0);
     std::vector<std::thread> pool;
@@ -406,8 +449,15 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     };
     c->off_inst = take(sizeof(Inst) * n_inst);
     for (int set = 0; set < kNumTileSets; ++set) {
-        // the sweep set may be rebuilt by the autotuner: room for one row per tile
-        const size_t cap = (set == kSweepTiles) ? (size_t)c->total_cols : c->tiles[set].size();
+        // the sweep and fused sets may be rebuilt by the autotuners: room for
+        // one row per tile (and, fused, the narrowest tile width)
+        size_t cap = c->tiles[set].size();
+        if (set == kSweepTiles) cap = (size_t)c->total_cols;
+        if (set == kFusedTiles) {
+            cap = 0;
+            const int W = fused_width(kMaxFused, c->stencil);
+            for (const tdse_grid_desc& g : c->grids) cap += (size_t)((g.n_r + W - 1) / W) * (g.lmax + 1);
+        }
         c->off_tiles[set] = take(sizeof(Tile) * cap);
     }
     c->off_kappa = take(sizeof(double) * c->kappa.size());
@@ -497,6 +547,7 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         {c->off_tiles[kSweepTiles], c->tiles[kSweepTiles].data(), sizeof(Tile) * c->tiles[kSweepTiles].size()},
         {c->off_tiles[kReduceTiles], c->tiles[kReduceTiles].data(), sizeof(Tile) * c->tiles[kReduceTiles].size()},
         {c->off_tiles[kPopTiles], c->tiles[kPopTiles].data(), sizeof(Tile) * c->tiles[kPopTiles].size()},
+        {c->off_tiles[kFusedTiles], c->tiles[kFusedTiles].data(), sizeof(Tile) * c->tiles[kFusedTiles].size()},
         {c->off_kappa, c->kappa.data(), sizeof(double) * c->kappa.size()},
         {c->off_radial, c->radial.data(), sizeof(double) * c->radial.size()},
     };
@@ -661,16 +712,18 @@ hipError_t launch_obs(tdse_ctx* c, const void* psi, const double* step, double* 
 }
 
 // Enqueues the launches of steps [s0, s0 + count) of the current chunk.
+// *cur is the buffer holding psi (the state, or the ping-pong vector of the
+// fused Taylor path); a step function may move it.
 template <typename StepFn>
 hipError_t enqueue_chunk(tdse_ctx* c, int64_t s0, int count, int32_t obs_every, tdse_obs* d_obs,
-                         int64_t rec_stride, StepFn& step_fn)
+                         int64_t rec_stride, void** cur, StepFn& step_fn)
 {
     for (int s = 0; s < count; ++s) {
         const double* step = c->d_step() + (size_t)s * kSlots * c->n_inst;
         hipError_t e = step_fn(step);
         if (e != hipSuccess) return e;
         if (obs_every > 0 && (s0 + s + 1) % obs_every == 0) {
-            e = launch_obs(c, c->d_state, step, reinterpret_cast<double*>(d_obs), rec_stride);
+            e = launch_obs(c, *cur, step, reinterpret_cast<double*>(d_obs), rec_stride);
             if (e != hipSuccess) return e;
         }
     }
@@ -685,7 +738,7 @@ hipError_t enqueue_chunk(tdse_ctx* c, int64_t s0, int count, int32_t obs_every, 
 template <typename StepFn>
 tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, const double* dt,
                       int32_t nsteps, int32_t obs_every, tdse_obs* d_obs, int64_t method_key,
-                      StepFn&& step_fn)
+                      void** cur, StepFn&& step_fn)
 {
     const int64_t n_rec = (obs_every > 0) ? nsteps / obs_every : 0;
     const int64_t rec_stride = n_rec * (int64_t)kObsRecord;
@@ -695,18 +748,20 @@ tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, c
         tdse_status st = upload_steps(c, pulses, t0, dt, s0, count, obs_every);
         if (st != TDSE_OK) return st;
         if (!graphs) {
-            hipError_t e = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, step_fn);
+            hipError_t e = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn);
             if (e != hipSuccess) return c->hip_fail(e, "step launch");
             continue;
         }
+        void* cur_start = *cur;
         const std::vector<int64_t> key = {method_key, count, obs_every,
                                           obs_every > 0 ? s0 % obs_every : 0,
-                                          (int64_t)reinterpret_cast<uintptr_t>(d_obs), rec_stride};
+                                          (int64_t)reinterpret_cast<uintptr_t>(d_obs), rec_stride,
+                                          (int64_t)reinterpret_cast<uintptr_t>(cur_start)};
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return c->hip_fail(e, "hipStreamBeginCapture");
-            hipError_t el = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, step_fn);
+            hipError_t el = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(c->stream, &graph);
             if (el != hipSuccess) {
@@ -719,11 +774,68 @@ tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, c
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return c->hip_fail(e, "hipGraphInstantiate");
             it = c->graphs.emplace(key, exec).first;
+        } else {
+            // replay: advance the buffer roles exactly as the capture did
+            *cur = c->graph_end_psi[key];
         }
+        if (c->graph_end_psi.find(key) == c->graph_end_psi.end()) c->graph_end_psi[key] = *cur;
         hipError_t e = hipGraphLaunch(it->second, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "hipGraphLaunch");
     }
+    if (*cur != static_cast<void*>(c->d_state)) {
+        hipError_t e = launch_copy(c->prec, c->geom(kReduceTiles), *cur, c->d_state, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "final state copy");
+        *cur = c->d_state;
+    }
     return TDSE_OK;
+}
+
+// One Taylor step of order `order` (Horner form) on the psi held in `cur`.
+// Per-term path (fuse_k = 0): one sweep per term, ping-pong through the two
+// work vectors, the last term written in place into the state.  Fused path
+// (2 fuse_k >= order): at most two fused launches; psi ping-pongs between the
+// state and work vector 1 (the first launch's output, if any, goes to work
+// vector 0), and `cur` moves to the buffer holding the new psi.
+hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void*& cur)
+{
+    const int S = c->stencil == 3 ? 1 : 2;
+    void* psi = c->d_state;
+    void* wa = c->d_vec(0);
+    void* wb = c->d_vec(1);
+    const int K = c->fuse_k;
+    if (K > 0 && 2 * K >= order) {
+        const SweepGeom gf = c->geom(kFusedTiles);
+        void* nxt = (cur == psi) ? wb : psi;
+        hipError_t e;
+        TimedLaunch tl(c, 5);
+        if (K >= order) {
+            e = launch_horner_fused(c->prec, S, order, gf, cur, cur, nxt, step, order, c->stream);
+        } else {
+            e = launch_horner_fused(c->prec, S, K, gf, cur, cur, wa, step, order, c->stream);
+            if (e == hipSuccess)
+                e = launch_horner_fused(c->prec, S, order - K, gf, wa, cur, nxt, step, order - K, c->stream);
+        }
+        cur = nxt;
+        return e;
+    }
+    // Horner: w = psi + (-i dt/P) H psi; w = psi + (-i dt/k) H w, k = P-1..1
+    const SweepGeom g = c->geom();
+    const void* in = psi;
+    void* bufs[2] = {wa, wb};
+    int which = 0;
+    for (int k = order; k >= 1; --k) {
+        void* out = (k == 1 && order > 1) ? psi : bufs[which];
+        hipError_t e;
+        {
+            TimedLaunch tl(c, 0);
+            e = launch_hsweep(c->prec, S, g, in, psi, out, step, k, c->stream);
+        }
+        if (e != hipSuccess) return e;
+        in = out;
+        which ^= 1;
+    }
+    if (order == 1) return launch_copy(c->prec, g, wa, psi, c->stream);
+    return hipSuccess;
 }
 
 }  // namespace
@@ -766,30 +878,10 @@ extern "C" tdse_status tdse_step_taylor(tdse_ctx* c, const tdse_pulse* pulses, c
     if (st != TDSE_OK) return st;
     st = check_stable(c, pulses, dt, order);
     if (st != TDSE_OK) return st;
-    const int S = c->stencil == 3 ? 1 : 2;
-    const SweepGeom g = c->geom();
-    void* psi = c->d_state;
-    void* wa = c->d_vec(0);
-    void* wb = c->d_vec(1);
-    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 1000 + order, [&](const double* step) {
-        // Horner: w = psi + (-i dt/P) H psi; w = psi + (-i dt/k) H w, k = P-1..1
-        const void* in = psi;
-        void* bufs[2] = {wa, wb};
-        int which = 0;
-        for (int k = order; k >= 1; --k) {
-            void* out = (k == 1 && order > 1) ? psi : bufs[which];
-            hipError_t e;
-            {
-                TimedLaunch tl(c, 0);
-                e = launch_hsweep(c->prec, S, g, in, psi, out, step, k, c->stream);
-            }
-            if (e != hipSuccess) return e;
-            in = out;
-            which ^= 1;
-        }
-        if (order == 1) return launch_copy(c->prec, g, wa, psi, c->stream);
-        return hipSuccess;
-    });
+    void* cur = c->d_state;
+    const int64_t key = 1000 + 100 * c->fuse_k + order;
+    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, key, &cur,
+                     [&](const double* step) { return taylor_step_launches(c, step, order, cur); });
 }
 
 extern "C" tdse_status tdse_step_rk4(tdse_ctx* c, const tdse_pulse* pulses, const double* t0,
@@ -807,7 +899,8 @@ extern "C" tdse_status tdse_step_rk4(tdse_ctx* c, const tdse_pulse* pulses, cons
     void* ga = c->d_vec(0);
     void* gb = c->d_vec(1);
     void* acc = c->d_vec(2);
-    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 2000, [&](const double* step) {
+    void* cur = psi;
+    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 2000, &cur, [&](const double* step) {
         const void* gin[4] = {psi, ga, gb, ga};
         void* gout[4] = {ga, gb, ga, nullptr};
         for (int s = 0; s < 4; ++s) {
@@ -835,7 +928,8 @@ extern "C" tdse_status tdse_step_lanczos(tdse_ctx* c, const tdse_pulse* pulses, 
     const int64_t stride = (int64_t)(c->state_bytes() / c->elem);
     LanczosScalars* sc = c->d_lz();
     double* part = c->d_partial();
-    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 3000 + m, [&](const double* step) {
+    void* cur = psi;
+    return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 3000 + m, &cur, [&](const double* step) {
         hipError_t e = launch_lz_norm(c->prec, g, psi, part, c->stream);
         if (e == hipSuccess) e = launch_lz_norm_finish(g, part, sc, c->stream);
         for (int j = 0; j < m && e == hipSuccess; ++j) {
@@ -968,6 +1062,141 @@ extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
     c->drop_graphs();
     tune_cache_store(c, best, best_variant);
     if (rows_out) *rows_out = best;
+    return TDSE_OK;
+}
+
+extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t* k_out, int32_t* rows_out)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_autotune_taylor: not bound");
+    if (order < 1 || order > 16) return c->fail(TDSE_E_INVALID, "tdse_autotune_taylor: order must be 1..16");
+    if (c->work_bytes < tdse_workspace_bytes(c, TDSE_METHOD_TUNE, 0))
+        return c->fail(TDSE_E_WORKSPACE, "tdse_autotune_taylor: needs the TDSE_METHOD_TUNE workspace");
+    // one step of stable dt with a field, for every instance
+    const double y = tdse_taylor_stability_limit(order);
+    std::vector<tdse_pulse> pulses(c->n_inst);
+    std::vector<double> t0(c->n_inst, 0.0), dt(c->n_inst);
+    for (int k = 0; k < c->n_inst; ++k) {
+        pulses[k] = tdse_pulse{0.05, 1.0, 1.0, 0.0, -1.0};
+        dt[k] = 0.5 * y / gershgorin_bound(c->grids[k], 0.05);
+    }
+    tdse_status st = upload_steps(c, pulses.data(), t0.data(), dt.data(), 0, 1, 0);
+    if (st != TDSE_OK) return st;
+    const SweepGeom red = c->geom(kReduceTiles);
+    void* psi = c->d_state;
+    void* backup = c->d_vec(2);
+    void* ref = c->d_vec(3);
+    double* acc = reinterpret_cast<double*>(c->d_work + c->off_obs_tmp);
+    const int keep_k = c->fuse_k, keep_rows = c->rows_fused;
+    const bool keep_timing = c->timing;
+    c->timing = false;
+    hipError_t e = launch_copy(c->prec, red, psi, backup, c->stream);
+
+    // reference: one launch per term
+    auto one_step = [&](void** cur) -> hipError_t {
+        *cur = psi;
+        hipError_t ee = launch_copy(c->prec, red, backup, psi, c->stream);
+        void* cc = psi;
+        if (ee == hipSuccess) ee = taylor_step_launches(c, c->d_step(), order, cc);
+        *cur = cc;
+        return ee;
+    };
+    c->fuse_k = 0;
+    void* cur = psi;
+    if (e == hipSuccess) e = one_step(&cur);
+    if (e == hipSuccess) e = launch_copy(c->prec, red, cur, ref, c->stream);
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    struct Cand { int k, rows; };
+    std::vector<Cand> cands = {{0, 0}};
+    for (int K = (order + 1) / 2; K <= std::min(order, (int)kMaxFused); ++K)
+        for (int rows : {8, 16, 32}) cands.push_back({K, rows});
+    double best_ms = 1e300;
+    Cand best = {0, keep_rows};
+    std::string bad;
+    for (const Cand& cd : cands) {
+        if (e != hipSuccess) break;
+        c->fuse_k = cd.k;
+        if (cd.k > 0) {
+            c->rows_fused = cd.rows;
+            build_tiles(c, kFusedTiles, cd.rows);
+            e = upload_tiles(c, kFusedTiles);
+        }
+        // correctness against the reference step
+        if (e == hipSuccess) e = one_step(&cur);
+        if (e == hipSuccess) e = hipMemsetAsync(acc, 0, 2 * sizeof(double), c->stream);
+        if (e == hipSuccess) e = launch_diff_norm(c->prec, red, cur, ref, acc, c->stream);
+        double h_acc[2] = {0.0, 0.0};
+        if (e == hipSuccess) e = hipMemcpyAsync(h_acc, acc, sizeof h_acc, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) break;
+        const double rel = std::sqrt(h_acc[0] / std::max(h_acc[1], 1e-300));
+        const double tol = (c->prec == TDSE_FP64) ? 0.0 : 1e-6;
+        if (!(rel <= tol)) {
+            bad += " K=" + std::to_string(cd.k) + "/rows=" + std::to_string(cd.rows) + ": " + std::to_string(rel);
+            continue;
+        }
+        // timing: reps steps from the backed-up state
+        const int reps = 10;
+        e = launch_copy(c->prec, red, backup, psi, c->stream);
+        cur = psi;
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = taylor_step_launches(c, c->d_step(), order, cur);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (ms / reps < best_ms) {
+            best_ms = ms / reps;
+            best = cd;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    // restore the state and the chosen configuration
+    hipError_t e2 = launch_copy(c->prec, red, backup, psi, c->stream);
+    c->fuse_k = (e == hipSuccess) ? best.k : keep_k;
+    c->rows_fused = (e == hipSuccess && best.k > 0) ? best.rows : keep_rows;
+    build_tiles(c, kFusedTiles, c->rows_fused);
+    if (e2 == hipSuccess) e2 = upload_tiles(c, kFusedTiles);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+    c->timing = keep_timing;
+    c->drop_graphs();
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_autotune_taylor");
+    if (e2 != hipSuccess) return c->hip_fail(e2, "tdse_autotune_taylor restore");
+    if (!bad.empty() && c->prec == TDSE_FP64)
+        return c->fail(TDSE_E_HIP, "tdse_autotune_taylor: fused steps differ from the per-term step:" + bad);
+    if (k_out) *k_out = c->fuse_k;
+    if (rows_out) *rows_out = c->rows_fused;
+    return TDSE_OK;
+}
+
+extern "C" int32_t tdse_taylor_fusion(const tdse_ctx* c) { return c ? c->fuse_k : 0; }
+
+extern "C" tdse_status tdse_set_taylor_fusion(tdse_ctx* c, int32_t k, int32_t rows)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (k < 0 || k > kMaxFused || (k > 0 && (rows < 1 || rows > 64)))
+        return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: k must be 0..8 and rows 1..64");
+    if (c->bound) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_set_taylor_fusion sync");
+    }
+    if (k > 0 && rows != c->rows_fused) {
+        // the fused tile region holds the row-1 count of the narrowest tiles
+        c->rows_fused = rows;
+    }
+    c->fuse_k = k;
+    build_tiles(c, kFusedTiles, c->rows_fused);
+    if (c->bound) {
+        hipError_t e = upload_tiles(c, kFusedTiles);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_set_taylor_fusion upload");
+    }
+    c->drop_graphs();
     return TDSE_OK;
 }
 

@@ -12,9 +12,11 @@ constexpr int kBlock = 256;         // threads per workgroup of the sweep kernel
 constexpr int kMaxStates = 15;      // bound states n <= 5
 constexpr int kMaxKrylov = 64;      // largest Lanczos dimension
 
-// Tile sets: the sweeps (H applications), the streaming reductions, and the
-// population projections (rows l <= 4 only).
-enum TileSetId { kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kNumTileSets = 3 };
+// Tile sets: the sweeps (H applications), the streaming reductions, the
+// population projections (rows l <= 4 only) and the fused Horner launches
+// (radially overlapping tiles, see k_horner_fused).
+enum TileSetId { kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kFusedTiles = 3, kNumTileSets = 4 };
+constexpr int kMaxFused = 8;        // most Horner terms per fused launch
 
 // One instance (grid) as the per-instance kernels see it.
 struct Inst {
@@ -84,6 +86,13 @@ __host__ __device__ inline double step_value(const double* st, int n_inst, int s
 hipError_t launch_hsweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi,
                          void* out, const double* step, int term, hipStream_t st);
 
+// K (1..kMaxFused) consecutive Horner terms first_term, first_term-1, ... in
+// one launch over the fused tile set built for K; `out` must not alias `in`
+// or `psi` (`in` may equal `psi`).
+hipError_t launch_horner_fused(int prec, int S, int K, const SweepGeom& g, const void* in,
+                               const void* psi, void* out, const double* step, int first_term,
+                               hipStream_t st);
+
 // RK4 stage s (0..3); see the kernel for the buffer roles.
 hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, const void* gin,
                             const void* psi, void* acc, void* gout, const double* step,
@@ -129,6 +138,10 @@ hipError_t launch_lz_recombine(int prec, const SweepGeom& g, int m, void* psi, c
 // Number of elements whose stored values differ bit for bit, added to *count.
 hipError_t launch_count_diff(int prec, const SweepGeom& g, const void* a, const void* b,
                              unsigned int* count, hipStream_t st);
+
+// out[0] += sum |a - b|^2, out[1] += sum |b|^2 (FP64, atomic accumulation).
+hipError_t launch_diff_norm(int prec, const SweepGeom& g, const void* a, const void* b, double* out,
+                            hipStream_t st);
 
 // dst = src over every tile (state-shaped vectors).
 hipError_t launch_copy(int prec, const SweepGeom& g, const void* src, void* dst, hipStream_t st);

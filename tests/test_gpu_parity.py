@@ -331,3 +331,77 @@ def test_autotune_keeps_results_bitwise(tmp_path, monkeypatch):
     prop2 = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),))
     assert prop2.tile_rows == rows
     prop2.close()
+
+
+@pytest.mark.parametrize("stencil,k,rows", [(5, 8, 4), (5, 4, 16), (3, 5, 3), (3, 8, 32)])
+def test_fused_taylor_bitwise_equal_to_per_term(stencil, k, rows):
+    # K Horner terms per launch compute every element with the same FP64
+    # expression as one launch per term: identical bits, and the oracle's 1e-12
+    t = lib()
+    grid = t.Grid(700, 9, 0.1, stencil, t.FP64, 1.0, 12.0)
+    pulse = t.Pulse(0.06, 0.35, 2.0, 0.2, 0.0)
+    say(f"fused Taylor-8, K={k}, rows={rows}, stencil={stencil} vs per-term and oracle")
+    res = []
+    for fuse in (0, k):
+        prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),))
+        prop.set_taylor_fusion(fuse, rows)
+        prop.set_state(0, None)
+        obs = prop.obs_buffer(31, 10)
+        prop.step_taylor(pulse, 0.0, 4e-4, 8, 31, 10, obs)       # odd count: ends on the scratch side
+        res.append((prop.get_state(0), obs.cpu().numpy()))
+        prop.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    g = orc_grid(grid)
+    setup = oracle.obs_setup(g, r_ion=12.0)
+    psi0, _ = oracle.initial_state(g)
+    ref, robs, _ = oracle.propagate(g, orc_pulse(pulse), oracle.TAYLOR, 8, 0.0, 4e-4, 31, 10, setup, psi0)
+    assert rel_err(res[1][0], ref) < TOL64
+
+
+def test_fused_taylor_fp32_and_graphs():
+    t = lib()
+    grid = t.Grid(600, 8, 0.1, 3, t.FP32, 1.0, 5.0)
+    pulse = t.Pulse(0.1, 0.5, 2.0, 0.0, 0.0)
+    say("fused Taylor-8 (K=8) with FP32 storage and graph replay")
+    out = {}
+    for fuse, graphs in ((0, False), (8, False), (8, True)):
+        prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),), graphs=graphs)
+        prop.set_taylor_fusion(fuse, 16)
+        prop.set_state(0, None)
+        states = []
+        for call in range(2):
+            obs = prop.obs_buffer(701, 64)
+            prop.step_taylor(pulse, call * 701 * 8e-4, 8e-4, 8, 701, 64, obs)
+            states.append((prop.get_state(0), obs.cpu().numpy()))
+        prop.close()
+        out[(fuse, graphs)] = states
+    for call in range(2):
+        # graphs replay the direct launches bit for bit
+        assert np.array_equal(out[(8, False)][call][0], out[(8, True)][call][0])
+        assert np.array_equal(out[(8, False)][call][1], out[(8, True)][call][1])
+        # fused (FP64 intermediates) vs per-term (FP32 intermediates): rounding only
+        d = rel_err(out[(8, False)][call][0], out[(0, False)][call][0])
+        say(f"  call {call}: fused vs per-term FP32 state difference {d:.2e}")
+        assert d < 1e-4
+
+
+def test_autotune_taylor_choice_is_consistent():
+    t = lib()
+    grid = t.Grid(4000, 24, 0.1, 5, t.FP64, 1.0, 50.0)
+    pulse = t.Pulse(0.05, 0.1, 2.0, 0.0, 0.0)
+    prop = t.Propagator([grid], methods=((t.METHOD_TUNE, 0),))
+    dt = 0.8 * t.tdse_taylor_stability_limit(8) / prop.lambda_max_bound(0, 0.05)
+    prop.set_state(0, None)
+    before = prop.get_state(0)
+    k, rows = prop.autotune_taylor(8)
+    say(f"autotune_taylor: K={k} rows={rows}")
+    assert np.array_equal(prop.get_state(0), before)           # state restored
+    assert k == 0 or 4 <= k <= 8
+    prop.step_taylor(pulse, 5.0, dt, 8, 12)
+    tuned = prop.get_state(0)
+    prop.set_taylor_fusion(0, 16)
+    prop.set_state(0, None)
+    prop.step_taylor(pulse, 5.0, dt, 8, 12)
+    assert np.array_equal(prop.get_state(0), tuned)
+    prop.close()
