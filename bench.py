@@ -108,6 +108,13 @@ def timed(prop, tdse, wl, torch, steps, warmup, kernel, graphs):
     return wall, launches, kms, obs
 
 
+def dominant_kernel(prop, method):
+    """Timing family of the launch that carries a step's sweeps."""
+    if method == "taylor":
+        return "taylor_fused" if prop.taylor_fusion > 0 else "taylor_term"
+    return {"rk4": "rk4_stage", "lanczos": "lanczos_sweep_a"}[method]
+
+
 def batch_setup(tdse, precision):
     members = workloads.batch_members()
     grids, pulses = [], []
@@ -123,9 +130,13 @@ def batch_setup(tdse, precision):
 def run_batch_prec(tdse, torch, precision, args):
     members, grids, pulses = batch_setup(tdse, precision)
     order = workloads.BATCH_ORDER
-    prop = tdse.Propagator(grids, methods=((tdse.METHOD_TAYLOR, order),), graphs=bool(args.graphs))
+    prop = tdse.Propagator(grids, methods=((tdse.METHOD_TAYLOR, order),
+                                           (tdse.METHOD_TUNE, 0)), graphs=bool(args.graphs))
     if args.autotune:
         prop.autotune()
+        if args.autotune > 1:
+            prop.autotune_taylor(order)
+    kernel = dominant_kernel(prop, "taylor")
     y = tdse.tdse_taylor_stability_limit(order)
     dts = [workloads.BATCH_DT_SAFETY * y / prop.lambda_max_bound(k, abs(p.e0)) for k, p in enumerate(pulses)]
     for k in range(len(grids)):
@@ -149,15 +160,16 @@ def run_batch_prec(tdse, torch, precision, args):
     wall = time.perf_counter() - t0
     prop.timing(True)
     run(args.steps, obs)
-    launches, kms = prop.timing_read("taylor_term")
+    launches, kms = prop.timing_read(kernel)
     prop.timing(False)
-    rows = (prop.tile_rows, prop.sweep_variant)
+    rows = (prop.tile_rows, prop.sweep_variant, prop.taylor_fusion)
     o = obs.cpu().numpy()[:, -1, :]
     prop.close()
     del prop
     torch.cuda.empty_cache()
     U = sum((g.lmax + 1) * g.n for g in grids)
-    return dict(wall=wall, launches=launches, kms=kms, rows=rows, obs=o, U=U, dts=dts, n=len(grids))
+    return dict(wall=wall, launches=launches, kms=kms, rows=rows, obs=o, U=U, dts=dts, n=len(grids),
+                kernel=kernel)
 
 
 def run_batch(args, tdse, torch):
@@ -182,15 +194,15 @@ def run_batch(args, tdse, torch):
                    "seed": workloads.BATCH_SEED, "dr": workloads.BATCH_DR, "stencil": workloads.BATCH_STENCIL,
                    "method": "taylor", "order": workloads.BATCH_ORDER, "obs_every": 1,
                    "dt_range": [min(r32["dts"]), max(r32["dts"])], "parallelism": "single GPU",
-                   "tile_rows": r32["rows"], "graphs": bool(args.graphs)},
+                   "tile_rows_variant_fusion": r32["rows"], "graphs": bool(args.graphs)},
         "steps_per_s": sps,
-        "roofline": {"bound": "hbm", "kernel": "taylor_term", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": r32["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": 3 * 8 * U, "mean_launch_us": avg_ms * 1e3,
                      "launches_timed": r32["launches"]},
         "fp64_batched": {"steps_per_s": args.steps / r64["wall"],
                          "fp32_speedup_vs_fp64": sps / (args.steps / r64["wall"]),
-                         "kernel_mean_us": avg64 * 1e3,
+                         "kernel": r64["kernel"], "kernel_mean_us": avg64 * 1e3,
                          "kernel_gbs": 3 * 16 * U / (avg64 * 1e-3) / 1e9,
                          "max_norm_diff_fp32_vs_fp64": drift,
                          "max_p_bound_rel_diff_fp32_vs_fp64": pb,
@@ -225,7 +237,6 @@ def main():
     prec = tdse.FP64 if wl.precision == "fp64" else tdse.FP32
     mcode = {"taylor": tdse.METHOD_TAYLOR, "rk4": tdse.METHOD_RK4,
              "lanczos": tdse.METHOD_LANCZOS}[wl.method]
-    kernel = {"taylor": "taylor_term", "rk4": "rk4_stage", "lanczos": "lanczos_sweep_a"}[wl.method]
     applies_per_step = {"taylor": wl.order, "rk4": 4, "lanczos": wl.order}[wl.method]
     U = wl.unknowns
     elem = 16 if prec == tdse.FP64 else 8
@@ -236,6 +247,8 @@ def main():
     prop = make_prop(tdse, wl, prec, mcode, args.graphs, args.autotune)
     tile_rows = prop.tile_rows
     variant = prop.sweep_variant
+    fusion = prop.taylor_fusion
+    kernel = dominant_kernel(prop, wl.method)
     wall, launches, kms, obs = timed(prop, tdse, wl, torch, args.steps, args.warmup, kernel, args.graphs)
     psi_main = prop.get_state(0)
     steps_per_s = args.steps / wall
@@ -268,7 +281,8 @@ def main():
                    "stencil": wl.stencil, "method": wl.method, "order": wl.order,
                    "dt": wl.dt, "dt_nominal": wl.dt_nominal, "unknowns": U,
                    "obs_every": wl.obs_every, "parallelism": "single GPU",
-                   "tile_rows": tile_rows, "sweep_variant": variant, "graphs": bool(args.graphs)},
+                   "tile_rows": tile_rows, "sweep_variant": variant, "taylor_fusion": fusion,
+                   "graphs": bool(args.graphs)},
         "steps_per_s": steps_per_s,
         "roofline": {
             "bound": "hbm",
@@ -289,7 +303,8 @@ def main():
     if not args.no_fp32 and prec == tdse.FP64:
         wl32 = wl.with_(precision="fp32")
         prop = make_prop(tdse, wl32, tdse.FP32, mcode, args.graphs, args.autotune)
-        wall32, l32, k32, obs32 = timed(prop, tdse, wl32, torch, args.steps, args.warmup, kernel, args.graphs)
+        kernel32 = dominant_kernel(prop, wl.method)
+        wall32, l32, k32, obs32 = timed(prop, tdse, wl32, torch, args.steps, args.warmup, kernel32, args.graphs)
         psi32 = prop.get_state(0)
         o32 = obs32.cpu().numpy()[0, -1]
         prop.close()
@@ -301,6 +316,7 @@ def main():
             "steps_per_s": sps32,
             "applies_per_s": applies_per_step * sps32,
             "speedup_vs_fp64": sps32 / steps_per_s,
+            "kernel": kernel32,
             "kernel_mean_us": 1e3 * k32 / max(l32, 1),
             "kernel_gbs": (3 * 8 * U / (k32 / max(l32, 1) * 1e-3) / 1e9) if wl.method == "taylor" else None,
             "rel_state_error_vs_fp64": rel_state,

@@ -193,12 +193,14 @@ double tdse_lambda_max_bound(const tdse_ctx* ctx, int32_t inst, double e_max);
  * largest y with |sum_{k<=P} (i y')^k / k!| <= 1 + 1e-12 for all y' <= y. */
 double tdse_taylor_stability_limit(int32_t order);
 
-/* Autotuner for the sweep kernels (H.psi, Horner terms, RK4 stages): times a
- * Horner-term sweep of the bound state for each tile shape (256 radii x 1, 2,
- * 4, 8, 16 or 32 rows per workgroup) and each loop variant (one row at a
- * time, or software-pipelined one row ahead), checks that every choice produces
- * bit-identical results to the current one (a sweep's arithmetic does not
- * depend on the tile shape), keeps the fastest and appends it to the tuning
+/* Autotuner for the sweep kernels (H.psi, Horner terms; RK4 stages take the
+ * row count): times a Horner-term sweep of the bound state for each tile
+ * shape (1, 2, 4, 8, 16 or 32 rows per workgroup) and each sweep variant
+ * (bit 0: one radius per thread on 256-radius tiles, or two adjacent radii
+ * per thread on 512-radius tiles; bit 1: workgroups take tiles in order, or
+ * each XCD takes a contiguous run of tiles), checks that every choice
+ * produces bit-identical results to the current one (a sweep's arithmetic
+ * depends on neither), keeps the fastest and appends it to the tuning
  * cache named by the environment variable TDSE_TUNE_CACHE (if set; read by
  * tdse_init_grid for grids of the same shape class).  Needs the Taylor
  * workspace (two state-shaped vectors, overwritten); leaves the state
@@ -223,8 +225,8 @@ tdse_status tdse_autotune_taylor(tdse_ctx* ctx, int32_t order, int32_t* fuse_k_o
 int32_t tdse_taylor_fusion(const tdse_ctx* ctx);
 tdse_status tdse_set_taylor_fusion(tdse_ctx* ctx, int32_t k, int32_t rows);
 
-/* Rows per workgroup of the sweep tile set in use, and the loop variant
- * (0 one row at a time, 1 software-pipelined). */
+/* Rows per workgroup of the sweep tile set in use, and the sweep variant
+ * (0..3, bits as in tdse_autotune). */
 int32_t tdse_tile_rows(const tdse_ctx* ctx);
 int32_t tdse_sweep_variant(const tdse_ctx* ctx);
 

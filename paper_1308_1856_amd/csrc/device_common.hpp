@@ -24,6 +24,15 @@ __device__ __forceinline__ void stc(float2* p, int64_t k, double2 v)
 
 __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
 
+// A value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Sum over the 64 lanes of a wave; every lane gets the total.
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -56,12 +65,16 @@ __device__ __forceinline__ double block_sum(double (&v)[NQ], double* lds /* [kBl
     return out;
 }
 
-// The tile handled by this workgroup.  The hardware deals workgroup b to XCD
-// b mod 8; each XCD gets a contiguous run of tiles (so the radial and l halos
-// of neighbouring tiles meet in that XCD's L2).  A bijection of [0, n_tiles).
+// The tile handled by this workgroup.  order 0: tile = blockIdx.x (the
+// hardware deals workgroup b to XCD b mod 8, so consecutive tiles land on
+// different XCDs).  order 1: each XCD gets a contiguous run of tiles, so the
+// radial and l halos of neighbouring tiles meet in that XCD's L2.  Both are
+// bijections of [0, n_tiles); which one streams faster depends on the shape
+// and is left to the autotuner.
 __device__ __forceinline__ int my_tile_index(const SweepGeom& g)
 {
     const int b = (int)blockIdx.x;
+    if (g.order == 0) return b;
     const int q = g.n_tiles >> 3, rem = g.n_tiles & 7;
     const int x = b & 7, j = b >> 3;
     return x * q + min(x, rem) + j;
@@ -91,25 +104,44 @@ __device__ __forceinline__ RadialPoint radial_point(const Tile& I, int i)
     return p;
 }
 
+// Diagonal potential of row l: l(l+1)/(2 r^2) - Z/r.
+__device__ __forceinline__ double row_potential(int l, double inv_r2, double z_over_r)
+{
+    return fma(0.5 * (double)l * (double)(l + 1), inv_r2, -z_over_r);
+}
+
 // (H f)_{l,i} from the centre value, its radial neighbours (already zero
 // outside the box) and the values of rows l-1, l+1 at the same radius.
+// Every multiply-add is an explicit fma in a fixed order (the library is
+// built without implicit contraction), so every kernel that evaluates H
+// through this function rounds identically, whatever its loop shape.
 template <int S>
 __device__ __forceinline__ double2 h_point(double2 cur, double2 m1, double2 p1, double2 m2, double2 p2,
                                            double2 lm, double2 lp, double kin_scale, double v,
                                            double er, double kl, double klp)
 {
-    const double d0 = Kin<S>::c0 * kin_scale + v;
+    const double d0 = fma(Kin<S>::c0, kin_scale, v);
     const double d1 = Kin<S>::c1 * kin_scale;
     const double d2 = Kin<S>::c2 * kin_scale;
     const double ekl = er * kl, eklp = er * klp;
-    double2 h;
-    h.x = d0 * cur.x + d1 * (m1.x + p1.x) + ekl * lm.x + eklp * lp.x;
-    h.y = d0 * cur.y + d1 * (m1.y + p1.y) + ekl * lm.y + eklp * lp.y;
+    double hx = eklp * lp.x, hy = eklp * lp.y;
+    hx = fma(ekl, lm.x, hx);
+    hy = fma(ekl, lm.y, hy);
     if (S == 2) {
-        h.x += d2 * (m2.x + p2.x);
-        h.y += d2 * (m2.y + p2.y);
+        hx = fma(d2, m2.x + p2.x, hx);
+        hy = fma(d2, m2.y + p2.y, hy);
     }
-    return h;
+    hx = fma(d1, m1.x + p1.x, hx);
+    hy = fma(d1, m1.y + p1.y, hy);
+    hx = fma(d0, cur.x, hx);
+    hy = fma(d0, cur.y, hy);
+    return make_double2(hx, hy);
+}
+
+// One Horner term: psi + (-i c) h, with (-i c)(x + i y) = c y - i c x.
+__device__ __forceinline__ double2 horner_update(double2 psi, double2 h, double c)
+{
+    return make_double2(fma(c, h.y, psi.x), fma(-c, h.x, psi.y));
 }
 
 // Radial neighbours of element i of a row (zero outside [0, n)).

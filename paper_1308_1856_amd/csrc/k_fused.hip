@@ -21,8 +21,9 @@
 // outside [0, lmax] and radii outside [0, N) are zero, as in the single-term
 // sweep.
 //
-// Every element of every level is computed by the same expression as in
-// k_hsweep, so FP64 results are bit-identical to K single-term launches; in
+// Every element of every level is computed by the same functions (h_point,
+// horner_update) as in the single-term sweeps, so FP64 results are
+// bit-identical to K single-term launches; in
 // FP32 storage mode the intermediates stay FP64 (rounded once per launch).
 // HBM traffic per unknown and launch: read `in` and psi once, write out once,
 // instead of K times each.  `out` must not alias `in` or `psi`.
@@ -87,11 +88,10 @@ k_horner_fused(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
             if (inside && rho >= 0 && rho <= lmax) {
                 Neighbours<S, C> nb;
                 nb.load(in + base + (int64_t)rho * n, jc, n);
-                const double vpot = 0.5 * (double)rho * (double)(rho + 1) * inv_r2 - z_over_r;
+                const double vpot = row_potential(rho, inv_r2, z_over_r);
                 const double2 h = h_point<S>(in_cur, nb.m1, nb.p1, nb.m2, nb.p2, in_prev, in_next,
                                              I.inv_dr2, vpot, er, g.kappa[rho], g.kappa[rho + 1]);
-                const double c = dt / (double)first_term;
-                v = make_double2(pr[0].x + c * h.y, pr[0].y - c * h.x);
+                v = horner_update(pr[0], h, dt / (double)first_term);
             }
             in_prev = in_cur;
             in_cur = in_next;
@@ -126,12 +126,10 @@ k_horner_fused(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
                     m2 = (tid >= 2) ? row0[tid - 2] : zero2();
                     p2 = (tid + 2 < kBlock) ? row0[tid + 2] : zero2();
                 }
-                const double vpot = 0.5 * (double)rho * (double)(rho + 1) * inv_r2 - z_over_r;
+                const double vpot = row_potential(rho, inv_r2, z_over_r);
                 const double2 h = h_point<S>(cur, m1, p1, m2, p2, lm, lp, I.inv_dr2, vpot, er,
                                              g.kappa[rho], g.kappa[rho + 1]);
-                const double c = dt / (double)(first_term - k + 1);
-                const double2 ps = pr[k - 1];
-                v = make_double2(ps.x + c * h.y, ps.y - c * h.x);
+                v = horner_update(pr[k - 1], h, dt / (double)(first_term - k + 1));
             }
             if (k == K) {
                 if (writes && active && rho >= I.l0 && rho < I.l1) stc(out, base + (int64_t)rho * n + jc, v);

@@ -39,7 +39,7 @@ k_lz_norm(SweepGeom g, const typename Cplx<T>::type* __restrict__ psi, double* _
     if (i < I.n) {
         for (int l = tile.l0; l < tile.l1; ++l) {
             const double2 v = ldc(psi, I.off + (int64_t)l * I.n + i);
-            acc[0] += v.x * v.x + v.y * v.y;
+            acc[0] = fma(v.x, v.x, fma(v.y, v.y, acc[0]));
         }
     }
     const double s = block_sum<1>(acc, lds);
@@ -114,7 +114,7 @@ k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
             const double2 next = (l < I.lmax) ? ldc(qj, row + n + i) : zero2();
             Neighbours<S, C> nb;
             nb.load(qj + row, i, n);
-            const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
+            const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
             double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
                                    g.kappa[l], g.kappa[l + 1]);
             h.x *= sj;
@@ -139,8 +139,8 @@ k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
                         const double s = sc.scale[i0 + u];
                         const double2 q = ldc(basis_vec(psi, basis, stride, i0 + u), k);
                         // conj(s q) w
-                        acc[2 * u] += s * (q.x * wv.x + q.y * wv.y);
-                        acc[2 * u + 1] += s * (q.x * wv.y - q.y * wv.x);
+                        acc[2 * u] = fma(s, fma(q.x, wv.x, q.y * wv.y), acc[2 * u]);
+                        acc[2 * u + 1] = fma(s, fma(q.x, wv.y, -(q.y * wv.x)), acc[2 * u + 1]);
                     }
                 }
             }
@@ -194,13 +194,13 @@ k_lz_sweep_b(SweepGeom g, int j, const typename Cplx<T>::type* psi, typename Cpl
                 const double s = sc.scale[q];
                 const double hr = s * sc.h[2 * q], hi = s * sc.h[2 * q + 1];
                 const double2 b = ldc(basis_vec(psi, (const typename Cplx<T>::type*)basis, stride, q), k);
-                v.x -= hr * b.x - hi * b.y;
-                v.y -= hr * b.y + hi * b.x;
+                v.x = fma(-hr, b.x, fma(hi, b.y, v.x));
+                v.y = fma(-hr, b.y, fma(-hi, b.x, v.y));
             }
             stc(out, k, v);
             // the norm is taken of the stored (possibly rounded) vector
             const double2 vs = ldc(out, k);
-            acc[0] += vs.x * vs.x + vs.y * vs.y;
+            acc[0] = fma(vs.x, vs.x, fma(vs.y, vs.y, acc[0]));
         }
     }
     const double s = block_sum<1>(acc, lds);
@@ -341,8 +341,8 @@ k_lz_recombine(SweepGeom g, typename Cplx<T>::type* psi, const typename Cplx<T>:
         for (int q = 0; q < m; ++q) {
             const double cr = sc.coef[2 * q], ci = sc.coef[2 * q + 1];
             const double2 b = ldc(basis_vec((const typename Cplx<T>::type*)psi, basis, stride, q), k);
-            v.x += cr * b.x - ci * b.y;
-            v.y += cr * b.y + ci * b.x;
+            v.x = fma(cr, b.x, fma(-ci, b.y, v.x));
+            v.y = fma(cr, b.y, fma(ci, b.x, v.y));
         }
         stc(psi, k, v);
     }

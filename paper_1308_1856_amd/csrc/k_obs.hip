@@ -27,12 +27,12 @@ __device__ __forceinline__ void obs_main(const SweepGeom& g, const typename Cplx
         for (int l = I.l0; l < I.l1; ++l) {
             const int64_t row = I.off + (int64_t)l * n;
             const double2 next = (l < I.lmax) ? ldc(psi, row + n + i) : zero2();
-            const double a2 = cur.x * cur.x + cur.y * cur.y;
+            const double a2 = fma(cur.x, cur.x, cur.y * cur.y);
             acc[0] += a2;
             if (outer) acc[1] += a2;
-            const double re = (cur.x * next.x + cur.y * next.y) * g.kappa[l + 1];
-            acc[2] += rp.r * re;
-            acc[3] += re * rp.inv_r2;
+            const double re = fma(cur.x, next.x, cur.y * next.y) * g.kappa[l + 1];
+            acc[2] = fma(rp.r, re, acc[2]);
+            acc[3] = fma(re, rp.inv_r2, acc[3]);
             cur = next;
         }
     }

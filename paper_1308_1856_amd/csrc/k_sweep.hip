@@ -2,18 +2,31 @@
 // Taylor step (Sec. 5.2, eq. Taylor) and the fused classic RK4 stage
 // (Sec. 5.2, eq. RKDeriv).
 //
-// Work decomposition: a workgroup of 256 threads owns 256 consecutive radial
-// points of rows [l0, l1) of one instance.  Each thread walks down its rows
-// keeping f_{l-1}, f_l, f_{l+1} at its radius in registers, so the l +- 1
-// coupling costs one new load per row; the radial neighbours come from the
-// same row through the L1/L2 caches.  All arithmetic is FP64; storage is FP64
-// or FP32.  HBM traffic per unknown and term: read `in` once, read psi once,
+// Work decomposition: a workgroup of 256 threads owns a radial segment of
+// rows [l0, l1) of one instance.  Each thread walks down its rows keeping
+// f_{l-1}, f_l, f_{l+1} at its radii in registers, so the l +- 1 coupling
+// costs one new load per row.  All arithmetic is FP64; storage is FP64 or
+// FP32.  HBM traffic per unknown and term: read `in` once, read psi once,
 // write out once.
+//
+// Two sweep shapes (the autotuner picks per problem shape):
+//   k_hsweep       one radius per thread (256 radii per tile); the radial
+//                  neighbours come from the same row through L1.
+//   k_hsweep_pair  two adjacent radii per thread (512 radii per tile): one
+//                  16-byte FP32 (or two 16-byte FP64) load per row and
+//                  stream, radial neighbours from the adjacent lanes by
+//                  shuffles, only the first and last lane of a wave load a
+//                  neighbour from memory.  Twice the bytes in flight per
+//                  wave, which the FP32 sweep needs to approach the HBM
+//                  ceiling; values are held in storage precision until use
+//                  to keep the register count (and so the occupancy) up.
+// Both evaluate H through h_point and the term through horner_update, so
+// they agree bit for bit.
 #include "device_common.hpp"
 
 namespace tdse {
 
-template <int S, typename T, bool PIPE>
+template <int S, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_hsweep(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
          const typename Cplx<T>::type* psi, typename Cplx<T>::type* out,
@@ -25,66 +38,153 @@ k_hsweep(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
     const int i = I.r0 + (int)threadIdx.x;
     if (i >= n) return;
     const RadialPoint rp = radial_point(I, i);
-    const double e = step_value(step, g.n_inst, kEMid, I.inst);
-    const double er = e * rp.r;
-    // Horner term: out = psi + (-i dt/term) h;  (-i c)(x + i y) = c y - i c x
+    const double er = step_value(step, g.n_inst, kEMid, I.inst) * rp.r;
     const double c = (term > 0) ? step_value(step, g.n_inst, kDt, I.inst) / (double)term : 0.0;
     const int64_t base = I.off;
-
-    if (!PIPE) {
-        // plain loop: one row at a time (fewer registers, more waves)
-        double2 prev = (I.l0 > 0) ? ldc(in, base + (int64_t)(I.l0 - 1) * n + i) : zero2();
-        double2 cur = ldc(in, base + (int64_t)I.l0 * n + i);
-        for (int l = I.l0; l < I.l1; ++l) {
-            const int64_t row = base + (int64_t)l * n;
-            const double2 next = (l < I.lmax) ? ldc(in, row + n + i) : zero2();
-            Neighbours<S, C> nb;
-            nb.load(in + row, i, n);
-            const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
-            const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v,
-                                         er, g.kappa[l], g.kappa[l + 1]);
-            if (term > 0) {
-                const double2 p = ldc(psi, row + i);
-                stc(out, row + i, make_double2(p.x + c * h.y, p.y - c * h.x));
-            } else {
-                stc(out, row + i, h);
-            }
-            prev = cur;
-            cur = next;
-        }
-        return;
-    }
-    // Software pipeline: the loads row l + 1 needs (the input two rows ahead,
-    // the radial neighbours of row l + 1, psi of row l + 1) are issued before
-    // row l is computed and stored.  Safe when out == psi: a thread reads
-    // psi(l + 1, i) and writes out(l, i), never the same element.
-    const C* row0 = in + base + (int64_t)I.l0 * n;
-    double2 prev = (I.l0 > 0) ? ldc(row0 - n, i) : zero2();
-    double2 cur = ldc(row0, i);
-    double2 next = (I.l0 < I.lmax) ? ldc(row0 + n, i) : zero2();
-    Neighbours<S, C> nb;
-    nb.load(row0, i, n);
-    double2 p = (term > 0) ? ldc(psi + base + (int64_t)I.l0 * n, i) : zero2();
+    double2 prev = (I.l0 > 0) ? ldc(in, base + (int64_t)(I.l0 - 1) * n + i) : zero2();
+    double2 cur = ldc(in, base + (int64_t)I.l0 * n + i);
     for (int l = I.l0; l < I.l1; ++l) {
         const int64_t row = base + (int64_t)l * n;
-        const bool more = l + 1 < I.l1;
-        const double2 next2 = (l + 2 <= I.lmax) ? ldc(in, row + 2 * n + i) : zero2();
-        Neighbours<S, C> nb_next;
-        if (more) nb_next.load(in + row + n, i, n);
-        const double2 p_next = (more && term > 0) ? ldc(psi, row + n + i) : zero2();
-
-        const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
+        const double2 next = (l < I.lmax) ? ldc(in, row + n + i) : zero2();
+        Neighbours<S, C> nb;
+        nb.load(in + row, i, n);
+        const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
         const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
                                      g.kappa[l], g.kappa[l + 1]);
         if (term > 0)
-            stc(out, row + i, make_double2(p.x + c * h.y, p.y - c * h.x));
+            stc(out, row + i, horner_update(ldc(psi, row + i), h, c));
         else
             stc(out, row + i, h);
         prev = cur;
         cur = next;
-        next = next2;
-        if (more) nb = nb_next;
-        p = p_next;
+    }
+}
+
+// Two adjacent elements of a row, kept in storage precision.
+template <typename C> struct PairReg;
+template <> struct PairReg<float2> {
+    float2 a, b;
+    __device__ __forceinline__ double2 da() const { return make_double2((double)a.x, (double)a.y); }
+    __device__ __forceinline__ double2 db() const { return make_double2((double)b.x, (double)b.y); }
+};
+template <> struct PairReg<double2> {
+    double2 a, b;
+    __device__ __forceinline__ double2 da() const { return a; }
+    __device__ __forceinline__ double2 db() const { return b; }
+};
+// Four floats at 8-byte alignment: one 16-byte access for an FP32 pair whose
+// first element sits at an odd element offset (rows of odd length).
+struct alignas(8) Float4a8 {
+    float x, y, z, w;
+};
+
+// Loads elements k, k + 1 (both < the row end when `full`; only k when only
+// `live`; none otherwise, giving zeros).
+template <typename C>
+__device__ __forceinline__ void load_pair(const C* p, int64_t k, bool full, bool live, PairReg<C>& v)
+{
+    if (full) {
+        if constexpr (sizeof(C) == 8) {
+            const Float4a8 w = *reinterpret_cast<const Float4a8*>(p + k);
+            v.a = make_float2(w.x, w.y);
+            v.b = make_float2(w.z, w.w);
+        } else {
+            v.a = p[k];
+            v.b = p[k + 1];
+        }
+    } else if (live) {
+        v.a = p[k];
+        v.b = C{};
+    } else {
+        v.a = C{};
+        v.b = C{};
+    }
+}
+__device__ __forceinline__ void store_pair(float2* p, int64_t k, double2 a, double2 b)
+{
+    *reinterpret_cast<Float4a8*>(p + k) = Float4a8{(float)a.x, (float)a.y, (float)b.x, (float)b.y};
+}
+__device__ __forceinline__ void store_pair(double2* p, int64_t k, double2 a, double2 b)
+{
+    p[k] = a;
+    p[k + 1] = b;
+}
+__device__ __forceinline__ double2 from_lane_below(double2 v)
+{
+    return make_double2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
+}
+__device__ __forceinline__ double2 from_lane_above(double2 v)
+{
+    return make_double2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
+}
+
+// Thread t of a tile owns radii e = r0 + 2t and e + 1 (tiles are 512 radii
+// wide).  Row values of the pair: a = f(e), b = f(e + 1); the neighbours
+// e - 1, e - 2 are lane t-1's b, a and e + 2, e + 3 are lane t+1's a, b.
+// Every lane executes the shuffles (no early exit); lanes past the row end
+// hold zeros and store nothing.  Safe when out == psi: a thread reads psi
+// of row l + 1 after writing row l, and psi of row l before it.
+template <int S, typename T, bool TERM>
+__global__ void __launch_bounds__(kBlock)
+k_hsweep_pair(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
+              const typename Cplx<T>::type* psi, typename Cplx<T>::type* out,
+              const double* __restrict__ step, int term)
+{
+    using C = typename Cplx<T>::type;
+    const Tile I = my_tile(g);
+    const int n = I.n;
+    const int lane = (int)threadIdx.x & 63;
+    const int e = I.r0 + 2 * (int)threadIdx.x;
+    const bool live = e < n, full = e + 1 < n;
+    const int ec = live ? e : 0;
+    const double ra = (double)(ec + 1) * I.dr, rb = (double)(ec + 2) * I.dr;
+    const double ira = 1.0 / ra, irb = 1.0 / rb;
+    const double ira2 = ira * ira, irb2 = irb * irb, zra = I.z * ira, zrb = I.z * irb;
+    const double ef = step_value(step, g.n_inst, kEMid, I.inst);
+    // wave-uniform: kept in scalar registers
+    const double c = TERM ? wave_uniform(step_value(step, g.n_inst, kDt, I.inst) / (double)term) : 0.0;
+    const C* in_i = in + I.off;
+    const C* psi_i = psi + I.off;
+    C* out_i = out + I.off;
+
+    PairReg<C> P, Cu, N, Q;
+    P.a = P.b = N.a = N.b = Q.a = Q.b = C{};
+    if (I.l0 > 0) load_pair(in_i, (int64_t)(I.l0 - 1) * n + ec, full, live, P);
+    load_pair(in_i, (int64_t)I.l0 * n + ec, full, live, Cu);
+    if (I.l0 < I.lmax) load_pair(in_i, (int64_t)(I.l0 + 1) * n + ec, full, live, N);
+    if (TERM) load_pair(psi_i, (int64_t)I.l0 * n + ec, full, live, Q);
+    for (int l = I.l0; l < I.l1; ++l) {
+        const int64_t row = (int64_t)l * n;
+        const double2 ca = Cu.da(), cb = Cu.db();
+        double2 xm1 = from_lane_below(cb), xp2 = from_lane_above(ca), xm2 = zero2(), xp3 = zero2();
+        if (S == 2) {
+            xm2 = from_lane_below(ca);
+            xp3 = from_lane_above(cb);
+        }
+        if (lane == 0) {
+            xm1 = (live && ec >= 1) ? ldc(in_i, row + ec - 1) : zero2();
+            if (S == 2) xm2 = (live && ec >= 2) ? ldc(in_i, row + ec - 2) : zero2();
+        }
+        if (lane == 63) {
+            xp2 = (live && ec + 2 < n) ? ldc(in_i, row + ec + 2) : zero2();
+            if (S == 2) xp3 = (live && ec + 3 < n) ? ldc(in_i, row + ec + 3) : zero2();
+        }
+        const double kl = g.kappa[l], klp = g.kappa[l + 1];
+        const double2 ha = h_point<S>(ca, xm1, cb, xm2, xp2, P.da(), N.da(), I.inv_dr2,
+                                      row_potential(l, ira2, zra), ef * ra, kl, klp);
+        const double2 hb = h_point<S>(cb, ca, xp2, xm1, xp3, P.db(), N.db(), I.inv_dr2,
+                                      row_potential(l, irb2, zrb), ef * rb, kl, klp);
+        const double2 oa = TERM ? horner_update(Q.da(), ha, c) : ha;
+        const double2 ob = TERM ? horner_update(Q.db(), hb, c) : hb;
+        if (full)
+            store_pair(out_i, row + ec, oa, ob);
+        else if (live)
+            stc(out_i, row + ec, oa);
+        P = Cu;
+        Cu = N;
+        if (l + 2 <= I.lmax) load_pair(in_i, row + 2 * (int64_t)n + ec, full, live, N);
+        else N.a = N.b = C{};
+        if (TERM && l + 1 < I.l1) load_pair(psi_i, row + n + ec, full, live, Q);
     }
 }
 
@@ -115,7 +215,7 @@ k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
     constexpr bool kReadAcc = STAGE > 0;
     constexpr bool kReadPsi = STAGE == 1 || STAGE == 2;
 
-    // software pipeline as in k_hsweep: row l + 1's loads go out before row l
+    // software pipeline: row l + 1's loads go out before row l
     // is stored (acc and psi are read and written only at a thread's own
     // elements, one row apart)
     const C* row0 = gin + base + (int64_t)I.l0 * n;
@@ -135,18 +235,18 @@ k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
         const double2 a_next = (kReadAcc && more) ? ldc(acc, row + n + i) : zero2();
         const double2 p_next = (kReadPsi && more) ? ldc(psi, row + n + i) : zero2();
 
-        const double v = 0.5 * (double)l * (double)(l + 1) * rp.inv_r2 - rp.z_over_r;
+        const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
         const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
                                      g.kappa[l], g.kappa[l + 1]);
-        const double2 k = make_double2(h.y, -h.x);  // -i h
+        // x + w k with k = -i h
         if (STAGE == 0) {
-            stc(acc, row + i, make_double2(cur.x + bw * k.x, cur.y + bw * k.y));
-            stc(gout, row + i, make_double2(cur.x + aw * k.x, cur.y + aw * k.y));
+            stc(acc, row + i, horner_update(cur, h, bw));
+            stc(gout, row + i, horner_update(cur, h, aw));
         } else if (STAGE < 3) {
-            stc(acc, row + i, make_double2(a.x + bw * k.x, a.y + bw * k.y));
-            stc(gout, row + i, make_double2(p.x + aw * k.x, p.y + aw * k.y));
+            stc(acc, row + i, horner_update(a, h, bw));
+            stc(gout, row + i, horner_update(p, h, aw));
         } else {
-            stc(psi, row + i, make_double2(a.x + bw * k.x, a.y + bw * k.y));
+            stc(psi, row + i, horner_update(a, h, bw));
         }
         prev = cur;
         cur = next;
@@ -228,12 +328,16 @@ static hipError_t hsweep_t(const SweepGeom& g, const void* in, const void* psi, 
                            const double* step, int term, hipStream_t st)
 {
     using C = typename Cplx<T>::type;
-    if (g.variant == 1)
-        hipLaunchKernelGGL((k_hsweep<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+    if (g.variant == 1 && term > 0)
+        hipLaunchKernelGGL((k_hsweep_pair<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                           step, term);
+    else if (g.variant == 1)
+        hipLaunchKernelGGL((k_hsweep_pair<S, T, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
                            static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
                            step, term);
     else
-        hipLaunchKernelGGL((k_hsweep<S, T, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+        hipLaunchKernelGGL((k_hsweep<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
                            static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
                            step, term);
     return hipGetLastError();

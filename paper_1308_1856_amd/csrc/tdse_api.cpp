@@ -44,7 +44,7 @@ struct tdse_ctx {
     std::vector<Inst> inst;
     std::vector<Tile> tiles[kNumTileSets];
     int rows_sweep = 1, rows_reduce = 1;
-    int sweep_variant = 0;              // 0 plain loop, 1 software-pipelined (autotuned)
+    int sweep_variant = 0;              // bit 0: two radii per thread, bit 1: XCD-contiguous order (autotuned)
     int fuse_k = 0;                     // Horner terms per fused launch (0: one launch per term)
     int rows_fused = 16;
     int64_t total_cols = 0;             // sum over instances of ceil(N/256) * (lmax+1)
@@ -59,7 +59,7 @@ struct tdse_ctx {
     size_t work_bytes = 0;
     hipStream_t stream = nullptr;
     // workspace layout (bytes from d_work)
-    size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0, 0}, off_kappa = 0, off_radial = 0,
+    size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0, 0, 0}, off_kappa = 0, off_radial = 0,
            off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0;
     size_t partial_doubles = 0;
     // pinned staging for the per-step scalars (double buffered)
@@ -102,7 +102,16 @@ struct tdse_ctx {
         g.n_tiles = (int32_t)tiles[set].size();
         g.n_inst = n_inst;
         g.set = set;
-        g.variant = (set == kSweepTiles) ? sweep_variant : 0;
+        g.variant = 0;
+        g.order = 0;
+        return g;
+    }
+    // geometry of the H sweeps (apply_H, Taylor terms) in the tuned shape
+    SweepGeom hgeom() const
+    {
+        SweepGeom g = geom((sweep_variant & 1) ? kPairTiles : kSweepTiles);
+        g.variant = sweep_variant & 1;
+        g.order = (sweep_variant >> 1) & 1;
         return g;
     }
     double* d_step() const { return reinterpret_cast<double*>(d_work + off_step); }
@@ -259,13 +268,14 @@ static void build_tiles(tdse_ctx* c, int set, int rows)
         }
         return;
     }
+    const int width = (set == kPairTiles) ? 2 * kBlock : kBlock;
     for (int k = 0; k < c->n_inst; ++k) {
         Inst& I = c->inst[k];
         I.tbegin[set] = (int32_t)c->tiles[set].size();
         const int lhi = (set == kPopTiles) ? std::min(I.lmax, 4) + 1 : I.lmax + 1;
         const int step = (set == kPopTiles) ? lhi : rows;
         for (int l0 = 0; l0 < lhi; l0 += step) {
-            for (int r0 = 0; r0 < I.n; r0 += kBlock) {
+            for (int r0 = 0; r0 < I.n; r0 += width) {
                 Tile t;
                 std::memset(&t, 0, sizeof t);
                 t.off = I.off;
@@ -403,6 +413,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     build_tiles(c, kReduceTiles, c->rows_reduce);
     build_tiles(c, kPopTiles, 0);
     build_tiles(c, kFusedTiles, c->rows_fused);
+    build_tiles(c, kPairTiles, c->rows_sweep);
     // radial tables: u0 (normalised r exp(-z r)) and the bound eigenvectors
     c->radial.assign(tab, 0.0);
     std::vector<std::thread> pool;
@@ -453,6 +464,10 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         // one row per tile (and, fused, the narrowest tile width)
         size_t cap = c->tiles[set].size();
         if (set == kSweepTiles) cap = (size_t)c->total_cols;
+        if (set == kPairTiles) {
+            cap = 0;
+            for (const tdse_grid_desc& g : c->grids) cap += (size_t)((g.n_r + 2 * kBlock - 1) / (2 * kBlock)) * (g.lmax + 1);
+        }
         if (set == kFusedTiles) {
             cap = 0;
             const int W = fused_width(kMaxFused, c->stencil);
@@ -548,6 +563,7 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         {c->off_tiles[kReduceTiles], c->tiles[kReduceTiles].data(), sizeof(Tile) * c->tiles[kReduceTiles].size()},
         {c->off_tiles[kPopTiles], c->tiles[kPopTiles].data(), sizeof(Tile) * c->tiles[kPopTiles].size()},
         {c->off_tiles[kFusedTiles], c->tiles[kFusedTiles].data(), sizeof(Tile) * c->tiles[kFusedTiles].size()},
+        {c->off_tiles[kPairTiles], c->tiles[kPairTiles].data(), sizeof(Tile) * c->tiles[kPairTiles].size()},
         {c->off_kappa, c->kappa.data(), sizeof(double) * c->kappa.size()},
         {c->off_radial, c->radial.data(), sizeof(double) * c->radial.size()},
     };
@@ -819,7 +835,7 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
         return e;
     }
     // Horner: w = psi + (-i dt/P) H psi; w = psi + (-i dt/k) H w, k = P-1..1
-    const SweepGeom g = c->geom();
+    const SweepGeom g = c->hgeom();
     const void* in = psi;
     void* bufs[2] = {wa, wb};
     int which = 0;
@@ -834,7 +850,7 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
         in = out;
         which ^= 1;
     }
-    if (order == 1) return launch_copy(c->prec, g, wa, psi, c->stream);
+    if (order == 1) return launch_copy(c->prec, c->geom(), wa, psi, c->stream);
     return hipSuccess;
 }
 
@@ -863,7 +879,7 @@ extern "C" tdse_status tdse_apply_H(tdse_ctx* c, const double* e_field, const vo
     e = hipStreamSynchronize(c->stream);  // e_field is pageable caller memory
     if (e != hipSuccess) return c->hip_fail(e, "tdse_apply_H sync");
     TimedLaunch tl(c, 4);
-    e = launch_hsweep(c->prec, c->stencil == 3 ? 1 : 2, c->geom(), d_in, nullptr, d_out, c->d_step(), 0,
+    e = launch_hsweep(c->prec, c->stencil == 3 ? 1 : 2, c->hgeom(), d_in, nullptr, d_out, c->d_step(), 0,
                       c->stream);
     return (e == hipSuccess) ? TDSE_OK : c->hip_fail(e, "tdse_apply_H launch");
 }
@@ -1005,19 +1021,21 @@ extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     // reference sweep with the current tiles
-    if (e == hipSuccess) e = launch_hsweep(c->prec, S, c->geom(), psi, psi, ref, c->d_step(), 1, c->stream);
+    if (e == hipSuccess) e = launch_hsweep(c->prec, S, c->hgeom(), psi, psi, ref, c->d_step(), 1, c->stream);
     double best_ms = 1e300;
     int best = start_rows, best_variant = start_variant;
     const int cands[] = {1, 2, 4, 8, 16, 32};
-    for (int cand = 0; cand < 12; ++cand) {
+    // rows x variant (bit 0: two radii per thread, bit 1: XCD-contiguous order)
+    for (int cand = 0; cand < 24; ++cand) {
         const int rows = cands[cand % 6];
         const int variant = cand / 6;
         if (e != hipSuccess) break;
         if (rows != 1 && c->total_cols / rows < 64) continue;
         c->sweep_variant = variant;
-        build_tiles(c, kSweepTiles, rows);
-        e = upload_tiles(c, kSweepTiles);
-        const SweepGeom g = c->geom();
+        const int set = (variant & 1) ? kPairTiles : kSweepTiles;
+        build_tiles(c, set, rows);
+        e = upload_tiles(c, set);
+        const SweepGeom g = c->hgeom();
         for (int w = 0; w < 2 && e == hipSuccess; ++w)
             e = launch_hsweep(c->prec, S, g, psi, psi, out, c->d_step(), 1, c->stream);
         const int reps = 20;
@@ -1037,8 +1055,10 @@ extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             build_tiles(c, kSweepTiles, start_rows);
+            build_tiles(c, kPairTiles, start_rows);
             c->sweep_variant = start_variant;
             (void)upload_tiles(c, kSweepTiles);
+            (void)upload_tiles(c, kPairTiles);
             (void)hipStreamSynchronize(c->stream);
             return c->fail(TDSE_E_HIP, "tdse_autotune: a tile shape changed the result of a sweep (" +
                                            std::to_string(diff) + " elements, rows " + std::to_string(rows) +
@@ -1053,8 +1073,10 @@ extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     build_tiles(c, kSweepTiles, (e == hipSuccess) ? best : start_rows);
+    build_tiles(c, kPairTiles, (e == hipSuccess) ? best : start_rows);
     c->sweep_variant = (e == hipSuccess) ? best_variant : start_variant;
     hipError_t e2 = upload_tiles(c, kSweepTiles);
+    if (e2 == hipSuccess) e2 = upload_tiles(c, kPairTiles);
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "tdse_autotune");
     if (e2 != hipSuccess) return c->hip_fail(e2, "tdse_autotune upload");

@@ -15,7 +15,10 @@ constexpr int kMaxKrylov = 64;      // largest Lanczos dimension
 // Tile sets: the sweeps (H applications), the streaming reductions, the
 // population projections (rows l <= 4 only) and the fused Horner launches
 // (radially overlapping tiles, see k_horner_fused).
-enum TileSetId { kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kFusedTiles = 3, kNumTileSets = 4 };
+// Tile sets: sweeps at 256 radii per tile (also RK4 stages), reductions,
+// populations, fused Horner terms, and sweeps at 512 radii per tile (two
+// radii per thread).
+enum TileSetId { kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kFusedTiles = 3, kPairTiles = 4, kNumTileSets = 5 };
 constexpr int kMaxFused = 8;        // most Horner terms per fused launch
 
 // One instance (grid) as the per-instance kernels see it.
@@ -69,7 +72,8 @@ struct SweepGeom {
     int32_t n_tiles;
     int32_t n_inst;
     int32_t set;           // TileSetId of `tiles`
-    int32_t variant;       // sweep loop: 0 one row at a time, 1 software-pipelined
+    int32_t variant;       // H sweep: 0 one radius per thread, 1 two radii per thread
+    int32_t order;         // block -> tile map: 0 identity, 1 XCD-contiguous runs
 };
 
 // Per-step scalars, FP64, laid out [slot][instance] with these slots:
