@@ -151,7 +151,11 @@ tdse_status tdse_apply_H(tdse_ctx* ctx, const double* e_field, const void* d_in,
 
 /* Taylor propagator of order `order` (1..16), Sec. 5.2 eq. Taylor:
  *   F <- sum_{p=0..P} (-i dt H(t_s + dt/2))^p / p! F
- * evaluated in Horner form, one fused sweep per term.  For each instance k
+ * evaluated in Horner form, one fused sweep per term (or several terms per
+ * launch, see tdse_set_taylor_fusion).  Within the call psi rotates through
+ * the state and the first two workspace vectors (no launch writes a buffer
+ * it reads); the state buffer holds the result once the call's launches
+ * have completed.  For each instance k
  * advances the bound state by nsteps steps of dt[k] from t0[k]; step s
  * spans [t0 + s dt, t0 + (s+1) dt].  If obs_every > 0 and d_obs != NULL the
  * observables after every obs_every-th step are written to d_obs (device
@@ -209,21 +213,26 @@ tdse_status tdse_autotune(tdse_ctx* ctx, int32_t* rows_out);
 /* Autotuner for the Taylor step of order `order` (1..16): times whole steps
  * of the bound state (field-free, stable dt) with one launch per Horner term
  * (the sweep tiles in use) and with K = ceil(order/2)..min(order, 8) terms
- * fused per launch on 256-radius tiles of 8, 16 or 32 rows, verifies each
- * candidate's step against the one-launch-per-term step (bit for bit in
- * FP64; relative 2-norm difference <= 1e-6 with FP32 storage, where the
- * fused launches keep their intermediates in FP64), and keeps the fastest for
- * later tdse_step_taylor calls.  Needs the TDSE_METHOD_TUNE workspace; the
- * state is restored.  *fuse_k_out (0: one launch per term) and *rows_out (may
- * be NULL) receive the choice.  Synchronises. */
+ * per fused launch, for both fused kernels (kind 0: workgroup tiles of 256
+ * radii with the intermediate levels in LDS rings, 8, 16 or 32 rows; kind 1:
+ * independent 64-radius wave strips with the intermediate levels in
+ * registers, 8, 16, 32 or 64 rows), verifies each candidate's step against
+ * the one-launch-per-term step (bit for bit in FP64; relative 2-norm
+ * difference <= 1e-6 with FP32 storage, where the fused launches keep their
+ * intermediates in FP64), and keeps the fastest for later tdse_step_taylor
+ * calls.  Needs the TDSE_METHOD_TUNE workspace; the state is restored.
+ * *fuse_k_out (0: one launch per term) and *rows_out (may be NULL) receive
+ * the choice; tdse_taylor_fusion_kind gives the kernel.  Synchronises. */
 tdse_status tdse_autotune_taylor(tdse_ctx* ctx, int32_t order, int32_t* fuse_k_out, int32_t* rows_out);
-/* Horner terms per fused Taylor launch in use (0: one launch per term), and
- * an explicit choice: k = 0 (one launch per term) or 1..8 terms per fused
- * launch on tiles of `rows` rows (1..64).  The fused path is used by
+/* Horner terms per fused Taylor launch in use (0: one launch per term), the
+ * fused kernel in use (0 LDS rings, 1 wave strips), and an explicit choice:
+ * k = 0 (one launch per term) or 1..8 terms per fused launch of kernel
+ * `kind` on tiles of `rows` rows (1..64).  The fused path is used by
  * tdse_step_taylor when 2k >= order (at most two launches per step).
  * Synchronises. */
 int32_t tdse_taylor_fusion(const tdse_ctx* ctx);
-tdse_status tdse_set_taylor_fusion(tdse_ctx* ctx, int32_t k, int32_t rows);
+int32_t tdse_taylor_fusion_kind(const tdse_ctx* ctx);
+tdse_status tdse_set_taylor_fusion(tdse_ctx* ctx, int32_t k, int32_t rows, int32_t kind);
 
 /* Rows per workgroup of the sweep tile set in use, and the sweep variant
  * (0..3, bits as in tdse_autotune). */

@@ -35,7 +35,8 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_step_rk4", "tdse_step_lanczos", "tdse_observables", "tdse_lambda_max_bound",
             "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read",
             "tdse_use_graphs", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
-            "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_set_taylor_fusion")
+            "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_taylor_fusion_kind",
+            "tdse_set_taylor_fusion")
 
 
 class TdseError(RuntimeError):
@@ -97,7 +98,8 @@ def _load():
         "tdse_sweep_variant": ([ctxp], i32),
         "tdse_autotune_taylor": ([ctxp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "tdse_taylor_fusion": ([ctxp], i32),
-        "tdse_set_taylor_fusion": ([ctxp, i32, i32], i32),
+        "tdse_taylor_fusion_kind": ([ctxp], i32),
+        "tdse_set_taylor_fusion": ([ctxp, i32, i32, i32], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -380,8 +382,13 @@ class Propagator:
     def taylor_fusion(self) -> int:
         return lib.tdse_taylor_fusion(self.ctx)
 
-    def set_taylor_fusion(self, k: int, rows: int = 16):
-        _check(self.ctx, lib.tdse_set_taylor_fusion(self.ctx, int(k), int(rows)))
+    @property
+    def taylor_fusion_kind(self) -> int:
+        """Fused kernel in use: 0 LDS rings, 1 wave strips."""
+        return lib.tdse_taylor_fusion_kind(self.ctx)
+
+    def set_taylor_fusion(self, k: int, rows: int = 16, kind: int = 0):
+        _check(self.ctx, lib.tdse_set_taylor_fusion(self.ctx, int(k), int(rows), int(kind)))
 
     def _pulse_list(self, pulses):
         if isinstance(pulses, (list, tuple)):

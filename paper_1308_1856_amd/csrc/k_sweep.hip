@@ -29,7 +29,7 @@ namespace tdse {
 template <int S, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_hsweep(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
-         const typename Cplx<T>::type* psi, typename Cplx<T>::type* out,
+         const typename Cplx<T>::type* __restrict__ psi, typename Cplx<T>::type* __restrict__ out,
          const double* __restrict__ step, int term)
 {
     using C = typename Cplx<T>::type;
@@ -122,12 +122,11 @@ __device__ __forceinline__ double2 from_lane_above(double2 v)
 // wide).  Row values of the pair: a = f(e), b = f(e + 1); the neighbours
 // e - 1, e - 2 are lane t-1's b, a and e + 2, e + 3 are lane t+1's a, b.
 // Every lane executes the shuffles (no early exit); lanes past the row end
-// hold zeros and store nothing.  Safe when out == psi: a thread reads psi
-// of row l + 1 after writing row l, and psi of row l before it.
+// hold zeros and store nothing.
 template <int S, typename T, bool TERM>
 __global__ void __launch_bounds__(kBlock)
 k_hsweep_pair(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
-              const typename Cplx<T>::type* psi, typename Cplx<T>::type* out,
+              const typename Cplx<T>::type* __restrict__ psi, typename Cplx<T>::type* __restrict__ out,
               const double* __restrict__ step, int term)
 {
     using C = typename Cplx<T>::type;

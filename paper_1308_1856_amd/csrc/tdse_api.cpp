@@ -46,6 +46,7 @@ struct tdse_ctx {
     int rows_sweep = 1, rows_reduce = 1;
     int sweep_variant = 0;              // bit 0: two radii per thread, bit 1: XCD-contiguous order (autotuned)
     int fuse_k = 0;                     // Horner terms per fused launch (0: one launch per term)
+    int fuse_kind = 0;                  // fused kernel: 0 LDS rings, 1 wave strips
     int rows_fused = 16;
     int64_t total_cols = 0;             // sum over instances of ceil(N/256) * (lmax+1)
     std::vector<double> kappa;
@@ -59,7 +60,7 @@ struct tdse_ctx {
     size_t work_bytes = 0;
     hipStream_t stream = nullptr;
     // workspace layout (bytes from d_work)
-    size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0, 0, 0}, off_kappa = 0, off_radial = 0,
+    size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0, 0, 0, 0}, off_kappa = 0, off_radial = 0,
            off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0;
     size_t partial_doubles = 0;
     // pinned staging for the per-step scalars (double buffered)
@@ -229,6 +230,8 @@ static int states_for(int lmax)
 }
 
 static int fused_width(int K, int stencil) { return kBlock - 2 * (K - 1) * (stencil == 3 ? 1 : 2); }
+// output radii of one strip tile (kStripWaves strips of 64 - 2 K s)
+static int strip_width(int K, int stencil) { return kStripWaves * (64 - 2 * K * (stencil == 3 ? 1 : 2)); }
 
 // (Re)builds one tile set.  rows = 0 for the population set.  The fused set
 // (K = c->fuse_k terms per launch) uses radially overlapping tiles: tile t
@@ -237,6 +240,37 @@ static int fused_width(int K, int stencil) { return kBlock - 2 * (K - 1) * (sten
 static void build_tiles(tdse_ctx* c, int set, int rows)
 {
     c->tiles[set].clear();
+    if (set == kStripTiles) {
+        // tile r0 = first output radius; the kernel places its strips
+        const int K = std::max(1, c->fuse_k);
+        const int W = strip_width(K, c->stencil);
+        for (int k = 0; k < c->n_inst; ++k) {
+            Inst& I = c->inst[k];
+            I.tbegin[set] = (int32_t)c->tiles[set].size();
+            for (int l0 = 0; l0 <= I.lmax; l0 += rows) {
+                for (int o0 = 0; o0 < I.n; o0 += W) {
+                    Tile t;
+                    std::memset(&t, 0, sizeof t);
+                    t.off = I.off;
+                    t.tab_off = I.tab_off;
+                    t.inst = k;
+                    t.r0 = o0;
+                    t.l0 = l0;
+                    t.l1 = std::min(l0 + rows, I.lmax + 1);
+                    t.n = I.n;
+                    t.lmax = I.lmax;
+                    t.i_ion = I.i_ion;
+                    t.n_states = I.n_states;
+                    t.dr = I.dr;
+                    t.inv_dr2 = I.inv_dr2;
+                    t.z = I.z;
+                    c->tiles[set].push_back(t);
+                }
+            }
+            I.tend[set] = (int32_t)c->tiles[set].size();
+        }
+        return;
+    }
     if (set == kFusedTiles) {
         const int K = std::max(1, c->fuse_k);
         const int s = (c->stencil == 3) ? 1 : 2;
@@ -414,6 +448,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     build_tiles(c, kPopTiles, 0);
     build_tiles(c, kFusedTiles, c->rows_fused);
     build_tiles(c, kPairTiles, c->rows_sweep);
+    build_tiles(c, kStripTiles, c->rows_fused);
     // radial tables: u0 (normalised r exp(-z r)) and the bound eigenvectors
     c->radial.assign(tab, 0.0);
     std::vector<std::thread> pool;
@@ -464,6 +499,11 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         // one row per tile (and, fused, the narrowest tile width)
         size_t cap = c->tiles[set].size();
         if (set == kSweepTiles) cap = (size_t)c->total_cols;
+        if (set == kStripTiles) {
+            cap = 0;
+            const int W = strip_width(kMaxFused, c->stencil);
+            for (const tdse_grid_desc& g : c->grids) cap += (size_t)((g.n_r + W - 1) / W) * (g.lmax + 1);
+        }
         if (set == kPairTiles) {
             cap = 0;
             for (const tdse_grid_desc& g : c->grids) cap += (size_t)((g.n_r + 2 * kBlock - 1) / (2 * kBlock)) * (g.lmax + 1);
@@ -564,6 +604,7 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         {c->off_tiles[kPopTiles], c->tiles[kPopTiles].data(), sizeof(Tile) * c->tiles[kPopTiles].size()},
         {c->off_tiles[kFusedTiles], c->tiles[kFusedTiles].data(), sizeof(Tile) * c->tiles[kFusedTiles].size()},
         {c->off_tiles[kPairTiles], c->tiles[kPairTiles].data(), sizeof(Tile) * c->tiles[kPairTiles].size()},
+        {c->off_tiles[kStripTiles], c->tiles[kStripTiles].data(), sizeof(Tile) * c->tiles[kStripTiles].size()},
         {c->off_kappa, c->kappa.data(), sizeof(double) * c->kappa.size()},
         {c->off_radial, c->radial.data(), sizeof(double) * c->radial.size()},
     };
@@ -807,40 +848,55 @@ tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, c
 }
 
 // One Taylor step of order `order` (Horner form) on the psi held in `cur`.
-// Per-term path (fuse_k = 0): one sweep per term, ping-pong through the two
-// work vectors, the last term written in place into the state.  Fused path
-// (2 fuse_k >= order): at most two fused launches; psi ping-pongs between the
-// state and work vector 1 (the first launch's output, if any, goes to work
-// vector 0), and `cur` moves to the buffer holding the new psi.
+// psi rotates through three buffers (the state and work vectors 0 and 1);
+// no launch ever writes a buffer it reads, and `cur` moves to the buffer that
+// holds the new psi (run_steps copies it back into the state at the end).
+// Per-term path (fuse_k = 0): one sweep per term, alternating between the two
+// buffers that do not hold psi; the last term's output is the new psi.
+// Fused path (2 fuse_k >= order): at most two fused launches (LDS-ring or
+// wave-strip kernel); psi ping-pongs between the state and work vector 1, and
+// the first launch's output (if there are two) goes to work vector 0.
 hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void*& cur)
 {
     const int S = c->stencil == 3 ? 1 : 2;
-    void* psi = c->d_state;
+    void* state = c->d_state;
     void* wa = c->d_vec(0);
     void* wb = c->d_vec(1);
     const int K = c->fuse_k;
     if (K > 0 && 2 * K >= order) {
-        const SweepGeom gf = c->geom(kFusedTiles);
-        void* nxt = (cur == psi) ? wb : psi;
+        const bool strips = c->fuse_kind == 1;
+        SweepGeom gf = c->geom(strips ? kStripTiles : kFusedTiles);
+        if (strips) gf.variant = K;   // the term count the strip tiles were built for
+        auto launch = strips ? launch_horner_strip : launch_horner_fused;
+        void* nxt = (cur == state) ? wb : state;
         hipError_t e;
-        TimedLaunch tl(c, 5);
         if (K >= order) {
-            e = launch_horner_fused(c->prec, S, order, gf, cur, cur, nxt, step, order, c->stream);
+            TimedLaunch tl(c, 5);
+            e = launch(c->prec, S, order, gf, cur, cur, nxt, step, order, c->stream);
         } else {
-            e = launch_horner_fused(c->prec, S, K, gf, cur, cur, wa, step, order, c->stream);
-            if (e == hipSuccess)
-                e = launch_horner_fused(c->prec, S, order - K, gf, wa, cur, nxt, step, order - K, c->stream);
+            {
+                TimedLaunch tl(c, 5);
+                e = launch(c->prec, S, K, gf, cur, cur, wa, step, order, c->stream);
+            }
+            if (e == hipSuccess) {
+                TimedLaunch tl(c, 5);
+                e = launch(c->prec, S, order - K, gf, wa, cur, nxt, step, order - K, c->stream);
+            }
         }
         cur = nxt;
         return e;
     }
     // Horner: w = psi + (-i dt/P) H psi; w = psi + (-i dt/k) H w, k = P-1..1
+    void* free_bufs[2];
+    int nf = 0;
+    for (void* b : {state, wa, wb})
+        if (b != cur && nf < 2) free_bufs[nf++] = b;
     const SweepGeom g = c->hgeom();
-    const void* in = psi;
-    void* bufs[2] = {wa, wb};
-    int which = 0;
+    const void* psi = cur;
+    const void* in = cur;
+    void* out = nullptr;
     for (int k = order; k >= 1; --k) {
-        void* out = (k == 1 && order > 1) ? psi : bufs[which];
+        out = free_bufs[(order - k) & 1];
         hipError_t e;
         {
             TimedLaunch tl(c, 0);
@@ -848,9 +904,8 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
         }
         if (e != hipSuccess) return e;
         in = out;
-        which ^= 1;
     }
-    if (order == 1) return launch_copy(c->prec, c->geom(), wa, psi, c->stream);
+    cur = out;
     return hipSuccess;
 }
 
@@ -895,7 +950,7 @@ extern "C" tdse_status tdse_step_taylor(tdse_ctx* c, const tdse_pulse* pulses, c
     st = check_stable(c, pulses, dt, order);
     if (st != TDSE_OK) return st;
     void* cur = c->d_state;
-    const int64_t key = 1000 + 100 * c->fuse_k + order;
+    const int64_t key = 1000 + 100 * c->fuse_k + 20 * c->fuse_kind + order;
     return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, key, &cur,
                      [&](const double* step) { return taylor_step_launches(c, step, order, cur); });
 }
@@ -1109,7 +1164,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     void* backup = c->d_vec(2);
     void* ref = c->d_vec(3);
     double* acc = reinterpret_cast<double*>(c->d_work + c->off_obs_tmp);
-    const int keep_k = c->fuse_k, keep_rows = c->rows_fused;
+    const int keep_k = c->fuse_k, keep_rows = c->rows_fused, keep_kind = c->fuse_kind;
     const bool keep_timing = c->timing;
     c->timing = false;
     hipError_t e = launch_copy(c->prec, red, psi, backup, c->stream);
@@ -1131,20 +1186,25 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    struct Cand { int k, rows; };
-    std::vector<Cand> cands = {{0, 0}};
-    for (int K = (order + 1) / 2; K <= std::min(order, (int)kMaxFused); ++K)
-        for (int rows : {8, 16, 32}) cands.push_back({K, rows});
+    // kind 0: LDS-ring kernel, kind 1: wave-strip kernel
+    struct Cand { int k, rows, kind; };
+    std::vector<Cand> cands = {{0, 0, 0}};
+    for (int K = (order + 1) / 2; K <= std::min(order, (int)kMaxFused); ++K) {
+        for (int rows : {8, 16, 32}) cands.push_back({K, rows, 0});
+        for (int rows : {8, 16, 32, 64}) cands.push_back({K, rows, 1});
+    }
     double best_ms = 1e300;
-    Cand best = {0, keep_rows};
+    Cand best = {0, keep_rows, keep_kind};
     std::string bad;
     for (const Cand& cd : cands) {
         if (e != hipSuccess) break;
         c->fuse_k = cd.k;
+        c->fuse_kind = cd.kind;
         if (cd.k > 0) {
+            const int set = cd.kind ? kStripTiles : kFusedTiles;
             c->rows_fused = cd.rows;
-            build_tiles(c, kFusedTiles, cd.rows);
-            e = upload_tiles(c, kFusedTiles);
+            build_tiles(c, set, cd.rows);
+            e = upload_tiles(c, set);
         }
         // correctness against the reference step
         if (e == hipSuccess) e = one_step(&cur);
@@ -1157,7 +1217,8 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
         const double rel = std::sqrt(h_acc[0] / std::max(h_acc[1], 1e-300));
         const double tol = (c->prec == TDSE_FP64) ? 0.0 : 1e-6;
         if (!(rel <= tol)) {
-            bad += " K=" + std::to_string(cd.k) + "/rows=" + std::to_string(cd.rows) + ": " + std::to_string(rel);
+            bad += " K=" + std::to_string(cd.k) + "/rows=" + std::to_string(cd.rows) + "/kind=" +
+                   std::to_string(cd.kind) + ": " + std::to_string(rel);
             continue;
         }
         // timing: reps steps from the backed-up state
@@ -1181,9 +1242,12 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     // restore the state and the chosen configuration
     hipError_t e2 = launch_copy(c->prec, red, backup, psi, c->stream);
     c->fuse_k = (e == hipSuccess) ? best.k : keep_k;
+    c->fuse_kind = (e == hipSuccess) ? best.kind : keep_kind;
     c->rows_fused = (e == hipSuccess && best.k > 0) ? best.rows : keep_rows;
     build_tiles(c, kFusedTiles, c->rows_fused);
+    build_tiles(c, kStripTiles, c->rows_fused);
     if (e2 == hipSuccess) e2 = upload_tiles(c, kFusedTiles);
+    if (e2 == hipSuccess) e2 = upload_tiles(c, kStripTiles);
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
     c->timing = keep_timing;
     c->drop_graphs();
@@ -1197,24 +1261,26 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
 }
 
 extern "C" int32_t tdse_taylor_fusion(const tdse_ctx* c) { return c ? c->fuse_k : 0; }
+extern "C" int32_t tdse_taylor_fusion_kind(const tdse_ctx* c) { return c ? c->fuse_kind : 0; }
 
-extern "C" tdse_status tdse_set_taylor_fusion(tdse_ctx* c, int32_t k, int32_t rows)
+extern "C" tdse_status tdse_set_taylor_fusion(tdse_ctx* c, int32_t k, int32_t rows, int32_t kind)
 {
     if (!c) return TDSE_E_INVALID;
-    if (k < 0 || k > kMaxFused || (k > 0 && (rows < 1 || rows > 64)))
-        return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: k must be 0..8 and rows 1..64");
+    if (k < 0 || k > kMaxFused || (k > 0 && (rows < 1 || rows > 64)) || kind < 0 || kind > 1)
+        return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: k must be 0..8, rows 1..64, kind 0 or 1");
     if (c->bound) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "tdse_set_taylor_fusion sync");
     }
-    if (k > 0 && rows != c->rows_fused) {
-        // the fused tile region holds the row-1 count of the narrowest tiles
-        c->rows_fused = rows;
-    }
+    // the tile regions hold the row-1 count of the narrowest tiles of either kind
+    if (k > 0) c->rows_fused = rows;
     c->fuse_k = k;
+    c->fuse_kind = kind;
     build_tiles(c, kFusedTiles, c->rows_fused);
+    build_tiles(c, kStripTiles, c->rows_fused);
     if (c->bound) {
         hipError_t e = upload_tiles(c, kFusedTiles);
+        if (e == hipSuccess) e = upload_tiles(c, kStripTiles);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "tdse_set_taylor_fusion upload");
     }

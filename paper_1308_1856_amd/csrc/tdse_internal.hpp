@@ -16,9 +16,12 @@ constexpr int kMaxKrylov = 64;      // largest Lanczos dimension
 // population projections (rows l <= 4 only) and the fused Horner launches
 // (radially overlapping tiles, see k_horner_fused).
 // Tile sets: sweeps at 256 radii per tile (also RK4 stages), reductions,
-// populations, fused Horner terms, and sweeps at 512 radii per tile (two
-// radii per thread).
-enum TileSetId { kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kFusedTiles = 3, kPairTiles = 4, kNumTileSets = 5 };
+// populations, fused Horner terms (LDS rings), sweeps at 512 radii per tile
+// (two radii per thread), and fused Horner terms on wave strips.
+enum TileSetId {
+    kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kFusedTiles = 3, kPairTiles = 4, kStripTiles = 5,
+    kNumTileSets = 6
+};
 constexpr int kMaxFused = 8;        // most Horner terms per fused launch
 
 // One instance (grid) as the per-instance kernels see it.
@@ -86,7 +89,7 @@ __host__ __device__ inline double step_value(const double* st, int n_inst, int s
 
 // out = H(E_mid) in                              (term == 0)
 // out = psi + (-i dt / term) H(E_mid) in         (term >= 1: one Horner term)
-// `in` must not overlap `out`; `out` may equal `psi`.
+// `out` must not overlap `in` or `psi` (`in` may equal `psi`).
 hipError_t launch_hsweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi,
                          void* out, const double* step, int term, hipStream_t st);
 
@@ -96,6 +99,13 @@ hipError_t launch_hsweep(int prec, int S, const SweepGeom& g, const void* in, co
 hipError_t launch_horner_fused(int prec, int S, int K, const SweepGeom& g, const void* in,
                                const void* psi, void* out, const double* step, int first_term,
                                hipStream_t st);
+// The same K terms on the wave-strip tile set built for Kt >= K terms
+// (g.variant = Kt; tiles of 4 strips of 64 - 2 Kt s output radii); same
+// aliasing rules.
+hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const void* in,
+                               const void* psi, void* out, const double* step, int first_term,
+                               hipStream_t st);
+constexpr int kStripWaves = kBlock / 64;   // strips per strip tile
 
 // RK4 stage s (0..3); see the kernel for the buffer roles.
 hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, const void* gin,

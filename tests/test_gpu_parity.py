@@ -333,18 +333,21 @@ def test_autotune_keeps_results_bitwise(tmp_path, monkeypatch):
     prop2.close()
 
 
-@pytest.mark.parametrize("stencil,k,rows", [(5, 8, 4), (5, 4, 16), (3, 5, 3), (3, 8, 32)])
-def test_fused_taylor_bitwise_equal_to_per_term(stencil, k, rows):
-    # K Horner terms per launch compute every element with the same FP64
-    # expression as one launch per term: identical bits, and the oracle's 1e-12
+@pytest.mark.parametrize("stencil,k,rows,kind", [(5, 8, 4, 0), (5, 4, 16, 0), (3, 5, 3, 0), (3, 8, 32, 0),
+                                                 (5, 8, 4, 1), (5, 4, 16, 1), (3, 5, 3, 1), (3, 8, 64, 1),
+                                                 (3, 6, 1, 1), (5, 7, 9, 1)])
+def test_fused_taylor_bitwise_equal_to_per_term(stencil, k, rows, kind):
+    # K Horner terms per launch (either fused kernel) compute every element
+    # with the same FP64 expression as one launch per term: identical bits,
+    # and the oracle's 1e-12
     t = lib()
     grid = t.Grid(700, 9, 0.1, stencil, t.FP64, 1.0, 12.0)
     pulse = t.Pulse(0.06, 0.35, 2.0, 0.2, 0.0)
-    say(f"fused Taylor-8, K={k}, rows={rows}, stencil={stencil} vs per-term and oracle")
+    say(f"fused Taylor-8, K={k}, rows={rows}, stencil={stencil}, kind={kind} vs per-term and oracle")
     res = []
     for fuse in (0, k):
         prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),))
-        prop.set_taylor_fusion(fuse, rows)
+        prop.set_taylor_fusion(fuse, rows, kind)
         prop.set_state(0, None)
         obs = prop.obs_buffer(31, 10)
         prop.step_taylor(pulse, 0.0, 4e-4, 8, 31, 10, obs)       # odd count: ends on the scratch side
@@ -359,15 +362,16 @@ def test_fused_taylor_bitwise_equal_to_per_term(stencil, k, rows):
     assert rel_err(res[1][0], ref) < TOL64
 
 
-def test_fused_taylor_fp32_and_graphs():
+@pytest.mark.parametrize("kind", [0, 1])
+def test_fused_taylor_fp32_and_graphs(kind):
     t = lib()
     grid = t.Grid(600, 8, 0.1, 3, t.FP32, 1.0, 5.0)
     pulse = t.Pulse(0.1, 0.5, 2.0, 0.0, 0.0)
-    say("fused Taylor-8 (K=8) with FP32 storage and graph replay")
+    say(f"fused Taylor-8 (K=8, kind {kind}) with FP32 storage and graph replay")
     out = {}
     for fuse, graphs in ((0, False), (8, False), (8, True)):
         prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),), graphs=graphs)
-        prop.set_taylor_fusion(fuse, 16)
+        prop.set_taylor_fusion(fuse, 16, kind)
         prop.set_state(0, None)
         states = []
         for call in range(2):
@@ -395,9 +399,10 @@ def test_autotune_taylor_choice_is_consistent():
     prop.set_state(0, None)
     before = prop.get_state(0)
     k, rows = prop.autotune_taylor(8)
-    say(f"autotune_taylor: K={k} rows={rows}")
+    say(f"autotune_taylor: K={k} rows={rows} kind={prop.taylor_fusion_kind}")
     assert np.array_equal(prop.get_state(0), before)           # state restored
     assert k == 0 or 4 <= k <= 8
+    assert prop.taylor_fusion_kind in (0, 1)
     prop.step_taylor(pulse, 5.0, dt, 8, 12)
     tuned = prop.get_state(0)
     prop.set_taylor_fusion(0, 16)
@@ -405,3 +410,28 @@ def test_autotune_taylor_choice_is_consistent():
     prop.step_taylor(pulse, 5.0, dt, 8, 12)
     assert np.array_equal(prop.get_state(0), tuned)
     prop.close()
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_fused_taylor_batch_bitwise(kind):
+    # uneven instances in one launch: each fused kernel matches the per-term
+    # path bit for bit on every instance (FP64)
+    t = lib()
+    grids = [t.Grid(n, lmax, 0.1, 3, t.FP64, 1.0, 0.25 * n * 0.1)
+             for n, lmax in ((1500, 12), (333, 3), (2047, 21))]
+    pulses = [t.Pulse(0.05, 0.3, 2.0, 0.0, 0.0), t.Pulse(0.02, 0.1, 3.0, 0.5, 0.0),
+              t.Pulse(0.08, 0.2, 2.0, -1.0, 0.0)]
+    say(f"batch of 3, Taylor-8, fused kind {kind} (K=4, rows 8) vs per-term")
+    res = []
+    for fuse in (0, 4):
+        prop = t.Propagator(grids, methods=((t.METHOD_TAYLOR, 8),))
+        y = t.tdse_taylor_stability_limit(8)
+        dts = [0.8 * y / prop.lambda_max_bound(k, abs(p.e0)) for k, p in enumerate(pulses)]
+        prop.set_taylor_fusion(fuse, 8, kind)
+        for k in range(3):
+            prop.set_state(k, None)
+        prop.step_taylor(pulses, [1.0] * 3, dts, 8, 17)
+        res.append([prop.get_state(k) for k in range(3)])
+        prop.close()
+    for k in range(3):
+        assert np.array_equal(res[0][k], res[1][k]), k
