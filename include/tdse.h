@@ -212,8 +212,8 @@ double tdse_taylor_stability_limit(int32_t order);
 tdse_status tdse_autotune(tdse_ctx* ctx, int32_t* rows_out);
 /* Autotuner for the Taylor step of order `order` (1..16): times whole steps
  * of the bound state (field-free, stable dt) with one launch per Horner term
- * (the sweep tiles in use) and with K = ceil(order/2)..min(order, 8) terms
- * per fused launch, for both fused kernels (kind 0: workgroup tiles of 256
+ * (the sweep tiles in use) and with K = 2..min(order, 8) terms per fused
+ * launch (ceil(order/K) launches per step), for both fused kernels (kind 0: workgroup tiles of 256
  * radii with the intermediate levels in LDS rings, 8, 16 or 32 rows; kind 1:
  * independent 64-radius wave strips with the intermediate levels in
  * registers, 8, 16, 32 or 64 rows), verifies each candidate's step against
@@ -227,8 +227,8 @@ tdse_status tdse_autotune_taylor(tdse_ctx* ctx, int32_t order, int32_t* fuse_k_o
 /* Horner terms per fused Taylor launch in use (0: one launch per term), the
  * fused kernel in use (0 LDS rings, 1 wave strips), and an explicit choice:
  * k = 0 (one launch per term) or 1..8 terms per fused launch of kernel
- * `kind` on tiles of `rows` rows (1..64).  The fused path is used by
- * tdse_step_taylor when 2k >= order (at most two launches per step).
+ * `kind` on tiles of `rows` rows (1..64); tdse_step_taylor then makes
+ * ceil(order/k) launches per step, the last one with the remaining terms.
  * Synchronises. */
 int32_t tdse_taylor_fusion(const tdse_ctx* ctx);
 int32_t tdse_taylor_fusion_kind(const tdse_ctx* ctx);

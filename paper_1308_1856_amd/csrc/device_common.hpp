@@ -104,10 +104,11 @@ __device__ __forceinline__ RadialPoint radial_point(const Tile& I, int i)
     return p;
 }
 
-// Diagonal potential of row l: l(l+1)/(2 r^2) - Z/r.
+// Diagonal potential of row l: l(l+1)/(2 r^2) - Z/r.  l(l+1)/2 is formed in
+// integers (exact; scalar unit when l is wave-uniform) and converted once.
 __device__ __forceinline__ double row_potential(int l, double inv_r2, double z_over_r)
 {
-    return fma(0.5 * (double)l * (double)(l + 1), inv_r2, -z_over_r);
+    return fma((double)((l * (l + 1)) >> 1), inv_r2, -z_over_r);
 }
 
 // (H f)_{l,i} from the centre value, its radial neighbours (already zero

@@ -11,7 +11,7 @@
 // them: every level needs its radial neighbours (lane +- 1, +- 2 by
 // shuffles), so the lanes whose values are exact shrink by s per side and
 // level.  Adjacent strips overlap by 2 Kt s radii; each output radius is
-// written by exactly one strip.  Along l, level k runs one row behind level k-1 within an iteration:
+// written by exactly one strip.  The shuffles are DPP whole-wave shifts.  Along l, level k runs one row behind level k-1 within an iteration:
 //   rho_k(it) = l0 - K + 2 - k + it,   it = 0 .. (l1 - l0) + 2K - 3,
 // so level k at row rho needs level k-1 at rows rho-1 (two iterations ago),
 // rho (one iteration ago) and rho+1 (this iteration): each level keeps its
@@ -27,6 +27,8 @@
 // [0, N) are zero at every level, as in the single-term sweep.  HBM traffic
 // per unknown and launch: read `in` and psi once (plus the row and radial
 // overlaps), write out once.  `out` must not alias `in` or `psi`.
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace tdse {
@@ -40,13 +42,130 @@ __device__ __forceinline__ double2 pick2(bool c, double2 a, double2 b)
 {
     return make_double2(c ? a.x : b.x, c ? a.y : b.y);
 }
+// Radial neighbours across the wave by DPP whole-wave shifts (a VALU move,
+// no LDS round trip): wave_shr:1 gives lane i the value of lane i-1,
+// wave_shl:1 the value of lane i+1.  The end lanes receive 0; they are outside
+// the strip's exact region anyway.
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ double2 dpp_shift2(double2 v)
+{
+    return make_double2(dpp_shift<CTRL>(v.x), dpp_shift<CTRL>(v.y));
+}
+// value of lane - d / lane + d (d = 1 or 2)
 __device__ __forceinline__ double2 lane_below(double2 v, int d)
 {
-    return make_double2(__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64));
+    v = dpp_shift2<kDppWaveShr1>(v);
+    return d == 2 ? dpp_shift2<kDppWaveShr1>(v) : v;
 }
 __device__ __forceinline__ double2 lane_above(double2 v, int d)
 {
-    return make_double2(__shfl_down(v.x, d, 64), __shfl_down(v.y, d, 64));
+    v = dpp_shift2<kDppWaveShl1>(v);
+    return d == 2 ? dpp_shift2<kDppWaveShl1>(v) : v;
+}
+
+// The strip loop.  MASKED: some lanes of this wave lie outside [0, N) and
+// their values are forced to zero at every level; waves wholly inside skip
+// those selects.  Rows outside [0, lmax] cost no vector work: their input and
+// psi values are read from the all-zero row (a wave-uniform pointer choice),
+// and their l couplings are zero, so every level is exactly +0 there, as the
+// single-term sweep's zero padding in l.  For the valid rows the coupling
+// coefficients are the sweep's (kappa_{lmax+1} multiplies the zero row above
+// lmax in the sweep; zero here gives the same bits).
+template <int S, typename T, int K, bool MASKED>
+__device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, const typename Cplx<T>::type* in_i,
+                                           const typename Cplx<T>::type* psi_i, typename Cplx<T>::type* out_i,
+                                           int jc, bool inside, bool writes, double er, double inv_r2,
+                                           double z_over_r, const double (&coef)[K])
+{
+    using C = typename Cplx<T>::type;
+    const int n = I.n, lmax = I.lmax;
+    const C* zrow = static_cast<const C*>(g.zero_row);
+    auto rowp = [&](const C* base, int rr) -> const C* {
+        return (rr >= 0 && rr <= lmax) ? base + (int64_t)rr * n : zrow;
+    };
+    auto widen_lane = [&](C raw) -> double2 {
+        const double2 v = widen(raw);
+        return MASKED ? pick2(inside, v, zero2()) : v;
+    };
+    // H at row rr of the level below: centre c, rows rr-1 / rr+1 at this radius
+    auto h_row = [&](double2 c, double2 lm, double2 lp, int rr) -> double2 {
+        const double2 m1 = lane_below(c, 1), p1 = lane_above(c, 1);
+        double2 m2 = zero2(), p2 = zero2();
+        if (S == 2) {
+            m2 = lane_below(c, 2);
+            p2 = lane_above(c, 2);
+        }
+        const double kl = (rr >= 1 && rr <= lmax) ? g.kappa[rr] : 0.0;
+        const double klp = (rr >= 0 && rr < lmax) ? g.kappa[rr + 1] : 0.0;
+        return h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2, row_potential(rr, inv_r2, z_over_r), er, kl, klp);
+    };
+
+    const int rho0 = I.l0 - K + 1;              // level-1 row at it = 0
+    // input rows rho-1, rho (FP64) and rho+1 (raw, in flight) of the current iteration
+    double2 xm = widen_lane(rowp(in_i, rho0 - 1)[jc]);
+    double2 xc = widen_lane(rowp(in_i, rho0)[jc]);
+    C x_p = rowp(in_i, rho0 + 1)[jc];
+    // psi(rho_k) for level k = 1..K: pr[k-1]; pr[0] arrives one iteration ahead
+    C pr[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) pr[k] = zero_c<C>();
+    pr[0] = rowp(psi_i, rho0)[jc];
+    // level k (1..K-1): a = row rho_k - 1, b = row rho_k - 2 (FP64)
+    double2 ra[K > 1 ? K - 1 : 1], rb[K > 1 ? K - 1 : 1];
+#pragma unroll
+    for (int k = 0; k < (K > 1 ? K - 1 : 1); ++k) ra[k] = rb[k] = zero2();
+
+    // one iteration; CHECK: some levels may not have reached their first row yet
+    auto body = [&](int it, auto check) {
+        constexpr bool CHECK = decltype(check)::value;
+        const int rho = rho0 + it;
+        // prefetch for the next iteration
+        const C x_n = rowp(in_i, rho + 2)[jc];
+        const C p_n = rowp(psi_i, rho + 1)[jc];
+        const double2 xp = widen_lane(x_p);
+
+        // level 1 from the input
+        double2 up = horner_update(widen(pr[0]), h_row(xc, xm, xp, rho), coef[0]);
+        if (MASKED) up = pick2(inside, up, zero2());
+        if (K == 1 && writes && rho >= I.l0 && rho < I.l1) stc(out_i, (int64_t)rho * n + jc, up);
+        // levels 2..K from the registers of the level below
+#pragma unroll
+        for (int k = 2; k <= K; ++k) {
+            const int rk = rho - (k - 1);
+            double2 v = zero2();
+            if (!CHECK || it >= 2 * (k - 1)) {
+                // level k-1 at rows rk (ra), rk - 1 (rb) and rk + 1 (this iteration)
+                v = horner_update(widen(pr[k - 1]), h_row(ra[k - 2], rb[k - 2], up, rk), coef[k - 1]);
+                if (MASKED) v = pick2(inside, v, zero2());
+            }
+            rb[k - 2] = ra[k - 2];
+            ra[k - 2] = up;
+            up = v;
+            if (k == K && writes && rk >= I.l0 && rk < I.l1) stc(out_i, (int64_t)rk * n + jc, v);
+        }
+        // shift the window and the psi register
+        xm = xc;
+        xc = xp;
+        x_p = x_n;
+#pragma unroll
+        for (int k = K - 1; k > 0; --k) pr[k] = pr[k - 1];
+        pr[0] = p_n;
+    };
+    const int iters = (I.l1 - I.l0) + 2 * K - 2;
+    const int warm = min(2 * (K - 1), iters);
+    int it = 0;
+    for (; it < warm; ++it) body(it, std::true_type{});
+    for (; it < iters; ++it) body(it, std::false_type{});
 }
 
 template <int S, typename T, int K>
@@ -55,16 +174,16 @@ k_horner_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
                const typename Cplx<T>::type* __restrict__ psi, typename Cplx<T>::type* __restrict__ out,
                const double* __restrict__ step, int first_term)
 {
-    using C = typename Cplx<T>::type;
     const int halo = g.variant * S;             // >= K * S: lanes lost per side after K levels
     const int valid = 64 - 2 * halo;            // output radii per wave
     const Tile I = my_tile(g);
-    const int n = I.n, lmax = I.lmax;
+    const int n = I.n;
     const int lane = (int)threadIdx.x & 63;
     const int wave = (int)threadIdx.x >> 6;
-    const int j = I.r0 + wave * valid - halo + lane;    // this lane's radius
+    const int j0 = I.r0 + wave * valid - halo;  // radius of lane 0
+    const int j = j0 + lane;                    // this lane's radius
     const bool inside = j >= 0 && j < n;
-    const int jc = min(max(j, 0), n - 1);               // clamped: every load is in bounds
+    const int jc = min(max(j, 0), n - 1);       // clamped: every load is in bounds
     const bool writes = inside && lane >= halo && lane < 64 - halo;
 
     const double r = (double)(jc + 1) * I.dr;
@@ -77,92 +196,13 @@ k_horner_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
 #pragma unroll
     for (int k = 0; k < K; ++k) coef[k] = wave_uniform(dt / (double)(first_term - k));
 
-    const C* in_i = in + I.off;
-    const C* psi_i = psi + I.off;
-    C* out_i = out + I.off;
-    auto row_of = [&](int rr) -> int64_t { return (int64_t)min(max(rr, 0), lmax) * n + jc; };
-
-    const int rho0 = I.l0 - K + 1;              // level-1 row at it = 0
-    // input rows rho-1, rho, rho+1 of the current iteration (raw), prefetched rho+2
-    C x_m = in_i[row_of(rho0 - 1)];
-    C x_c = in_i[row_of(rho0)];
-    C x_p = in_i[row_of(rho0 + 1)];
-    // psi(rho_k) for level k = 1..K: pr[k-1]; pr[0] arrives one iteration ahead
-    C pr[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) pr[k] = zero_c<C>();
-    pr[0] = psi_i[row_of(rho0)];
-    // level k (1..K-1): a = row rho_k - 1, b = row rho_k - 2 (FP64)
-    double2 ra[K > 1 ? K - 1 : 1], rb[K > 1 ? K - 1 : 1];
-#pragma unroll
-    for (int k = 0; k < (K > 1 ? K - 1 : 1); ++k) ra[k] = rb[k] = zero2();
-
-    const int iters = (I.l1 - I.l0) + 2 * K - 2;
-    for (int it = 0; it < iters; ++it) {
-        const int rho = rho0 + it;
-        // prefetch for the next iteration (clamped rows; zeroed at use)
-        const C x_n = in_i[row_of(rho + 2)];
-        const C p_n = psi_i[row_of(rho + 1)];
-
-        // ---- level 1 from the input ----------------------------------------
-        double2 up;   // the newest level value, passed to the next level as its row rho_k + 1
-        {
-            const bool ok_c = inside && rho >= 0 && rho <= lmax;
-            const double2 c = pick2(ok_c, widen(x_c), zero2());
-            const double2 lm = pick2(inside && rho - 1 >= 0 && rho - 1 <= lmax, widen(x_m), zero2());
-            const double2 lp = pick2(inside && rho + 1 >= 0 && rho + 1 <= lmax, widen(x_p), zero2());
-            const double2 m1 = lane_below(c, 1), p1 = lane_above(c, 1);
-            double2 m2 = zero2(), p2 = zero2();
-            if (S == 2) {
-                m2 = lane_below(c, 2);
-                p2 = lane_above(c, 2);
-            }
-            const int rk = min(max(rho, 0), lmax);
-            const double2 h = h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2,
-                                         row_potential(rk, inv_r2, z_over_r), er, g.kappa[rk],
-                                         g.kappa[rk + 1]);
-            const double2 v = horner_update(widen(pr[0]), h, coef[0]);
-            up = pick2(ok_c, v, zero2());
-        }
-        if (K == 1) {
-            if (writes && rho >= I.l0 && rho < I.l1) stc(out_i, (int64_t)rho * n + jc, up);
-        }
-        // ---- levels 2..K from the registers of the level below -------------
-#pragma unroll
-        for (int k = 2; k <= K; ++k) {
-            const int rk_row = rho - (k - 1);
-            double2 v = zero2();
-            if (it >= 2 * (k - 1)) {
-                const bool ok = inside && rk_row >= 0 && rk_row <= lmax;
-                const double2 c = ra[k - 2];              // level k-1 at row rk_row
-                const double2 lm = rb[k - 2];             // level k-1 at row rk_row - 1
-                const double2 lp = up;                    // level k-1 at row rk_row + 1
-                const double2 m1 = lane_below(c, 1), p1 = lane_above(c, 1);
-                double2 m2 = zero2(), p2 = zero2();
-                if (S == 2) {
-                    m2 = lane_below(c, 2);
-                    p2 = lane_above(c, 2);
-                }
-                const int rk = min(max(rk_row, 0), lmax);
-                const double2 h = h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2,
-                                             row_potential(rk, inv_r2, z_over_r), er, g.kappa[rk],
-                                             g.kappa[rk + 1]);
-                v = pick2(ok, horner_update(widen(pr[k - 1]), h, coef[k - 1]), zero2());
-            }
-            // the level below moves on by one row
-            rb[k - 2] = ra[k - 2];
-            ra[k - 2] = up;
-            up = v;
-            if (k == K && writes && rk_row >= I.l0 && rk_row < I.l1) stc(out_i, (int64_t)rk_row * n + jc, v);
-        }
-        // shift the window and the psi register
-        x_m = x_c;
-        x_c = x_p;
-        x_p = x_n;
-#pragma unroll
-        for (int k = K - 1; k > 0; --k) pr[k] = pr[k - 1];
-        pr[0] = p_n;
-    }
+    const auto* in_i = in + I.off;
+    const auto* psi_i = psi + I.off;
+    auto* out_i = out + I.off;
+    if (j0 >= 0 && j0 + 63 < n)   // wave-uniform
+        strip_loop<S, T, K, false>(g, I, in_i, psi_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, coef);
+    else
+        strip_loop<S, T, K, true>(g, I, in_i, psi_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, coef);
 }
 
 template <int S, typename T, int K>

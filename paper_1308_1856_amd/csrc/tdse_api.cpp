@@ -61,7 +61,8 @@ struct tdse_ctx {
     hipStream_t stream = nullptr;
     // workspace layout (bytes from d_work)
     size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0, 0, 0, 0}, off_kappa = 0, off_radial = 0,
-           off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0;
+           off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0,
+           off_zero = 0, zero_bytes = 0;
     size_t partial_doubles = 0;
     // pinned staging for the per-step scalars (double buffered)
     double* h_step[2] = {nullptr, nullptr};
@@ -78,6 +79,9 @@ struct tdse_ctx {
         graphs.clear();
         graph_end_psi.clear();
     }
+    // Gershgorin bounds already computed, keyed by (instance, |E|): the bound
+    // costs one pass over the grid, too much to repeat on every step call
+    mutable std::map<std::pair<int, double>, double> bound_cache;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -97,6 +101,7 @@ struct tdse_ctx {
     SweepGeom geom(int set = kSweepTiles) const
     {
         SweepGeom g;
+        g.zero_row = d_work + off_zero;
         g.inst = reinterpret_cast<const Inst*>(d_work + off_inst);
         g.tiles = reinterpret_cast<const Tile*>(d_work + off_tiles[set]);
         g.kappa = reinterpret_cast<const double*>(d_work + off_kappa);
@@ -220,6 +225,16 @@ static double gershgorin_bound(const tdse_grid_desc& g, double e_max)
         }
     }
     return best;
+}
+
+static double cached_bound(const tdse_ctx* c, int k, double e_max)
+{
+    const std::pair<int, double> key(k, std::fabs(e_max));
+    auto it = c->bound_cache.find(key);
+    if (it != c->bound_cache.end()) return it->second;
+    const double b = gershgorin_bound(c->grids[k], key.second);
+    c->bound_cache.emplace(key, b);
+    return b;
 }
 
 static int states_for(int lmax)
@@ -516,6 +531,12 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         c->off_tiles[set] = take(sizeof(Tile) * cap);
     }
     c->off_kappa = take(sizeof(double) * c->kappa.size());
+    // one all-zero row (the longest N, FP64 complex): the strip kernel reads
+    // rows outside [0, lmax] from it
+    int max_n = 0;
+    for (const tdse_grid_desc& g : c->grids) max_n = std::max(max_n, g.n_r);
+    c->zero_bytes = (size_t)max_n * 16;
+    c->off_zero = take(c->zero_bytes);
     c->off_radial = take(sizeof(double) * c->radial.size());
     c->off_step = take(sizeof(double) * kSlots * (size_t)n_inst * kEtabSteps);
     c->off_obs_tmp = take(sizeof(tdse_obs) * n_inst);
@@ -564,7 +585,7 @@ extern "C" size_t tdse_workspace_bytes(const tdse_ctx* c, int32_t method, int32_
 extern "C" double tdse_lambda_max_bound(const tdse_ctx* c, int32_t k, double e_max)
 {
     if (!c || k < 0 || k >= c->n_inst) return -1.0;
-    return gershgorin_bound(c->grids[k], e_max);
+    return cached_bound(c, k, e_max);
 }
 
 // ---------------------------------------------------------------------------
@@ -612,7 +633,9 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         hipError_t e = hipMemcpyAsync(c->d_work + u.off, u.src, u.bytes, hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "tdse_bind upload");
     }
-    hipError_t e = hipStreamSynchronize(c->stream);
+    hipError_t e = hipMemsetAsync(c->d_work + c->off_zero, 0, c->zero_bytes, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_bind zero row");
+    e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "tdse_bind sync");
     c->bound = true;
     return TDSE_OK;
@@ -743,7 +766,7 @@ tdse_status check_stable(tdse_ctx* c, const tdse_pulse* pulses, const double* dt
 {
     const double y = tdse_taylor_stability_limit(order);
     for (int k = 0; k < c->n_inst; ++k) {
-        const double lam = gershgorin_bound(c->grids[k], std::fabs(pulses[k].e0));
+        const double lam = cached_bound(c, k, pulses[k].e0);
         if (dt[k] * lam > y) {
             char buf[256];
             std::snprintf(buf, sizeof buf,
@@ -848,53 +871,46 @@ tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, c
 }
 
 // One Taylor step of order `order` (Horner form) on the psi held in `cur`.
-// psi rotates through three buffers (the state and work vectors 0 and 1);
-// no launch ever writes a buffer it reads, and `cur` moves to the buffer that
-// holds the new psi (run_steps copies it back into the state at the end).
-// Per-term path (fuse_k = 0): one sweep per term, alternating between the two
-// buffers that do not hold psi; the last term's output is the new psi.
-// Fused path (2 fuse_k >= order): at most two fused launches (LDS-ring or
-// wave-strip kernel); psi ping-pongs between the state and work vector 1, and
-// the first launch's output (if there are two) goes to work vector 0.
+// psi rotates through three buffers (the state and work vectors 0 and 1):
+// launches alternate between the two buffers that do not hold psi, no launch
+// writes a buffer it reads, and `cur` moves to the buffer that holds the new
+// psi (run_steps copies it back into the state at the end).  With fuse_k = 0
+// each Horner term is one sweep; with fuse_k = K each launch of the fused
+// kernel (LDS-ring or wave-strip) does K terms (the last one the remainder).
 hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void*& cur)
 {
     const int S = c->stencil == 3 ? 1 : 2;
-    void* state = c->d_state;
-    void* wa = c->d_vec(0);
-    void* wb = c->d_vec(1);
+    void* free_bufs[2];
+    int nf = 0;
+    for (void* b : {static_cast<void*>(c->d_state), static_cast<void*>(c->d_vec(0)), static_cast<void*>(c->d_vec(1))})
+        if (b != cur && nf < 2) free_bufs[nf++] = b;
+    const void* psi = cur;
+    const void* in = cur;
+    void* out = nullptr;
     const int K = c->fuse_k;
-    if (K > 0 && 2 * K >= order) {
+    if (K > 0) {
         const bool strips = c->fuse_kind == 1;
         SweepGeom gf = c->geom(strips ? kStripTiles : kFusedTiles);
         if (strips) gf.variant = K;   // the term count the strip tiles were built for
         auto launch = strips ? launch_horner_strip : launch_horner_fused;
-        void* nxt = (cur == state) ? wb : state;
-        hipError_t e;
-        if (K >= order) {
-            TimedLaunch tl(c, 5);
-            e = launch(c->prec, S, order, gf, cur, cur, nxt, step, order, c->stream);
-        } else {
+        int which = 0;
+        for (int first = order; first >= 1; first -= K) {
+            const int terms = std::min(K, first);
+            out = free_bufs[which];
+            hipError_t e;
             {
                 TimedLaunch tl(c, 5);
-                e = launch(c->prec, S, K, gf, cur, cur, wa, step, order, c->stream);
+                e = launch(c->prec, S, terms, gf, in, psi, out, step, first, c->stream);
             }
-            if (e == hipSuccess) {
-                TimedLaunch tl(c, 5);
-                e = launch(c->prec, S, order - K, gf, wa, cur, nxt, step, order - K, c->stream);
-            }
+            if (e != hipSuccess) return e;
+            in = out;
+            which ^= 1;
         }
-        cur = nxt;
-        return e;
+        cur = out;
+        return hipSuccess;
     }
     // Horner: w = psi + (-i dt/P) H psi; w = psi + (-i dt/k) H w, k = P-1..1
-    void* free_bufs[2];
-    int nf = 0;
-    for (void* b : {state, wa, wb})
-        if (b != cur && nf < 2) free_bufs[nf++] = b;
     const SweepGeom g = c->hgeom();
-    const void* psi = cur;
-    const void* in = cur;
-    void* out = nullptr;
     for (int k = order; k >= 1; --k) {
         out = free_bufs[(order - k) & 1];
         hipError_t e;
@@ -1155,7 +1171,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     std::vector<double> t0(c->n_inst, 0.0), dt(c->n_inst);
     for (int k = 0; k < c->n_inst; ++k) {
         pulses[k] = tdse_pulse{0.05, 1.0, 1.0, 0.0, -1.0};
-        dt[k] = 0.5 * y / gershgorin_bound(c->grids[k], 0.05);
+        dt[k] = 0.5 * y / cached_bound(c, k, 0.05);
     }
     tdse_status st = upload_steps(c, pulses.data(), t0.data(), dt.data(), 0, 1, 0);
     if (st != TDSE_OK) return st;
@@ -1189,7 +1205,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     // kind 0: LDS-ring kernel, kind 1: wave-strip kernel
     struct Cand { int k, rows, kind; };
     std::vector<Cand> cands = {{0, 0, 0}};
-    for (int K = (order + 1) / 2; K <= std::min(order, (int)kMaxFused); ++K) {
+    for (int K = 2; K <= std::min(order, (int)kMaxFused); ++K) {
         for (int rows : {8, 16, 32}) cands.push_back({K, rows, 0});
         for (int rows : {8, 16, 32, 64}) cands.push_back({K, rows, 1});
     }

@@ -77,6 +77,7 @@ struct SweepGeom {
     int32_t set;           // TileSetId of `tiles`
     int32_t variant;       // H sweep: 0 one radius per thread, 1 two radii per thread
     int32_t order;         // block -> tile map: 0 identity, 1 XCD-contiguous runs
+    const void* zero_row;  // device zeros, at least max N complex FP64 values
 };
 
 // Per-step scalars, FP64, laid out [slot][instance] with these slots:
