@@ -372,7 +372,7 @@ static int tune_cache_lookup(const tdse_ctx* c, int* variant)
     char kbuf[128];
     int rows = 0, var = 0, found = 0;
     while (std::fscanf(f, "%127s %d %d", kbuf, &rows, &var) == 3) {
-        if (key == kbuf && rows >= 1 && rows <= kTileRows && (var == 0 || var == 1)) {
+        if (key == kbuf && rows >= 1 && rows <= kTileRows && var >= 0 && var <= 3) {
             found = rows;  // last entry wins
             *variant = var;
         }
