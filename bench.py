@@ -3,15 +3,24 @@
 
 One step = one Taylor-8 time step of the FP64 single-instance workload
 (N = 20000, dr = 0.05, lmax = 64, 5-point stencil): the field at the step
-midpoint, eight fused Horner sweeps of H(t).psi and the FP64 observables
-(norm, p_g, the 15 populations n <= 5, p_ion, dipole, dipole acceleration)
-after every step.  `value` is H.psi applications per second (8 per step).
+midpoint, eight Horner terms of H(t).psi and the FP64 observables (norm,
+p_g, the 15 populations n <= 5, p_ion, dipole, dipole acceleration) after
+every step.  `value` is H.psi applications per second (8 per step).  The
+execution shape (sweep tiles; one launch per Horner term or K terms per
+fused launch, and which fused kernel) is chosen by the library's autotuners
+before the timed region (--autotune 2, the default).
 
 Also reported on the same line:
-  roofline      the Horner-term kernel: algorithmic bytes per launch (read
-                w, read psi, write w: 3 x 16 B per unknown) over its mean
-                duration from HIP events on the library's stream, against
-                the 8 TB/s HBM peak;
+  roofline      the dominant kernel of the step (the Horner-term sweep, or
+                the fused K-term kernel): algorithmic bytes per launch (read
+                the input vector, read psi, write the output: 3 x c B per
+                unknown, c = 16 B FP64 / 8 B FP32) over its mean duration
+                from HIP events on the library's stream, against the 8 TB/s
+                HBM peak; `traffic` comes from the committed rocprofv3
+                counter summary for the same kernel and shape (null if there
+                is none, or if the kernel source changed since);
+  hpsi_sweep    the plain H.psi apply (tdse_apply_H: read psi, write H psi,
+                2c B per unknown) on the same grid, same report;
   fp32_mixed    the same workload with FP32 storage and FP64 arithmetic and
                 reductions: steps/s, speedup over FP64, and its error against
                 the FP64 GPU run;
@@ -50,9 +59,27 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", type=int, default=1, help="replay step chunks as HIP graphs")
-    ap.add_argument("--autotune", type=int, default=1,
-                    help="1: autotune the sweep tiles; 2: also choose the Taylor fusion depth")
+    ap.add_argument("--autotune", type=int, default=2,
+                    help="0: fixed shapes; 1: autotune the sweep tiles; 2: also choose the Taylor fusion")
+    ap.add_argument("--sweep", default=None, metavar="ROWS,VARIANT",
+                    help="fixed sweep tile shape instead of the sweep autotuner (profiling runs)")
+    ap.add_argument("--fusion", default=None, metavar="K,ROWS,KIND",
+                    help="fixed Taylor fusion instead of the Taylor autotuner (profiling runs)")
     return ap.parse_args()
+
+
+def apply_shape(prop, args, autotune, order):
+    """Execution shape: explicit (--sweep / --fusion) or from the autotuners."""
+    if args.sweep:
+        rows, variant = (int(x) for x in args.sweep.split(","))
+        prop.set_sweep_shape(rows, variant)
+    elif autotune:
+        prop.autotune()
+    if args.fusion:
+        k, rows, kind = (int(x) for x in args.fusion.split(","))
+        prop.set_taylor_fusion(k, rows, kind)
+    elif autotune > 1 and order:
+        prop.autotune_taylor(order)
 
 
 def log(msg):
@@ -63,10 +90,7 @@ def make_prop(tdse, wl, precision, method_code, graphs=True, autotune=True):
     g = tdse.Grid(wl.n, wl.lmax, wl.dr, wl.stencil, precision, wl.z, wl.r_ion)
     methods = ((method_code, wl.order), (tdse.METHOD_TAYLOR, 2), (tdse.METHOD_TUNE, 0))
     prop = tdse.Propagator([g], methods=methods, graphs=bool(graphs))
-    if autotune:
-        prop.autotune()
-        if wl.method == "taylor" and autotune > 1:
-            prop.autotune_taylor(wl.order)
+    apply_shape(prop, ARGS, autotune, wl.order if wl.method == "taylor" else 0)
     prop.set_state(0, None)
     return prop
 
@@ -108,6 +132,75 @@ def timed(prop, tdse, wl, torch, steps, warmup, kernel, graphs):
     return wall, launches, kms, obs
 
 
+def source_digest(name):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1308_1856_amd", "csrc", name)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+KERNEL_SOURCE = {"taylor_term": "k_sweep.hip", "apply_h": "k_sweep.hip", "rk4_stage": "k_sweep.hip",
+                 "lanczos_sweep_a": "k_lanczos.hip"}
+
+
+def shape_of(prop, kernel):
+    if kernel == "taylor_fused":
+        return {"fuse_k": prop.taylor_fusion, "rows": getattr(prop, "fusion_rows", None),
+                "kind": prop.taylor_fusion_kind}
+    return {"tile_rows": prop.tile_rows, "sweep_variant": prop.sweep_variant}
+
+
+def traffic_for(workload, kernel, precision, shape):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    for e in table.get("entries", []):
+        if (e["workload"], e["kernel"], e["precision"]) != (workload, kernel, precision):
+            continue
+        if any(e["shape"].get(k) != v for k, v in shape.items() if k in e["shape"]):
+            continue
+        if e.get("source_sha256") != source_digest(e["source"]):
+            return None          # the kernel changed since the counters were taken
+        return e["hbm_bytes_per_launch"]
+    return None
+
+
+def hpsi_sweep(prop, tdse, torch, U, elem, reps=40):
+    """Mean duration of the plain H.psi apply on the bound grid (HIP events)."""
+    out = prop.new_vector()
+    e = 0.01
+    for _ in range(3):
+        prop.apply_H(e, prop.state, out)
+    torch.cuda.synchronize()
+    prop.timing(True)
+    for _ in range(reps):
+        prop.apply_H(e, prop.state, out)
+    launches, kms = prop.timing_read("apply_h")
+    prop.timing(False)
+    torch.cuda.synchronize()
+    us = 1e3 * kms / max(launches, 1)
+    bytes_ = 2 * elem * U
+    gbs = bytes_ / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "kernel": "apply_h", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_, "mean_launch_us": us,
+            "launches_timed": launches, "applies_per_s": 1e6 / us,
+            "shape": {"tile_rows": prop.tile_rows, "sweep_variant": prop.sweep_variant}}
+
+
+def taylor_bytes_per_launch(elem, U, launches, steps):
+    """Algorithmic bytes per Horner launch, averaged over a step's L launches.
+
+    Each launch reads its input vector and psi and writes its output (3 c U);
+    the first launch of a step reads psi as its input, so it reads it once
+    (2 c U): (3 L - 1) c U per step.
+    """
+    L = max(launches, 1) / max(steps, 1)
+    return (3.0 * L - 1.0) / L * elem * U
+
+
 def dominant_kernel(prop, method):
     """Timing family of the launch that carries a step's sweeps."""
     if method == "taylor":
@@ -127,15 +220,19 @@ def batch_setup(tdse, precision):
     return members, grids, pulses
 
 
-def run_batch_prec(tdse, torch, precision, args):
+def run_batch_prec(tdse, torch, precision, args, autotune=None):
     members, grids, pulses = batch_setup(tdse, precision)
     order = workloads.BATCH_ORDER
+    autotune = args.autotune if autotune is None else autotune
     prop = tdse.Propagator(grids, methods=((tdse.METHOD_TAYLOR, order),
                                            (tdse.METHOD_TUNE, 0)), graphs=bool(args.graphs))
-    if args.autotune:
-        prop.autotune()
-        if args.autotune > 1:
-            prop.autotune_taylor(order)
+    if autotune <= 1:
+        # the plain path: one launch per term, whatever --fusion says
+        saved, args.fusion = args.fusion, None
+        apply_shape(prop, args, autotune, order)
+        args.fusion = saved
+    else:
+        apply_shape(prop, args, autotune, order)
     kernel = dominant_kernel(prop, "taylor")
     y = tdse.tdse_taylor_stability_limit(order)
     dts = [workloads.BATCH_DT_SAFETY * y / prop.lambda_max_bound(k, abs(p.e0)) for k, p in enumerate(pulses)]
@@ -164,12 +261,18 @@ def run_batch_prec(tdse, torch, precision, args):
     prop.timing(False)
     rows = (prop.tile_rows, prop.sweep_variant, prop.taylor_fusion)
     o = obs.cpu().numpy()[:, -1, :]
+    U = sum((g.lmax + 1) * g.n for g in grids)
+    elem = 16 if precision == tdse.FP64 else 8
+    prec_name = "fp64" if precision == tdse.FP64 else "fp32"
+    shape = shape_of(prop, kernel)
+    traffic = traffic_for(BATCH_NAME, kernel, prec_name, shape)
+    sweep = hpsi_sweep(prop, tdse, torch, U, elem)
+    sweep["traffic"] = traffic_for(BATCH_NAME, "apply_h", prec_name, sweep["shape"])
     prop.close()
     del prop
     torch.cuda.empty_cache()
-    U = sum((g.lmax + 1) * g.n for g in grids)
     return dict(wall=wall, launches=launches, kms=kms, rows=rows, obs=o, U=U, dts=dts, n=len(grids),
-                kernel=kernel)
+                kernel=kernel, shape=shape, traffic=traffic, sweep=sweep)
 
 
 def run_batch(args, tdse, torch):
@@ -178,11 +281,16 @@ def run_batch(args, tdse, torch):
     log(f"bench: batch FP32 {args.steps / r32['wall']:.1f} steps/s")
     r64 = run_batch_prec(tdse, torch, tdse.FP64, args)
     log(f"bench: batch FP64 {args.steps / r64['wall']:.1f} steps/s")
+    # the plain FP64 path: one launch per Horner term (sweep tiles tuned, no fusion)
+    r64p = run_batch_prec(tdse, torch, tdse.FP64, args, autotune=min(args.autotune, 1))
+    log(f"bench: batch FP64 one launch per term {args.steps / r64p['wall']:.1f} steps/s")
     sps = args.steps / r32["wall"]
     U = r32["U"]
     avg_ms = r32["kms"] / max(r32["launches"], 1)
-    achieved = 3 * 8 * U / (avg_ms * 1e-3) / 1e9
+    bpl32 = taylor_bytes_per_launch(8, U, r32["launches"], args.steps)
+    achieved = bpl32 / (avg_ms * 1e-3) / 1e9
     avg64 = r64["kms"] / max(r64["launches"], 1)
+    bpl64 = taylor_bytes_per_launch(16, U, r64["launches"], args.steps)
     drift = float(np.max(np.abs(r32["obs"][:, 2] - r64["obs"][:, 2])))
     pb = float(np.max(np.abs(r32["obs"][:, 4] - r64["obs"][:, 4]) / np.abs(r64["obs"][:, 4])))
     out = {
@@ -194,19 +302,26 @@ def run_batch(args, tdse, torch):
                    "seed": workloads.BATCH_SEED, "dr": workloads.BATCH_DR, "stencil": workloads.BATCH_STENCIL,
                    "method": "taylor", "order": workloads.BATCH_ORDER, "obs_every": 1,
                    "dt_range": [min(r32["dts"]), max(r32["dts"])], "parallelism": "single GPU",
-                   "tile_rows_variant_fusion": r32["rows"], "graphs": bool(args.graphs)},
+                   "tile_rows_variant_fusion": r32["rows"], "kernel_shape": r32["shape"],
+                   "graphs": bool(args.graphs)},
         "steps_per_s": sps,
         "roofline": {"bound": "hbm", "kernel": r32["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": 3 * 8 * U, "mean_launch_us": avg_ms * 1e3,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": r32["traffic"],
+                     "algorithmic_bytes_per_launch": bpl32, "mean_launch_us": avg_ms * 1e3,
                      "launches_timed": r32["launches"]},
+        "hpsi_sweep": r32["sweep"],
         "fp64_batched": {"steps_per_s": args.steps / r64["wall"],
                          "fp32_speedup_vs_fp64": sps / (args.steps / r64["wall"]),
                          "kernel": r64["kernel"], "kernel_mean_us": avg64 * 1e3,
-                         "kernel_gbs": 3 * 16 * U / (avg64 * 1e-3) / 1e9,
+                         "kernel_gbs": bpl64 / (avg64 * 1e-3) / 1e9,
                          "max_norm_diff_fp32_vs_fp64": drift,
                          "max_p_bound_rel_diff_fp32_vs_fp64": pb,
-                         "steps_compared": (3 if args.graphs else 2) * args.steps + args.warmup},
+                         "steps_compared": (3 if args.graphs else 2) * args.steps + args.warmup,
+                         "hpsi_sweep": r64["sweep"]},
+        "fp64_one_launch_per_term": {"steps_per_s": args.steps / r64p["wall"],
+                                     "fp32_speedup_vs_it": sps / (args.steps / r64p["wall"]),
+                                     "kernel": r64p["kernel"],
+                                     "kernel_mean_us": 1e3 * r64p["kms"] / max(r64p["launches"], 1)},
     }
     if not args.no_cpu_baseline:
         members = workloads.batch_members()
@@ -222,8 +337,13 @@ def run_batch(args, tdse, torch):
     print(json.dumps(out), flush=True)
 
 
+ARGS = None
+
+
 def main():
+    global ARGS
     args = parse()
+    ARGS = args
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU sharding is described, not built)"}))
@@ -256,10 +376,20 @@ def main():
     avg_ms = kms / max(launches, 1)
     log(f"bench: {steps_per_s:.1f} steps/s, {value:.1f} applies/s, {kernel} mean {avg_ms * 1e3:.2f} us "
         f"over {launches} launches")
-    achieved = None
-    if bytes_per_unknown:
-        achieved = bytes_per_unknown * U / (avg_ms * 1e-3) / 1e9
+    bytes_per_launch = None
+    if wl.method == "taylor":
+        bytes_per_launch = taylor_bytes_per_launch(elem, U, launches, args.steps)
+    elif bytes_per_unknown:
+        bytes_per_launch = bytes_per_unknown * U
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if bytes_per_launch else None
     obs_last = obs.cpu().numpy()[0, -1]
+    shape = shape_of(prop, kernel)
+    prec_name = "fp64" if prec == tdse.FP64 else "fp32"
+    traffic = traffic_for(wl.name, kernel, prec_name, shape)
+    sweep = hpsi_sweep(prop, tdse, torch, U, elem)
+    sweep["traffic"] = traffic_for(wl.name, "apply_h", prec_name, sweep["shape"])
+    log(f"bench: H.psi apply {sweep['mean_launch_us']:.2f} us = {sweep['achieved']:.0f} GB/s "
+        f"(frac {sweep['frac']:.3f})")
     prop.close()
     del prop
     torch.cuda.empty_cache()
@@ -282,7 +412,7 @@ def main():
                    "dt": wl.dt, "dt_nominal": wl.dt_nominal, "unknowns": U,
                    "obs_every": wl.obs_every, "parallelism": "single GPU",
                    "tile_rows": tile_rows, "sweep_variant": variant, "taylor_fusion": fusion,
-                   "graphs": bool(args.graphs)},
+                   "kernel_shape": shape, "graphs": bool(args.graphs)},
         "steps_per_s": steps_per_s,
         "roofline": {
             "bound": "hbm",
@@ -291,11 +421,12 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
-            "algorithmic_bytes_per_launch": (bytes_per_unknown * U) if bytes_per_unknown else None,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
             "mean_launch_us": avg_ms * 1e3,
             "launches_timed": launches,
         },
+        "hpsi_sweep": sweep,
         "final_observables": {"norm": float(obs_last[2]), "p_ion": float(obs_last[5]),
                               "p_bound": float(obs_last[4])},
     }
@@ -318,7 +449,8 @@ def main():
             "speedup_vs_fp64": sps32 / steps_per_s,
             "kernel": kernel32,
             "kernel_mean_us": 1e3 * k32 / max(l32, 1),
-            "kernel_gbs": (3 * 8 * U / (k32 / max(l32, 1) * 1e-3) / 1e9) if wl.method == "taylor" else None,
+            "kernel_gbs": (taylor_bytes_per_launch(8, U, l32, args.steps) / (k32 / max(l32, 1) * 1e-3) / 1e9)
+                          if wl.method == "taylor" else None,
             "rel_state_error_vs_fp64": rel_state,
             "norm_drift_vs_fp64": float(abs(o32[2] - obs_last[2])),
             "p_bound_rel_error_vs_fp64": float(abs(o32[4] - obs_last[4]) / abs(obs_last[4])),

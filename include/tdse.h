@@ -235,9 +235,12 @@ int32_t tdse_taylor_fusion_kind(const tdse_ctx* ctx);
 tdse_status tdse_set_taylor_fusion(tdse_ctx* ctx, int32_t k, int32_t rows, int32_t kind);
 
 /* Rows per workgroup of the sweep tile set in use, and the sweep variant
- * (0..3, bits as in tdse_autotune). */
+ * (0..3, bits as in tdse_autotune); and an explicit choice of both (rows
+ * 1..32), e.g. to reproduce a tuned shape.  Results do not depend on it.
+ * Synchronises. */
 int32_t tdse_tile_rows(const tdse_ctx* ctx);
 int32_t tdse_sweep_variant(const tdse_ctx* ctx);
+tdse_status tdse_set_sweep_shape(tdse_ctx* ctx, int32_t rows, int32_t variant);
 
 /* Step-loop replay through HIP graphs (default off).  When on, and timing is
  * off, and the bound stream is not the null stream, each step call captures

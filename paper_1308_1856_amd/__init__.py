@@ -36,7 +36,7 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read",
             "tdse_use_graphs", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
             "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_taylor_fusion_kind",
-            "tdse_set_taylor_fusion")
+            "tdse_set_taylor_fusion", "tdse_set_sweep_shape")
 
 
 class TdseError(RuntimeError):
@@ -100,6 +100,7 @@ def _load():
         "tdse_taylor_fusion": ([ctxp], i32),
         "tdse_taylor_fusion_kind": ([ctxp], i32),
         "tdse_set_taylor_fusion": ([ctxp, i32, i32, i32], i32),
+        "tdse_set_sweep_shape": ([ctxp, i32, i32], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -280,6 +281,7 @@ class Propagator:
                   self.stream.cuda_stream)
         self.offsets = [lib.tdse_state_offset(self.ctx, k) for k in range(self.n_inst)]
         self.elem = 16 if self.grids[0].precision == FP64 else 8
+        self.fusion_rows = 16   # rows of the fused tiles (the library's default until set or tuned)
         if graphs:
             tdse_use_graphs(self.ctx, True)
 
@@ -371,11 +373,15 @@ class Propagator:
     def sweep_variant(self) -> int:
         return lib.tdse_sweep_variant(self.ctx)
 
+    def set_sweep_shape(self, rows: int, variant: int):
+        _check(self.ctx, lib.tdse_set_sweep_shape(self.ctx, int(rows), int(variant)))
+
     def autotune_taylor(self, order: int):
         """(fused terms per launch or 0, rows per fused tile) chosen for `order`."""
         self._enter()
         out = tdse_autotune_taylor(self.ctx, order)
         self._leave()
+        self.fusion_rows = out[1]
         return out
 
     @property
@@ -389,6 +395,7 @@ class Propagator:
 
     def set_taylor_fusion(self, k: int, rows: int = 16, kind: int = 0):
         _check(self.ctx, lib.tdse_set_taylor_fusion(self.ctx, int(k), int(rows), int(kind)))
+        self.fusion_rows = int(rows)
 
     def _pulse_list(self, pulses):
         if isinstance(pulses, (list, tuple)):

@@ -1304,6 +1304,29 @@ extern "C" tdse_status tdse_set_taylor_fusion(tdse_ctx* c, int32_t k, int32_t ro
     return TDSE_OK;
 }
 
+extern "C" tdse_status tdse_set_sweep_shape(tdse_ctx* c, int32_t rows, int32_t variant)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (rows < 1 || rows > kTileRows || variant < 0 || variant > 3)
+        return c->fail(TDSE_E_INVALID, "tdse_set_sweep_shape: rows must be 1..32 and variant 0..3");
+    if (c->bound) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_set_sweep_shape sync");
+    }
+    c->rows_sweep = rows;
+    c->sweep_variant = variant;
+    build_tiles(c, kSweepTiles, rows);
+    build_tiles(c, kPairTiles, rows);
+    if (c->bound) {
+        hipError_t e = upload_tiles(c, kSweepTiles);
+        if (e == hipSuccess) e = upload_tiles(c, kPairTiles);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_set_sweep_shape upload");
+    }
+    c->drop_graphs();
+    return TDSE_OK;
+}
+
 extern "C" int32_t tdse_tile_rows(const tdse_ctx* c) { return c ? c->rows_sweep : 0; }
 extern "C" int32_t tdse_sweep_variant(const tdse_ctx* c) { return c ? c->sweep_variant : 0; }
 

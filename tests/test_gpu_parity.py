@@ -435,3 +435,23 @@ def test_fused_taylor_batch_bitwise(kind):
         prop.close()
     for k in range(3):
         assert np.array_equal(res[0][k], res[1][k]), k
+
+
+def test_explicit_sweep_shape_bitwise():
+    # an explicit sweep shape (as the bench uses to reproduce a tuned one) gives the same bits
+    t = lib()
+    grid = t.Grid(3001, 11, 0.1, 5, t.FP64, 1.0, 50.0)
+    pulse = t.Pulse(0.05, 0.2, 2.0, 0.3, 0.0)
+    say("explicit sweep shapes: Taylor-8 bitwise across (rows, variant)")
+    out = []
+    for rows, variant in ((1, 0), (8, 1), (4, 2), (32, 3)):
+        prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),))
+        prop.set_sweep_shape(rows, variant)
+        assert (prop.tile_rows, prop.sweep_variant) == (rows, variant)
+        dt = 0.8 * t.tdse_taylor_stability_limit(8) / prop.lambda_max_bound(0, 0.05)
+        prop.set_state(0, None)
+        prop.step_taylor(pulse, 0.0, dt, 8, 9)
+        out.append(prop.get_state(0))
+        prop.close()
+    for o in out[1:]:
+        assert np.array_equal(o, out[0])
