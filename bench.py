@@ -133,10 +133,13 @@ def timed(prop, tdse, wl, torch, steps, warmup, kernel, graphs):
 
 
 def source_digest(name):
+    """sha256 over a kernel source and the device headers it includes."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1308_1856_amd", "csrc", name)
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for part in (name, "device_common.hpp", "tdse_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1308_1856_amd", "csrc", part), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 KERNEL_SOURCE = {"taylor_term": "k_sweep.hip", "apply_h": "k_sweep.hip", "rk4_stage": "k_sweep.hip",

@@ -33,27 +33,34 @@ __device__ __forceinline__ double wave_uniform(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Sum over the 64 lanes of a wave; every lane gets the total.
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // Block-wide sums of NQ values for a kBlock-thread block.  Thread q < NQ of
 // the block receives the sum of value q in `out_q` (others get 0).  The
 // summation tree depends only on thread indices, so results are bitwise
-// reproducible.  Must be reached by every thread of the block.
+// reproducible.  The butterfly runs stage by stage over groups of up to 4
+// values (not value by value), so the independent shuffles of a stage overlap
+// instead of paying the shuffle latency once per value; each value's tree is the xor
+// butterfly 32, 16, ..., 1 over the wave's lanes.  Must be reached by every
+// thread of the block.
 template <int NQ>
 __device__ __forceinline__ double block_sum(double (&v)[NQ], double* lds /* [kBlock/64][NQ] */)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    // groups of (at most) 4 values: independent shuffles per stage to hide
+    // their latency, few enough not to raise the register count of the caller
+    constexpr int G = NQ < 4 ? NQ : 4;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const double s = wave_sum(v[q]);
-        if (lane == 0) lds[wave * NQ + q] = s;
+    for (int q0 = 0; q0 < NQ; q0 += G) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+            for (int q = q0; q < q0 + G && q < NQ; ++q) v[q] += __shfl_xor(v[q], off, 64);
+        }
+        // each group's totals leave the registers at once
+        if (lane == 0) {
+#pragma unroll
+            for (int q = q0; q < q0 + G && q < NQ; ++q) lds[wave * NQ + q] = v[q];
+        }
     }
     __syncthreads();
     double out = 0.0;
