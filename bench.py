@@ -382,6 +382,10 @@ def main():
     bytes_per_launch = None
     if wl.method == "taylor":
         bytes_per_launch = taylor_bytes_per_launch(elem, U, launches, args.steps)
+    elif wl.method == "lanczos":
+        # sweep A of iteration j reads q_0..q_j and writes w: (j + 2) c U,
+        # averaged over j = 0 .. m-1
+        bytes_per_launch = (wl.order + 3) / 2.0 * elem * U
     elif bytes_per_unknown:
         bytes_per_launch = bytes_per_unknown * U
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if bytes_per_launch else None

@@ -9,9 +9,8 @@
 //             against every earlier vector: three-term recurrence plus full
 //             re-orthogonalisation), partial sums of ||.||^2
 //   finish B: beta_j, scale of q_{j+1} = 1/beta_j, breakdown test
-// then the eigen-decomposition of the tridiagonal T (one wave per instance,
-// implicit QR with Wilkinson shifts) gives c = S exp(-i Lambda dt) S^T e_1 and
-// F <- ||F|| sum_k c_k q_k.
+// then c = ||F|| exp(-i T dt) e_1 for the tridiagonal T (one workgroup per
+// instance, scaling and squaring in LDS) and F <- sum_k c_k q_k.
 //
 // Basis vectors are stored unnormalised (FP64 or FP32) and scaled on load by
 // FP64 factors; q_0 is the state buffer itself.  All inner products, norms
@@ -161,13 +160,16 @@ k_lz_finish_a(SweepGeom g, int j, int m, const double* __restrict__ partial,
     LanczosScalars& sc = scs[k];
     if (sc.done) return;
     const Inst& I = g.inst[k];
-    for (int i0 = 0; i0 <= j; i0 += JB) {
-        const int nq = min(2 * JB, 2 * (j + 1 - i0));
-        const double s = instance_sum<2 * JB>(I, partial + 2 * i0, 2 * m, nq, lds);
-        if ((int)threadIdx.x < nq) sc.h[2 * i0 + threadIdx.x] = s;
-        if ((int)threadIdx.x == 2 * (j - i0)) sc.alpha[j] = s;  // Re <q_j, H q_j>
-    }
-    if (threadIdx.x == 0) sc.meff = j + 1;
+    // workgroup (k, y) sums the products i0 = y JB .. i0 + JB - 1 (all groups
+    // of an instance run side by side)
+    const int i0 = (int)blockIdx.y * JB;
+    if (i0 > j) return;
+    const int nq = min(2 * JB, 2 * (j + 1 - i0));
+    const double s = instance_sum<2 * JB>(I, partial + 2 * i0, 2 * m, nq, lds);
+    if ((int)threadIdx.x < nq) sc.h[2 * i0 + threadIdx.x] = s;
+    // Re <q_j, H q_j>, from the one group that holds product j
+    if (j - i0 < JB && (int)threadIdx.x == 2 * (j - i0)) sc.alpha[j] = s;
+    if (blockIdx.y == 0 && threadIdx.x == 0) sc.meff = j + 1;
 }
 
 // q_{j+1} (stored unnormalised) = w - sum_{i<=j} h_i q_i, and ||.||^2 partials.
@@ -226,100 +228,130 @@ k_lz_finish_b(SweepGeom g, int j, const double* __restrict__ partial, LanczosSca
     }
 }
 
-// Givens pair (c, s) with [c s; -s c]^T [x; z] = [r; 0] (Golub & Van Loan).
-__device__ __forceinline__ void givens(double x, double z, double& c, double& s)
+// Exponential of the Krylov matrix, c = ||F|| exp(-i T dt) e_1 (Sec. 5.2 and
+// the appendix on Lanczos methods; the exponential by scaling and squaring):
+//   B = T dt / 2^s with ||B||_inf <= 1/2,
+//   exp(-i B) = X - i Y,  X = sum_{k even} (-1)^{k/2} B^k / k!,
+//                         Y = sum_{k odd} (-1)^{(k-1)/2} B^k / k!  (k <= 17;
+//   the remainder is below 0.5^18 / 18! < 1e-21),
+//   then s squarings (X - iY)^2 = (X^2 - Y^2) - i (XY + YX).
+// One workgroup per instance; the m x m real matrices live in LDS, each
+// thread computes a fixed set of entries of every product (fixed summation
+// order: results do not depend on scheduling).  T is exponentiated as a
+// whole; no eigen-decomposition, unlike the oracle, which diagonalises T.
+constexpr int kExpmTerms = 17;
+constexpr int kExpmPerThread = (kMaxKrylov * kMaxKrylov + kBlock - 1) / kBlock;
+
+// Row r of L times column c of R, with four independent partial sums (a
+// fixed order, so the result does not depend on scheduling).
+__device__ __forceinline__ double lds_dot(const double* L, const double* R, int m, int r, int c)
 {
-    if (z == 0.0) {
-        c = 1.0;
-        s = 0.0;
-    } else if (fabs(z) > fabs(x)) {
-        const double tau = -x / z;
-        s = 1.0 / sqrt(1.0 + tau * tau);
-        c = s * tau;
-    } else {
-        const double tau = -z / x;
-        c = 1.0 / sqrt(1.0 + tau * tau);
-        s = c * tau;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = 0;
+    for (; j + 3 < m; j += 4) {
+        a0 = fma(L[r * m + j], R[j * m + c], a0);
+        a1 = fma(L[r * m + j + 1], R[(j + 1) * m + c], a1);
+        a2 = fma(L[r * m + j + 2], R[(j + 2) * m + c], a2);
+        a3 = fma(L[r * m + j + 3], R[(j + 3) * m + c], a3);
     }
+    for (; j < m; ++j) a0 = fma(L[r * m + j], R[j * m + c], a0);
+    return (a0 + a1) + (a2 + a3);
 }
 
-// One wave per instance.  Every lane runs the same scalar QR iteration on
-// (a, b) (so no lane waits for another) and applies each rotation to its own
-// row of the eigenvector matrix S held in LDS.
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(kBlock)
 k_lz_expm(SweepGeom g, const double* __restrict__ step, LanczosScalars* __restrict__ scs)
 {
-    constexpr int LD = kMaxKrylov + 1;
-    __shared__ double sm[kMaxKrylov * LD];
+    __shared__ double Bm[kMaxKrylov * kMaxKrylov];
+    __shared__ double Pm[kMaxKrylov * kMaxKrylov];
+    __shared__ double Xm[kMaxKrylov * kMaxKrylov];
+    __shared__ double Ym[kMaxKrylov * kMaxKrylov];
     const int inst = blockIdx.x;
     LanczosScalars& sc = scs[inst];
     const int m = sc.meff;
-    const int lane = threadIdx.x;
+    const int mm = m * m;
+    const int tid = (int)threadIdx.x;
     const double dt = step_value(step, g.n_inst, kDt, inst);
-    double a[kMaxKrylov], b[kMaxKrylov];
-    for (int k = 0; k < m; ++k) {
-        a[k] = sc.alpha[k];
-        b[k] = (k + 1 < m) ? sc.beta[k] : 0.0;
-    }
-    double* srow = sm + lane * LD;
-    if (lane < m)
-        for (int k = 0; k < m; ++k) srow[k] = (k == lane) ? 1.0 : 0.0;
 
-    const double eps = 2.220446049250313e-16;
-    int hi = m - 1;
-    int iter = 0;
-    while (hi > 0 && iter < 40 * m) {
-        if (fabs(b[hi - 1]) <= eps * (fabs(a[hi - 1]) + fabs(a[hi]))) {
-            b[hi - 1] = 0.0;
-            --hi;
-            continue;
+    // ||T dt||_inf and the number of squarings (the same in every thread)
+    double tn = 0.0;
+    for (int k = 0; k < m; ++k) {
+        double row = fabs(sc.alpha[k]);
+        if (k > 0) row += fabs(sc.beta[k - 1]);
+        if (k + 1 < m) row += fabs(sc.beta[k]);
+        tn = fmax(tn, row);
+    }
+    tn *= dt;
+    int nsq = 0;
+    while (tn > 0.5 && nsq < 60) {
+        tn *= 0.5;
+        ++nsq;
+    }
+    const double scl = ldexp(dt, -nsq);
+
+    for (int e = 0; e < kExpmPerThread; ++e) {
+        const int idx = tid + e * kBlock;
+        if (idx < mm) {
+            const int r = idx / m, c = idx - r * m;
+            double v = 0.0;
+            if (r == c) v = sc.alpha[r];
+            else if (c == r + 1) v = sc.beta[r];
+            else if (r == c + 1) v = sc.beta[c];
+            v *= scl;
+            Bm[idx] = v;
+            Pm[idx] = v;
+            Xm[idx] = (r == c) ? 1.0 : 0.0;
+            Ym[idx] = v;
         }
-        int lo = hi - 1;
-        while (lo > 0 && fabs(b[lo - 1]) > eps * (fabs(a[lo - 1]) + fabs(a[lo]))) --lo;
-        if (lo > 0) b[lo - 1] = 0.0;
-        // Wilkinson shift: eigenvalue of the trailing 2x2 closer to a[hi]
-        const double d = 0.5 * (a[hi - 1] - a[hi]);
-        const double bb = b[hi - 1];
-        const double den = d + copysign(sqrt(d * d + bb * bb), d);
-        const double mu = a[hi] - bb * bb / den;
-        double x = a[lo] - mu, z = b[lo], bulge = 0.0;
-        for (int k = lo; k < hi; ++k) {
-            double c, s;
-            givens(x, z, c, s);
-            if (k > lo) b[k - 1] = c * b[k - 1] - s * bulge;
-            const double ap = a[k], aq = a[k + 1], bp = b[k];
-            a[k] = c * c * ap - 2.0 * c * s * bp + s * s * aq;
-            a[k + 1] = s * s * ap + 2.0 * c * s * bp + c * c * aq;
-            b[k] = c * s * (ap - aq) + (c * c - s * s) * bp;
-            if (k + 1 < hi) {
-                bulge = -s * b[k + 1];
-                b[k + 1] = c * b[k + 1];
-                x = b[k];
-                z = bulge;
-            }
-            if (lane < m) {
-                const double sp = srow[k], sq = srow[k + 1];
-                srow[k] = c * sp - s * sq;
-                srow[k + 1] = s * sp + c * sq;
-            }
-        }
-        ++iter;
     }
     __syncthreads();
-    // c_k = sum_j S[k][j] exp(-i lambda_j dt) S[0][j], weighted by ||F|| and
-    // the storage scale of basis vector k
-    if (lane < m) {
-        double cr = 0.0, ci = 0.0;
-        for (int jj = 0; jj < m; ++jj) {
-            double sn, cs;
-            sincos(a[jj] * dt, &sn, &cs);
-            const double w = srow[jj] * sm[jj];  // S[k][j] * S[0][j]
-            cr += w * cs;
-            ci -= w * sn;
+    // Taylor terms: P <- P B / k, added to X (even k) or Y (odd k) with sign
+    for (int k = 2; k <= kExpmTerms; ++k) {
+        double nv[kExpmPerThread];
+        const double inv_k = 1.0 / (double)k;
+        for (int e = 0; e < kExpmPerThread; ++e) {
+            const int idx = tid + e * kBlock;
+            nv[e] = 0.0;
+            if (idx < mm) nv[e] = lds_dot(Pm, Bm, m, idx / m, idx % m) * inv_k;
         }
-        const double f = sc.norm0 * sc.scale[lane];
-        sc.coef[2 * lane] = f * cr;
-        sc.coef[2 * lane + 1] = f * ci;
+        __syncthreads();
+        const double sgn = ((k / 2) & 1) ? -1.0 : 1.0;   // (-1)^{k/2} even, (-1)^{(k-1)/2} odd
+        for (int e = 0; e < kExpmPerThread; ++e) {
+            const int idx = tid + e * kBlock;
+            if (idx < mm) {
+                Pm[idx] = nv[e];
+                if (k & 1) Ym[idx] = fma(sgn, nv[e], Ym[idx]);
+                else Xm[idx] = fma(sgn, nv[e], Xm[idx]);
+            }
+        }
+        __syncthreads();
+    }
+    // squarings
+    for (int q = 0; q < nsq; ++q) {
+        double nx[kExpmPerThread], ny[kExpmPerThread];
+        for (int e = 0; e < kExpmPerThread; ++e) {
+            const int idx = tid + e * kBlock;
+            nx[e] = ny[e] = 0.0;
+            if (idx < mm) {
+                const int r = idx / m, c = idx - r * m;
+                nx[e] = lds_dot(Xm, Xm, m, r, c) - lds_dot(Ym, Ym, m, r, c);
+                ny[e] = lds_dot(Xm, Ym, m, r, c) + lds_dot(Ym, Xm, m, r, c);
+            }
+        }
+        __syncthreads();
+        for (int e = 0; e < kExpmPerThread; ++e) {
+            const int idx = tid + e * kBlock;
+            if (idx < mm) {
+                Xm[idx] = nx[e];
+                Ym[idx] = ny[e];
+            }
+        }
+        __syncthreads();
+    }
+    // c_k = ||F|| scale_k (X[k][0] - i Y[k][0])
+    if (tid < m) {
+        const double f = sc.norm0 * sc.scale[tid];
+        sc.coef[2 * tid] = f * Xm[tid * m];
+        sc.coef[2 * tid + 1] = -f * Ym[tid * m];
     }
 }
 
@@ -394,7 +426,8 @@ hipError_t launch_lz_sweep_a(int prec, int S, const SweepGeom& g, int j, int m, 
 hipError_t launch_lz_finish_a(const SweepGeom& g, int j, int m, const double* partial,
                               LanczosScalars* sc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_lz_finish_a, dim3(g.n_inst), dim3(kBlock), 0, st, g, j, m, partial, sc);
+    constexpr int JB = 8;
+    hipLaunchKernelGGL(k_lz_finish_a, dim3(g.n_inst, (j + JB) / JB), dim3(kBlock), 0, st, g, j, m, partial, sc);
     return hipGetLastError();
 }
 
@@ -425,7 +458,7 @@ hipError_t launch_lz_finish_b(const SweepGeom& g, int j, const double* partial,
 hipError_t launch_lz_expm(const SweepGeom& g, const double* step, LanczosScalars* sc,
                           hipStream_t st)
 {
-    hipLaunchKernelGGL(k_lz_expm, dim3(g.n_inst), dim3(64), 0, st, g, step, sc);
+    hipLaunchKernelGGL(k_lz_expm, dim3(g.n_inst), dim3(kBlock), 0, st, g, step, sc);
     return hipGetLastError();
 }
 
