@@ -11,6 +11,8 @@ benchmark uses.
 - the 256-member batch (104,476,250 unknowns, FP32 storage, per-member dt):
   one batched launch sequence, with four sampled members propagated by the
   oracle one by one.
+Each runs with one launch per Horner term and with the execution shapes the
+autotuners pick for the benchmark (wave-strip fused kernel, two-radii sweep).
 """
 import math
 
@@ -24,12 +26,21 @@ from gpu_helpers import lib, obs_abs_tol, obs_columns, orc_grid, orc_pulse, read
 pytestmark = pytest.mark.gpu
 
 
-def test_n20000_l64_fp64_taylor8_three_steps():
+def shape(prop, sweep, fusion):
+    if sweep is not None:
+        prop.set_sweep_shape(*sweep)
+    if fusion is not None:
+        prop.set_taylor_fusion(*fusion)
+
+
+@pytest.mark.parametrize("sweep,fusion", [(None, None), ((4, 1), (3, 8, 1)), ((2, 3), (4, 16, 0))])
+def test_n20000_l64_fp64_taylor8_three_steps(sweep, fusion):
     t = lib()
     wl = workloads.WORKLOADS["hydrogen_n20000_l64_fp64_taylor8"]
-    say(f"full size {wl.name}: 3 Taylor-8 steps vs oracle")
+    say(f"full size {wl.name}: 3 Taylor-8 steps vs oracle, sweep {sweep}, fusion {fusion}")
     g = t.Grid(wl.n, wl.lmax, wl.dr, wl.stencil, t.FP64, 1.0, wl.r_ion)
     prop = t.Propagator([g], methods=((t.METHOD_TAYLOR, 8),))
+    shape(prop, sweep, fusion)
     prop.set_state(0, None)
     p = t.Pulse(wl.pulse.e0, wl.pulse.omega, wl.pulse.n_cycles, wl.pulse.cep, wl.pulse.t_on)
     t0 = 0.5 * wl.pulse.duration          # mid-pulse, strong field
@@ -48,12 +59,14 @@ def test_n20000_l64_fp64_taylor8_three_steps():
     assert err < 1e-12 and np.all(ratio <= 1.0)
 
 
-def test_n100000_l256_fp32_apply_and_two_steps():
+@pytest.mark.parametrize("sweep,fusion", [(None, None), ((8, 1), (4, 32, 1))])
+def test_n100000_l256_fp32_apply_and_two_steps(sweep, fusion):
     t = lib()
     wl = workloads.WORKLOADS["hydrogen_n100000_l256_fp32_taylor8"]
-    say(f"full size {wl.name}: apply_H and 2 Taylor-8 steps vs oracle")
+    say(f"full size {wl.name}: apply_H and 2 Taylor-8 steps vs oracle, sweep {sweep}, fusion {fusion}")
     g = t.Grid(wl.n, wl.lmax, wl.dr, wl.stencil, t.FP32, 1.0, wl.r_ion)
     prop = t.Propagator([g], methods=((t.METHOD_TAYLOR, 8),))
+    shape(prop, sweep, fusion)
     og = orc_grid(g)
     # a smooth FP32-representable state spread over every partial wave
     psi = to_fp32(workloads.random_state(3, wl.n, wl.lmax, smooth=True))
@@ -85,7 +98,8 @@ def test_n100000_l256_fp32_apply_and_two_steps():
     assert err < 5e-7          # a few FP32 roundings of each element
 
 
-def test_batch_256_sampled_members():
+@pytest.mark.parametrize("sweep,fusion", [(None, None), ((4, 3), (5, 64, 1))])
+def test_batch_256_sampled_members(sweep, fusion):
     t = lib()
     members = workloads.batch_members()
     grids, pulses, dts = [], [], []
@@ -97,6 +111,7 @@ def test_batch_256_sampled_members():
         pulses.append(t.Pulse(pp.e0, pp.omega, pp.n_cycles, pp.cep, pp.t_on))
     say(f"batch of {len(grids)} members, {sum((g.lmax + 1) * g.n for g in grids)} unknowns")
     prop = t.Propagator(grids, methods=((t.METHOD_TAYLOR, workloads.BATCH_ORDER),))
+    shape(prop, sweep, fusion)
     y8 = t.tdse_taylor_stability_limit(workloads.BATCH_ORDER)
     for k, pp in enumerate(pulses):
         dts.append(workloads.BATCH_DT_SAFETY * y8 / prop.lambda_max_bound(k, abs(pp.e0)))

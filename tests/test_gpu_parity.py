@@ -455,3 +455,29 @@ def test_explicit_sweep_shape_bitwise():
         prop.close()
     for o in out[1:]:
         assert np.array_equal(o, out[0])
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_fused_degenerate_shapes(kind):
+    # the smallest grids (N = 8, a single row lmax = 0, strips wider than the
+    # grid), order 1 and order 2, zero steps: fused == per-term bit for bit,
+    # and zero steps leave the state alone
+    t = lib()
+    say(f"fused kind {kind}: degenerate shapes")
+    for n, lmax, stencil in ((8, 0, 3), (8, 3, 5), (63, 0, 5), (65, 2, 3)):
+        grid = t.Grid(n, lmax, 0.1, stencil, t.FP64, 1.0, 0.4)
+        pulse = t.Pulse(0.05, 0.3, 2.0, 0.0, 0.0)
+        for order in (1, 2, 5):
+            res = []
+            for fuse in (0, min(order, 4)):
+                prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, order),))
+                dt = 0.5 * t.tdse_taylor_stability_limit(order) / prop.lambda_max_bound(0, 0.05)
+                prop.set_taylor_fusion(fuse, 3, kind)
+                prop.set_state(0, None)
+                before = prop.get_state(0)
+                prop.step_taylor(pulse, 1.0, dt, order, 0)
+                assert np.array_equal(prop.get_state(0), before)
+                prop.step_taylor(pulse, 1.0, dt, order, 7)
+                res.append(prop.get_state(0))
+                prop.close()
+            assert np.array_equal(res[0], res[1]), (n, lmax, stencil, order)
