@@ -23,17 +23,30 @@ __device__ __forceinline__ void obs_main(const SweepGeom& g, const typename Cplx
     if (i < n) {
         const RadialPoint rp = radial_point(I, i);
         const bool outer = i >= I.i_ion;
+        // rows in chunks of four: the four loads of a chunk are independent and
+        // in flight together (one memory latency per chunk, not per row)
+        const int last = min(I.l1, I.lmax);     // the highest row a tile reads
         double2 cur = ldc(psi, I.off + (int64_t)I.l0 * n + i);
-        for (int l = I.l0; l < I.l1; ++l) {
-            const int64_t row = I.off + (int64_t)l * n;
-            const double2 next = (l < I.lmax) ? ldc(psi, row + n + i) : zero2();
-            const double a2 = fma(cur.x, cur.x, cur.y * cur.y);
-            acc[0] += a2;
-            if (outer) acc[1] += a2;
-            const double re = fma(cur.x, next.x, cur.y * next.y) * g.kappa[l + 1];
-            acc[2] = fma(rp.r, re, acc[2]);
-            acc[3] = fma(re, rp.inv_r2, acc[3]);
-            cur = next;
+        for (int l = I.l0; l < I.l1; l += 4) {
+            double2 r[5];
+            r[0] = cur;
+#pragma unroll
+            for (int u = 1; u <= 4; ++u) {
+                const double2 v = ldc(psi, I.off + (int64_t)min(l + u, last) * n + i);
+                r[u] = (l + u <= I.lmax) ? v : zero2();
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (l + u < I.l1) {
+                    const double a2 = fma(r[u].x, r[u].x, r[u].y * r[u].y);
+                    acc[0] += a2;
+                    if (outer) acc[1] += a2;
+                    const double re = fma(r[u].x, r[u + 1].x, r[u].y * r[u + 1].y) * g.kappa[l + u + 1];
+                    acc[2] = fma(rp.r, re, acc[2]);
+                    acc[3] = fma(re, rp.inv_r2, acc[3]);
+                }
+            }
+            cur = r[4];
         }
     }
     const double s = block_sum<kObsMainQ>(acc, lds);
