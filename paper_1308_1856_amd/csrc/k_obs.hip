@@ -1,8 +1,8 @@
 // Observables of Sec. 4 as FP64 reductions in a fixed order:
 //   norm, p_ion (eq. yield_1), <z> (eq. Dipole), <z''> (eq. DipoleAccel),
 //   p_g (eq. p_g) and the bound-state projections P_nl.
-// Pass 1 has two roles in one launch: workgroups [0, n_reduce) stream every
-// row of their reduce tile and sum 4 values; the remaining workgroups each
+// Pass 1 has two roles in one launch: workgroups [0, n_obs) stream every
+// row of their tile (the observables' tile set) and sum 4 values; the remaining workgroups each
 // take one population tile (rows l <= 4 of 256 radial points) and sum the 32
 // projection values.  Partials are stored [q][tile] so that pass 2 (one
 // workgroup per instance, adding its tiles in tile order) reads them
@@ -112,7 +112,7 @@ k_obs_finish(SweepGeom red, SweepGeom pop, const double* __restrict__ pmain,
     double acc[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-    for (int t = I.tbegin[kReduceTiles] + (int)threadIdx.x; t < I.tend[kReduceTiles]; t += kBlock) {
+    for (int t = I.tbegin[kObsTiles] + (int)threadIdx.x; t < I.tend[kObsTiles]; t += kBlock) {
 #pragma unroll
         for (int q = 0; q < kObsMainQ; ++q) acc[q] += pmain[(int64_t)q * red.n_tiles + t];
     }

@@ -43,7 +43,7 @@ struct tdse_ctx {
     std::vector<tdse_grid_desc> grids;
     std::vector<Inst> inst;
     std::vector<Tile> tiles[kNumTileSets];
-    int rows_sweep = 1, rows_reduce = 1;
+    int rows_sweep = 1, rows_reduce = 1, rows_obs = 1;
     int sweep_variant = 0;              // bit 0: two radii per thread, bit 1: XCD-contiguous order (autotuned)
     int fuse_k = 0;                     // Horner terms per fused launch (0: one launch per term)
     int fuse_kind = 0;                  // fused kernel: 0 LDS rings, 1 wave strips
@@ -60,7 +60,7 @@ struct tdse_ctx {
     size_t work_bytes = 0;
     hipStream_t stream = nullptr;
     // workspace layout (bytes from d_work)
-    size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0, 0, 0, 0}, off_kappa = 0, off_radial = 0,
+    size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0, 0, 0, 0, 0}, off_kappa = 0, off_radial = 0,
            off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0,
            off_zero = 0, zero_bytes = 0;
     size_t partial_doubles = 0;
@@ -443,7 +443,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         c->kappa[l] = (l > 0) ? std::sqrt((double)l * l / (4.0 * l * l - 1.0)) : 0.0;
     // Tile sets.  Sweeps: rows per tile from the tuning cache if it has this
     // shape, else chosen so the launch has >= kTargetTiles workgroups.
-    // Reductions (observables, Lanczos): up to 16 rows, >= 1024 workgroups.
+    // Reductions (Lanczos, copies): up to 16 rows, >= 1024 workgroups.
     // Populations: one tile per 256 radial points covering rows 0..min(lmax, 4).
     int64_t total_cols = 0;
     for (int k = 0; k < n_inst; ++k)
@@ -460,6 +460,12 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->rows_reduce = rr;
     build_tiles(c, kSweepTiles, c->rows_sweep);
     build_tiles(c, kReduceTiles, c->rows_reduce);
+    // observables: up to 16 rows, >= 256 workgroups (their rows are loaded in
+    // independent chunks, and fewer tiles leave less to finish)
+    int ro = 16;
+    while (ro > 1 && total_cols / ro < 256) ro /= 2;
+    c->rows_obs = ro;
+    build_tiles(c, kObsTiles, c->rows_obs);
     build_tiles(c, kPopTiles, 0);
     build_tiles(c, kFusedTiles, c->rows_fused);
     build_tiles(c, kPairTiles, c->rows_sweep);
@@ -542,7 +548,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->off_obs_tmp = take(sizeof(tdse_obs) * n_inst);
     c->off_lz = take(sizeof(LanczosScalars) * n_inst);
     c->partial_doubles = std::max((size_t)c->tiles[kReduceTiles].size() * 2 * kMaxKrylov,
-                                  (size_t)c->tiles[kReduceTiles].size() * kObsMainQ +
+                                  (size_t)c->tiles[kObsTiles].size() * kObsMainQ +
                                       (size_t)c->tiles[kPopTiles].size() * kObsPopQ);
     c->off_partial = take(sizeof(double) * c->partial_doubles);
     c->off_vecs = o;
@@ -622,6 +628,7 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         {c->off_inst, c->inst.data(), sizeof(Inst) * c->inst.size()},
         {c->off_tiles[kSweepTiles], c->tiles[kSweepTiles].data(), sizeof(Tile) * c->tiles[kSweepTiles].size()},
         {c->off_tiles[kReduceTiles], c->tiles[kReduceTiles].data(), sizeof(Tile) * c->tiles[kReduceTiles].size()},
+        {c->off_tiles[kObsTiles], c->tiles[kObsTiles].data(), sizeof(Tile) * c->tiles[kObsTiles].size()},
         {c->off_tiles[kPopTiles], c->tiles[kPopTiles].data(), sizeof(Tile) * c->tiles[kPopTiles].size()},
         {c->off_tiles[kFusedTiles], c->tiles[kFusedTiles].data(), sizeof(Tile) * c->tiles[kFusedTiles].size()},
         {c->off_tiles[kPairTiles], c->tiles[kPairTiles].data(), sizeof(Tile) * c->tiles[kPairTiles].size()},
@@ -783,7 +790,7 @@ hipError_t launch_obs(tdse_ctx* c, const void* psi, const double* step, double* 
                       int64_t rec_stride)
 {
     TimedLaunch tl(c, 2);
-    const SweepGeom red = c->geom(kReduceTiles), pop = c->geom(kPopTiles);
+    const SweepGeom red = c->geom(kObsTiles), pop = c->geom(kPopTiles);
     double* pmain = c->d_partial();
     double* ppop = pmain + (size_t)red.n_tiles * kObsMainQ;
     hipError_t e = launch_obs_partial(c->prec, red, pop, c->d_radial(), psi, pmain, ppop, c->stream);

@@ -15,12 +15,14 @@ constexpr int kMaxKrylov = 64;      // largest Lanczos dimension
 // Tile sets: the sweeps (H applications), the streaming reductions, the
 // population projections (rows l <= 4 only) and the fused Horner launches
 // (radially overlapping tiles, see k_horner_fused).
-// Tile sets: sweeps at 256 radii per tile (also RK4 stages), reductions,
-// populations, fused Horner terms (LDS rings), sweeps at 512 radii per tile
-// (two radii per thread), and fused Horner terms on wave strips.
+// Tile sets: sweeps at 256 radii per tile (also RK4 stages), reductions
+// (Lanczos, copies), populations, fused Horner terms (LDS rings), sweeps at
+// 512 radii per tile (two radii per thread), fused Horner terms on wave
+// strips, and the observables' norm / dipole pass (taller tiles: fewer
+// partial sums to finish).
 enum TileSetId {
     kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kFusedTiles = 3, kPairTiles = 4, kStripTiles = 5,
-    kNumTileSets = 6
+    kObsTiles = 6, kNumTileSets = 7
 };
 constexpr int kMaxFused = 8;        // most Horner terms per fused launch
 

@@ -136,3 +136,33 @@ def test_batch_256_sampled_members(sweep, fusion):
             f"norm diff {norm_d:.2e} p_bound rel {pb:.2e}")
         assert err < 5e-7 and norm_d < 1e-6 and pb < 1e-5
     prop.close()
+
+
+def test_n20000_l64_fp32_lanczos20_steps():
+    # the Lanczos workload at full size: FP32 basis vectors and state, FP64
+    # dots, re-orthogonalisation and exponential, against the FP64 oracle
+    t = lib()
+    wl = workloads.WORKLOADS["hydrogen_n20000_l64_fp32_lanczos20"]
+    say(f"full size {wl.name}: 3 Lanczos-20 steps vs the FP64 oracle")
+    g = t.Grid(wl.n, wl.lmax, wl.dr, wl.stencil, t.FP32, 1.0, wl.r_ion)
+    prop = t.Propagator([g], methods=((t.METHOD_LANCZOS, wl.order),))
+    prop.set_state(0, None)
+    p = t.Pulse(wl.pulse.e0, wl.pulse.omega, wl.pulse.n_cycles, wl.pulse.cep, wl.pulse.t_on)
+    t0 = 0.5 * wl.pulse.duration
+    obs = prop.obs_buffer(3, 1)
+    prop.step_lanczos(p, t0, wl.dt, wl.order, 3, 1, obs)
+    got = prop.get_state(0)
+    gobs = obs.cpu().numpy()[0]
+    prop.close()
+    og = orc_grid(g)
+    setup = oracle.obs_setup(og, r_ion=wl.r_ion)
+    psi0, _ = oracle.initial_state(og)
+    ref, robs, _ = oracle.propagate(og, orc_pulse(p), oracle.LANCZOS, wl.order, t0, wl.dt, 3, 1, setup,
+                                    to_fp32(psi0))
+    err = rel_err(got, ref)
+    norm_d = np.max(np.abs(gobs[:, 2] - robs[:, 2]))
+    pb = np.max(np.abs(gobs[:, 4] - robs[:, 4]) / robs[:, 4])
+    say(f"  state {err:.2e}  norm diff {norm_d:.2e}  p_bound rel {pb:.2e}")
+    # FP32 storage of the state and of 20 basis vectors per step: a few FP32
+    # roundings per element and step
+    assert err < 2e-6 and norm_d < 1e-6 and pb < 1e-5
