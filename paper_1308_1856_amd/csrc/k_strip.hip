@@ -17,8 +17,8 @@
 // rho (one iteration ago) and rho+1 (this iteration): each level keeps its
 // last two rows in registers, per thread.  Level k is skipped while
 // it < 2(k-1) (rows no output depends on).  The input rows and psi are read
-// once per iteration with one iteration of prefetch; psi(rho_1) is passed
-// down a shift register to the later levels.
+// once per iteration, one iteration ahead of use; psi(rho_1) is passed down a
+// shift register to the later levels.
 //
 // Every element is computed by h_point and horner_update, the functions of
 // the single-term sweeps, from the same FP64 operands, so FP64 results are
@@ -44,16 +44,17 @@ __device__ __forceinline__ double2 pick2(bool c, double2 a, double2 b)
 }
 // Radial neighbours across the wave by DPP whole-wave shifts (a VALU move,
 // no LDS round trip): wave_shr:1 gives lane i the value of lane i-1,
-// wave_shl:1 the value of lane i+1.  The end lanes receive 0; they are outside
-// the strip's exact region anyway.
+// wave_shl:1 the value of lane i+1.  The end lanes receive 0 (bound_ctrl: the
+// move writes zero where the source lane does not exist, so the destination
+// needs no initial value); they are outside the strip's exact region anyway.
 constexpr int kDppWaveShr1 = 0x138;
 constexpr int kDppWaveShl1 = 0x130;
 template <int CTRL>
 __device__ __forceinline__ double dpp_shift(double v)
 {
     const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, true);
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 template <int CTRL>
@@ -61,6 +62,20 @@ __device__ __forceinline__ double2 dpp_shift2(double2 v)
 {
     return make_double2(dpp_shift<CTRL>(v.x), dpp_shift<CTRL>(v.y));
 }
+// kappa_l at a wave-uniform row l in [0, lmax], read through the constant
+// address space so that it becomes a scalar load: the table is read-only in
+// every launch, and scalar loads are counted apart from the vector loads of
+// the rows in flight, so using kappa does not wait for the prefetch.
+using ConstDouble = const __attribute__((address_space(4))) double;
+__device__ __forceinline__ double kappa_at(const double* kappa, int l)
+{
+    return ((ConstDouble*)kappa)[l];
+}
+// An empty statement that reads and may rewrite v in registers and may touch
+// memory: whatever computes v stays before it, and no load or store moves
+// across it.  It emits no instruction.
+__device__ __forceinline__ void pin(double2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y) : : "memory"); }
+__device__ __forceinline__ void pin(float2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y) : : "memory"); }
 // value of lane - d / lane + d (d = 1 or 2)
 __device__ __forceinline__ double2 lane_below(double2 v, int d)
 {
@@ -97,6 +112,12 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         const double2 v = widen(raw);
         return MASKED ? pick2(inside, v, zero2()) : v;
     };
+    // kappa_l for 1 <= l <= lmax, else 0 (the index is clamped so the load
+    // itself is always in bounds)
+    auto kap = [&](int l) -> double {
+        const double v = kappa_at(g.kappa, min(max(l, 0), lmax));
+        return (l >= 1 && l <= lmax) ? v : 0.0;
+    };
     // H at row rr of the level below: centre c, rows rr-1 / rr+1 at this radius
     auto h_row = [&](double2 c, double2 lm, double2 lp, int rr) -> double2 {
         const double2 m1 = lane_below(c, 1), p1 = lane_above(c, 1);
@@ -105,21 +126,23 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
             m2 = lane_below(c, 2);
             p2 = lane_above(c, 2);
         }
-        const double kl = (rr >= 1 && rr <= lmax) ? g.kappa[rr] : 0.0;
-        const double klp = (rr >= 0 && rr < lmax) ? g.kappa[rr + 1] : 0.0;
-        return h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2, row_potential(rr, inv_r2, z_over_r), er, kl, klp);
+        // coupling to row rr-1 is kappa_rr, to row rr+1 kappa_{rr+1}; both zero
+        // where the other row is outside [0, lmax]
+        return h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2, row_potential(rr, inv_r2, z_over_r), er,
+                          kap(rr), kap(rr + 1));
     };
 
     const int rho0 = I.l0 - K + 1;              // level-1 row at it = 0
-    // input rows rho-1, rho (FP64) and rho+1 (raw, in flight) of the current iteration
+    // input rows rho-1, rho (FP64) of the current iteration; x_p (raw) holds
+    // row rho+1 and ps psi(rho), both loaded one iteration ahead
     double2 xm = widen_lane(rowp(in_i, rho0 - 1)[jc]);
     double2 xc = widen_lane(rowp(in_i, rho0)[jc]);
     C x_p = rowp(in_i, rho0 + 1)[jc];
-    // psi(rho_k) for level k = 1..K: pr[k-1]; pr[0] arrives one iteration ahead
+    C ps = rowp(psi_i, rho0)[jc];
+    // psi(rho_k) for level k = 1..K: pr[k-1]
     C pr[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) pr[k] = zero_c<C>();
-    pr[0] = rowp(psi_i, rho0)[jc];
     // level k (1..K-1): a = row rho_k - 1, b = row rho_k - 2 (FP64)
     double2 ra[K > 1 ? K - 1 : 1], rb[K > 1 ? K - 1 : 1];
 #pragma unroll
@@ -129,10 +152,19 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     auto body = [&](int it, auto check) {
         constexpr bool CHECK = decltype(check)::value;
         const int rho = rho0 + it;
-        // prefetch for the next iteration
-        const C x_n = rowp(in_i, rho + 2)[jc];
-        const C p_n = rowp(psi_i, rho + 1)[jc];
-        const double2 xp = widen_lane(x_p);
+        // take the rows loaded one iteration ago, then reload the same
+        // registers for the next iteration.  pin() keeps the reads of the old
+        // values ahead of the new loads; otherwise the compiler sinks them past
+        // the loads, the old and new values overlap, and the register copy it
+        // then needs at the loop end waits for the load just issued.
+        double2 xp = widen_lane(x_p);
+#pragma unroll
+        for (int k = K - 1; k > 0; --k) pr[k] = pr[k - 1];
+        pr[0] = ps;
+        pin(xp);
+        pin(pr[0]);
+        x_p = rowp(in_i, rho + 2)[jc];
+        ps = rowp(psi_i, rho + 1)[jc];
 
         // level 1 from the input
         double2 up = horner_update(widen(pr[0]), h_row(xc, xm, xp, rho), coef[0]);
@@ -153,13 +185,9 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
             up = v;
             if (k == K && writes && rk >= I.l0 && rk < I.l1) stc(out_i, (int64_t)rk * n + jc, v);
         }
-        // shift the window and the psi register
+        // shift the window
         xm = xc;
         xc = xp;
-        x_p = x_n;
-#pragma unroll
-        for (int k = K - 1; k > 0; --k) pr[k] = pr[k - 1];
-        pr[0] = p_n;
     };
     const int iters = (I.l1 - I.l0) + 2 * K - 2;
     const int warm = min(2 * (K - 1), iters);

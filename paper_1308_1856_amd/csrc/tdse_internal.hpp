@@ -12,9 +12,6 @@ constexpr int kBlock = 256;         // threads per workgroup of the sweep kernel
 constexpr int kMaxStates = 15;      // bound states n <= 5
 constexpr int kMaxKrylov = 64;      // largest Lanczos dimension
 
-// Tile sets: the sweeps (H applications), the streaming reductions, the
-// population projections (rows l <= 4 only) and the fused Horner launches
-// (radially overlapping tiles, see k_horner_fused).
 // Tile sets: sweeps at 256 radii per tile (also RK4 stages), reductions
 // (Lanczos, copies), populations, fused Horner terms (LDS rings), sweeps at
 // 512 radii per tile (two radii per thread), fused Horner terms on wave
