@@ -88,6 +88,17 @@ __device__ __forceinline__ int my_tile_index(const SweepGeom& g)
 }
 __device__ __forceinline__ Tile my_tile(const SweepGeom& g) { return g.tiles[my_tile_index(g)]; }
 
+// A load through the constant address space, for tables that no launch
+// writes, read at wave-uniform indexes: it becomes a scalar load, which is
+// counted apart from the vector loads in flight, so using the value does not
+// wait for them (a plain load after a store in the same kernel stays a vector
+// load: the compiler cannot tell that the store does not reach the table).
+template <typename X>
+__device__ __forceinline__ X ld_const(const X* p, int64_t i)
+{
+    return ((const __attribute__((address_space(4))) X*)p)[i];
+}
+
 // Stencil weights of -1/2 D2 (zero-padded 3- or 5-point second difference).
 template <int S> struct Kin;
 template <> struct Kin<1> {

@@ -62,15 +62,6 @@ __device__ __forceinline__ double2 dpp_shift2(double2 v)
 {
     return make_double2(dpp_shift<CTRL>(v.x), dpp_shift<CTRL>(v.y));
 }
-// kappa_l at a wave-uniform row l in [0, lmax], read through the constant
-// address space so that it becomes a scalar load: the table is read-only in
-// every launch, and scalar loads are counted apart from the vector loads of
-// the rows in flight, so using kappa does not wait for the prefetch.
-using ConstDouble = const __attribute__((address_space(4))) double;
-__device__ __forceinline__ double kappa_at(const double* kappa, int l)
-{
-    return ((ConstDouble*)kappa)[l];
-}
 // An empty statement that reads and may rewrite v in registers and may touch
 // memory: whatever computes v stays before it, and no load or store moves
 // across it.  It emits no instruction.
@@ -115,7 +106,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     // kappa_l for 1 <= l <= lmax, else 0 (the index is clamped so the load
     // itself is always in bounds)
     auto kap = [&](int l) -> double {
-        const double v = kappa_at(g.kappa, min(max(l, 0), lmax));
+        const double v = ld_const(g.kappa, min(max(l, 0), lmax));  // a scalar load
         return (l >= 1 && l <= lmax) ? v : 0.0;
     };
     // H at row rr of the level below: centre c, rows rr-1 / rr+1 at this radius
@@ -133,12 +124,20 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     };
 
     const int rho0 = I.l0 - K + 1;              // level-1 row at it = 0
-    // input rows rho-1, rho (FP64) of the current iteration; x_p (raw) holds
-    // row rho+1 and ps psi(rho), both loaded one iteration ahead
+    // input rows rho-1, rho (FP64) of the current iteration
     double2 xm = widen_lane(rowp(in_i, rho0 - 1)[jc]);
     double2 xc = widen_lane(rowp(in_i, rho0)[jc]);
-    C x_p = rowp(in_i, rho0 + 1)[jc];
-    C ps = rowp(psi_i, rho0)[jc];
+    // Rows are loaded two iterations ahead, into two register slots that the
+    // even and odd iterations take in turn: the slot of iteration it holds
+    // input row rho+1 and psi(rho) and is reloaded, in place, with the rows
+    // of iteration it+2.  Two iterations of loads in flight per wave instead
+    // of one: with 8-byte FP32 elements one iteration of loads is too little
+    // to cover the memory latency.
+    struct Slot {
+        C x, p;
+    };
+    Slot sa{rowp(in_i, rho0 + 1)[jc], rowp(psi_i, rho0)[jc]};
+    Slot sb{rowp(in_i, rho0 + 2)[jc], rowp(psi_i, rho0 + 1)[jc]};
     // psi(rho_k) for level k = 1..K: pr[k-1]
     C pr[K];
 #pragma unroll
@@ -149,22 +148,22 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     for (int k = 0; k < (K > 1 ? K - 1 : 1); ++k) ra[k] = rb[k] = zero2();
 
     // one iteration; CHECK: some levels may not have reached their first row yet
-    auto body = [&](int it, auto check) {
+    auto body = [&](int it, Slot& sl, auto check) {
         constexpr bool CHECK = decltype(check)::value;
         const int rho = rho0 + it;
-        // take the rows loaded one iteration ago, then reload the same
-        // registers for the next iteration.  pin() keeps the reads of the old
-        // values ahead of the new loads; otherwise the compiler sinks them past
-        // the loads, the old and new values overlap, and the register copy it
-        // then needs at the loop end waits for the load just issued.
-        double2 xp = widen_lane(x_p);
+        // take the slot's rows, then reload the same registers for iteration
+        // it+2.  pin() keeps the reads of the old values ahead of the new
+        // loads; otherwise the compiler sinks them past the loads, the old and
+        // new values overlap, and the register copy it then needs at the loop
+        // end waits for the load just issued.
+        double2 xp = widen_lane(sl.x);
 #pragma unroll
         for (int k = K - 1; k > 0; --k) pr[k] = pr[k - 1];
-        pr[0] = ps;
+        pr[0] = sl.p;
         pin(xp);
         pin(pr[0]);
-        x_p = rowp(in_i, rho + 2)[jc];
-        ps = rowp(psi_i, rho + 1)[jc];
+        sl.x = rowp(in_i, rho + 3)[jc];
+        sl.p = rowp(psi_i, rho + 2)[jc];
 
         // level 1 from the input
         double2 up = horner_update(widen(pr[0]), h_row(xc, xm, xp, rho), coef[0]);
@@ -188,12 +187,26 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         // shift the window
         xm = xc;
         xc = xp;
+        // keep the two iterations of a loop trip apart: interleaving them
+        // would hold both iterations' values in registers at once
+        __builtin_amdgcn_sched_barrier(0);
     };
+    // iters > warm = 2(K-1), an even count: even iterations take slot a
     const int iters = (I.l1 - I.l0) + 2 * K - 2;
-    const int warm = min(2 * (K - 1), iters);
+    const int warm = 2 * (K - 1);
     int it = 0;
-    for (; it < warm; ++it) body(it, std::true_type{});
-    for (; it < iters; ++it) body(it, std::false_type{});
+    // not unrolled: its trip count K-1 is a constant, and the straight-line
+    // code of a full unroll would be scheduled into many more live registers
+#pragma clang loop unroll(disable)
+    for (; it < warm; it += 2) {
+        body(it, sa, std::true_type{});
+        body(it + 1, sb, std::true_type{});
+    }
+    for (; it + 1 < iters; it += 2) {
+        body(it, sa, std::false_type{});
+        body(it + 1, sb, std::false_type{});
+    }
+    if (it < iters) body(it, sa, std::false_type{});
 }
 
 template <int S, typename T, int K>
