@@ -33,33 +33,84 @@ __device__ __forceinline__ double wave_uniform(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// A lane's value of v, as a wave-uniform (scalar) value.
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// DPP lane permutations inside each row of 16 lanes (every source lane exists).
+constexpr int kDppQuadXor1 = 0xB1;       // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int kDppQuadXor2 = 0x4E;       // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int kDppRowHalfMirror = 0x141; // lane 7 - i within each 8 lanes
+constexpr int kDppRowMirror = 0x140;     // lane 15 - i within each 16 lanes
+// Across rows: lane 15 of row r to every lane of row r + 1, lane 31 to rows 2
+// and 3 (only the rows enabled by the row mask are written).
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// v of the lane that the row broadcast CTRL names, in the rows ROW_MASK
+// enables; 0 in the other rows.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_bcast(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum of v over the 64 lanes of the wave, in registers (no LDS round trip),
+// returned as a wave-uniform value.  Inside each row of 16 lanes, v is added
+// to its partner at lane ^ 1, then at lane ^ 2, then at its mirror in the half
+// row and in the row: each step adds two values that the partner lane adds in
+// the other order, and a + b = b + a exactly, so every lane of row r ends
+// with the same row sum s_r.  Then rows 1 and 3 add the sums of rows 0 and 2,
+// and row 3 adds the result of row 1: lane 63 holds
+// (s_2 + s_3) + (s_0 + s_1).  Every lane of the wave must be active.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_row<kDppQuadXor1>(v);
+    v += dpp_row<kDppQuadXor2>(v);
+    v += dpp_row<kDppRowHalfMirror>(v);
+    v += dpp_row<kDppRowMirror>(v);
+    v += dpp_bcast<kDppRowBcast15, 0xa>(v);   // rows 1, 3; rows 0, 2 add +0 (exact)
+    v += dpp_bcast<kDppRowBcast31, 0xc>(v);   // rows 2, 3
+    return lane_value(v, 63);
+}
+
 // Block-wide sums of NQ values for a kBlock-thread block.  Thread q < NQ of
-// the block receives the sum of value q in `out_q` (others get 0).  The
-// summation tree depends only on thread indices, so results are bitwise
-// reproducible.  The butterfly runs stage by stage over groups of up to 4
-// values (not value by value), so the independent shuffles of a stage overlap
-// instead of paying the shuffle latency once per value; each value's tree is the xor
-// butterfly 32, 16, ..., 1 over the wave's lanes.  Must be reached by every
-// thread of the block.
+// the block receives the sum of value q (others get 0): wave_sum in each
+// wave, then the kBlock / 64 wave sums in wave order.  The summation tree
+// depends only on lane and wave indices, so results are bitwise reproducible.
+// Values go through in groups of 4, each group's sums stored before the next
+// group starts, so few sums are held in registers at once.  Must be reached by
+// every thread of the block.
 template <int NQ>
 __device__ __forceinline__ double block_sum(double (&v)[NQ], double* lds /* [kBlock/64][NQ] */)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    // groups of (at most) 4 values: independent shuffles per stage to hide
-    // their latency, few enough not to raise the register count of the caller
     constexpr int G = NQ < 4 ? NQ : 4;
 #pragma unroll
     for (int q0 = 0; q0 < NQ; q0 += G) {
+        double s[G];
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int q = q0; q < q0 + G && q < NQ; ++q) v[q] += __shfl_xor(v[q], off, 64);
-        }
-        // each group's totals leave the registers at once
+        for (int q = q0; q < q0 + G && q < NQ; ++q) s[q - q0] = wave_sum(v[q]);
         if (lane == 0) {
 #pragma unroll
-            for (int q = q0; q < q0 + G && q < NQ; ++q) lds[wave * NQ + q] = v[q];
+            for (int q = q0; q < q0 + G && q < NQ; ++q) lds[wave * NQ + q] = s[q - q0];
         }
     }
     __syncthreads();

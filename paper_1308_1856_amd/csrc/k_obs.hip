@@ -1,10 +1,10 @@
 // Observables of Sec. 4 as FP64 reductions in a fixed order:
 //   norm, p_ion (eq. yield_1), <z> (eq. Dipole), <z''> (eq. DipoleAccel),
 //   p_g (eq. p_g) and the bound-state projections P_nl.
-// Pass 1 has two roles in one launch: workgroups [0, n_obs) stream every
-// row of their tile (the observables' tile set) and sum 4 values; the remaining workgroups each
-// take one population tile (rows l <= 4 of 256 radial points) and sum the 32
-// projection values.  Partials are stored [q][tile] so that pass 2 (one
+// Pass 1 has two roles in one launch: the first workgroups each take one
+// population tile (rows l <= 4 of 256 radial points) and sum the 32
+// projection values; the others each stream the rows of one tile of the
+// observables' tile set (at most kObsRows rows) and sum 4 values.  Partials are stored [q][tile] so that pass 2 (one
 // workgroup per instance, adding its tiles in tile order) reads them
 // coalesced.  Results do not depend on scheduling.
 #include "device_common.hpp"
@@ -12,10 +12,9 @@
 namespace tdse {
 
 template <typename T>
-__device__ __forceinline__ void obs_main(const SweepGeom& g, const typename Cplx<T>::type* __restrict__ psi,
+__device__ __forceinline__ void obs_main(const SweepGeom& g, int t, const typename Cplx<T>::type* __restrict__ psi,
                                          double* __restrict__ partial, double* lds)
 {
-    const int t = my_tile_index(g);
     const Tile I = g.tiles[t];
     const int n = I.n;
     const int i = I.r0 + (int)threadIdx.x;
@@ -23,30 +22,27 @@ __device__ __forceinline__ void obs_main(const SweepGeom& g, const typename Cplx
     if (i < n) {
         const RadialPoint rp = radial_point(I, i);
         const bool outer = i >= I.i_ion;
-        // rows in chunks of four: the four loads of a chunk are independent and
-        // in flight together (one memory latency per chunk, not per row)
-        const int last = min(I.l1, I.lmax);     // the highest row a tile reads
-        double2 cur = ldc(psi, I.off + (int64_t)I.l0 * n + i);
-        for (int l = I.l0; l < I.l1; l += 4) {
-            double2 r[5];
-            r[0] = cur;
+        // all rows of the tile (at most kObsRows) and the row above it are
+        // loaded before any is used: one memory latency per tile
+        const int nr = I.l1 - I.l0;
+        const int last = min(I.l1, I.lmax);     // the highest row the tile reads
+        double2 r[kObsRows + 1];
 #pragma unroll
-            for (int u = 1; u <= 4; ++u) {
-                const double2 v = ldc(psi, I.off + (int64_t)min(l + u, last) * n + i);
-                r[u] = (l + u <= I.lmax) ? v : zero2();
-            }
+        for (int u = 0; u <= kObsRows; ++u) {
+            const int l = I.l0 + u;
+            r[u] = (u <= nr && l <= I.lmax) ? ldc(psi, I.off + (int64_t)min(l, last) * n + i) : zero2();
+        }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (l + u < I.l1) {
-                    const double a2 = fma(r[u].x, r[u].x, r[u].y * r[u].y);
-                    acc[0] += a2;
-                    if (outer) acc[1] += a2;
-                    const double re = fma(r[u].x, r[u + 1].x, r[u].y * r[u + 1].y) * g.kappa[l + u + 1];
-                    acc[2] = fma(rp.r, re, acc[2]);
-                    acc[3] = fma(re, rp.inv_r2, acc[3]);
-                }
+        for (int u = 0; u < kObsRows; ++u) {
+            if (u < nr) {
+                const int l = I.l0 + u;
+                const double a2 = fma(r[u].x, r[u].x, r[u].y * r[u].y);
+                acc[0] += a2;
+                if (outer) acc[1] += a2;
+                const double re = fma(r[u].x, r[u + 1].x, r[u].y * r[u + 1].y) * ld_const(g.kappa, l + 1);
+                acc[2] = fma(rp.r, re, acc[2]);
+                acc[3] = fma(re, rp.inv_r2, acc[3]);
             }
-            cur = r[4];
         }
     }
     const double s = block_sum<kObsMainQ>(acc, lds);
@@ -93,11 +89,15 @@ k_obs_partial(SweepGeom red, SweepGeom pop, const double* __restrict__ radial,
               double* __restrict__ partial_pop)
 {
     __shared__ double lds[(kBlock / 64) * kObsPopQ];
-    if ((int)blockIdx.x < red.n_tiles)
-        obs_main<T>(red, psi, partial_main, lds);
+    // the population tiles (more loads and sums each) go first, so they are
+    // not the last workgroups of the launch
+    if ((int)blockIdx.x < pop.n_tiles)
+        obs_pop<T>(pop, (int)blockIdx.x, radial, psi, partial_pop, lds);
     else
-        obs_pop<T>(pop, (int)blockIdx.x - red.n_tiles, radial, psi, partial_pop, lds);
+        obs_main<T>(red, (int)blockIdx.x - pop.n_tiles, psi, partial_main, lds);
 }
+
+constexpr int kFinishU = 8;
 
 __global__ void __launch_bounds__(kBlock)
 k_obs_finish(SweepGeom red, SweepGeom pop, const double* __restrict__ pmain,
@@ -109,12 +109,29 @@ k_obs_finish(SweepGeom red, SweepGeom pop, const double* __restrict__ pmain,
     __shared__ double tot[Q];
     const int k = blockIdx.x;
     const Inst& I = red.inst[k];
+    // the step scalars of the record, loaded now rather than after the sums
+    const double t_end = step_value(step, red.n_inst, kTEnd, k);
+    const double e = step_value(step, red.n_inst, kEEnd, k);
+    const int64_t ridx = (int64_t)step_value(step, red.n_inst, kRec, k);
     double acc[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-    for (int t = I.tbegin[kObsTiles] + (int)threadIdx.x; t < I.tend[kObsTiles]; t += kBlock) {
+    // up to kFinishU tiles per thread per pass, loaded before any is added:
+    // the partials come from every XCD, so each pass costs one memory latency
+    const int tb = I.tbegin[kObsTiles], te = I.tend[kObsTiles];
+    for (int t0 = tb + (int)threadIdx.x; t0 < te; t0 += kFinishU * kBlock) {
+        double v[kFinishU][kObsMainQ];
 #pragma unroll
-        for (int q = 0; q < kObsMainQ; ++q) acc[q] += pmain[(int64_t)q * red.n_tiles + t];
+        for (int u = 0; u < kFinishU; ++u) {
+            const int t = t0 + u * kBlock;
+#pragma unroll
+            for (int q = 0; q < kObsMainQ; ++q) v[u][q] = (t < te) ? pmain[(int64_t)q * red.n_tiles + t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinishU; ++u) {
+#pragma unroll
+            for (int q = 0; q < kObsMainQ; ++q) acc[q] += v[u][q];
+        }
     }
     for (int t = I.tbegin[kPopTiles] + (int)threadIdx.x; t < I.tend[kPopTiles]; t += kBlock) {
 #pragma unroll
@@ -125,11 +142,9 @@ k_obs_finish(SweepGeom red, SweepGeom pop, const double* __restrict__ pmain,
     __syncthreads();
     if (threadIdx.x == 0) {
         const double dr = I.dr;
-        const double e = step_value(step, red.n_inst, kEEnd, k);
-        const int64_t ridx = (int64_t)step_value(step, red.n_inst, kRec, k);
         double* rec = records + (int64_t)k * rec_stride + ridx * kObsRecord;
         const double* pp = tot + kObsMainQ;
-        rec[0] = step_value(step, red.n_inst, kTEnd, k);
+        rec[0] = t_end;
         rec[1] = e;
         rec[2] = dr * tot[0];
         const double pgr = dr * pp[0], pgi = dr * pp[1];

@@ -460,9 +460,9 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->rows_reduce = rr;
     build_tiles(c, kSweepTiles, c->rows_sweep);
     build_tiles(c, kReduceTiles, c->rows_reduce);
-    // observables: up to 16 rows, >= 256 workgroups (their rows are loaded in
-    // independent chunks, and fewer tiles leave less to finish)
-    int ro = 16;
+    // observables: up to kObsRows rows (a thread loads all of its rows at
+    // once), >= 256 workgroups; taller tiles leave fewer partial sums to finish
+    int ro = kObsRows;
     while (ro > 1 && total_cols / ro < 256) ro /= 2;
     c->rows_obs = ro;
     build_tiles(c, kObsTiles, c->rows_obs);

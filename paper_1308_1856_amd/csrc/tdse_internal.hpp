@@ -116,6 +116,7 @@ hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, cons
 // over the reduce tiles (kObsMainQ per tile, stored [q][tile]) and of p_g and
 // the projections over the population tiles (kObsPopQ per tile, [q][tile]).
 constexpr int kObsMainQ = 4;
+constexpr int kObsRows = 16;   // most rows per tile of the observables' tile set
 constexpr int kObsRecord = 8 + kMaxStates;   // doubles per tdse_obs record
 constexpr int kObsPopQ = 2 + 2 * kMaxStates;
 hipError_t launch_obs_partial(int prec, const SweepGeom& red, const SweepGeom& pop,
