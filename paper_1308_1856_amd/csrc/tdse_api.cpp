@@ -69,6 +69,10 @@ struct tdse_ctx {
     hipEvent_t step_ev[2] = {nullptr, nullptr};
     bool step_ev_used[2] = {false, false};
     int step_buf = 0;
+    // the observables of the Taylor path run on a second stream (default
+    // priority), overlapping the next step; created on first use
+    hipStream_t obs_stream = nullptr;
+    hipEvent_t obs_fork = nullptr, obs_join = nullptr, obs_done[2] = {nullptr, nullptr};
     // captured step graphs, keyed by the launch pattern of a chunk
     bool use_graphs = false;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
@@ -561,6 +565,11 @@ extern "C" void tdse_destroy(tdse_ctx* c)
 {
     if (!c) return;
     c->drop_graphs();
+    if (c->obs_stream) {
+        (void)hipStreamSynchronize(c->obs_stream);
+        (void)hipStreamDestroy(c->obs_stream);
+        for (hipEvent_t ev : {c->obs_fork, c->obs_join, c->obs_done[0], c->obs_done[1]}) (void)hipEventDestroy(ev);
+    }
     for (auto& e : c->ev_pool) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -787,32 +796,66 @@ tdse_status check_stable(tdse_ctx* c, const tdse_pulse* pulses, const double* dt
 
 // observables of the state after step s (within the uploaded chunk at `step`)
 hipError_t launch_obs(tdse_ctx* c, const void* psi, const double* step, double* records,
-                      int64_t rec_stride)
+                      int64_t rec_stride, hipStream_t st)
 {
     TimedLaunch tl(c, 2);
     const SweepGeom red = c->geom(kObsTiles), pop = c->geom(kPopTiles);
     double* pmain = c->d_partial();
     double* ppop = pmain + (size_t)red.n_tiles * kObsMainQ;
-    hipError_t e = launch_obs_partial(c->prec, red, pop, c->d_radial(), psi, pmain, ppop, c->stream);
+    hipError_t e = launch_obs_partial(c->prec, red, pop, c->d_radial(), psi, pmain, ppop, st);
     if (e != hipSuccess) return e;
-    return launch_obs_finish(red, pop, pmain, ppop, step, rec_stride, records, c->stream);
+    return launch_obs_finish(red, pop, pmain, ppop, step, rec_stride, records, st);
+}
+
+static hipError_t ensure_obs_stream(tdse_ctx* c)
+{
+    if (c->obs_stream) return hipSuccess;
+    hipError_t e = hipStreamCreateWithFlags(&c->obs_stream, hipStreamNonBlocking);
+    for (hipEvent_t* ev : {&c->obs_fork, &c->obs_join, &c->obs_done[0], &c->obs_done[1]})
+        if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    return e;
 }
 
 // Enqueues the launches of steps [s0, s0 + count) of the current chunk.
 // *cur is the buffer holding psi (the state, or the ping-pong vector of the
 // fused Taylor path); a step function may move it.
+//
+// side: the observables of step s run on the second stream, concurrently with
+// step s+1.  This needs a step function that never writes the buffer holding
+// psi at its start (the Taylor rotation: psi(s) is overwritten first in step
+// s+2), and no timing.  Step s+2 waits for the observables of step s; the
+// second stream runs them in order (they share the partial-sum buffer) and
+// rejoins the main stream at the end of the chunk, so a chunk (and its
+// captured graph) leaves nothing running on it.
 template <typename StepFn>
 hipError_t enqueue_chunk(tdse_ctx* c, int64_t s0, int count, int32_t obs_every, tdse_obs* d_obs,
-                         int64_t rec_stride, void** cur, StepFn& step_fn)
+                         int64_t rec_stride, void** cur, StepFn& step_fn, bool side)
 {
+    auto obs_at = [&](int s) { return obs_every > 0 && s >= 0 && (s0 + s + 1) % obs_every == 0; };
+    bool forked = false;
     for (int s = 0; s < count; ++s) {
         const double* step = c->d_step() + (size_t)s * kSlots * c->n_inst;
-        hipError_t e = step_fn(step);
+        hipError_t e = hipSuccess;
+        if (side && obs_at(s - 2)) e = hipStreamWaitEvent(c->stream, c->obs_done[s & 1], 0);
+        if (e == hipSuccess) e = step_fn(step);
         if (e != hipSuccess) return e;
-        if (obs_every > 0 && (s0 + s + 1) % obs_every == 0) {
-            e = launch_obs(c, *cur, step, reinterpret_cast<double*>(d_obs), rec_stride);
-            if (e != hipSuccess) return e;
+        if (!obs_at(s)) continue;
+        if (!side) {
+            e = launch_obs(c, *cur, step, reinterpret_cast<double*>(d_obs), rec_stride, c->stream);
+        } else {
+            e = hipEventRecord(c->obs_fork, c->stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(c->obs_stream, c->obs_fork, 0);
+            if (e == hipSuccess)
+                e = launch_obs(c, *cur, step, reinterpret_cast<double*>(d_obs), rec_stride, c->obs_stream);
+            if (e == hipSuccess) e = hipEventRecord(c->obs_done[s & 1], c->obs_stream);
+            forked = true;
         }
+        if (e != hipSuccess) return e;
+    }
+    if (forked) {
+        hipError_t e = hipEventRecord(c->obs_join, c->obs_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->obs_join, 0);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -825,17 +868,22 @@ hipError_t enqueue_chunk(tdse_ctx* c, int64_t s0, int count, int32_t obs_every, 
 template <typename StepFn>
 tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, const double* dt,
                       int32_t nsteps, int32_t obs_every, tdse_obs* d_obs, int64_t method_key,
-                      void** cur, StepFn&& step_fn)
+                      void** cur, StepFn&& step_fn, bool obs_side_ok = false)
 {
     const int64_t n_rec = (obs_every > 0) ? nsteps / obs_every : 0;
     const int64_t rec_stride = n_rec * (int64_t)kObsRecord;
     const bool graphs = c->use_graphs && !c->timing && c->stream != nullptr;
+    const bool side = obs_side_ok && obs_every > 0 && !c->timing;
+    if (side) {
+        hipError_t e = ensure_obs_stream(c);
+        if (e != hipSuccess) return c->hip_fail(e, "observables stream");
+    }
     for (int64_t s0 = 0; s0 < nsteps; s0 += kEtabSteps) {
         const int count = (int)std::min<int64_t>(kEtabSteps, nsteps - s0);
         tdse_status st = upload_steps(c, pulses, t0, dt, s0, count, obs_every);
         if (st != TDSE_OK) return st;
         if (!graphs) {
-            hipError_t e = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn);
+            hipError_t e = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn, side);
             if (e != hipSuccess) return c->hip_fail(e, "step launch");
             continue;
         }
@@ -848,7 +896,7 @@ tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, c
         if (it == c->graphs.end()) {
             hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return c->hip_fail(e, "hipStreamBeginCapture");
-            hipError_t el = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn);
+            hipError_t el = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn, side);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(c->stream, &graph);
             if (el != hipSuccess) {
@@ -974,8 +1022,10 @@ extern "C" tdse_status tdse_step_taylor(tdse_ctx* c, const tdse_pulse* pulses, c
     if (st != TDSE_OK) return st;
     void* cur = c->d_state;
     const int64_t key = 1000 + 100 * c->fuse_k + 20 * c->fuse_kind + order;
+    // the Taylor rotation never writes the buffer holding psi at the start of
+    // a step, so the observables may overlap the next step
     return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, key, &cur,
-                     [&](const double* step) { return taylor_step_launches(c, step, order, cur); });
+                     [&](const double* step) { return taylor_step_launches(c, step, order, cur); }, true);
 }
 
 extern "C" tdse_status tdse_step_rk4(tdse_ctx* c, const tdse_pulse* pulses, const double* t0,
@@ -1063,7 +1113,7 @@ extern "C" tdse_status tdse_observables(tdse_ctx* c, const tdse_pulse* pulses, c
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_step() + kEEnd * c->n_inst, ee.data(), sizeof(double) * c->n_inst,
                            hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = launch_obs(c, c->d_state, c->d_step(), tmp, kObsRecord);
+    if (e == hipSuccess) e = launch_obs(c, c->d_state, c->d_step(), tmp, kObsRecord, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host_out, tmp, sizeof(tdse_obs) * c->n_inst, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -437,6 +437,34 @@ def test_fused_taylor_batch_bitwise(kind):
         assert np.array_equal(res[0][k], res[1][k]), k
 
 
+@pytest.mark.parametrize("obs_every", [1, 2, 3])
+def test_observables_beside_next_step_bitwise(obs_every):
+    # The Taylor path computes the observables of step s on a second stream,
+    # beside step s+1.  States and records must equal a timed run (timing keeps
+    # every launch on one stream, in order), with and without graphs, over
+    # more than one chunk of steps.
+    t = lib()
+    grid = t.Grid(4000, 16, 0.1, 5, t.FP64, 1.0, 100.0)
+    pulse = t.Pulse(0.05, 0.2, 2.0, 0.0, 0.0)
+    nsteps = 300
+    say(f"observables every {obs_every} step(s) beside the next step vs serial (timed) launches")
+    out = []
+    for mode in ("timed", "direct", "graphs"):
+        prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),), graphs=(mode == "graphs"))
+        prop.set_taylor_fusion(4, 8, 1)
+        if mode == "timed":
+            prop.timing(True)
+        dt = 0.8 * t.tdse_taylor_stability_limit(8) / prop.lambda_max_bound(0, 0.05)
+        prop.set_state(0, None)
+        obs = prop.obs_buffer(nsteps, obs_every)
+        prop.step_taylor(pulse, 0.0, dt, 8, nsteps, obs_every, obs)
+        out.append((prop.get_state(0), obs.cpu().numpy()))
+        prop.close()
+    for state, rec in out[1:]:
+        assert np.array_equal(state, out[0][0])
+        assert np.array_equal(rec, out[0][1])
+
+
 def test_explicit_sweep_shape_bitwise():
     # an explicit sweep shape (as the bench uses to reproduce a tuned one) gives the same bits
     t = lib()
