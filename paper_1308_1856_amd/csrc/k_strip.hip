@@ -87,6 +87,8 @@ __device__ __forceinline__ double2 lane_above(double2 v, int d)
 // single-term sweep's zero padding in l.  For the valid rows the coupling
 // coefficients are the sweep's (kappa_{lmax+1} multiplies the zero row above
 // lmax in the sweep; zero here gives the same bits).
+constexpr int kStripDepth = 3;   // iterations of row loads in flight per wave (measured: 3 beats 2 and 4)
+
 template <int S, typename T, int K, bool MASKED>
 __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, const typename Cplx<T>::type* in_i,
                                            const typename Cplx<T>::type* psi_i, typename Cplx<T>::type* out_i,
@@ -127,17 +129,19 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     // input rows rho-1, rho (FP64) of the current iteration
     double2 xm = widen_lane(rowp(in_i, rho0 - 1)[jc]);
     double2 xc = widen_lane(rowp(in_i, rho0)[jc]);
-    // Rows are loaded two iterations ahead, into two register slots that the
-    // even and odd iterations take in turn: the slot of iteration it holds
-    // input row rho+1 and psi(rho) and is reloaded, in place, with the rows
-    // of iteration it+2.  Two iterations of loads in flight per wave instead
-    // of one: with 8-byte FP32 elements one iteration of loads is too little
-    // to cover the memory latency.
+    // Rows are loaded D = kStripDepth iterations ahead, into D register slots
+    // that the iterations take in turn (iteration it uses slot it mod D): the
+    // slot holds input row rho+1 and psi(rho) and is reloaded, in place, with
+    // the rows of iteration it+D.  One iteration of loads in flight per wave
+    // is too little to cover the memory latency (with 8-byte FP32 elements
+    // above all).
+    constexpr int D = kStripDepth;
     struct Slot {
         C x, p;
     };
-    Slot sa{rowp(in_i, rho0 + 1)[jc], rowp(psi_i, rho0)[jc]};
-    Slot sb{rowp(in_i, rho0 + 2)[jc], rowp(psi_i, rho0 + 1)[jc]};
+    Slot sl[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) sl[u] = Slot{rowp(in_i, rho0 + 1 + u)[jc], rowp(psi_i, rho0 + u)[jc]};
     // psi(rho_k) for level k = 1..K: pr[k-1]
     C pr[K];
 #pragma unroll
@@ -152,7 +156,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         constexpr bool CHECK = decltype(check)::value;
         const int rho = rho0 + it;
         // take the slot's rows, then reload the same registers for iteration
-        // it+2.  pin() keeps the reads of the old values ahead of the new
+        // it+D.  pin() keeps the reads of the old values ahead of the new
         // loads; otherwise the compiler sinks them past the loads, the old and
         // new values overlap, and the register copy it then needs at the loop
         // end waits for the load just issued.
@@ -162,8 +166,8 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         pr[0] = sl.p;
         pin(xp);
         pin(pr[0]);
-        sl.x = rowp(in_i, rho + 3)[jc];
-        sl.p = rowp(psi_i, rho + 2)[jc];
+        sl.x = rowp(in_i, rho + 1 + D)[jc];
+        sl.p = rowp(psi_i, rho + D)[jc];
 
         // level 1 from the input
         double2 up = horner_update(widen(pr[0]), h_row(xc, xm, xp, rho), coef[0]);
@@ -187,26 +191,33 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         // shift the window
         xm = xc;
         xc = xp;
-        // keep the two iterations of a loop trip apart: interleaving them
-        // would hold both iterations' values in registers at once
+        // keep the iterations of a loop trip apart: interleaving them would
+        // hold several iterations' values in registers at once
         __builtin_amdgcn_sched_barrier(0);
     };
-    // iters > warm = 2(K-1), an even count: even iterations take slot a
-    const int iters = (I.l1 - I.l0) + 2 * K - 2;
-    const int warm = 2 * (K - 1);
+    // Loop trips of D iterations (iteration it + u takes slot u): first the
+    // trips that hold the warm-up iterations it < 2(K-1) (levels still
+    // starting; kept rolled, as the trip count is a constant and the
+    // straight-line code of a full unroll would be scheduled into many more
+    // live registers), then the steady trips, then a tail of fewer than D
+    // iterations.  A tile too short to reach the end of the warm-up trips
+    // runs on to it: the extra iterations compute rows past l1 (inputs
+    // outside [0, lmax] read as zero) and store nothing.
+    const int warm_trips_end = (2 * (K - 1) + D - 1) / D * D;
+    const int iters = max((I.l1 - I.l0) + 2 * K - 2, warm_trips_end);
     int it = 0;
-    // not unrolled: its trip count K-1 is a constant, and the straight-line
-    // code of a full unroll would be scheduled into many more live registers
 #pragma clang loop unroll(disable)
-    for (; it < warm; it += 2) {
-        body(it, sa, std::true_type{});
-        body(it + 1, sb, std::true_type{});
+    for (; it < warm_trips_end; it += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) body(it + u, sl[u], std::true_type{});
     }
-    for (; it + 1 < iters; it += 2) {
-        body(it, sa, std::false_type{});
-        body(it + 1, sb, std::false_type{});
+    for (; it + D <= iters; it += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) body(it + u, sl[u], std::false_type{});
     }
-    if (it < iters) body(it, sa, std::false_type{});
+#pragma unroll
+    for (int u = 0; u < D - 1; ++u)
+        if (it + u < iters) body(it + u, sl[u], std::false_type{});
 }
 
 template <int S, typename T, int K>
