@@ -250,6 +250,17 @@ tdse_status tdse_set_sweep_shape(tdse_ctx* ctx, int32_t rows, int32_t variant);
  * observable spacing, d_obs) and dropped on rebind.  Synchronises the stream. */
 tdse_status tdse_use_graphs(tdse_ctx* ctx, int32_t enable);
 
+/* Observables beside the next step (default on).  With the Taylor methods the
+ * observables of step s (the Sec. 4 reductions over the state after step s)
+ * run on a second stream of the library, concurrently with step s+1: the
+ * state rotates through three buffers and the one holding psi(s) is first
+ * overwritten in step s+2, which waits for them.  The second stream rejoins
+ * the bound stream before a step call returns (and at the end of every
+ * 256-step chunk, so captured graphs contain both branches).  Off: every
+ * launch goes to the bound stream in order.  Results are bitwise identical
+ * either way.  Synchronises the bound stream; drops captured graphs. */
+tdse_status tdse_set_obs_overlap(tdse_ctx* ctx, int32_t enable);
+
 /* Kernel timing with HIP events recorded around every launch of the named
  * kernel family on the bound stream ("taylor_term", "rk4_stage",
  * "observables", "lanczos_sweep_a", "apply_h", "taylor_fused").  tdse_timing_enable(ctx, 1)

@@ -34,7 +34,7 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_set_state", "tdse_get_state", "tdse_apply_H", "tdse_step_taylor",
             "tdse_step_rk4", "tdse_step_lanczos", "tdse_observables", "tdse_lambda_max_bound",
             "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read",
-            "tdse_use_graphs", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
+            "tdse_use_graphs", "tdse_set_obs_overlap", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
             "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_taylor_fusion_kind",
             "tdse_set_taylor_fusion", "tdse_set_sweep_shape")
 
@@ -93,6 +93,7 @@ def _load():
         "tdse_timing_enable": ([ctxp, i32], i32),
         "tdse_timing_read": ([ctxp, ctypes.c_char_p, ctypes.POINTER(i64), dp], i32),
         "tdse_use_graphs": ([ctxp, i32], i32),
+        "tdse_set_obs_overlap": ([ctxp, i32], i32),
         "tdse_autotune": ([ctxp, ctypes.POINTER(i32)], i32),
         "tdse_tile_rows": ([ctxp], i32),
         "tdse_sweep_variant": ([ctxp], i32),
@@ -224,6 +225,10 @@ def tdse_tile_rows(ctx) -> int:
 
 def tdse_use_graphs(ctx, enable: bool):
     _check(ctx, lib.tdse_use_graphs(ctx, 1 if enable else 0))
+
+
+def tdse_set_obs_overlap(ctx, enable: bool):
+    _check(ctx, lib.tdse_set_obs_overlap(ctx, 1 if enable else 0))
 
 
 def tdse_timing_read(ctx, kernel: str):
@@ -358,6 +363,9 @@ class Propagator:
 
     def use_graphs(self, enable: bool):
         tdse_use_graphs(self.ctx, enable)
+
+    def set_obs_overlap(self, enable: bool):
+        tdse_set_obs_overlap(self.ctx, enable)
 
     def autotune(self) -> int:
         self._enter()

@@ -71,6 +71,7 @@ struct tdse_ctx {
     int step_buf = 0;
     // the observables of the Taylor path run on a second stream (default
     // priority), overlapping the next step; created on first use
+    bool obs_overlap = true;
     hipStream_t obs_stream = nullptr;
     hipEvent_t obs_fork = nullptr, obs_join = nullptr, obs_done[2] = {nullptr, nullptr};
     // captured step graphs, keyed by the launch pattern of a chunk
@@ -152,11 +153,14 @@ int timed_kind(const char* name)
     return -1;
 }
 
+// HIP events around one launch, on the stream the launch goes to.
 struct TimedLaunch {
     tdse_ctx* c;
     int kind;
+    hipStream_t st;
     size_t slot = (size_t)-1;
-    TimedLaunch(tdse_ctx* ctx, int k) : c(ctx), kind(k)
+    TimedLaunch(tdse_ctx* ctx, int k) : TimedLaunch(ctx, k, ctx->stream) {}
+    TimedLaunch(tdse_ctx* ctx, int k, hipStream_t stream) : c(ctx), kind(k), st(stream)
     {
         if (!c->timing) return;
         if (c->ev_used == c->ev_pool.size()) {
@@ -167,11 +171,11 @@ struct TimedLaunch {
         }
         slot = c->ev_used++;
         c->ev_kind[slot] = kind;
-        (void)hipEventRecord(c->ev_pool[slot].first, c->stream);
+        (void)hipEventRecord(c->ev_pool[slot].first, st);
     }
     ~TimedLaunch()
     {
-        if (slot != (size_t)-1) (void)hipEventRecord(c->ev_pool[slot].second, c->stream);
+        if (slot != (size_t)-1) (void)hipEventRecord(c->ev_pool[slot].second, st);
     }
 };
 
@@ -798,7 +802,7 @@ tdse_status check_stable(tdse_ctx* c, const tdse_pulse* pulses, const double* dt
 hipError_t launch_obs(tdse_ctx* c, const void* psi, const double* step, double* records,
                       int64_t rec_stride, hipStream_t st)
 {
-    TimedLaunch tl(c, 2);
+    TimedLaunch tl(c, 2, st);
     const SweepGeom red = c->geom(kObsTiles), pop = c->geom(kPopTiles);
     double* pmain = c->d_partial();
     double* ppop = pmain + (size_t)red.n_tiles * kObsMainQ;
@@ -823,7 +827,7 @@ static hipError_t ensure_obs_stream(tdse_ctx* c)
 // side: the observables of step s run on the second stream, concurrently with
 // step s+1.  This needs a step function that never writes the buffer holding
 // psi at its start (the Taylor rotation: psi(s) is overwritten first in step
-// s+2), and no timing.  Step s+2 waits for the observables of step s; the
+// s+2).  Step s+2 waits for the observables of step s; the
 // second stream runs them in order (they share the partial-sum buffer) and
 // rejoins the main stream at the end of the chunk, so a chunk (and its
 // captured graph) leaves nothing running on it.
@@ -873,7 +877,7 @@ tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, c
     const int64_t n_rec = (obs_every > 0) ? nsteps / obs_every : 0;
     const int64_t rec_stride = n_rec * (int64_t)kObsRecord;
     const bool graphs = c->use_graphs && !c->timing && c->stream != nullptr;
-    const bool side = obs_side_ok && obs_every > 0 && !c->timing;
+    const bool side = obs_side_ok && obs_every > 0 && c->obs_overlap;
     if (side) {
         hipError_t e = ensure_obs_stream(c);
         if (e != hipSuccess) return c->hip_fail(e, "observables stream");
@@ -1396,6 +1400,19 @@ extern "C" tdse_status tdse_use_graphs(tdse_ctx* c, int32_t enable)
     }
     c->use_graphs = enable != 0;
     if (!c->use_graphs) c->drop_graphs();
+    return TDSE_OK;
+}
+
+extern "C" tdse_status tdse_set_obs_overlap(tdse_ctx* c, int32_t enable)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (c->bound) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess && c->obs_stream) e = hipStreamSynchronize(c->obs_stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_set_obs_overlap sync");
+    }
+    c->obs_overlap = enable != 0;
+    c->drop_graphs();
     return TDSE_OK;
 }
 

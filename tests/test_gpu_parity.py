@@ -440,18 +440,20 @@ def test_fused_taylor_batch_bitwise(kind):
 @pytest.mark.parametrize("obs_every", [1, 2, 3])
 def test_observables_beside_next_step_bitwise(obs_every):
     # The Taylor path computes the observables of step s on a second stream,
-    # beside step s+1.  States and records must equal a timed run (timing keeps
-    # every launch on one stream, in order), with and without graphs, over
-    # more than one chunk of steps.
+    # beside step s+1.  States and records must equal serial launches (overlap
+    # off: every launch on one stream, in order), with direct launches, with
+    # timing events on both streams and with graphs, over more than one chunk
+    # of steps.
     t = lib()
     grid = t.Grid(4000, 16, 0.1, 5, t.FP64, 1.0, 100.0)
     pulse = t.Pulse(0.05, 0.2, 2.0, 0.0, 0.0)
     nsteps = 300
-    say(f"observables every {obs_every} step(s) beside the next step vs serial (timed) launches")
+    say(f"observables every {obs_every} step(s) beside the next step vs serial launches")
     out = []
-    for mode in ("timed", "direct", "graphs"):
+    for mode in ("serial", "direct", "timed", "graphs"):
         prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),), graphs=(mode == "graphs"))
         prop.set_taylor_fusion(4, 8, 1)
+        prop.set_obs_overlap(mode != "serial")
         if mode == "timed":
             prop.timing(True)
         dt = 0.8 * t.tdse_taylor_stability_limit(8) / prop.lambda_max_bound(0, 0.05)
