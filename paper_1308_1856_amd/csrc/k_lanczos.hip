@@ -51,13 +51,30 @@ template <int NQ>
 __device__ __forceinline__ double instance_sum(const Inst& I, const double* partial, int stride,
                                                int nq, double* lds)
 {
+    // U tiles per thread per pass, all loaded before any is added (the
+    // partials come from every XCD: one memory latency per pass); each thread
+    // still adds its tiles in increasing order
+    constexpr int U = NQ >= 8 ? 4 : 8;
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-    for (int t = I.tbegin[kReduceTiles] + (int)threadIdx.x; t < I.tend[kReduceTiles]; t += kBlock) {
+    const int tb = I.tbegin[kReduceTiles], te = I.tend[kReduceTiles];
+    for (int t0 = tb + (int)threadIdx.x; t0 < te; t0 += U * kBlock) {
+        double v[U][NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            if (q < nq) acc[q] += partial[(int64_t)t * stride + q];
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * kBlock;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) v[u][q] = (t < te && q < nq) ? partial[(int64_t)t * stride + q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (t0 + u * kBlock < te) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (q < nq) acc[q] += v[u][q];
+            }
+        }
     }
     return block_sum<NQ>(acc, lds);
 }
@@ -237,7 +254,8 @@ k_lz_finish_b(SweepGeom g, int j, const double* __restrict__ partial, LanczosSca
 //   then s squarings (X - iY)^2 = (X^2 - Y^2) - i (XY + YX).
 // One workgroup per instance; the m x m real matrices live in LDS, each
 // thread computes a fixed set of entries of every product (fixed summation
-// order: results do not depend on scheduling).  T is exponentiated as a
+// order: results do not depend on scheduling).  The Taylor products P B take
+// three terms per entry (B is tridiagonal); the squarings are full products.  T is exponentiated as a
 // whole; no eigen-decomposition, unlike the oracle, which diagonalises T.
 constexpr int kExpmTerms = 17;
 constexpr int kExpmPerThread = (kMaxKrylov * kMaxKrylov + kBlock - 1) / kBlock;
@@ -311,7 +329,14 @@ k_lz_expm(SweepGeom g, const double* __restrict__ step, LanczosScalars* __restri
         for (int e = 0; e < kExpmPerThread; ++e) {
             const int idx = tid + e * kBlock;
             nv[e] = 0.0;
-            if (idx < mm) nv[e] = lds_dot(Pm, Bm, m, idx / m, idx % m) * inv_k;
+            if (idx < mm) {
+                // (P B)[r][c] with B tridiagonal: three terms
+                const int r = idx / m, c = idx - r * m;
+                double v = Pm[r * m + c] * Bm[c * m + c];
+                if (c > 0) v = fma(Pm[r * m + c - 1], Bm[(c - 1) * m + c], v);
+                if (c + 1 < m) v = fma(Pm[r * m + c + 1], Bm[(c + 1) * m + c], v);
+                nv[e] = v * inv_k;
+            }
         }
         __syncthreads();
         const double sgn = ((k / 2) & 1) ? -1.0 : 1.0;   // (-1)^{k/2} even, (-1)^{(k-1)/2} odd
