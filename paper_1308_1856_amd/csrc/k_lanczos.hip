@@ -254,11 +254,14 @@ k_lz_finish_b(SweepGeom g, int j, const double* __restrict__ partial, LanczosSca
 //   then s squarings (X - iY)^2 = (X^2 - Y^2) - i (XY + YX).
 // One workgroup per instance; the m x m real matrices live in LDS, each
 // thread computes a fixed set of entries of every product (fixed summation
-// order: results do not depend on scheduling).  The Taylor products P B take
-// three terms per entry (B is tridiagonal); the squarings are full products.  T is exponentiated as a
+// order: results do not depend on scheduling).  Every matrix is a polynomial
+// in the symmetric B, so each product is formed on the upper triangle and
+// mirrored, X and Y commute (XY + YX = 2XY), and the Taylor products P B take
+// three terms per entry (B is tridiagonal).  T is exponentiated as a
 // whole; no eigen-decomposition, unlike the oracle, which diagonalises T.
 constexpr int kExpmTerms = 17;
 constexpr int kExpmPerThread = (kMaxKrylov * kMaxKrylov + kBlock - 1) / kBlock;
+constexpr int kExpmUpper = (kMaxKrylov * (kMaxKrylov + 1) / 2 + kBlock - 1) / kBlock;   // upper-triangle entries per thread
 
 // Row r of L times column c of R, with four independent partial sums (a
 // fixed order, so the result does not depend on scheduling).
@@ -321,17 +324,33 @@ k_lz_expm(SweepGeom g, const double* __restrict__ step, LanczosScalars* __restri
             Ym[idx] = v;
         }
     }
+    // Every matrix here is a polynomial in the symmetric B: symmetric, and X
+    // and Y commute.  Each product is formed on the upper triangle (entry
+    // (r, c), r <= c, the thread's fixed entries) and mirrored.
+    const int nut = m * (m + 1) / 2;
+    int ur[kExpmUpper], uc[kExpmUpper];
+    for (int e = 0; e < kExpmUpper; ++e) {
+        int t = tid + e * kBlock, r = 0;
+        ur[e] = uc[e] = 0;
+        if (t < nut) {
+            while (t >= m - r) {
+                t -= m - r;
+                ++r;
+            }
+            ur[e] = r;
+            uc[e] = r + t;
+        }
+    }
     __syncthreads();
     // Taylor terms: P <- P B / k, added to X (even k) or Y (odd k) with sign
     for (int k = 2; k <= kExpmTerms; ++k) {
-        double nv[kExpmPerThread];
+        double nv[kExpmUpper];
         const double inv_k = 1.0 / (double)k;
-        for (int e = 0; e < kExpmPerThread; ++e) {
-            const int idx = tid + e * kBlock;
+        for (int e = 0; e < kExpmUpper; ++e) {
             nv[e] = 0.0;
-            if (idx < mm) {
+            if (tid + e * kBlock < nut) {
                 // (P B)[r][c] with B tridiagonal: three terms
-                const int r = idx / m, c = idx - r * m;
+                const int r = ur[e], c = uc[e];
                 double v = Pm[r * m + c] * Bm[c * m + c];
                 if (c > 0) v = fma(Pm[r * m + c - 1], Bm[(c - 1) * m + c], v);
                 if (c + 1 < m) v = fma(Pm[r * m + c + 1], Bm[(c + 1) * m + c], v);
@@ -340,34 +359,33 @@ k_lz_expm(SweepGeom g, const double* __restrict__ step, LanczosScalars* __restri
         }
         __syncthreads();
         const double sgn = ((k / 2) & 1) ? -1.0 : 1.0;   // (-1)^{k/2} even, (-1)^{(k-1)/2} odd
-        for (int e = 0; e < kExpmPerThread; ++e) {
-            const int idx = tid + e * kBlock;
-            if (idx < mm) {
-                Pm[idx] = nv[e];
-                if (k & 1) Ym[idx] = fma(sgn, nv[e], Ym[idx]);
-                else Xm[idx] = fma(sgn, nv[e], Xm[idx]);
+        for (int e = 0; e < kExpmUpper; ++e) {
+            if (tid + e * kBlock < nut) {
+                const int a = ur[e] * m + uc[e], b = uc[e] * m + ur[e];
+                Pm[a] = Pm[b] = nv[e];
+                if (k & 1) Ym[a] = Ym[b] = fma(sgn, nv[e], Ym[a]);
+                else Xm[a] = Xm[b] = fma(sgn, nv[e], Xm[a]);
             }
         }
         __syncthreads();
     }
-    // squarings
+    // squarings: (X - iY)^2 = (X^2 - Y^2) - i 2XY
     for (int q = 0; q < nsq; ++q) {
-        double nx[kExpmPerThread], ny[kExpmPerThread];
-        for (int e = 0; e < kExpmPerThread; ++e) {
-            const int idx = tid + e * kBlock;
+        double nx[kExpmUpper], ny[kExpmUpper];
+        for (int e = 0; e < kExpmUpper; ++e) {
             nx[e] = ny[e] = 0.0;
-            if (idx < mm) {
-                const int r = idx / m, c = idx - r * m;
+            if (tid + e * kBlock < nut) {
+                const int r = ur[e], c = uc[e];
                 nx[e] = lds_dot(Xm, Xm, m, r, c) - lds_dot(Ym, Ym, m, r, c);
-                ny[e] = lds_dot(Xm, Ym, m, r, c) + lds_dot(Ym, Xm, m, r, c);
+                ny[e] = 2.0 * lds_dot(Xm, Ym, m, r, c);
             }
         }
         __syncthreads();
-        for (int e = 0; e < kExpmPerThread; ++e) {
-            const int idx = tid + e * kBlock;
-            if (idx < mm) {
-                Xm[idx] = nx[e];
-                Ym[idx] = ny[e];
+        for (int e = 0; e < kExpmUpper; ++e) {
+            if (tid + e * kBlock < nut) {
+                const int a = ur[e] * m + uc[e], b = uc[e] * m + ur[e];
+                Xm[a] = Xm[b] = nx[e];
+                Ym[a] = Ym[b] = ny[e];
             }
         }
         __syncthreads();
