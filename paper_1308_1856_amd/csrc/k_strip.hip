@@ -62,11 +62,25 @@ __device__ __forceinline__ double2 dpp_shift2(double2 v)
 {
     return make_double2(dpp_shift<CTRL>(v.x), dpp_shift<CTRL>(v.y));
 }
-// An empty statement that reads and may rewrite v in registers and may touch
-// memory: whatever computes v stays before it, and no load or store moves
-// across it.  It emits no instruction.
-__device__ __forceinline__ void pin(double2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y) : : "memory"); }
-__device__ __forceinline__ void pin(float2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y) : : "memory"); }
+// A copy of v in registers of its own (an actual move, which the compiler
+// cannot fold into v's registers), ordered before every later memory access:
+// the registers of v are then free for a reload of v's variable, so a loop
+// that reloads it needs no register copy at its end (a copy that would wait
+// for the reload just issued).
+__device__ __forceinline__ double2 take(double2 v)
+{
+    double2 r;
+    asm volatile("v_mov_b64 %0, %1" : "=&v"(r.x) : "v"(v.x) : "memory");
+    asm volatile("v_mov_b64 %0, %1" : "=&v"(r.y) : "v"(v.y) : "memory");
+    return r;
+}
+__device__ __forceinline__ float2 take(float2 v)
+{
+    float2 r;
+    asm volatile("v_mov_b32 %0, %1" : "=&v"(r.x) : "v"(v.x) : "memory");
+    asm volatile("v_mov_b32 %0, %1" : "=&v"(r.y) : "v"(v.y) : "memory");
+    return r;
+}
 // value of lane - d / lane + d (d = 1 or 2)
 __device__ __forceinline__ double2 lane_below(double2 v, int d)
 {
@@ -111,18 +125,17 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         const double v = ld_const(g.kappa, min(max(l, 0), lmax));  // a scalar load
         return (l >= 1 && l <= lmax) ? v : 0.0;
     };
-    // H at row rr of the level below: centre c, rows rr-1 / rr+1 at this radius
-    auto h_row = [&](double2 c, double2 lm, double2 lp, int rr) -> double2 {
+    // H at row rr of the level below: centre c, rows rr-1 / rr+1 at this
+    // radius; the coupling to row rr-1 is kl = kappa_rr, to row rr+1
+    // klp = kappa_{rr+1} (zero where the other row is outside [0, lmax])
+    auto h_row = [&](double2 c, double2 lm, double2 lp, int rr, double kl, double klp) -> double2 {
         const double2 m1 = lane_below(c, 1), p1 = lane_above(c, 1);
         double2 m2 = zero2(), p2 = zero2();
         if (S == 2) {
             m2 = lane_below(c, 2);
             p2 = lane_above(c, 2);
         }
-        // coupling to row rr-1 is kappa_rr, to row rr+1 kappa_{rr+1}; both zero
-        // where the other row is outside [0, lmax]
-        return h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2, row_potential(rr, inv_r2, z_over_r), er,
-                          kap(rr), kap(rr + 1));
+        return h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2, row_potential(rr, inv_r2, z_over_r), er, kl, klp);
     };
 
     const int rho0 = I.l0 - K + 1;              // level-1 row at it = 0
@@ -150,27 +163,30 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     double2 ra[K > 1 ? K - 1 : 1], rb[K > 1 ? K - 1 : 1];
 #pragma unroll
     for (int k = 0; k < (K > 1 ? K - 1 : 1); ++k) ra[k] = rb[k] = zero2();
+    // kappa of rows rho + 1 - j, j = 0..K (wave-uniform, scalar registers):
+    // the rows of an iteration's levels and their upper neighbours.  One new
+    // value per iteration, loaded an iteration ahead (kn).
+    double kq[K + 1];
+#pragma unroll
+    for (int j = 0; j <= K; ++j) kq[j] = kap(rho0 + 1 - j);
+    double kn = kap(rho0 + 2);
 
     // one iteration; CHECK: some levels may not have reached their first row yet
     auto body = [&](int it, Slot& sl, auto check) {
         constexpr bool CHECK = decltype(check)::value;
         const int rho = rho0 + it;
-        // take the slot's rows, then reload the same registers for iteration
-        // it+D.  pin() keeps the reads of the old values ahead of the new
-        // loads; otherwise the compiler sinks them past the loads, the old and
-        // new values overlap, and the register copy it then needs at the loop
-        // end waits for the load just issued.
-        double2 xp = widen_lane(sl.x);
-#pragma unroll
-        for (int k = K - 1; k > 0; --k) pr[k] = pr[k - 1];
-        pr[0] = sl.p;
-        pin(xp);
-        pin(pr[0]);
+        // move the slot's rows out, then reload the slot for iteration it+D
+        const C xo = take(sl.x);
+        const C po = take(sl.p);
         sl.x = rowp(in_i, rho + 1 + D)[jc];
         sl.p = rowp(psi_i, rho + D)[jc];
+        const double2 xp = widen_lane(xo);
+#pragma unroll
+        for (int k = K - 1; k > 0; --k) pr[k] = pr[k - 1];
+        pr[0] = po;
 
         // level 1 from the input
-        double2 up = horner_update(widen(pr[0]), h_row(xc, xm, xp, rho), coef[0]);
+        double2 up = horner_update(widen(pr[0]), h_row(xc, xm, xp, rho, kq[1], kq[0]), coef[0]);
         if (MASKED) up = pick2(inside, up, zero2());
         if (K == 1 && writes && rho >= I.l0 && rho < I.l1) stc(out_i, (int64_t)rho * n + jc, up);
         // levels 2..K from the registers of the level below
@@ -180,7 +196,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
             double2 v = zero2();
             if (!CHECK || it >= 2 * (k - 1)) {
                 // level k-1 at rows rk (ra), rk - 1 (rb) and rk + 1 (this iteration)
-                v = horner_update(widen(pr[k - 1]), h_row(ra[k - 2], rb[k - 2], up, rk), coef[k - 1]);
+                v = horner_update(widen(pr[k - 1]), h_row(ra[k - 2], rb[k - 2], up, rk, kq[k], kq[k - 1]), coef[k - 1]);
                 if (MASKED) v = pick2(inside, v, zero2());
             }
             rb[k - 2] = ra[k - 2];
@@ -188,7 +204,11 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
             up = v;
             if (k == K && writes && rk >= I.l0 && rk < I.l1) stc(out_i, (int64_t)rk * n + jc, v);
         }
-        // shift the window
+        // shift the window and the kappa register; fetch kappa for it + 2
+#pragma unroll
+        for (int j = K; j > 0; --j) kq[j] = kq[j - 1];
+        kq[0] = kn;
+        kn = kap(rho + 3);
         xm = xc;
         xc = xp;
         // keep the iterations of a loop trip apart: interleaving them would
