@@ -170,6 +170,11 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
 #pragma unroll
     for (int j = 0; j <= K; ++j) kq[j] = kap(rho0 + 1 - j);
     double kn = kap(rho0 + 2);
+    // element offsets of the rows an iteration reloads (input row rho+1+D,
+    // psi row rho+D) and stores (level K at rho-(K-1)); each advances by one
+    // row per iteration
+    int64_t ox = (int64_t)(rho0 + 1 + D) * n, op = (int64_t)(rho0 + D) * n;
+    int64_t os = (int64_t)(rho0 - (K - 1)) * n + jc;
 
     // one iteration; CHECK: some levels may not have reached their first row yet
     auto body = [&](int it, Slot& sl, auto check) {
@@ -178,8 +183,10 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         // move the slot's rows out, then reload the slot for iteration it+D
         const C xo = take(sl.x);
         const C po = take(sl.p);
-        sl.x = rowp(in_i, rho + 1 + D)[jc];
-        sl.p = rowp(psi_i, rho + D)[jc];
+        sl.x = ((unsigned)(rho + 1 + D) <= (unsigned)lmax ? in_i + ox : zrow)[jc];
+        sl.p = ((unsigned)(rho + D) <= (unsigned)lmax ? psi_i + op : zrow)[jc];
+        ox += n;
+        op += n;
         const double2 xp = widen_lane(xo);
 #pragma unroll
         for (int k = K - 1; k > 0; --k) pr[k] = pr[k - 1];
@@ -188,7 +195,9 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         // level 1 from the input
         double2 up = horner_update(widen(pr[0]), h_row(xc, xm, xp, rho, kq[1], kq[0]), coef[0]);
         if (MASKED) up = pick2(inside, up, zero2());
-        if (K == 1 && writes && rho >= I.l0 && rho < I.l1) stc(out_i, (int64_t)rho * n + jc, up);
+        // the stored row: in [l0, l1) at every iteration past the warm-up trips
+        auto store_row = [&](int rr) { return !CHECK || (rr >= I.l0 && rr < I.l1); };
+        if (K == 1 && writes && store_row(rho)) stc(out_i, os, up);
         // levels 2..K from the registers of the level below
 #pragma unroll
         for (int k = 2; k <= K; ++k) {
@@ -202,13 +211,14 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
             rb[k - 2] = ra[k - 2];
             ra[k - 2] = up;
             up = v;
-            if (k == K && writes && rk >= I.l0 && rk < I.l1) stc(out_i, (int64_t)rk * n + jc, v);
+            if (k == K && writes && store_row(rk)) stc(out_i, os, v);
         }
         // shift the window and the kappa register; fetch kappa for it + 2
 #pragma unroll
         for (int j = K; j > 0; --j) kq[j] = kq[j - 1];
         kq[0] = kn;
         kn = kap(rho + 3);
+        os += n;
         xm = xc;
         xc = xp;
         // keep the iterations of a loop trip apart: interleaving them would
