@@ -45,8 +45,10 @@ k_lz_norm(SweepGeom g, const typename Cplx<T>::type* __restrict__ psi, double* _
     if (threadIdx.x == 0) partial[t] = s;
 }
 
-// One workgroup per instance: sum nq partials of stride `stride` over the
-// instance's tiles in a fixed order; thread q < nq receives sum q.
+// One workgroup per instance: sum nq partials over the instance's tiles in a
+// fixed order (partial q of tile t at partial[q * stride + t]: the tiles of one
+// q are contiguous, so the loads of a wave are coalesced); thread q < nq
+// receives sum q.
 template <int NQ>
 __device__ __forceinline__ double instance_sum(const Inst& I, const double* partial, int stride,
                                                int nq, double* lds)
@@ -65,7 +67,7 @@ __device__ __forceinline__ double instance_sum(const Inst& I, const double* part
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u * kBlock;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) v[u][q] = (t < te && q < nq) ? partial[(int64_t)t * stride + q] : 0.0;
+            for (int q = 0; q < NQ; ++q) v[u][q] = (t < te && q < nq) ? partial[(int64_t)q * stride + t] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -140,19 +142,22 @@ k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
             cur = next;
         }
     }
-    const int stride_p = 2 * m;
     for (int i0 = 0; i0 <= j; i0 += JB) {
         double acc[2 * JB];
 #pragma unroll
         for (int q = 0; q < 2 * JB; ++q) acc[q] = 0.0;
         if (active) {
+            // the group's scale factors, read once (not per row)
+            double su[JB];
+#pragma unroll
+            for (int u = 0; u < JB; ++u) su[u] = (i0 + u <= j) ? sc.scale[i0 + u] : 0.0;
             for (int l = tile.l0; l < tile.l1; ++l) {
                 const int64_t k = I.off + (int64_t)l * n + i;
                 const double2 wv = ldc(w, k);
 #pragma unroll
                 for (int u = 0; u < JB; ++u) {
                     if (i0 + u <= j) {
-                        const double s = sc.scale[i0 + u];
+                        const double s = su[u];
                         const double2 q = ldc(basis_vec(psi, basis, stride, i0 + u), k);
                         // conj(s q) w
                         acc[2 * u] = fma(s, fma(q.x, wv.x, q.y * wv.y), acc[2 * u]);
@@ -163,7 +168,7 @@ k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
         }
         const double s = block_sum<2 * JB>(acc, lds);
         if ((int)threadIdx.x < 2 * JB && i0 + (int)threadIdx.x / 2 <= j)
-            partial[(int64_t)t * stride_p + 2 * i0 + threadIdx.x] = s;
+            partial[(int64_t)(2 * i0 + threadIdx.x) * g.n_tiles + t] = s;
     }
 }
 
@@ -182,7 +187,7 @@ k_lz_finish_a(SweepGeom g, int j, int m, const double* __restrict__ partial,
     const int i0 = (int)blockIdx.y * JB;
     if (i0 > j) return;
     const int nq = min(2 * JB, 2 * (j + 1 - i0));
-    const double s = instance_sum<2 * JB>(I, partial + 2 * i0, 2 * m, nq, lds);
+    const double s = instance_sum<2 * JB>(I, partial + (int64_t)2 * i0 * g.n_tiles, g.n_tiles, nq, lds);
     if ((int)threadIdx.x < nq) sc.h[2 * i0 + threadIdx.x] = s;
     // Re <q_j, H q_j>, from the one group that holds product j
     if (j - i0 < JB && (int)threadIdx.x == 2 * (j - i0)) sc.alpha[j] = s;
