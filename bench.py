@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", type=int, default=1, help="replay step chunks as HIP graphs")
+    ap.add_argument("--rk4-stages", action="store_true",
+                    help="RK4 in four stage launches per step (default: one launch per step)")
     ap.add_argument("--autotune", type=int, default=2,
                     help="0: fixed shapes; 1: autotune the sweep tiles; 2: also choose the Taylor fusion")
     ap.add_argument("--sweep", default=None, metavar="ROWS,VARIANT",
@@ -91,6 +93,8 @@ def make_prop(tdse, wl, precision, method_code, graphs=True, autotune=True):
     methods = ((method_code, wl.order), (tdse.METHOD_TAYLOR, 2), (tdse.METHOD_TUNE, 0))
     prop = tdse.Propagator([g], methods=methods, graphs=bool(graphs))
     apply_shape(prop, ARGS, autotune, wl.order if wl.method == "taylor" else 0)
+    if wl.method == "rk4" and ARGS is not None and ARGS.rk4_stages:
+        prop.set_rk4_fusion(False)
     prop.set_state(0, None)
     return prop
 
@@ -143,7 +147,7 @@ def source_digest(name):
 
 
 KERNEL_SOURCE = {"taylor_term": "k_sweep.hip", "apply_h": "k_sweep.hip", "rk4_stage": "k_sweep.hip",
-                 "lanczos_sweep_a": "k_lanczos.hip"}
+                 "rk4_fused": "k_strip.hip", "lanczos_sweep_a": "k_lanczos.hip"}
 
 
 def shape_of(prop, kernel):
@@ -208,7 +212,9 @@ def dominant_kernel(prop, method):
     """Timing family of the launch that carries a step's sweeps."""
     if method == "taylor":
         return "taylor_fused" if prop.taylor_fusion > 0 else "taylor_term"
-    return {"rk4": "rk4_stage", "lanczos": "lanczos_sweep_a"}[method]
+    if method == "rk4":
+        return "rk4_fused" if prop.rk4_fusion else "rk4_stage"
+    return {"lanczos": "lanczos_sweep_a"}[method]
 
 
 def batch_setup(tdse, precision):
@@ -386,6 +392,9 @@ def main():
         # sweep A of iteration j reads q_0..q_j and writes w: (j + 2) c U,
         # averaged over j = 0 .. m-1
         bytes_per_launch = (wl.order + 3) / 2.0 * elem * U
+    elif kernel == "rk4_fused":
+        # one launch per step: read psi, write the new psi
+        bytes_per_launch = 2.0 * elem * U
     elif bytes_per_unknown:
         bytes_per_launch = bytes_per_unknown * U
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if bytes_per_launch else None

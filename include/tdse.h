@@ -169,7 +169,10 @@ tdse_status tdse_step_taylor(tdse_ctx* ctx, const tdse_pulse* pulses, const doub
 
 /* Classic fourth-order Runge-Kutta (Sec. 5.2 eq. RKDeriv, tableau c = 0, 1/2,
  * 1/2, 1; b = 1/6, 1/3, 1/3, 1/6) on dF/dt = -i H(t) F.  Arguments,
- * stability check and observables as tdse_step_taylor (limit of order 4). */
+ * stability check and observables as tdse_step_taylor (limit of order 4).
+ * By default one launch per step computes the four stages on wave strips
+ * (see tdse_set_rk4_fusion); with FP64 storage its results are bit-identical
+ * to four stage launches. */
 tdse_status tdse_step_rk4(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0,
                           const double* dt, int32_t nsteps, int32_t obs_every, tdse_obs* d_obs);
 
@@ -260,6 +263,15 @@ tdse_status tdse_use_graphs(tdse_ctx* ctx, int32_t enable);
  * launch goes to the bound stream in order.  Results are bitwise identical
  * either way.  Synchronises the bound stream; drops captured graphs. */
 tdse_status tdse_set_obs_overlap(tdse_ctx* ctx, int32_t enable);
+
+/* RK4 in one launch per step (default on: the four stages as the levels of
+ * wave strips, reading the state once and writing the new state once, the
+ * stage vectors and the accumulator held in FP64 registers) or in four stage
+ * launches (off: each stage reads and writes state-shaped vectors in the
+ * storage precision).  tdse_rk4_fusion gives the setting.  Synchronises the
+ * bound stream; drops captured graphs. */
+tdse_status tdse_set_rk4_fusion(tdse_ctx* ctx, int32_t enable);
+int32_t tdse_rk4_fusion(const tdse_ctx* ctx);
 
 /* Kernel timing with HIP events recorded around every launch of the named
  * kernel family on the bound stream ("taylor_term", "rk4_stage",

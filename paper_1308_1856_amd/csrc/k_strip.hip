@@ -325,4 +325,197 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
                   : strip_k<2, float>(K, g, in, psi, out, step, first_term, st);
 }
 
+// One classic RK4 step (eq. RKDeriv) per launch on the wave strips, the four
+// stages being the levels of the strip (each one row behind the last):
+//   stage s at row r_s = rho - s:  k_s = -i H(t_s) g_s  (g_0 = psi),
+//     g_{s+1} = psi + a_s dt k_s                (a = 1/2, 1/2, 1),
+//     acc_0 = psi + dt/6 k_0,  acc_s = acc_{s-1} + dt/3 k_s  (s = 1, 2),
+//     psi' = acc_2 + dt/6 k_3,
+// with t_0 = t_n, t_1 = t_2 = t_n + dt/2, t_3 = t_n + dt.  Stage s reads g_s
+// at rows r_s - 1, r_s, r_s + 1 (two from its registers, one just computed by
+// stage s-1) and radial neighbours by DPP shifts; the acc of a row passes from
+// stage s to stage s+1 in a register (stage s+1 reaches the row one iteration
+// later).  psi is the input and the base of every stage: read once per row,
+// rows rho-3 .. rho+1 kept in registers.  Every element is computed by
+// h_point and horner_update from the same FP64 operands as the four stage
+// launches (k_rk4_stage), so FP64 results are bit-identical to them; with
+// FP32 storage g and acc stay FP64 between stages.  HBM traffic per unknown
+// and step: read psi, write psi' (2c, against 16c for the stage launches).
+template <int S, typename T, bool MASKED>
+__device__ __forceinline__ void rk4_strip_loop(const SweepGeom& g, const Tile& I, const typename Cplx<T>::type* in_i,
+                                               typename Cplx<T>::type* out_i, int jc, bool inside, bool writes,
+                                               const double (&er)[4], double inv_r2, double z_over_r, double dt)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int K = 4;
+    const int n = I.n, lmax = I.lmax;
+    const C* zrow = static_cast<const C*>(g.zero_row);
+    auto rowp = [&](const C* base, int rr) -> const C* {
+        return (rr >= 0 && rr <= lmax) ? base + (int64_t)rr * n : zrow;
+    };
+    auto widen_lane = [&](C raw) -> double2 {
+        const double2 v = widen(raw);
+        return MASKED ? pick2(inside, v, zero2()) : v;
+    };
+    auto kap = [&](int l) -> double {
+        const double v = ld_const(g.kappa, min(max(l, 0), lmax));  // a scalar load
+        return (l >= 1 && l <= lmax) ? v : 0.0;
+    };
+    auto h_row = [&](double2 c, double2 lm, double2 lp, int rr, double kl, double klp, double e_r) -> double2 {
+        const double2 m1 = lane_below(c, 1), p1 = lane_above(c, 1);
+        double2 m2 = zero2(), p2 = zero2();
+        if (S == 2) {
+            m2 = lane_below(c, 2);
+            p2 = lane_above(c, 2);
+        }
+        return h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2, row_potential(rr, inv_r2, z_over_r), e_r, kl, klp);
+    };
+    // the stage weights, as the stage launches form them
+    const double b06 = dt / 6.0, b13 = dt / 3.0, a_half = 0.5 * dt;
+
+    const int rho0 = I.l0 - K + 1;              // stage-0 row at it = 0
+    // psi rows rho-3 .. rho (FP64)
+    double2 x3 = widen_lane(rowp(in_i, rho0 - 3)[jc]);
+    double2 x2 = widen_lane(rowp(in_i, rho0 - 2)[jc]);
+    double2 xm = widen_lane(rowp(in_i, rho0 - 1)[jc]);
+    double2 xc = widen_lane(rowp(in_i, rho0)[jc]);
+    // psi row rho+1, loaded D iterations ahead into D slots (as in strip_loop)
+    constexpr int D = kStripDepth;
+    C sl[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) sl[u] = rowp(in_i, rho0 + 1 + u)[jc];
+    // g_{s} (s = 1..3) at rows r_s (ra) and r_s - 1 (rb); acc of stage s-1
+    // for the row stage s takes (acc_in[s-1])
+    double2 ra[3], rb[3], acc_in[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) ra[s] = rb[s] = acc_in[s] = zero2();
+    double kq[K + 1];
+#pragma unroll
+    for (int j = 0; j <= K; ++j) kq[j] = kap(rho0 + 1 - j);
+    double kn = kap(rho0 + 2);
+    int64_t ox = (int64_t)(rho0 + 1 + D) * n;
+    int64_t os = (int64_t)(rho0 - (K - 1)) * n + jc;
+
+    auto body = [&](int it, C& slot, auto check) {
+        constexpr bool CHECK = decltype(check)::value;
+        const int rho = rho0 + it;
+        const C xo = take(slot);
+        slot = ((unsigned)(rho + 1 + D) <= (unsigned)lmax ? in_i + ox : zrow)[jc];
+        ox += n;
+        const double2 xp = widen_lane(xo);
+
+        // stage 0 at row rho, from psi
+        const double2 h0 = h_row(xc, xm, xp, rho, kq[1], kq[0], er[0]);
+        double2 acc_new[3];
+        acc_new[0] = horner_update(xc, h0, b06);
+        double2 up = horner_update(xc, h0, a_half);     // g_1 at row rho
+        if (MASKED) up = pick2(inside, up, zero2());
+        // stages 1..3 at rows rho - s
+        const double2 psi_s[3] = {xm, x2, x3};
+#pragma unroll
+        for (int st = 1; st <= 3; ++st) {
+            const int rs = rho - st;
+            double2 v = zero2();
+            if (!CHECK || it >= 2 * st) {
+                const double2 hs = h_row(ra[st - 1], rb[st - 1], up, rs, kq[st + 1], kq[st], er[st]);
+                if (st < 3) {
+                    acc_new[st] = horner_update(acc_in[st - 1], hs, b13);
+                    v = horner_update(psi_s[st - 1], hs, st == 2 ? dt : a_half);
+                    if (MASKED) v = pick2(inside, v, zero2());
+                } else if (writes && (!CHECK || (rs >= I.l0 && rs < I.l1))) {
+                    stc(out_i, os, horner_update(acc_in[2], hs, b06));
+                }
+            } else if (st < 3) {
+                acc_new[st] = zero2();
+            }
+            rb[st - 1] = ra[st - 1];
+            ra[st - 1] = up;
+            up = v;
+        }
+#pragma unroll
+        for (int st = 0; st < 3; ++st) acc_in[st] = acc_new[st];
+#pragma unroll
+        for (int j = K; j > 0; --j) kq[j] = kq[j - 1];
+        kq[0] = kn;
+        kn = kap(rho + 3);
+        os += n;
+        x3 = x2;
+        x2 = xm;
+        xm = xc;
+        xc = xp;
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    const int warm_trips_end = (2 * (K - 1) + D - 1) / D * D;
+    const int iters = max((I.l1 - I.l0) + 2 * K - 2, warm_trips_end);
+    int it = 0;
+#pragma clang loop unroll(disable)
+    for (; it < warm_trips_end; it += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) body(it + u, sl[u], std::true_type{});
+    }
+    for (; it + D <= iters; it += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) body(it + u, sl[u], std::false_type{});
+    }
+#pragma unroll
+    for (int u = 0; u < D - 1; ++u)
+        if (it + u < iters) body(it + u, sl[u], std::false_type{});
+}
+
+template <int S, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_rk4_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in, typename Cplx<T>::type* __restrict__ out,
+            const double* __restrict__ step)
+{
+    const int halo = g.variant * S;             // = 4 S: lanes lost per side after the four stages
+    const int valid = 64 - 2 * halo;
+    const Tile I = my_tile(g);
+    const int n = I.n;
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = (int)threadIdx.x >> 6;
+    const int j0 = I.r0 + wave * valid - halo;
+    const int j = j0 + lane;
+    const bool inside = j >= 0 && j < n;
+    const int jc = min(max(j, 0), n - 1);
+    const bool writes = inside && lane >= halo && lane < 64 - halo;
+
+    const double r = (double)(jc + 1) * I.dr;
+    const double inv_r = 1.0 / r;
+    const double inv_r2 = inv_r * inv_r;
+    const double z_over_r = I.z * inv_r;
+    const double e_mid = step_value(step, g.n_inst, kEMid, I.inst) * r;
+    const double er[4] = {step_value(step, g.n_inst, kEStart, I.inst) * r, e_mid, e_mid,
+                          step_value(step, g.n_inst, kEEnd, I.inst) * r};
+    const double dt = step_value(step, g.n_inst, kDt, I.inst);
+
+    const auto* in_i = in + I.off;
+    auto* out_i = out + I.off;
+    if (j0 >= 0 && j0 + 63 < n)   // wave-uniform
+        rk4_strip_loop<S, T, false>(g, I, in_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, dt);
+    else
+        rk4_strip_loop<S, T, true>(g, I, in_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, dt);
+}
+
+hipError_t launch_rk4_strip(int prec, int S, const SweepGeom& g, const void* in, void* out, const double* step,
+                            hipStream_t st)
+{
+    if (g.variant != 4) return hipErrorInvalidValue;   // tiles built for the four stages
+    if (prec == 0) {
+        if (S == 1)
+            hipLaunchKernelGGL((k_rk4_strip<1, double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const double2*>(in), static_cast<double2*>(out), step);
+        else
+            hipLaunchKernelGGL((k_rk4_strip<2, double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const double2*>(in), static_cast<double2*>(out), step);
+    } else {
+        if (S == 1)
+            hipLaunchKernelGGL((k_rk4_strip<1, float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const float2*>(in), static_cast<float2*>(out), step);
+        else
+            hipLaunchKernelGGL((k_rk4_strip<2, float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const float2*>(in), static_cast<float2*>(out), step);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace tdse

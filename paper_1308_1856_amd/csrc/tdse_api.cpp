@@ -31,8 +31,8 @@ constexpr int kTargetTiles = 2048;       // aim for >= 8 workgroups per CU on 25
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 const char* kTimedNames[] = {"taylor_term", "rk4_stage", "observables", "lanczos_sweep_a", "apply_h",
-                             "taylor_fused"};
-constexpr int kNumTimed = 6;
+                             "taylor_fused", "rk4_fused"};
+constexpr int kNumTimed = 7;
 
 }  // namespace
 
@@ -47,6 +47,8 @@ struct tdse_ctx {
     int sweep_variant = 0;              // bit 0: two radii per thread, bit 1: XCD-contiguous order (autotuned)
     int fuse_k = 0;                     // Horner terms per fused launch (0: one launch per term)
     int fuse_kind = 0;                  // fused kernel: 0 LDS rings, 1 wave strips
+    bool rk4_fused = true;              // RK4: one strip launch per step (else four stage launches)
+    int rows_rk4 = 16;
     int rows_fused = 16;
     int64_t total_cols = 0;             // sum over instances of ceil(N/256) * (lmax+1)
     std::vector<double> kappa;
@@ -263,9 +265,10 @@ static int strip_width(int K, int stencil) { return kStripWaves * (64 - 2 * K * 
 static void build_tiles(tdse_ctx* c, int set, int rows)
 {
     c->tiles[set].clear();
-    if (set == kStripTiles) {
-        // tile r0 = first output radius; the kernel places its strips
-        const int K = std::max(1, c->fuse_k);
+    if (set == kStripTiles || set == kRk4Tiles) {
+        // tile r0 = first output radius; the kernel places its strips (the
+        // RK4 strips are built for its four stages)
+        const int K = (set == kRk4Tiles) ? 4 : std::max(1, c->fuse_k);
         const int W = strip_width(K, c->stencil);
         for (int k = 0; k < c->n_inst; ++k) {
             Inst& I = c->inst[k];
@@ -473,11 +476,20 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     int ro = kObsRows;
     while (ro > 1 && total_cols / ro < 256) ro /= 2;
     c->rows_obs = ro;
+    // RK4 strips: up to 16 rows, >= 1024 workgroups where the grid allows
+    int64_t rk4_cols = 0;
+    for (int k = 0; k < n_inst; ++k)
+        rk4_cols += (int64_t)((grids[k].n_r + strip_width(4, c->stencil) - 1) / strip_width(4, c->stencil)) *
+                    (grids[k].lmax + 1);
+    int r4 = 16;
+    while (r4 > 1 && rk4_cols / r4 < 1024) r4 /= 2;
+    c->rows_rk4 = r4;
     build_tiles(c, kObsTiles, c->rows_obs);
     build_tiles(c, kPopTiles, 0);
     build_tiles(c, kFusedTiles, c->rows_fused);
     build_tiles(c, kPairTiles, c->rows_sweep);
     build_tiles(c, kStripTiles, c->rows_fused);
+    build_tiles(c, kRk4Tiles, c->rows_rk4);
     // radial tables: u0 (normalised r exp(-z r)) and the bound eigenvectors
     c->radial.assign(tab, 0.0);
     std::vector<std::thread> pool;
@@ -528,7 +540,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         // one row per tile (and, fused, the narrowest tile width)
         size_t cap = c->tiles[set].size();
         if (set == kSweepTiles) cap = (size_t)c->total_cols;
-        if (set == kStripTiles) {
+        if (set == kStripTiles || set == kRk4Tiles) {
             cap = 0;
             const int W = strip_width(kMaxFused, c->stencil);
             for (const tdse_grid_desc& g : c->grids) cap += (size_t)((g.n_r + W - 1) / W) * (g.lmax + 1);
@@ -646,6 +658,7 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         {c->off_tiles[kFusedTiles], c->tiles[kFusedTiles].data(), sizeof(Tile) * c->tiles[kFusedTiles].size()},
         {c->off_tiles[kPairTiles], c->tiles[kPairTiles].data(), sizeof(Tile) * c->tiles[kPairTiles].size()},
         {c->off_tiles[kStripTiles], c->tiles[kStripTiles].data(), sizeof(Tile) * c->tiles[kStripTiles].size()},
+        {c->off_tiles[kRk4Tiles], c->tiles[kRk4Tiles].data(), sizeof(Tile) * c->tiles[kRk4Tiles].size()},
         {c->off_kappa, c->kappa.data(), sizeof(double) * c->kappa.size()},
         {c->off_radial, c->radial.data(), sizeof(double) * c->radial.size()},
     };
@@ -1042,6 +1055,28 @@ extern "C" tdse_status tdse_step_rk4(tdse_ctx* c, const tdse_pulse* pulses, cons
     st = check_stable(c, pulses, dt, 4);
     if (st != TDSE_OK) return st;
     const int S = c->stencil == 3 ? 1 : 2;
+    if (c->rk4_fused) {
+        // one strip launch per step; psi rotates through the state and work
+        // vectors 0 and 1 (a launch writes a buffer it does not read, and the
+        // buffer holding psi(s) is first overwritten in step s+2), so the
+        // observables may overlap the next step
+        SweepGeom g4 = c->geom(kRk4Tiles);
+        g4.variant = 4;
+        void* cur = c->d_state;
+        return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 2001, &cur, [&](const double* step) {
+            void* out = nullptr;
+            for (void* b : {static_cast<void*>(c->d_state), static_cast<void*>(c->d_vec(0)),
+                            static_cast<void*>(c->d_vec(1))})
+                if (b != cur && !out) out = b;
+            hipError_t e;
+            {
+                TimedLaunch tl(c, 6);
+                e = launch_rk4_strip(c->prec, S, g4, cur, out, step, c->stream);
+            }
+            if (e == hipSuccess) cur = out;
+            return e;
+        }, true);
+    }
     const SweepGeom g = c->geom();
     void* psi = c->d_state;
     void* ga = c->d_vec(0);
@@ -1402,6 +1437,20 @@ extern "C" tdse_status tdse_use_graphs(tdse_ctx* c, int32_t enable)
     if (!c->use_graphs) c->drop_graphs();
     return TDSE_OK;
 }
+
+extern "C" tdse_status tdse_set_rk4_fusion(tdse_ctx* c, int32_t enable)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (c->bound) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_set_rk4_fusion sync");
+    }
+    c->rk4_fused = enable != 0;
+    c->drop_graphs();
+    return TDSE_OK;
+}
+
+extern "C" int32_t tdse_rk4_fusion(const tdse_ctx* c) { return (c && c->rk4_fused) ? 1 : 0; }
 
 extern "C" tdse_status tdse_set_obs_overlap(tdse_ctx* c, int32_t enable)
 {

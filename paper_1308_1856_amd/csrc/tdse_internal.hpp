@@ -15,11 +15,11 @@ constexpr int kMaxKrylov = 64;      // largest Lanczos dimension
 // Tile sets: sweeps at 256 radii per tile (also RK4 stages), reductions
 // (Lanczos, copies), populations, fused Horner terms (LDS rings), sweeps at
 // 512 radii per tile (two radii per thread), fused Horner terms on wave
-// strips, and the observables' norm / dipole pass (taller tiles: fewer
-// partial sums to finish).
+// strips, the observables' norm / dipole pass (taller tiles: fewer partial
+// sums to finish), and RK4 steps on wave strips (built for the four stages).
 enum TileSetId {
     kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kFusedTiles = 3, kPairTiles = 4, kStripTiles = 5,
-    kObsTiles = 6, kNumTileSets = 7
+    kObsTiles = 6, kRk4Tiles = 7, kNumTileSets = 8
 };
 constexpr int kMaxFused = 8;        // most Horner terms per fused launch
 
@@ -106,6 +106,10 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
                                const void* psi, void* out, const double* step, int first_term,
                                hipStream_t st);
 constexpr int kStripWaves = kBlock / 64;   // strips per strip tile
+// One RK4 step on the strip tile set built for four levels (g.variant = 4):
+// reads psi from `in`, writes the new psi to `out` (must not alias `in`).
+hipError_t launch_rk4_strip(int prec, int S, const SweepGeom& g, const void* in, void* out, const double* step,
+                            hipStream_t st);
 
 // RK4 stage s (0..3); see the kernel for the buffer roles.
 hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, const void* gin,

@@ -121,6 +121,64 @@ def test_explicit_steps_fp64(method, order, stencil):
     assert np.all(gobs[:, 1] == robs[:, 1])          # fields identical (same libm on the host)
 
 
+@pytest.mark.parametrize("stencil", [3, 5])
+def test_rk4_one_launch_equals_stage_launches(stencil):
+    # the four RK4 stages in one strip launch per step compute every element
+    # from the same FP64 operands as the four stage launches: identical bits
+    # (states and observable records), on a grid of odd N, a single row and an
+    # uneven batch
+    t = lib()
+    say(f"RK4 in one launch vs four stage launches, stencil {stencil}")
+    pulse = t.Pulse(0.06, 0.35, 2.0, 0.2, 0.0)
+    cases = [[(523, 7, 0.1, stencil, 12.0)], [(65, 0, 0.1, stencil, 2.0)],
+             [(1500, 12, 0.1, stencil, 50.0), (333, 3, 0.1, stencil, 10.0), (2047, 21, 0.1, stencil, 60.0)]]
+    for grids in cases:
+        res = []
+        for fused in (False, True):
+            prop = make(grids, [(t.METHOD_RK4, 4)], 0)
+            prop.set_rk4_fusion(fused)
+            assert prop.rk4_fusion == fused
+            dts = [0.8 * t.tdse_taylor_stability_limit(4) / prop.lambda_max_bound(k, 0.06)
+                   for k in range(len(grids))]
+            for k in range(len(grids)):
+                prop.set_state(k, None)
+            obs = prop.obs_buffer(30, 3)
+            prop.step_rk4(pulse, 0.5, dts, 30, 3, obs)
+            res.append(([prop.get_state(k) for k in range(len(grids))], obs.cpu().numpy()))
+            prop.close()
+        for k in range(len(grids)):
+            assert np.array_equal(res[0][0][k], res[1][0][k]), (grids, k)
+        assert np.array_equal(res[0][1], res[1][1])
+
+
+def test_rk4_one_launch_fp32_tracks_fp64_oracle():
+    # FP32 storage: the one-launch step keeps the stage vectors in FP64, the
+    # stage launches round them to FP32; both stay within a few FP32 roundings
+    # per step of the FP64 oracle
+    t = lib()
+    say("RK4 FP32: one launch and stage launches vs the FP64 oracle")
+    grid = (700, 9, 0.1, 5, 20.0)
+    pulse = t.Pulse(0.06, 0.35, 2.0, 0.2, 0.0)
+    g = None
+    errs = []
+    for fused in (True, False):
+        prop = make([grid], [(t.METHOD_RK4, 4)], 1)
+        prop.set_rk4_fusion(fused)
+        g = orc_grid(prop.grids[0])
+        psi, _ = oracle.initial_state(g)
+        psi = to_fp32(psi)
+        prop.set_state(0, psi)
+        dt = 0.5 * t.tdse_taylor_stability_limit(4) / prop.lambda_max_bound(0, 0.06)
+        prop.step_rk4(pulse, 0.0, dt, 40)
+        got = prop.get_state(0)
+        prop.close()
+        setup = oracle.obs_setup(g, r_ion=20.0)
+        ref, _, _ = oracle.propagate(g, orc_pulse(pulse), oracle.RK4, 4, 0.0, dt, 40, 0, setup, psi)
+        errs.append(rel_err(got, ref))
+    say(f"  one launch {errs[0]:.2e}, stage launches {errs[1]:.2e}")
+    assert errs[0] < 4e-6 and errs[1] < 4e-6
+
+
 @pytest.mark.parametrize("m,stencil,dt", [(12, 5, 1e-3), (20, 3, 2e-3), (1, 3, 1e-3)])
 def test_lanczos_fp64(m, stencil, dt):
     say(f"lanczos m={m} stencil={stencil} dt={dt} FP64 vs oracle (converged Krylov space)")
