@@ -205,7 +205,10 @@ double tdse_taylor_stability_limit(int32_t order);
  * shape (1, 2, 4, 8, 16 or 32 rows per workgroup) and each sweep variant
  * (bit 0: one radius per thread on 256-radius tiles, or two adjacent radii
  * per thread on 512-radius tiles; bit 1: workgroups take tiles in order, or
- * each XCD takes a contiguous run of tiles), checks that every choice
+ * each XCD takes a contiguous run of tiles; bit 2: instead of either, wave
+ * strips of 64 radii with radial neighbours by lane shifts and rows loaded
+ * three rows ahead, 62 or 60 output radii per strip; variants 0, 1, 2, 3, 4
+ * and 6 are timed), checks that every choice
  * produces bit-identical results to the current one (a sweep's arithmetic
  * depends on neither), keeps the fastest and appends it to the tuning
  * cache named by the environment variable TDSE_TUNE_CACHE (if set; read by
@@ -238,7 +241,7 @@ int32_t tdse_taylor_fusion_kind(const tdse_ctx* ctx);
 tdse_status tdse_set_taylor_fusion(tdse_ctx* ctx, int32_t k, int32_t rows, int32_t kind);
 
 /* Rows per workgroup of the sweep tile set in use, and the sweep variant
- * (0..3, bits as in tdse_autotune); and an explicit choice of both (rows
+ * (0..7, bits as in tdse_autotune); and an explicit choice of both (rows
  * 1..32), e.g. to reproduce a tuned shape.  Results do not depend on it.
  * Synchronises. */
 int32_t tdse_tile_rows(const tdse_ctx* ctx);

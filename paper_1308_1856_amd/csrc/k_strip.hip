@@ -103,7 +103,8 @@ __device__ __forceinline__ double2 lane_above(double2 v, int d)
 // lmax in the sweep; zero here gives the same bits).
 constexpr int kStripDepth = 3;   // iterations of row loads in flight per wave (measured: 3 beats 2 and 4)
 
-template <int S, typename T, int K, bool MASKED>
+// APPLY (K = 1 only): out = H in, with no psi (the plain H-psi sweep).
+template <int S, typename T, int K, bool MASKED, bool APPLY = false>
 __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, const typename Cplx<T>::type* in_i,
                                            const typename Cplx<T>::type* psi_i, typename Cplx<T>::type* out_i,
                                            int jc, bool inside, bool writes, double er, double inv_r2,
@@ -154,7 +155,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     };
     Slot sl[D];
 #pragma unroll
-    for (int u = 0; u < D; ++u) sl[u] = Slot{rowp(in_i, rho0 + 1 + u)[jc], rowp(psi_i, rho0 + u)[jc]};
+    for (int u = 0; u < D; ++u) sl[u] = Slot{rowp(in_i, rho0 + 1 + u)[jc], APPLY ? zero_c<C>() : rowp(psi_i, rho0 + u)[jc]};
     // psi(rho_k) for level k = 1..K: pr[k-1]
     C pr[K];
 #pragma unroll
@@ -182,9 +183,9 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         const int rho = rho0 + it;
         // move the slot's rows out, then reload the slot for iteration it+D
         const C xo = take(sl.x);
-        const C po = take(sl.p);
+        const C po = APPLY ? zero_c<C>() : take(sl.p);
         sl.x = ((unsigned)(rho + 1 + D) <= (unsigned)lmax ? in_i + ox : zrow)[jc];
-        sl.p = ((unsigned)(rho + D) <= (unsigned)lmax ? psi_i + op : zrow)[jc];
+        if (!APPLY) sl.p = ((unsigned)(rho + D) <= (unsigned)lmax ? psi_i + op : zrow)[jc];
         ox += n;
         op += n;
         const double2 xp = widen_lane(xo);
@@ -193,7 +194,8 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         pr[0] = po;
 
         // level 1 from the input
-        double2 up = horner_update(widen(pr[0]), h_row(xc, xm, xp, rho, kq[1], kq[0]), coef[0]);
+        const double2 h1 = h_row(xc, xm, xp, rho, kq[1], kq[0]);
+        double2 up = APPLY ? h1 : horner_update(widen(pr[0]), h1, coef[0]);
         if (MASKED) up = pick2(inside, up, zero2());
         // the stored row: in [l0, l1) at every iteration past the warm-up trips
         auto store_row = [&](int rr) { return !CHECK || (rr >= I.l0 && rr < I.l1); };
@@ -323,6 +325,63 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
                                  : strip_k<2, double>(K, g, in, psi, out, step, first_term, st);
     return S == 1 ? strip_k<1, float>(K, g, in, psi, out, step, first_term, st)
                   : strip_k<2, float>(K, g, in, psi, out, step, first_term, st);
+}
+
+// The plain H-psi sweep (term 0: out = H(E_mid) in) and single Horner terms
+// (term >= 1: out = psi + (-i dt / term) H(E_mid) in) on wave strips of one
+// level (g.variant = 1: tiles of 4 strips of 64 - 2s output radii), the same
+// elements as the workgroup sweeps of k_sweep.hip, bit for bit.
+template <int S, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_apply_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in, typename Cplx<T>::type* __restrict__ out,
+              const double* __restrict__ step)
+{
+    const int halo = S;
+    const int valid = 64 - 2 * halo;
+    const Tile I = my_tile(g);
+    const int n = I.n;
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = (int)threadIdx.x >> 6;
+    const int j0 = I.r0 + wave * valid - halo;
+    const int j = j0 + lane;
+    const bool inside = j >= 0 && j < n;
+    const int jc = min(max(j, 0), n - 1);
+    const bool writes = inside && lane >= halo && lane < 64 - halo;
+    const double r = (double)(jc + 1) * I.dr;
+    const double inv_r = 1.0 / r;
+    const double inv_r2 = inv_r * inv_r;
+    const double z_over_r = I.z * inv_r;
+    const double er = step_value(step, g.n_inst, kEMid, I.inst) * r;
+    const double coef[1] = {0.0};
+    const auto* in_i = in + I.off;
+    auto* out_i = out + I.off;
+    if (j0 >= 0 && j0 + 63 < n)
+        strip_loop<S, T, 1, false, true>(g, I, in_i, in_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, coef);
+    else
+        strip_loop<S, T, 1, true, true>(g, I, in_i, in_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, coef);
+}
+
+hipError_t launch_strip_sweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi, void* out,
+                              const double* step, int term, hipStream_t st)
+{
+    if (g.variant != 1) return hipErrorInvalidValue;   // tiles built for one level
+    if (term >= 1) return launch_horner_strip(prec, S, 1, g, in, psi, out, step, term, st);
+    if (prec == 0) {
+        if (S == 1)
+            hipLaunchKernelGGL((k_apply_strip<1, double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const double2*>(in), static_cast<double2*>(out), step);
+        else
+            hipLaunchKernelGGL((k_apply_strip<2, double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const double2*>(in), static_cast<double2*>(out), step);
+    } else {
+        if (S == 1)
+            hipLaunchKernelGGL((k_apply_strip<1, float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const float2*>(in), static_cast<float2*>(out), step);
+        else
+            hipLaunchKernelGGL((k_apply_strip<2, float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const float2*>(in), static_cast<float2*>(out), step);
+    }
+    return hipGetLastError();
 }
 
 // One classic RK4 step (eq. RKDeriv) per launch on the wave strips, the four

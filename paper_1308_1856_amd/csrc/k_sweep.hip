@@ -345,6 +345,7 @@ static hipError_t hsweep_t(const SweepGeom& g, const void* in, const void* psi, 
 hipError_t launch_hsweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi,
                          void* out, const double* step, int term, hipStream_t st)
 {
+    if (g.set == kApplyTiles) return launch_strip_sweep(prec, S, g, in, psi, out, step, term, st);
     if (prec == 0) return S == 1 ? hsweep_t<1, double>(g, in, psi, out, step, term, st)
                                  : hsweep_t<2, double>(g, in, psi, out, step, term, st);
     return S == 1 ? hsweep_t<1, float>(g, in, psi, out, step, term, st)

@@ -44,7 +44,8 @@ struct tdse_ctx {
     std::vector<Inst> inst;
     std::vector<Tile> tiles[kNumTileSets];
     int rows_sweep = 1, rows_reduce = 1, rows_obs = 1;
-    int sweep_variant = 0;              // bit 0: two radii per thread, bit 1: XCD-contiguous order (autotuned)
+    int sweep_variant = 0;              // bit 0: two radii per thread, bit 1: XCD-contiguous order,
+                                        // bit 2: wave strips of one level (autotuned)
     int fuse_k = 0;                     // Horner terms per fused launch (0: one launch per term)
     int fuse_kind = 0;                  // fused kernel: 0 LDS rings, 1 wave strips
     bool rk4_fused = true;              // RK4: one strip launch per step (else four stage launches)
@@ -122,8 +123,9 @@ struct tdse_ctx {
     // geometry of the H sweeps (apply_H, Taylor terms) in the tuned shape
     SweepGeom hgeom() const
     {
-        SweepGeom g = geom((sweep_variant & 1) ? kPairTiles : kSweepTiles);
-        g.variant = sweep_variant & 1;
+        const bool strip = (sweep_variant & 4) != 0;
+        SweepGeom g = geom(strip ? kApplyTiles : (sweep_variant & 1) ? kPairTiles : kSweepTiles);
+        g.variant = strip ? 1 : (sweep_variant & 1);
         g.order = (sweep_variant >> 1) & 1;
         return g;
     }
@@ -265,10 +267,10 @@ static int strip_width(int K, int stencil) { return kStripWaves * (64 - 2 * K * 
 static void build_tiles(tdse_ctx* c, int set, int rows)
 {
     c->tiles[set].clear();
-    if (set == kStripTiles || set == kRk4Tiles) {
+    if (set == kStripTiles || set == kRk4Tiles || set == kApplyTiles) {
         // tile r0 = first output radius; the kernel places its strips (the
-        // RK4 strips are built for its four stages)
-        const int K = (set == kRk4Tiles) ? 4 : std::max(1, c->fuse_k);
+        // RK4 strips are built for its four stages, the sweep strips for one)
+        const int K = (set == kRk4Tiles) ? 4 : (set == kApplyTiles) ? 1 : std::max(1, c->fuse_k);
         const int W = strip_width(K, c->stencil);
         for (int k = 0; k < c->n_inst; ++k) {
             Inst& I = c->inst[k];
@@ -383,7 +385,7 @@ static int tune_cache_lookup(const tdse_ctx* c, int* variant)
     char kbuf[128];
     int rows = 0, var = 0, found = 0;
     while (std::fscanf(f, "%127s %d %d", kbuf, &rows, &var) == 3) {
-        if (key == kbuf && rows >= 1 && rows <= kTileRows && var >= 0 && var <= 3) {
+        if (key == kbuf && rows >= 1 && rows <= kTileRows && var >= 0 && var <= 7) {
             found = rows;  // last entry wins
             *variant = var;
         }
@@ -490,6 +492,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     build_tiles(c, kPairTiles, c->rows_sweep);
     build_tiles(c, kStripTiles, c->rows_fused);
     build_tiles(c, kRk4Tiles, c->rows_rk4);
+    build_tiles(c, kApplyTiles, c->rows_sweep);
     // radial tables: u0 (normalised r exp(-z r)) and the bound eigenvectors
     c->radial.assign(tab, 0.0);
     std::vector<std::thread> pool;
@@ -540,7 +543,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         // one row per tile (and, fused, the narrowest tile width)
         size_t cap = c->tiles[set].size();
         if (set == kSweepTiles) cap = (size_t)c->total_cols;
-        if (set == kStripTiles || set == kRk4Tiles) {
+        if (set == kStripTiles || set == kRk4Tiles || set == kApplyTiles) {
             cap = 0;
             const int W = strip_width(kMaxFused, c->stencil);
             for (const tdse_grid_desc& g : c->grids) cap += (size_t)((g.n_r + W - 1) / W) * (g.lmax + 1);
@@ -659,6 +662,7 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         {c->off_tiles[kPairTiles], c->tiles[kPairTiles].data(), sizeof(Tile) * c->tiles[kPairTiles].size()},
         {c->off_tiles[kStripTiles], c->tiles[kStripTiles].data(), sizeof(Tile) * c->tiles[kStripTiles].size()},
         {c->off_tiles[kRk4Tiles], c->tiles[kRk4Tiles].data(), sizeof(Tile) * c->tiles[kRk4Tiles].size()},
+        {c->off_tiles[kApplyTiles], c->tiles[kApplyTiles].data(), sizeof(Tile) * c->tiles[kApplyTiles].size()},
         {c->off_kappa, c->kappa.data(), sizeof(double) * c->kappa.size()},
         {c->off_radial, c->radial.data(), sizeof(double) * c->radial.size()},
     };
@@ -1192,14 +1196,16 @@ extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
     double best_ms = 1e300;
     int best = start_rows, best_variant = start_variant;
     const int cands[] = {1, 2, 4, 8, 16, 32};
-    // rows x variant (bit 0: two radii per thread, bit 1: XCD-contiguous order)
-    for (int cand = 0; cand < 24; ++cand) {
+    // rows x variant (bit 0: two radii per thread, bit 1: XCD-contiguous
+    // order, bit 2: wave strips of one level; with bit 2, bit 0 is unused)
+    const int variants[] = {0, 1, 2, 3, 4, 6};
+    for (int cand = 0; cand < 36; ++cand) {
         const int rows = cands[cand % 6];
-        const int variant = cand / 6;
+        const int variant = variants[cand / 6];
         if (e != hipSuccess) break;
         if (rows != 1 && c->total_cols / rows < 64) continue;
         c->sweep_variant = variant;
-        const int set = (variant & 1) ? kPairTiles : kSweepTiles;
+        const int set = (variant & 4) ? kApplyTiles : (variant & 1) ? kPairTiles : kSweepTiles;
         build_tiles(c, set, rows);
         e = upload_tiles(c, set);
         const SweepGeom g = c->hgeom();
@@ -1223,9 +1229,11 @@ extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
             (void)hipEventDestroy(e1);
             build_tiles(c, kSweepTiles, start_rows);
             build_tiles(c, kPairTiles, start_rows);
+            build_tiles(c, kApplyTiles, start_rows);
             c->sweep_variant = start_variant;
             (void)upload_tiles(c, kSweepTiles);
             (void)upload_tiles(c, kPairTiles);
+            (void)upload_tiles(c, kApplyTiles);
             (void)hipStreamSynchronize(c->stream);
             return c->fail(TDSE_E_HIP, "tdse_autotune: a tile shape changed the result of a sweep (" +
                                            std::to_string(diff) + " elements, rows " + std::to_string(rows) +
@@ -1241,9 +1249,11 @@ extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
     if (e1) (void)hipEventDestroy(e1);
     build_tiles(c, kSweepTiles, (e == hipSuccess) ? best : start_rows);
     build_tiles(c, kPairTiles, (e == hipSuccess) ? best : start_rows);
+    build_tiles(c, kApplyTiles, (e == hipSuccess) ? best : start_rows);
     c->sweep_variant = (e == hipSuccess) ? best_variant : start_variant;
     hipError_t e2 = upload_tiles(c, kSweepTiles);
     if (e2 == hipSuccess) e2 = upload_tiles(c, kPairTiles);
+    if (e2 == hipSuccess) e2 = upload_tiles(c, kApplyTiles);
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "tdse_autotune");
     if (e2 != hipSuccess) return c->hip_fail(e2, "tdse_autotune upload");
@@ -1403,8 +1413,8 @@ extern "C" tdse_status tdse_set_taylor_fusion(tdse_ctx* c, int32_t k, int32_t ro
 extern "C" tdse_status tdse_set_sweep_shape(tdse_ctx* c, int32_t rows, int32_t variant)
 {
     if (!c) return TDSE_E_INVALID;
-    if (rows < 1 || rows > kTileRows || variant < 0 || variant > 3)
-        return c->fail(TDSE_E_INVALID, "tdse_set_sweep_shape: rows must be 1..32 and variant 0..3");
+    if (rows < 1 || rows > kTileRows || variant < 0 || variant > 7)
+        return c->fail(TDSE_E_INVALID, "tdse_set_sweep_shape: rows must be 1..32 and variant 0..7");
     if (c->bound) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "tdse_set_sweep_shape sync");
@@ -1413,9 +1423,11 @@ extern "C" tdse_status tdse_set_sweep_shape(tdse_ctx* c, int32_t rows, int32_t v
     c->sweep_variant = variant;
     build_tiles(c, kSweepTiles, rows);
     build_tiles(c, kPairTiles, rows);
+    build_tiles(c, kApplyTiles, rows);
     if (c->bound) {
         hipError_t e = upload_tiles(c, kSweepTiles);
         if (e == hipSuccess) e = upload_tiles(c, kPairTiles);
+        if (e == hipSuccess) e = upload_tiles(c, kApplyTiles);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "tdse_set_sweep_shape upload");
     }

@@ -16,10 +16,11 @@ constexpr int kMaxKrylov = 64;      // largest Lanczos dimension
 // (Lanczos, copies), populations, fused Horner terms (LDS rings), sweeps at
 // 512 radii per tile (two radii per thread), fused Horner terms on wave
 // strips, the observables' norm / dipole pass (taller tiles: fewer partial
-// sums to finish), and RK4 steps on wave strips (built for the four stages).
+// sums to finish), RK4 steps on wave strips (built for the four stages) and
+// the H sweeps on wave strips of one level.
 enum TileSetId {
     kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kFusedTiles = 3, kPairTiles = 4, kStripTiles = 5,
-    kObsTiles = 6, kRk4Tiles = 7, kNumTileSets = 8
+    kObsTiles = 6, kRk4Tiles = 7, kApplyTiles = 8, kNumTileSets = 9
 };
 constexpr int kMaxFused = 8;        // most Horner terms per fused launch
 
@@ -74,7 +75,8 @@ struct SweepGeom {
     int32_t n_tiles;
     int32_t n_inst;
     int32_t set;           // TileSetId of `tiles`
-    int32_t variant;       // H sweep: 0 one radius per thread, 1 two radii per thread
+    int32_t variant;       // H sweep: 0 one radius per thread, 1 two radii per thread;
+                           // strip sets: the level count the tiles were built for
     int32_t order;         // block -> tile map: 0 identity, 1 XCD-contiguous runs
     const void* zero_row;  // device zeros, at least max N complex FP64 values
 };
@@ -106,6 +108,10 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
                                const void* psi, void* out, const double* step, int first_term,
                                hipStream_t st);
 constexpr int kStripWaves = kBlock / 64;   // strips per strip tile
+// An H sweep (term 0) or one Horner term on the strip tile set built for one
+// level (g.variant = 1); same results and aliasing rules as launch_hsweep.
+hipError_t launch_strip_sweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi, void* out,
+                              const double* step, int term, hipStream_t st);
 // One RK4 step on the strip tile set built for four levels (g.variant = 4):
 // reads psi from `in`, writes the new psi to `out` (must not alias `in`).
 hipError_t launch_rk4_strip(int prec, int S, const SweepGeom& g, const void* in, void* out, const double* step,

@@ -68,6 +68,30 @@ def test_apply_h(stencil, prec):
     prop.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_h_strip_sweep_bitwise(prec):
+    # H psi on wave strips of one level (sweep variant 4) gives the bits of the
+    # workgroup sweeps (variants 0 and 1), for both stencils, odd N and a
+    # single row
+    t = lib()
+    say(f"apply_H on strips vs workgroup sweeps, prec {prec}")
+    for n, lmax, stencil in ((701, 9, 3), (1999, 14, 5), (65, 0, 5), (130, 3, 3)):
+        psi = workloads.random_state(5, n, lmax)
+        if prec == 1:
+            psi = to_fp32(psi)
+        outs = []
+        for rows, variant in ((4, 0), (8, 1), (4, 4), (1, 6), (16, 4)):
+            prop = make([(n, lmax, 0.1, stencil, 20.0)], [(t.METHOD_TAYLOR, 2)], prec)
+            prop.set_sweep_shape(rows, variant)
+            prop.set_state(0, psi)
+            out = prop.new_vector()
+            prop.apply_H(0.043, prop.state, out)
+            outs.append(read_vector(prop, out, 0))
+            prop.close()
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0]), (n, lmax, stencil)
+
+
 def _propagate_pair(method, order, n=520, lmax=7, dr=0.1, stencil=5, dt=4e-4, steps=40,
                     obs_every=10, prec=0, pulse=None, psi=None, t0=0.0, r_ion=12.0):
     t = lib()
@@ -532,7 +556,7 @@ def test_explicit_sweep_shape_bitwise():
     pulse = t.Pulse(0.05, 0.2, 2.0, 0.3, 0.0)
     say("explicit sweep shapes: Taylor-8 bitwise across (rows, variant)")
     out = []
-    for rows, variant in ((1, 0), (8, 1), (4, 2), (32, 3)):
+    for rows, variant in ((1, 0), (8, 1), (4, 2), (32, 3), (16, 4), (2, 6), (1, 4)):
         prop = t.Propagator([grid], methods=((t.METHOD_TAYLOR, 8),))
         prop.set_sweep_shape(rows, variant)
         assert (prop.tile_rows, prop.sweep_variant) == (rows, variant)
