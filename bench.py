@@ -146,10 +146,6 @@ def source_digest(name):
     return h.hexdigest()
 
 
-KERNEL_SOURCE = {"taylor_term": "k_sweep.hip", "apply_h": "k_sweep.hip", "rk4_stage": "k_sweep.hip",
-                 "rk4_fused": "k_strip.hip", "lanczos_sweep_a": "k_lanczos.hip"}
-
-
 def shape_of(prop, kernel):
     if kernel == "taylor_fused":
         return {"fuse_k": prop.taylor_fusion, "rows": getattr(prop, "fusion_rows", None),
