@@ -126,15 +126,25 @@ __device__ __forceinline__ double block_sum(double (&v)[NQ], double* lds /* [kBl
 // The tile handled by this workgroup.  order 0: tile = blockIdx.x (the
 // hardware deals workgroup b to XCD b mod 8, so consecutive tiles land on
 // different XCDs).  order 1: each XCD gets a contiguous run of tiles, so the
-// radial and l halos of neighbouring tiles meet in that XCD's L2.  Both are
-// bijections of [0, n_tiles); which one streams faster depends on the shape
-// and is left to the autotuner.
+// radial and l halos of neighbouring tiles meet in that XCD's L2.  order 2:
+// runs of kXcdGroup consecutive tiles go to one XCD, the runs dealt round
+// the XCDs: the 8 XCDs still sweep neighbouring tiles at the same time (as
+// order 0), and the radial halos inside a run meet in one L2 (the tiles
+// past the last whole round of runs keep order 0).  All are bijections of
+// [0, n_tiles); which one streams faster depends on the shape and is left to
+// the autotuner.
+constexpr int kXcdGroup = 4;
 __device__ __forceinline__ int my_tile_index(const SweepGeom& g)
 {
     const int b = (int)blockIdx.x;
     if (g.order == 0) return b;
-    const int q = g.n_tiles >> 3, rem = g.n_tiles & 7;
     const int x = b & 7, j = b >> 3;
+    if (g.order == 2) {
+        constexpr int round = 8 * kXcdGroup;
+        if (b >= g.n_tiles / round * round) return b;
+        return (j / kXcdGroup) * round + x * kXcdGroup + j % kXcdGroup;
+    }
+    const int q = g.n_tiles >> 3, rem = g.n_tiles & 7;
     return x * q + min(x, rem) + j;
 }
 __device__ __forceinline__ Tile my_tile(const SweepGeom& g) { return g.tiles[my_tile_index(g)]; }

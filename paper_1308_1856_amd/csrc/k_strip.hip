@@ -62,6 +62,23 @@ __device__ __forceinline__ double2 dpp_shift2(double2 v)
 {
     return make_double2(dpp_shift<CTRL>(v.x), dpp_shift<CTRL>(v.y));
 }
+// The same shift, with the lane that has no source (lane 0 for wave_shr,
+// lane 63 for wave_shl) keeping its value of `edge` instead of zero.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift_edge(double v, double edge)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long e = (unsigned long long)__double_as_longlong(edge);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)e, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(e >> 32), (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf,
+                                               false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ double2 dpp_shift2_edge(double2 v, double2 edge)
+{
+    return make_double2(dpp_shift_edge<CTRL>(v.x, edge.x), dpp_shift_edge<CTRL>(v.y, edge.y));
+}
 // A copy of v in registers of its own (an actual move, which the compiler
 // cannot fold into v's registers), ordered before every later memory access:
 // the registers of v are then free for a reload of v's variable, so a loop
@@ -103,13 +120,26 @@ __device__ __forceinline__ double2 lane_above(double2 v, int d)
 // lmax in the sweep; zero here gives the same bits).
 constexpr int kStripDepth = 3;   // iterations of row loads in flight per wave (measured: 3 beats 2 and 4)
 
+// Radii just outside an aligned strip (ALIGNED below): lanes 0..31 hold
+// j0 - 1 (e1) and j0 - 2 (e2), lanes 32..63 j0 + 64 and j0 + 65, clamped into
+// [0, N); in1 / in2: the unclamped radius lies in [0, N).
+struct StripEdge {
+    int e1 = 0, e2 = 0;
+    bool in1 = false, in2 = false;
+};
+
 // APPLY (K = 1 only): out = H in, with no psi (the plain H-psi sweep).
-template <int S, typename T, int K, bool MASKED, bool APPLY = false>
+// ALIGNED (K = 1 only): the wave writes all 64 of its radii; the radial
+// neighbours beyond its ends are read per row as two (s = 2: four) extra
+// values and enter the DPP shifts as the end lanes' values, so strips need
+// not overlap, and each wave's loads and stores cover whole aligned lines.
+template <int S, typename T, int K, bool MASKED, bool APPLY = false, bool ALIGNED = false, int D = kStripDepth>
 __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, const typename Cplx<T>::type* in_i,
                                            const typename Cplx<T>::type* psi_i, typename Cplx<T>::type* out_i,
                                            int jc, bool inside, bool writes, double er, double inv_r2,
-                                           double z_over_r, const double (&coef)[K])
+                                           double z_over_r, const double (&coef)[K], StripEdge edge = {})
 {
+    static_assert(!(APPLY || ALIGNED) || K == 1, "the plain sweep and the aligned strips have one level");
     using C = typename Cplx<T>::type;
     const int n = I.n, lmax = I.lmax;
     const C* zrow = static_cast<const C*>(g.zero_row);
@@ -138,24 +168,60 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         }
         return h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2, row_potential(rr, inv_r2, z_over_r), er, kl, klp);
     };
+    // the same with the centre row's values beyond the wave ends (c1: one
+    // radius out, c2: two)
+    auto h_row_edge = [&](double2 c, double2 c1, double2 c2, double2 lm, double2 lp, int rr, double kl,
+                          double klp) -> double2 {
+        const double2 m1 = dpp_shift2_edge<kDppWaveShr1>(c, c1), p1 = dpp_shift2_edge<kDppWaveShl1>(c, c1);
+        double2 m2 = zero2(), p2 = zero2();
+        if (S == 2) {
+            m2 = dpp_shift2_edge<kDppWaveShr1>(m1, c2);
+            p2 = dpp_shift2_edge<kDppWaveShl1>(p1, c2);
+        }
+        return h_point<S>(c, m1, p1, m2, p2, lm, lp, I.inv_dr2, row_potential(rr, inv_r2, z_over_r), er, kl, klp);
+    };
+    auto widen_edge = [&](C raw, bool in) -> double2 {
+        const double2 v = widen(raw);
+        return MASKED ? pick2(in, v, zero2()) : v;
+    };
 
     const int rho0 = I.l0 - K + 1;              // level-1 row at it = 0
     // input rows rho-1, rho (FP64) of the current iteration
     double2 xm = widen_lane(rowp(in_i, rho0 - 1)[jc]);
     double2 xc = widen_lane(rowp(in_i, rho0)[jc]);
-    // Rows are loaded D = kStripDepth iterations ahead, into D register slots
+    // ALIGNED: row rho's values beyond the wave ends
+    double2 xc1 = zero2(), xc2 = zero2();
+    if (ALIGNED) {
+        xc1 = widen_edge(rowp(in_i, rho0)[edge.e1], edge.in1);
+        if (S == 2) xc2 = widen_edge(rowp(in_i, rho0)[edge.e2], edge.in2);
+    }
+    // Rows are loaded D iterations ahead, into D register slots
     // that the iterations take in turn (iteration it uses slot it mod D): the
     // slot holds input row rho+1 and psi(rho) and is reloaded, in place, with
     // the rows of iteration it+D.  One iteration of loads in flight per wave
     // is too little to cover the memory latency (with 8-byte FP32 elements
     // above all).
-    constexpr int D = kStripDepth;
+    //
+    // Iterations it = 0 .. iters-1 run (loop trips below).  Their last reads
+    // the input row rho0 + iters and the psi row rho0 + iters - 1: the
+    // prefetches of later rows, for iterations that never run, read the zero
+    // row instead (no HBM traffic for rows the tile does not use).
+    const int warm_trips_end = (2 * (K - 1) + D - 1) / D * D;
+    const int iters = max((I.l1 - I.l0) + 2 * K - 2, warm_trips_end);
+    const int xhi = min(lmax, rho0 + iters);
+    const int phi = min(lmax, rho0 + iters - 1);
+    auto rowp_x = [&](int rr) -> const C* { return (unsigned)rr <= (unsigned)xhi ? in_i + (int64_t)rr * n : zrow; };
+    auto rowp_p = [&](int rr) -> const C* { return (unsigned)rr <= (unsigned)phi ? psi_i + (int64_t)rr * n : zrow; };
     struct Slot {
-        C x, p;
+        C x, p, x1, x2;   // x1, x2: row rho+1 beyond the wave ends (ALIGNED)
     };
     Slot sl[D];
 #pragma unroll
-    for (int u = 0; u < D; ++u) sl[u] = Slot{rowp(in_i, rho0 + 1 + u)[jc], APPLY ? zero_c<C>() : rowp(psi_i, rho0 + u)[jc]};
+    for (int u = 0; u < D; ++u) {
+        const C* xr = rowp_x(rho0 + 1 + u);
+        sl[u] = Slot{xr[jc], APPLY ? zero_c<C>() : rowp_p(rho0 + u)[jc], ALIGNED ? xr[edge.e1] : zero_c<C>(),
+                     ALIGNED && S == 2 ? xr[edge.e2] : zero_c<C>()};
+    }
     // psi(rho_k) for level k = 1..K: pr[k-1]
     C pr[K];
 #pragma unroll
@@ -184,17 +250,25 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         // move the slot's rows out, then reload the slot for iteration it+D
         const C xo = take(sl.x);
         const C po = APPLY ? zero_c<C>() : take(sl.p);
-        sl.x = ((unsigned)(rho + 1 + D) <= (unsigned)lmax ? in_i + ox : zrow)[jc];
-        if (!APPLY) sl.p = ((unsigned)(rho + D) <= (unsigned)lmax ? psi_i + op : zrow)[jc];
+        const C xo1 = ALIGNED ? take(sl.x1) : zero_c<C>();
+        const C xo2 = ALIGNED && S == 2 ? take(sl.x2) : zero_c<C>();
+        const C* xr = (unsigned)(rho + 1 + D) <= (unsigned)xhi ? in_i + ox : zrow;
+        sl.x = xr[jc];
+        if (!APPLY) sl.p = ((unsigned)(rho + D) <= (unsigned)phi ? psi_i + op : zrow)[jc];
+        if (ALIGNED) sl.x1 = xr[edge.e1];
+        if (ALIGNED && S == 2) sl.x2 = xr[edge.e2];
         ox += n;
         op += n;
         const double2 xp = widen_lane(xo);
+        const double2 xp1 = ALIGNED ? widen_edge(xo1, edge.in1) : zero2();
+        const double2 xp2 = ALIGNED && S == 2 ? widen_edge(xo2, edge.in2) : zero2();
 #pragma unroll
         for (int k = K - 1; k > 0; --k) pr[k] = pr[k - 1];
         pr[0] = po;
 
         // level 1 from the input
-        const double2 h1 = h_row(xc, xm, xp, rho, kq[1], kq[0]);
+        const double2 h1 = ALIGNED ? h_row_edge(xc, xc1, xc2, xm, xp, rho, kq[1], kq[0])
+                                   : h_row(xc, xm, xp, rho, kq[1], kq[0]);
         double2 up = APPLY ? h1 : horner_update(widen(pr[0]), h1, coef[0]);
         if (MASKED) up = pick2(inside, up, zero2());
         // the stored row: in [l0, l1) at every iteration past the warm-up trips
@@ -223,6 +297,8 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         os += n;
         xm = xc;
         xc = xp;
+        xc1 = xp1;
+        xc2 = xp2;
         // keep the iterations of a loop trip apart: interleaving them would
         // hold several iterations' values in registers at once
         __builtin_amdgcn_sched_barrier(0);
@@ -235,8 +311,6 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     // iterations.  A tile too short to reach the end of the warm-up trips
     // runs on to it: the extra iterations compute rows past l1 (inputs
     // outside [0, lmax] read as zero) and store nothing.
-    const int warm_trips_end = (2 * (K - 1) + D - 1) / D * D;
-    const int iters = max((I.l1 - I.l0) + 2 * K - 2, warm_trips_end);
     int it = 0;
 #pragma clang loop unroll(disable)
     for (; it < warm_trips_end; it += D) {
@@ -328,60 +402,74 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
 }
 
 // The plain H-psi sweep (term 0: out = H(E_mid) in) and single Horner terms
-// (term >= 1: out = psi + (-i dt / term) H(E_mid) in) on wave strips of one
-// level (g.variant = 1: tiles of 4 strips of 64 - 2s output radii), the same
-// elements as the workgroup sweeps of k_sweep.hip, bit for bit.
-template <int S, typename T>
+// (term >= 1: out = psi + (-i dt / term) H(E_mid) in) on aligned wave strips
+// of one level: a tile is 4 waves of 64 consecutive radii from a multiple of
+// 256, each wave writing all of its radii (the radial neighbours beyond its
+// ends come from two (s = 2: four) extra values per row).  The elements are
+// those of the workgroup sweeps of k_sweep.hip, bit for bit.
+template <int S, typename T, bool APPLY>
 __global__ void __launch_bounds__(kBlock)
-k_apply_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in, typename Cplx<T>::type* __restrict__ out,
-              const double* __restrict__ step)
+k_sweep_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
+              const typename Cplx<T>::type* __restrict__ psi, typename Cplx<T>::type* __restrict__ out,
+              const double* __restrict__ step, int term)
 {
-    const int halo = S;
-    const int valid = 64 - 2 * halo;
     const Tile I = my_tile(g);
     const int n = I.n;
     const int lane = (int)threadIdx.x & 63;
     const int wave = (int)threadIdx.x >> 6;
-    const int j0 = I.r0 + wave * valid - halo;
+    const int j0 = I.r0 + wave * 64;            // radius of lane 0
+    if (j0 >= n) return;                        // wave-uniform; no LDS, no barrier
     const int j = j0 + lane;
-    const bool inside = j >= 0 && j < n;
-    const int jc = min(max(j, 0), n - 1);
-    const bool writes = inside && lane >= halo && lane < 64 - halo;
+    const bool inside = j < n;
+    const int jc = min(j, n - 1);
+    StripEdge edge;
+    {
+        const int e1 = lane < 32 ? j0 - 1 : j0 + 64;
+        const int e2 = lane < 32 ? j0 - 2 : j0 + 65;
+        edge.in1 = e1 >= 0 && e1 < n;
+        edge.in2 = e2 >= 0 && e2 < n;
+        edge.e1 = min(max(e1, 0), n - 1);
+        edge.e2 = min(max(e2, 0), n - 1);
+    }
     const double r = (double)(jc + 1) * I.dr;
     const double inv_r = 1.0 / r;
     const double inv_r2 = inv_r * inv_r;
     const double z_over_r = I.z * inv_r;
     const double er = step_value(step, g.n_inst, kEMid, I.inst) * r;
-    const double coef[1] = {0.0};
+    const double coef[1] = {APPLY ? 0.0 : wave_uniform(step_value(step, g.n_inst, kDt, I.inst) / (double)term)};
     const auto* in_i = in + I.off;
+    const auto* psi_i = psi + I.off;
     auto* out_i = out + I.off;
-    if (j0 >= 0 && j0 + 63 < n)
-        strip_loop<S, T, 1, false, true>(g, I, in_i, in_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, coef);
+    if (j0 - S >= 0 && j0 + 63 + S < n)   // wave-uniform: every value the wave reads is inside
+        strip_loop<S, T, 1, false, APPLY, true>(g, I, in_i, psi_i, out_i, jc, inside, inside, er, inv_r2, z_over_r,
+                                                coef, edge);
     else
-        strip_loop<S, T, 1, true, true>(g, I, in_i, in_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, coef);
+        strip_loop<S, T, 1, true, APPLY, true>(g, I, in_i, psi_i, out_i, jc, inside, inside, er, inv_r2, z_over_r,
+                                               coef, edge);
+}
+
+template <int S, typename T>
+static hipError_t sweep_strip_t(const SweepGeom& g, const void* in, const void* psi, void* out, const double* step,
+                                int term, hipStream_t st)
+{
+    using C = typename Cplx<T>::type;
+    if (term == 0)
+        hipLaunchKernelGGL((k_sweep_strip<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const C*>(in), static_cast<const C*>(in), static_cast<C*>(out), step, term);
+    else
+        hipLaunchKernelGGL((k_sweep_strip<S, T, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out), step, term);
+    return hipGetLastError();
 }
 
 hipError_t launch_strip_sweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi, void* out,
                               const double* step, int term, hipStream_t st)
 {
-    if (g.variant != 1) return hipErrorInvalidValue;   // tiles built for one level
-    if (term >= 1) return launch_horner_strip(prec, S, 1, g, in, psi, out, step, term, st);
-    if (prec == 0) {
-        if (S == 1)
-            hipLaunchKernelGGL((k_apply_strip<1, double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                               static_cast<const double2*>(in), static_cast<double2*>(out), step);
-        else
-            hipLaunchKernelGGL((k_apply_strip<2, double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                               static_cast<const double2*>(in), static_cast<double2*>(out), step);
-    } else {
-        if (S == 1)
-            hipLaunchKernelGGL((k_apply_strip<1, float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                               static_cast<const float2*>(in), static_cast<float2*>(out), step);
-        else
-            hipLaunchKernelGGL((k_apply_strip<2, float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                               static_cast<const float2*>(in), static_cast<float2*>(out), step);
-    }
-    return hipGetLastError();
+    if (g.variant != 1 || term < 0) return hipErrorInvalidValue;   // aligned tiles of one level
+    if (prec == 0) return S == 1 ? sweep_strip_t<1, double>(g, in, psi, out, step, term, st)
+                                 : sweep_strip_t<2, double>(g, in, psi, out, step, term, st);
+    return S == 1 ? sweep_strip_t<1, float>(g, in, psi, out, step, term, st)
+                  : sweep_strip_t<2, float>(g, in, psi, out, step, term, st);
 }
 
 // One classic RK4 step (eq. RKDeriv) per launch on the wave strips, the four
@@ -438,11 +526,19 @@ __device__ __forceinline__ void rk4_strip_loop(const SweepGeom& g, const Tile& I
     double2 x2 = widen_lane(rowp(in_i, rho0 - 2)[jc]);
     double2 xm = widen_lane(rowp(in_i, rho0 - 1)[jc]);
     double2 xc = widen_lane(rowp(in_i, rho0)[jc]);
-    // psi row rho+1, loaded D iterations ahead into D slots (as in strip_loop)
+    // psi row rho+1, loaded D iterations ahead into D slots (as in strip_loop,
+    // with rows past the last one the tile's iterations read taken from the
+    // zero row)
     constexpr int D = kStripDepth;
+    const int warm_trips_end = (2 * (K - 1) + D - 1) / D * D;
+    const int iters = max((I.l1 - I.l0) + 2 * K - 2, warm_trips_end);
+    const int xhi = min(lmax, rho0 + iters);
     C sl[D];
 #pragma unroll
-    for (int u = 0; u < D; ++u) sl[u] = rowp(in_i, rho0 + 1 + u)[jc];
+    for (int u = 0; u < D; ++u) {
+        const int rr = rho0 + 1 + u;
+        sl[u] = ((unsigned)rr <= (unsigned)xhi ? in_i + (int64_t)rr * n : zrow)[jc];
+    }
     // g_{s} (s = 1..3) at rows r_s (ra) and r_s - 1 (rb); acc of stage s-1
     // for the row stage s takes (acc_in[s-1])
     double2 ra[3], rb[3], acc_in[3];
@@ -459,7 +555,7 @@ __device__ __forceinline__ void rk4_strip_loop(const SweepGeom& g, const Tile& I
         constexpr bool CHECK = decltype(check)::value;
         const int rho = rho0 + it;
         const C xo = take(slot);
-        slot = ((unsigned)(rho + 1 + D) <= (unsigned)lmax ? in_i + ox : zrow)[jc];
+        slot = ((unsigned)(rho + 1 + D) <= (unsigned)xhi ? in_i + ox : zrow)[jc];
         ox += n;
         const double2 xp = widen_lane(xo);
 
@@ -504,8 +600,6 @@ __device__ __forceinline__ void rk4_strip_loop(const SweepGeom& g, const Tile& I
         xc = xp;
         __builtin_amdgcn_sched_barrier(0);
     };
-    const int warm_trips_end = (2 * (K - 1) + D - 1) / D * D;
-    const int iters = max((I.l1 - I.l0) + 2 * K - 2, warm_trips_end);
     int it = 0;
 #pragma clang loop unroll(disable)
     for (; it < warm_trips_end; it += D) {

@@ -126,7 +126,9 @@ struct tdse_ctx {
         const bool strip = (sweep_variant & 4) != 0;
         SweepGeom g = geom(strip ? kApplyTiles : (sweep_variant & 1) ? kPairTiles : kSweepTiles);
         g.variant = strip ? 1 : (sweep_variant & 1);
-        g.order = (sweep_variant >> 1) & 1;
+        // bit 1: XCD-contiguous runs (workgroup sweeps), runs of kXcdGroup
+        // tiles per XCD (strips)
+        g.order = (sweep_variant & 2) ? (strip ? 2 : 1) : 0;
         return g;
     }
     double* d_step() const { return reinterpret_cast<double*>(d_work + off_step); }
@@ -270,12 +272,21 @@ static void build_tiles(tdse_ctx* c, int set, int rows)
     if (set == kStripTiles || set == kRk4Tiles || set == kApplyTiles) {
         // tile r0 = first output radius; the kernel places its strips (the
         // RK4 strips are built for its four stages, the sweep strips for one)
-        const int K = (set == kRk4Tiles) ? 4 : (set == kApplyTiles) ? 1 : std::max(1, c->fuse_k);
-        const int W = strip_width(K, c->stencil);
+        // (the sweep strips are aligned: 4 waves of 64 radii, no overlap)
+        const int K = (set == kRk4Tiles) ? 4 : std::max(1, c->fuse_k);
+        const int W = (set == kApplyTiles) ? kBlock : strip_width(K, c->stencil);
         for (int k = 0; k < c->n_inst; ++k) {
             Inst& I = c->inst[k];
             I.tbegin[set] = (int32_t)c->tiles[set].size();
-            for (int l0 = 0; l0 <= I.lmax; l0 += rows) {
+            // the rows split into the fewest blocks of at most `rows`, of
+            // near-equal height: a strip walks its block one row per
+            // iteration, so a short remainder block would finish early
+            // and leave its SIMD idle at the end of the launch
+            const int nrow = I.lmax + 1;
+            const int nblk = (nrow + rows - 1) / rows;
+            for (int b = 0; b < nblk; ++b) {
+                const int l0 = (int)((int64_t)b * nrow / nblk);
+                const int l1 = (int)((int64_t)(b + 1) * nrow / nblk);
                 for (int o0 = 0; o0 < I.n; o0 += W) {
                     Tile t;
                     std::memset(&t, 0, sizeof t);
@@ -284,7 +295,7 @@ static void build_tiles(tdse_ctx* c, int set, int rows)
                     t.inst = k;
                     t.r0 = o0;
                     t.l0 = l0;
-                    t.l1 = std::min(l0 + rows, I.lmax + 1);
+                    t.l1 = l1;
                     t.n = I.n;
                     t.lmax = I.lmax;
                     t.i_ion = I.i_ion;

@@ -17,7 +17,7 @@ constexpr int kMaxKrylov = 64;      // largest Lanczos dimension
 // 512 radii per tile (two radii per thread), fused Horner terms on wave
 // strips, the observables' norm / dipole pass (taller tiles: fewer partial
 // sums to finish), RK4 steps on wave strips (built for the four stages) and
-// the H sweeps on wave strips of one level.
+// the H sweeps on aligned wave strips of one level.
 enum TileSetId {
     kSweepTiles = 0, kReduceTiles = 1, kPopTiles = 2, kFusedTiles = 3, kPairTiles = 4, kStripTiles = 5,
     kObsTiles = 6, kRk4Tiles = 7, kApplyTiles = 8, kNumTileSets = 9
@@ -77,7 +77,7 @@ struct SweepGeom {
     int32_t set;           // TileSetId of `tiles`
     int32_t variant;       // H sweep: 0 one radius per thread, 1 two radii per thread;
                            // strip sets: the level count the tiles were built for
-    int32_t order;         // block -> tile map: 0 identity, 1 XCD-contiguous runs
+    int32_t order;         // block -> tile map: 0 identity, 1 XCD-contiguous runs, 2 short runs dealt round the XCDs
     const void* zero_row;  // device zeros, at least max N complex FP64 values
 };
 
@@ -108,8 +108,9 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
                                const void* psi, void* out, const double* step, int first_term,
                                hipStream_t st);
 constexpr int kStripWaves = kBlock / 64;   // strips per strip tile
-// An H sweep (term 0) or one Horner term on the strip tile set built for one
-// level (g.variant = 1); same results and aliasing rules as launch_hsweep.
+// An H sweep (term 0) or one Horner term on the aligned strip tile set of one
+// level (g.variant = 1; tiles of 4 waves of 64 radii from a multiple of 256);
+// same results and aliasing rules as launch_hsweep.
 hipError_t launch_strip_sweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi, void* out,
                               const double* step, int term, hipStream_t st);
 // One RK4 step on the strip tile set built for four levels (g.variant = 4):

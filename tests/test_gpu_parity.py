@@ -70,12 +70,12 @@ def test_apply_h(stencil, prec):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_apply_h_strip_sweep_bitwise(prec):
-    # H psi on wave strips of one level (sweep variant 4) gives the bits of the
-    # workgroup sweeps (variants 0 and 1), for both stencils, odd N and a
-    # single row
+    # H psi on aligned wave strips of one level (sweep variants 4, 6) gives the
+    # bits of the workgroup sweeps (variants 0 and 1), for both stencils, odd
+    # N, a single row, N a whole number of tiles and one radius past it
     t = lib()
     say(f"apply_H on strips vs workgroup sweeps, prec {prec}")
-    for n, lmax, stencil in ((701, 9, 3), (1999, 14, 5), (65, 0, 5), (130, 3, 3)):
+    for n, lmax, stencil in ((701, 9, 3), (1999, 14, 5), (65, 0, 5), (130, 3, 3), (256, 2, 5), (257, 1, 3)):
         psi = workloads.random_state(5, n, lmax)
         if prec == 1:
             psi = to_fp32(psi)
