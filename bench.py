@@ -153,8 +153,9 @@ def shape_of(prop, kernel):
     return {"tile_rows": prop.tile_rows, "sweep_variant": prop.sweep_variant}
 
 
-def traffic_for(workload, kernel, precision, shape):
-    """HBM bytes per launch from the committed counter summary, or None."""
+def profile_entry(workload, kernel, precision, shape):
+    """The committed counter summary of this kernel and shape, or None (also
+    when the kernel source changed since the counters were taken)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -166,9 +167,21 @@ def traffic_for(workload, kernel, precision, shape):
         if any(e["shape"].get(k) != v for k, v in shape.items() if k in e["shape"]):
             continue
         if e.get("source_sha256") != source_digest(e["source"]):
-            return None          # the kernel changed since the counters were taken
-        return e["hbm_bytes_per_launch"]
+            return None
+        return e
     return None
+
+
+def traffic_for(workload, kernel, precision, shape):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    e = profile_entry(workload, kernel, precision, shape)
+    return e["hbm_bytes_per_launch"] if e else None
+
+
+def valu_busy_for(workload, kernel, precision, shape):
+    """VALU busy percentage (rocprofv3 VALUBusy) from the committed summary, or None."""
+    e = profile_entry(workload, kernel, precision, shape)
+    return e.get("valu_busy_pct") if e else None
 
 
 def hpsi_sweep(prop, tdse, torch, U, elem, reps=40):
@@ -271,13 +284,15 @@ def run_batch_prec(tdse, torch, precision, args, autotune=None):
     prec_name = "fp64" if precision == tdse.FP64 else "fp32"
     shape = shape_of(prop, kernel)
     traffic = traffic_for(BATCH_NAME, kernel, prec_name, shape)
+    valu = valu_busy_for(BATCH_NAME, kernel, prec_name, shape)
     sweep = hpsi_sweep(prop, tdse, torch, U, elem)
     sweep["traffic"] = traffic_for(BATCH_NAME, "apply_h", prec_name, sweep["shape"])
+    sweep["valu_busy_pct"] = valu_busy_for(BATCH_NAME, "apply_h", prec_name, sweep["shape"])
     prop.close()
     del prop
     torch.cuda.empty_cache()
     return dict(wall=wall, launches=launches, kms=kms, rows=rows, obs=o, U=U, dts=dts, n=len(grids),
-                kernel=kernel, shape=shape, traffic=traffic, sweep=sweep)
+                kernel=kernel, shape=shape, traffic=traffic, valu=valu, sweep=sweep)
 
 
 def run_batch(args, tdse, torch):
@@ -312,6 +327,7 @@ def run_batch(args, tdse, torch):
         "steps_per_s": sps,
         "roofline": {"bound": "hbm", "kernel": r32["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": r32["traffic"],
+                     "valu_busy_pct": r32["valu"],
                      "algorithmic_bytes_per_launch": bpl32, "mean_launch_us": avg_ms * 1e3,
                      "launches_timed": r32["launches"]},
         "hpsi_sweep": r32["sweep"],
@@ -398,8 +414,10 @@ def main():
     shape = shape_of(prop, kernel)
     prec_name = "fp64" if prec == tdse.FP64 else "fp32"
     traffic = traffic_for(wl.name, kernel, prec_name, shape)
+    valu = valu_busy_for(wl.name, kernel, prec_name, shape)
     sweep = hpsi_sweep(prop, tdse, torch, U, elem)
     sweep["traffic"] = traffic_for(wl.name, "apply_h", prec_name, sweep["shape"])
+    sweep["valu_busy_pct"] = valu_busy_for(wl.name, "apply_h", prec_name, sweep["shape"])
     log(f"bench: H.psi apply {sweep['mean_launch_us']:.2f} us = {sweep['achieved']:.0f} GB/s "
         f"(frac {sweep['frac']:.3f})")
     prop.close()
@@ -434,6 +452,7 @@ def main():
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": traffic,
+            "valu_busy_pct": valu,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "mean_launch_us": avg_ms * 1e3,
             "launches_timed": launches,

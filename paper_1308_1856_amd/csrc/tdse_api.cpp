@@ -278,15 +278,8 @@ static void build_tiles(tdse_ctx* c, int set, int rows)
         for (int k = 0; k < c->n_inst; ++k) {
             Inst& I = c->inst[k];
             I.tbegin[set] = (int32_t)c->tiles[set].size();
-            // the rows split into the fewest blocks of at most `rows`, of
-            // near-equal height: a strip walks its block one row per
-            // iteration, so a short remainder block would finish early
-            // and leave its SIMD idle at the end of the launch
-            const int nrow = I.lmax + 1;
-            const int nblk = (nrow + rows - 1) / rows;
-            for (int b = 0; b < nblk; ++b) {
-                const int l0 = (int)((int64_t)b * nrow / nblk);
-                const int l1 = (int)((int64_t)(b + 1) * nrow / nblk);
+            for (int l0 = 0; l0 <= I.lmax; l0 += rows) {
+                const int l1 = std::min(l0 + rows, I.lmax + 1);
                 for (int o0 = 0; o0 < I.n; o0 += W) {
                     Tile t;
                     std::memset(&t, 0, sizeof t);
