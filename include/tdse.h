@@ -206,9 +206,10 @@ double tdse_taylor_stability_limit(int32_t order);
  * (bit 0: one radius per thread on 256-radius tiles, or two adjacent radii
  * per thread on 512-radius tiles; bit 1: workgroups take tiles in order, or
  * each XCD takes a contiguous run of tiles; bit 2: instead of either, wave
- * strips of 64 radii with radial neighbours by lane shifts and rows loaded
- * three rows ahead, 62 or 60 output radii per strip; variants 0, 1, 2, 3, 4
- * and 6 are timed), checks that every choice
+ * strips of 64 radii with radial neighbours by lane shifts (the values just
+ * beyond a strip's ends read per row) and rows loaded three rows ahead, four
+ * strips per 256-radius tile, with bit 1 runs of four tiles per XCD;
+ * variants 0, 1, 2, 3, 4 and 6 are timed), checks that every choice
  * produces bit-identical results to the current one (a sweep's arithmetic
  * depends on neither), keeps the fastest and appends it to the tuning
  * cache named by the environment variable TDSE_TUNE_CACHE (if set; read by
