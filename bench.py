@@ -65,8 +65,9 @@ def parse():
                     help="0: fixed shapes; 1: autotune the sweep tiles; 2: also choose the Taylor fusion")
     ap.add_argument("--sweep", default=None, metavar="ROWS,VARIANT",
                     help="fixed sweep tile shape instead of the sweep autotuner (profiling runs)")
-    ap.add_argument("--fusion", default=None, metavar="K,ROWS,KIND",
-                    help="fixed Taylor fusion instead of the Taylor autotuner (profiling runs)")
+    ap.add_argument("--fusion", default=None, metavar="K,ROWS,KIND[,OBS]",
+                    help="fixed Taylor fusion instead of the Taylor autotuner (profiling runs); OBS 1: the "
+                         "main observables summed in the step's last strip launch, 0: by their own pass")
     return ap.parse_args()
 
 
@@ -78,8 +79,10 @@ def apply_shape(prop, args, autotune, order):
     elif autotune:
         prop.autotune()
     if args.fusion:
-        k, rows, kind = (int(x) for x in args.fusion.split(","))
-        prop.set_taylor_fusion(k, rows, kind)
+        vals = [int(x) for x in args.fusion.split(",")]
+        prop.set_taylor_fusion(*vals[:3])
+        if len(vals) > 3:
+            prop.set_obs_fusion(bool(vals[3]))
     elif autotune > 1 and order:
         prop.autotune_taylor(order)
 
@@ -149,7 +152,7 @@ def source_digest(name):
 def shape_of(prop, kernel):
     if kernel == "taylor_fused":
         return {"fuse_k": prop.taylor_fusion, "rows": getattr(prop, "fusion_rows", None),
-                "kind": prop.taylor_fusion_kind}
+                "kind": prop.taylor_fusion_kind, "obs_fusion": int(prop.obs_fusion)}
     return {"tile_rows": prop.tile_rows, "sweep_variant": prop.sweep_variant}
 
 

@@ -227,7 +227,11 @@ tdse_status tdse_autotune(tdse_ctx* ctx, int32_t* rows_out);
  * the one-launch-per-term step (bit for bit in FP64; relative 2-norm
  * difference <= 1e-6 with FP32 storage, where the fused launches keep their
  * intermediates in FP64), and keeps the fastest for later tdse_step_taylor
- * calls.  Needs the TDSE_METHOD_TUNE workspace; the state is restored.
+ * calls.  With the wave-strip kernel chosen it then times 8 steps with a
+ * record after each, the main observables summed in the step's last launch
+ * and by their own pass (tdse_set_obs_fusion), and keeps the faster (when
+ * work vector 3 holds the 8 records of every instance; else the setting
+ * stays).  Needs the TDSE_METHOD_TUNE workspace; the state is restored.
  * *fuse_k_out (0: one launch per term) and *rows_out (may be NULL) receive
  * the choice; tdse_taylor_fusion_kind gives the kernel.  Synchronises. */
 tdse_status tdse_autotune_taylor(tdse_ctx* ctx, int32_t order, int32_t* fuse_k_out, int32_t* rows_out);
@@ -267,6 +271,20 @@ tdse_status tdse_use_graphs(tdse_ctx* ctx, int32_t enable);
  * launch goes to the bound stream in order.  Results are bitwise identical
  * either way.  Synchronises the bound stream; drops captured graphs. */
 tdse_status tdse_set_obs_overlap(tdse_ctx* ctx, int32_t enable);
+
+/* Observables summed inside the Taylor step (default on): with the wave-strip
+ * fused kernel in use, the last launch of a step whose record is due also
+ * sums the norm, p_ion, dipole and acceleration terms of the rows it writes
+ * (one partial sum per strip; the strip computes one row past its tile,
+ * unstored, for the l-coupling of its last row), so the observables' own pass
+ * reads only the rows l <= 4 of the populations; the finish adds the strips'
+ * partials in strip order.  Off: the observables pass reads the whole state
+ * (Sec. 4 reductions over its own tiles).  The two orders of summation differ
+ * by FP64 rounding only.  Other step methods and kernels always use the pass.
+ * tdse_obs_fusion gives the setting.  Synchronises the bound stream and the
+ * observables stream; drops captured graphs. */
+tdse_status tdse_set_obs_fusion(tdse_ctx* ctx, int32_t enable);
+int32_t tdse_obs_fusion(const tdse_ctx* ctx);
 
 /* RK4 in one launch per step (default on: the four stages as the levels of
  * wave strips, reading the state once and writing the new state once, the

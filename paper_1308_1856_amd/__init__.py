@@ -34,7 +34,7 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_set_state", "tdse_get_state", "tdse_apply_H", "tdse_step_taylor",
             "tdse_step_rk4", "tdse_step_lanczos", "tdse_observables", "tdse_lambda_max_bound",
             "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read",
-            "tdse_use_graphs", "tdse_set_obs_overlap", "tdse_set_rk4_fusion", "tdse_rk4_fusion", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
+            "tdse_use_graphs", "tdse_set_obs_overlap", "tdse_set_obs_fusion", "tdse_obs_fusion", "tdse_set_rk4_fusion", "tdse_rk4_fusion", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
             "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_taylor_fusion_kind",
             "tdse_set_taylor_fusion", "tdse_set_sweep_shape")
 
@@ -94,6 +94,8 @@ def _load():
         "tdse_timing_read": ([ctxp, ctypes.c_char_p, ctypes.POINTER(i64), dp], i32),
         "tdse_use_graphs": ([ctxp, i32], i32),
         "tdse_set_obs_overlap": ([ctxp, i32], i32),
+        "tdse_set_obs_fusion": ([ctxp, i32], i32),
+        "tdse_obs_fusion": ([ctxp], i32),
         "tdse_set_rk4_fusion": ([ctxp, i32], i32),
         "tdse_rk4_fusion": ([ctxp], i32),
         "tdse_autotune": ([ctxp, ctypes.POINTER(i32)], i32),
@@ -231,6 +233,14 @@ def tdse_use_graphs(ctx, enable: bool):
 
 def tdse_set_obs_overlap(ctx, enable: bool):
     _check(ctx, lib.tdse_set_obs_overlap(ctx, 1 if enable else 0))
+
+
+def tdse_set_obs_fusion(ctx, enable: bool):
+    _check(ctx, lib.tdse_set_obs_fusion(ctx, 1 if enable else 0))
+
+
+def tdse_obs_fusion(ctx) -> bool:
+    return bool(lib.tdse_obs_fusion(ctx))
 
 
 def tdse_set_rk4_fusion(ctx, enable: bool):
@@ -376,6 +386,14 @@ class Propagator:
 
     def set_obs_overlap(self, enable: bool):
         tdse_set_obs_overlap(self.ctx, enable)
+
+    def set_obs_fusion(self, enable: bool):
+        """Main observables summed in the Taylor step's last strip launch (on) or by their own pass."""
+        tdse_set_obs_fusion(self.ctx, enable)
+
+    @property
+    def obs_fusion(self) -> bool:
+        return tdse_obs_fusion(self.ctx)
 
     def set_rk4_fusion(self, enable: bool):
         tdse_set_rk4_fusion(self.ctx, enable)

@@ -102,7 +102,7 @@ constexpr int kFinishU = 8;
 __global__ void __launch_bounds__(kBlock)
 k_obs_finish(SweepGeom red, SweepGeom pop, const double* __restrict__ pmain,
              const double* __restrict__ ppop, const double* __restrict__ step, int64_t rec_stride,
-             double* __restrict__ records)
+             double* __restrict__ records, int main_set, int main_upt, int64_t main_stride)
 {
     constexpr int Q = kObsMainQ + kObsPopQ;
     __shared__ double lds[(kBlock / 64) * Q];
@@ -118,14 +118,14 @@ k_obs_finish(SweepGeom red, SweepGeom pop, const double* __restrict__ pmain,
     for (int q = 0; q < Q; ++q) acc[q] = 0.0;
     // up to kFinishU tiles per thread per pass, loaded before any is added:
     // the partials come from every XCD, so each pass costs one memory latency
-    const int tb = I.tbegin[kObsTiles], te = I.tend[kObsTiles];
+    const int tb = I.tbegin[main_set] * main_upt, te = I.tend[main_set] * main_upt;
     for (int t0 = tb + (int)threadIdx.x; t0 < te; t0 += kFinishU * kBlock) {
         double v[kFinishU][kObsMainQ];
 #pragma unroll
         for (int u = 0; u < kFinishU; ++u) {
             const int t = t0 + u * kBlock;
 #pragma unroll
-            for (int q = 0; q < kObsMainQ; ++q) v[u][q] = (t < te) ? pmain[(int64_t)q * red.n_tiles + t] : 0.0;
+            for (int q = 0; q < kObsMainQ; ++q) v[u][q] = (t < te) ? pmain[(int64_t)q * main_stride + t] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kFinishU; ++u) {
@@ -182,10 +182,12 @@ hipError_t launch_obs_partial(int prec, const SweepGeom& red, const SweepGeom& p
 
 hipError_t launch_obs_finish(const SweepGeom& red, const SweepGeom& pop, const double* partial_main,
                              const double* partial_pop, const double* step, int64_t rec_stride,
-                             double* out_records, hipStream_t st)
+                             double* out_records, hipStream_t st, int main_set, int main_upt,
+                             int64_t main_stride)
 {
+    if (main_stride < 0) main_stride = red.n_tiles;
     hipLaunchKernelGGL(k_obs_finish, dim3(red.n_inst), dim3(kBlock), 0, st, red, pop, partial_main,
-                       partial_pop, step, rec_stride, out_records);
+                       partial_pop, step, rec_stride, out_records, main_set, main_upt, main_stride);
     return hipGetLastError();
 }
 

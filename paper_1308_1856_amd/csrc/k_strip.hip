@@ -120,6 +120,18 @@ __device__ __forceinline__ double2 lane_above(double2 v, int d)
 // lmax in the sweep; zero here gives the same bits).
 constexpr int kStripDepth = 3;   // iterations of row loads in flight per wave (measured: 3 beats 2 and 4)
 
+// The observables' partial sums of the rows a strip writes (OBS below): the
+// wave's sums of norm, p_ion, dipole and acceleration terms go to
+// partial[q * stride + unit] (q = 0..3); r is the lane's radius, outer: the
+// radius lies beyond r_ion.
+struct StripObs {
+    double* partial = nullptr;
+    int64_t stride = 0, unit = 0;
+    double r = 0.0;
+    bool outer = false;
+    int lane = 0;
+};
+
 // Radii just outside an aligned strip (ALIGNED below): lanes 0..31 hold
 // j0 - 1 (e1) and j0 - 2 (e2), lanes 32..63 j0 + 64 and j0 + 65, clamped into
 // [0, N); in1 / in2: the unclamped radius lies in [0, N).
@@ -133,12 +145,22 @@ struct StripEdge {
 // neighbours beyond its ends are read per row as two (s = 2: four) extra
 // values and enter the DPP shifts as the end lanes' values, so strips need
 // not overlap, and each wave's loads and stores cover whole aligned lines.
-template <int S, typename T, int K, bool MASKED, bool APPLY = false, bool ALIGNED = false, int D = kStripDepth>
+// OBS (not with APPLY or ALIGNED): the strip also sums the observables of
+// the level-K rows it writes (the stored values, so FP32 storage rounds
+// first), as the observables pass does per element: |f|^2 (all radii and
+// those beyond r_ion) and, for each pair of rows (l, l+1) at one radius,
+// kappa_{l+1} Re(f_l* f_{l+1}) weighted by r and by 1/r^2.  The pair
+// (l1 - 1, l1) needs row l1 of level K, which the next tile writes: one more
+// iteration computes it (the same bits) without storing it.
+template <int S, typename T, int K, bool MASKED, bool APPLY = false, bool ALIGNED = false, int D = kStripDepth,
+          bool OBS = false>
 __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, const typename Cplx<T>::type* in_i,
                                            const typename Cplx<T>::type* psi_i, typename Cplx<T>::type* out_i,
                                            int jc, bool inside, bool writes, double er, double inv_r2,
-                                           double z_over_r, const double (&coef)[K], StripEdge edge = {})
+                                           double z_over_r, const double (&coef)[K], StripEdge edge = {},
+                                           StripObs ob = {})
 {
+    static_assert(!OBS || !(APPLY || ALIGNED), "observables ride on the Horner strips");
     static_assert(!(APPLY || ALIGNED) || K == 1, "the plain sweep and the aligned strips have one level");
     using C = typename Cplx<T>::type;
     const int n = I.n, lmax = I.lmax;
@@ -208,8 +230,8 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     // row instead (no HBM traffic for rows the tile does not use).
     const int warm_trips_end = (2 * (K - 1) + D - 1) / D * D;
     const int iters = max((I.l1 - I.l0) + 2 * K - 2, warm_trips_end);
-    const int xhi = min(lmax, rho0 + iters);
-    const int phi = min(lmax, rho0 + iters - 1);
+    const int xhi = min(lmax, rho0 + iters + (OBS ? 1 : 0));
+    const int phi = min(lmax, rho0 + iters - 1 + (OBS ? 1 : 0));
     auto rowp_x = [&](int rr) -> const C* { return (unsigned)rr <= (unsigned)xhi ? in_i + (int64_t)rr * n : zrow; };
     auto rowp_p = [&](int rr) -> const C* { return (unsigned)rr <= (unsigned)phi ? psi_i + (int64_t)rr * n : zrow; };
     struct Slot {
@@ -243,6 +265,26 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     int64_t ox = (int64_t)(rho0 + 1 + D) * n, op = (int64_t)(rho0 + D) * n;
     int64_t os = (int64_t)(rho0 - (K - 1)) * n + jc;
 
+    // OBS: sums per lane over the rows, and the previous level-K row as stored
+    double oacc[kObsMainQ] = {0.0, 0.0, 0.0, 0.0};
+    double2 fprev = zero2();
+    auto obs_row = [&](double2 v, int rk) {
+        if (!OBS) return;
+        double2 vs = v;
+        if (std::is_same<T, float>::value) vs = make_double2((double)(float)v.x, (double)(float)v.y);
+        if (rk > I.l0 && rk <= I.l1) {          // the pair (rk - 1, rk) is the tile's
+            const double re = fma(fprev.x, vs.x, fprev.y * vs.y) * kq[K];
+            oacc[2] = fma(ob.r, re, oacc[2]);
+            oacc[3] = fma(re, inv_r2, oacc[3]);
+        }
+        if (rk >= I.l0 && rk < I.l1) {          // row rk is the tile's
+            const double a2 = fma(vs.x, vs.x, vs.y * vs.y);
+            oacc[0] += a2;
+            oacc[1] += ob.outer ? a2 : 0.0;
+        }
+        fprev = vs;
+    };
+
     // one iteration; CHECK: some levels may not have reached their first row yet
     auto body = [&](int it, Slot& sl, auto check) {
         constexpr bool CHECK = decltype(check)::value;
@@ -274,6 +316,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         // the stored row: in [l0, l1) at every iteration past the warm-up trips
         auto store_row = [&](int rr) { return !CHECK || (rr >= I.l0 && rr < I.l1); };
         if (K == 1 && writes && store_row(rho)) stc(out_i, os, up);
+        if (K == 1) obs_row(up, rho);
         // levels 2..K from the registers of the level below
 #pragma unroll
         for (int k = 2; k <= K; ++k) {
@@ -288,6 +331,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
             ra[k - 2] = up;
             up = v;
             if (k == K && writes && store_row(rk)) stc(out_i, os, v);
+            if (k == K) obs_row(v, rk);
         }
         // shift the window and the kappa register; fetch kappa for it + 2
 #pragma unroll
@@ -324,13 +368,25 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
 #pragma unroll
     for (int u = 0; u < D - 1; ++u)
         if (it + u < iters) body(it + u, sl[u], std::false_type{});
+    if (OBS) {
+        // the iteration past the last (slot iters - it < D): level K at row
+        // l1 for the last pair, checked so that it stores nothing
+#pragma unroll
+        for (int u = 0; u < D; ++u)
+            if (it + u == iters) body(iters, sl[u], std::true_type{});
+#pragma unroll
+        for (int q = 0; q < kObsMainQ; ++q) {
+            const double sq = wave_sum(writes ? oacc[q] : 0.0);
+            if (ob.lane == 0) ob.partial[(int64_t)q * ob.stride + ob.unit] = sq;
+        }
+    }
 }
 
-template <int S, typename T, int K>
+template <int S, typename T, int K, bool OBS>
 __global__ void __launch_bounds__(kBlock)
 k_horner_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
                const typename Cplx<T>::type* __restrict__ psi, typename Cplx<T>::type* __restrict__ out,
-               const double* __restrict__ step, int first_term)
+               const double* __restrict__ step, int first_term, double* __restrict__ obs_partial)
 {
     const int halo = g.variant * S;             // >= K * S: lanes lost per side after K levels
     const int valid = 64 - 2 * halo;            // output radii per wave
@@ -357,48 +413,64 @@ k_horner_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
     const auto* in_i = in + I.off;
     const auto* psi_i = psi + I.off;
     auto* out_i = out + I.off;
+    StripObs ob;
+    if (OBS) {
+        ob.partial = obs_partial;
+        ob.stride = (int64_t)g.n_tiles * kStripWaves;
+        ob.unit = (int64_t)my_tile_index(g) * kStripWaves + wave;
+        ob.r = r;
+        ob.outer = jc >= I.i_ion;
+        ob.lane = lane;
+    }
     if (j0 >= 0 && j0 + 63 < n)   // wave-uniform
-        strip_loop<S, T, K, false>(g, I, in_i, psi_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, coef);
+        strip_loop<S, T, K, false, false, false, kStripDepth, OBS>(g, I, in_i, psi_i, out_i, jc, inside, writes, er,
+                                                                   inv_r2, z_over_r, coef, {}, ob);
     else
-        strip_loop<S, T, K, true>(g, I, in_i, psi_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, coef);
+        strip_loop<S, T, K, true, false, false, kStripDepth, OBS>(g, I, in_i, psi_i, out_i, jc, inside, writes, er,
+                                                                  inv_r2, z_over_r, coef, {}, ob);
 }
 
 template <int S, typename T, int K>
 static hipError_t strip_t(const SweepGeom& g, const void* in, const void* psi, void* out,
-                          const double* step, int first_term, hipStream_t st)
+                          const double* step, int first_term, double* obs_partial, hipStream_t st)
 {
     using C = typename Cplx<T>::type;
-    hipLaunchKernelGGL((k_horner_strip<S, T, K>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                       static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
-                       step, first_term);
+    if (obs_partial)
+        hipLaunchKernelGGL((k_horner_strip<S, T, K, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                           step, first_term, obs_partial);
+    else
+        hipLaunchKernelGGL((k_horner_strip<S, T, K, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                           step, first_term, obs_partial);
     return hipGetLastError();
 }
 
 template <int S, typename T>
 static hipError_t strip_k(int K, const SweepGeom& g, const void* in, const void* psi, void* out,
-                          const double* step, int first_term, hipStream_t st)
+                          const double* step, int first_term, double* obs_partial, hipStream_t st)
 {
     switch (K) {
-        case 1: return strip_t<S, T, 1>(g, in, psi, out, step, first_term, st);
-        case 2: return strip_t<S, T, 2>(g, in, psi, out, step, first_term, st);
-        case 3: return strip_t<S, T, 3>(g, in, psi, out, step, first_term, st);
-        case 4: return strip_t<S, T, 4>(g, in, psi, out, step, first_term, st);
-        case 5: return strip_t<S, T, 5>(g, in, psi, out, step, first_term, st);
-        case 6: return strip_t<S, T, 6>(g, in, psi, out, step, first_term, st);
-        case 7: return strip_t<S, T, 7>(g, in, psi, out, step, first_term, st);
-        case 8: return strip_t<S, T, 8>(g, in, psi, out, step, first_term, st);
+        case 1: return strip_t<S, T, 1>(g, in, psi, out, step, first_term, obs_partial, st);
+        case 2: return strip_t<S, T, 2>(g, in, psi, out, step, first_term, obs_partial, st);
+        case 3: return strip_t<S, T, 3>(g, in, psi, out, step, first_term, obs_partial, st);
+        case 4: return strip_t<S, T, 4>(g, in, psi, out, step, first_term, obs_partial, st);
+        case 5: return strip_t<S, T, 5>(g, in, psi, out, step, first_term, obs_partial, st);
+        case 6: return strip_t<S, T, 6>(g, in, psi, out, step, first_term, obs_partial, st);
+        case 7: return strip_t<S, T, 7>(g, in, psi, out, step, first_term, obs_partial, st);
+        case 8: return strip_t<S, T, 8>(g, in, psi, out, step, first_term, obs_partial, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const void* in,
                                const void* psi, void* out, const double* step, int first_term,
-                               hipStream_t st)
+                               hipStream_t st, double* obs_partial)
 {
-    if (prec == 0) return S == 1 ? strip_k<1, double>(K, g, in, psi, out, step, first_term, st)
-                                 : strip_k<2, double>(K, g, in, psi, out, step, first_term, st);
-    return S == 1 ? strip_k<1, float>(K, g, in, psi, out, step, first_term, st)
-                  : strip_k<2, float>(K, g, in, psi, out, step, first_term, st);
+    if (prec == 0) return S == 1 ? strip_k<1, double>(K, g, in, psi, out, step, first_term, obs_partial, st)
+                                 : strip_k<2, double>(K, g, in, psi, out, step, first_term, obs_partial, st);
+    return S == 1 ? strip_k<1, float>(K, g, in, psi, out, step, first_term, obs_partial, st)
+                  : strip_k<2, float>(K, g, in, psi, out, step, first_term, obs_partial, st);
 }
 
 // The plain H-psi sweep (term 0: out = H(E_mid) in) and single Horner terms

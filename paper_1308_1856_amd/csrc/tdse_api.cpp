@@ -67,6 +67,7 @@ struct tdse_ctx {
            off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0,
            off_zero = 0, zero_bytes = 0;
     size_t partial_doubles = 0;
+    size_t strip_units_cap = 0;         // most strips any wave-strip tile set can hold
     // pinned staging for the per-step scalars (double buffered)
     double* h_step[2] = {nullptr, nullptr};
     hipEvent_t step_ev[2] = {nullptr, nullptr};
@@ -75,6 +76,12 @@ struct tdse_ctx {
     // the observables of the Taylor path run on a second stream (default
     // priority), overlapping the next step; created on first use
     bool obs_overlap = true;
+    // the Taylor path on wave strips sums the main observables in the step's
+    // last launch (obs_req: where, set per step by the step loop;
+    // obs_main_done: the step function did it)
+    bool obs_fusion = true;
+    double* obs_req = nullptr;
+    bool obs_main_done = false;
     hipStream_t obs_stream = nullptr;
     hipEvent_t obs_fork = nullptr, obs_join = nullptr, obs_done[2] = {nullptr, nullptr};
     // captured step graphs, keyed by the launch pattern of a chunk
@@ -551,6 +558,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
             cap = 0;
             const int W = strip_width(kMaxFused, c->stencil);
             for (const tdse_grid_desc& g : c->grids) cap += (size_t)((g.n_r + W - 1) / W) * (g.lmax + 1);
+            if (set == kStripTiles) c->strip_units_cap = cap * kStripWaves;
         }
         if (set == kPairTiles) {
             cap = 0;
@@ -574,9 +582,13 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->off_step = take(sizeof(double) * kSlots * (size_t)n_inst * kEtabSteps);
     c->off_obs_tmp = take(sizeof(tdse_obs) * n_inst);
     c->off_lz = take(sizeof(LanczosScalars) * n_inst);
-    c->partial_doubles = std::max((size_t)c->tiles[kReduceTiles].size() * 2 * kMaxKrylov,
-                                  (size_t)c->tiles[kObsTiles].size() * kObsMainQ +
-                                      (size_t)c->tiles[kPopTiles].size() * kObsPopQ);
+    // Lanczos dots; the observables pass; or the strips' main partials (two
+    // sets, by step parity) and the population tiles
+    c->partial_doubles = std::max({(size_t)c->tiles[kReduceTiles].size() * 2 * kMaxKrylov,
+                                   (size_t)c->tiles[kObsTiles].size() * kObsMainQ +
+                                       (size_t)c->tiles[kPopTiles].size() * kObsPopQ,
+                                   2 * c->strip_units_cap * kObsMainQ +
+                                       (size_t)c->tiles[kPopTiles].size() * kObsPopQ});
     c->off_partial = take(sizeof(double) * c->partial_doubles);
     c->off_vecs = o;
     c->fixed_bytes = o;
@@ -832,6 +844,22 @@ hipError_t launch_obs(tdse_ctx* c, const void* psi, const double* step, double* 
     return launch_obs_finish(red, pop, pmain, ppop, step, rec_stride, records, st);
 }
 
+// observables of the state after a step whose last launch (Horner strips)
+// wrote the main partial sums to pstrip: the population tiles, then the
+// finish over the strips
+static hipError_t launch_obs_strips(tdse_ctx* c, const void* psi, const double* pstrip, const double* step,
+                                    double* records, int64_t rec_stride, hipStream_t st)
+{
+    TimedLaunch tl(c, 2, st);
+    SweepGeom red = c->geom(kObsTiles), pop = c->geom(kPopTiles);
+    red.n_tiles = 0;   // population tiles only
+    double* ppop = c->d_partial() + 2 * c->strip_units_cap * kObsMainQ;
+    hipError_t e = launch_obs_partial(c->prec, red, pop, c->d_radial(), psi, nullptr, ppop, st);
+    if (e != hipSuccess) return e;
+    return launch_obs_finish(red, pop, pstrip, ppop, step, rec_stride, records, st, kStripTiles, kStripWaves,
+                             (int64_t)c->tiles[kStripTiles].size() * kStripWaves);
+}
+
 static hipError_t ensure_obs_stream(tdse_ctx* c)
 {
     if (c->obs_stream) return hipSuccess;
@@ -862,16 +890,27 @@ hipError_t enqueue_chunk(tdse_ctx* c, int64_t s0, int count, int32_t obs_every, 
         const double* step = c->d_step() + (size_t)s * kSlots * c->n_inst;
         hipError_t e = hipSuccess;
         if (side && obs_at(s - 2)) e = hipStreamWaitEvent(c->stream, c->obs_done[s & 1], 0);
+        // a step function that can sum the main observables in its last
+        // launch does so into the partial set of this step's parity (the
+        // step two later, which reuses it, waits for these observables)
+        double* pstrip = c->d_partial() + (size_t)(s & 1) * c->strip_units_cap * kObsMainQ;
+        c->obs_req = (c->obs_fusion && obs_at(s)) ? pstrip : nullptr;
+        c->obs_main_done = false;
         if (e == hipSuccess) e = step_fn(step);
+        c->obs_req = nullptr;
         if (e != hipSuccess) return e;
         if (!obs_at(s)) continue;
+        const bool fused = c->obs_main_done;
+        auto obs_launch = [&](hipStream_t st) {
+            return fused ? launch_obs_strips(c, *cur, pstrip, step, reinterpret_cast<double*>(d_obs), rec_stride, st)
+                         : launch_obs(c, *cur, step, reinterpret_cast<double*>(d_obs), rec_stride, st);
+        };
         if (!side) {
-            e = launch_obs(c, *cur, step, reinterpret_cast<double*>(d_obs), rec_stride, c->stream);
+            e = obs_launch(c->stream);
         } else {
             e = hipEventRecord(c->obs_fork, c->stream);
             if (e == hipSuccess) e = hipStreamWaitEvent(c->obs_stream, c->obs_fork, 0);
-            if (e == hipSuccess)
-                e = launch_obs(c, *cur, step, reinterpret_cast<double*>(d_obs), rec_stride, c->obs_stream);
+            if (e == hipSuccess) e = obs_launch(c->obs_stream);
             if (e == hipSuccess) e = hipEventRecord(c->obs_done[s & 1], c->obs_stream);
             forked = true;
         }
@@ -972,16 +1011,20 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
         const bool strips = c->fuse_kind == 1;
         SweepGeom gf = c->geom(strips ? kStripTiles : kFusedTiles);
         if (strips) gf.variant = K;   // the term count the strip tiles were built for
-        auto launch = strips ? launch_horner_strip : launch_horner_fused;
         int which = 0;
         for (int first = order; first >= 1; first -= K) {
             const int terms = std::min(K, first);
             out = free_bufs[which];
+            // the step's last launch on strips also sums the main observables
+            // when the step loop asks for them
+            double* obs = (strips && first <= K) ? c->obs_req : nullptr;
             hipError_t e;
             {
                 TimedLaunch tl(c, 5);
-                e = launch(c->prec, S, terms, gf, in, psi, out, step, first, c->stream);
+                e = strips ? launch_horner_strip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs)
+                           : launch_horner_fused(c->prec, S, terms, gf, in, psi, out, step, first, c->stream);
             }
+            if (obs && e == hipSuccess) c->obs_main_done = true;
             if (e != hipSuccess) return e;
             in = out;
             which ^= 1;
@@ -1170,10 +1213,16 @@ extern "C" tdse_status tdse_observables(tdse_ctx* c, const tdse_pulse* pulses, c
     return TDSE_OK;
 }
 
+// A rebuilt tile set and the instance table (it holds each instance's tile
+// range of every set: the observables' finish reads the ranges).
 static hipError_t upload_tiles(tdse_ctx* c, int set)
 {
-    return hipMemcpyAsync(c->d_work + c->off_tiles[set], c->tiles[set].data(),
-                          sizeof(Tile) * c->tiles[set].size(), hipMemcpyHostToDevice, c->stream);
+    hipError_t e = hipMemcpyAsync(c->d_work + c->off_tiles[set], c->tiles[set].data(),
+                                  sizeof(Tile) * c->tiles[set].size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_work + c->off_inst, c->inst.data(), sizeof(Inst) * c->inst.size(),
+                           hipMemcpyHostToDevice, c->stream);
+    return e;
 }
 
 extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
@@ -1375,6 +1424,47 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     if (e2 == hipSuccess) e2 = upload_tiles(c, kFusedTiles);
     if (e2 == hipSuccess) e2 = upload_tiles(c, kStripTiles);
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+    // the observables, with the strip kernel chosen: time steps that record
+    // after every step, the main sums in the step's last launch or in their
+    // own pass (beside the next step, as the step loop runs them), and keep
+    // the faster.  The records go to work vector 3 (free by now), when it
+    // holds them.
+    const int obs_reps = 8;
+    if (e == hipSuccess && e2 == hipSuccess && c->fuse_k > 0 && c->fuse_kind == 1 &&
+        sizeof(double) * kObsRecord * obs_reps * (size_t)c->n_inst <= c->state_bytes()) {
+        tdse_obs* rec = reinterpret_cast<tdse_obs*>(ref);
+        const int64_t rec_stride = (int64_t)obs_reps * kObsRecord;
+        const bool side = c->obs_overlap;
+        if (side) e2 = ensure_obs_stream(c);
+        hipEvent_t o0 = nullptr, o1 = nullptr;
+        if (e2 == hipSuccess) e2 = hipEventCreate(&o0);
+        if (e2 == hipSuccess) e2 = hipEventCreate(&o1);
+        if (e2 == hipSuccess) {
+            tdse_status su = upload_steps(c, pulses.data(), t0.data(), dt.data(), 0, obs_reps, 1);
+            if (su != TDSE_OK) e2 = hipErrorUnknown;
+        }
+        float ms_mode[2] = {0.0f, 0.0f};
+        for (int pass = 0; pass < 3 && e2 == hipSuccess; ++pass) {   // pass 0 warms both up
+            for (int fused = 0; fused < 2 && e2 == hipSuccess; ++fused) {
+                c->obs_fusion = fused != 0;
+                void* oc = psi;
+                e2 = launch_copy(c->prec, red, backup, psi, c->stream);
+                auto fn = [&](const double* step) { return taylor_step_launches(c, step, order, oc); };
+                if (e2 == hipSuccess) e2 = hipEventRecord(o0, c->stream);
+                if (e2 == hipSuccess) e2 = enqueue_chunk(c, 0, obs_reps, 1, rec, rec_stride, &oc, fn, side);
+                if (e2 == hipSuccess) e2 = hipEventRecord(o1, c->stream);
+                if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+                float ms = 0.0f;
+                if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, o0, o1);
+                if (pass > 0) ms_mode[fused] += ms;
+            }
+        }
+        if (o0) (void)hipEventDestroy(o0);
+        if (o1) (void)hipEventDestroy(o1);
+        c->obs_fusion = (e2 == hipSuccess) ? (ms_mode[1] <= ms_mode[0]) : true;
+        if (e2 == hipSuccess) e2 = launch_copy(c->prec, red, backup, psi, c->stream);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+    }
     c->timing = keep_timing;
     c->drop_graphs();
     if (e != hipSuccess) return c->hip_fail(e, "tdse_autotune_taylor");
@@ -1467,6 +1557,21 @@ extern "C" tdse_status tdse_set_rk4_fusion(tdse_ctx* c, int32_t enable)
 }
 
 extern "C" int32_t tdse_rk4_fusion(const tdse_ctx* c) { return (c && c->rk4_fused) ? 1 : 0; }
+
+extern "C" tdse_status tdse_set_obs_fusion(tdse_ctx* c, int32_t enable)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (c->bound) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess && c->obs_stream) e = hipStreamSynchronize(c->obs_stream);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_set_obs_fusion sync");
+    }
+    c->obs_fusion = enable != 0;
+    c->drop_graphs();
+    return TDSE_OK;
+}
+
+extern "C" int32_t tdse_obs_fusion(const tdse_ctx* c) { return c && c->obs_fusion ? 1 : 0; }
 
 extern "C" tdse_status tdse_set_obs_overlap(tdse_ctx* c, int32_t enable)
 {

@@ -103,10 +103,12 @@ hipError_t launch_horner_fused(int prec, int S, int K, const SweepGeom& g, const
                                hipStream_t st);
 // The same K terms on the wave-strip tile set built for Kt >= K terms
 // (g.variant = Kt; tiles of 4 strips of 64 - 2 Kt s output radii); same
-// aliasing rules.
+// aliasing rules.  With obs_partial, the launch also writes the observables'
+// main partial sums of its output (norm, p_ion, dipole, acceleration), one
+// per strip: obs_partial[q * 4 n_tiles + 4 tile + wave], q < kObsMainQ.
 hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const void* in,
                                const void* psi, void* out, const double* step, int first_term,
-                               hipStream_t st);
+                               hipStream_t st, double* obs_partial = nullptr);
 constexpr int kStripWaves = kBlock / 64;   // strips per strip tile
 // An H sweep (term 0) or one Horner term on the aligned strip tile set of one
 // level (g.variant = 1; tiles of 4 waves of 64 radii from a multiple of 256);
@@ -135,10 +137,14 @@ hipError_t launch_obs_partial(int prec, const SweepGeom& red, const SweepGeom& p
                               double* partial_pop, hipStream_t st);
 // One block per instance: sums the partials in tile order and writes the
 // record of instance k at records + k * rec_stride + 23 * rec, with rec the
-// record index of the step (kRec slot).
+// record index of the step (kRec slot).  The main partials of instance k are
+// units [upt * tbegin[main_set], upt * tend[main_set]) at stride main_stride
+// (the observables pass: the kObsTiles set, one unit per tile; the Horner
+// strips: the kStripTiles set, one unit per strip).
 hipError_t launch_obs_finish(const SweepGeom& red, const SweepGeom& pop, const double* partial_main,
                              const double* partial_pop, const double* step, int64_t rec_stride,
-                             double* out_records, hipStream_t st);
+                             double* out_records, hipStream_t st, int main_set = kObsTiles, int main_upt = 1,
+                             int64_t main_stride = -1);
 
 // Lanczos pieces (basis vector j >= 1 lives at basis + (j-1)*vec_stride
 // elements; vector 0 is the state itself).
