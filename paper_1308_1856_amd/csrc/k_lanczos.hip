@@ -137,7 +137,7 @@ k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
                                    g.kappa[l], g.kappa[l + 1]);
             h.x *= sj;
             h.y *= sj;
-            stc(w, row + i, h);
+            stc_keep(w, row + i, h);
             prev = cur;
             cur = next;
         }
@@ -221,7 +221,7 @@ k_lz_sweep_b(SweepGeom g, int j, const typename Cplx<T>::type* psi, typename Cpl
                 v.x = fma(-hr, b.x, fma(hi, b.y, v.x));
                 v.y = fma(-hr, b.y, fma(-hi, b.x, v.y));
             }
-            stc(out, k, v);
+            stc_keep(out, k, v);
             // the norm is taken of the stored (possibly rounded) vector
             const double2 vs = ldc(out, k);
             acc[0] = fma(vs.x, vs.x, fma(vs.y, vs.y, acc[0]));
@@ -424,7 +424,7 @@ k_lz_recombine(SweepGeom g, typename Cplx<T>::type* psi, const typename Cplx<T>:
             v.x = fma(cr, b.x, fma(-ci, b.y, v.x));
             v.y = fma(cr, b.y, fma(ci, b.x, v.y));
         }
-        stc(psi, k, v);
+        stc_keep(psi, k, v);
     }
 }
 

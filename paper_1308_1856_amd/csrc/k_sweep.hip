@@ -100,14 +100,17 @@ __device__ __forceinline__ void load_pair(const C* p, int64_t k, bool full, bool
         v.b = C{};
     }
 }
+// (non-temporal, as stc)
+typedef float fvec4a8_t __attribute__((ext_vector_type(4), aligned(8)));
 __device__ __forceinline__ void store_pair(float2* p, int64_t k, double2 a, double2 b)
 {
-    *reinterpret_cast<Float4a8*>(p + k) = Float4a8{(float)a.x, (float)a.y, (float)b.x, (float)b.y};
+    const fvec4a8_t w = {(float)a.x, (float)a.y, (float)b.x, (float)b.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<fvec4a8_t*>(p + k));
 }
 __device__ __forceinline__ void store_pair(double2* p, int64_t k, double2 a, double2 b)
 {
-    p[k] = a;
-    p[k + 1] = b;
+    stc(p, k, a);
+    stc(p, k + 1, b);
 }
 __device__ __forceinline__ double2 from_lane_below(double2 v)
 {

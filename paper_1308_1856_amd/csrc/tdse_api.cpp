@@ -1443,25 +1443,54 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
             tdse_status su = upload_steps(c, pulses.data(), t0.data(), dt.data(), 0, obs_reps, 1);
             if (su != TDSE_OK) e2 = hipErrorUnknown;
         }
-        float ms_mode[2] = {0.0f, 0.0f};
-        for (int pass = 0; pass < 3 && e2 == hipSuccess; ++pass) {   // pass 0 warms both up
-            for (int fused = 0; fused < 2 && e2 == hipSuccess; ++fused) {
-                c->obs_fusion = fused != 0;
-                void* oc = psi;
-                e2 = launch_copy(c->prec, red, backup, psi, c->stream);
-                auto fn = [&](const double* step) { return taylor_step_launches(c, step, order, oc); };
-                if (e2 == hipSuccess) e2 = hipEventRecord(o0, c->stream);
-                if (e2 == hipSuccess) e2 = enqueue_chunk(c, 0, obs_reps, 1, rec, rec_stride, &oc, fn, side);
-                if (e2 == hipSuccess) e2 = hipEventRecord(o1, c->stream);
-                if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
-                float ms = 0.0f;
-                if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, o0, o1);
-                if (pass > 0) ms_mode[fused] += ms;
+        // the strip heights the step timing tried, with both modes: the
+        // launch with the sums does one more iteration per tile, which can
+        // move the best height
+        const int chosen_rows = c->rows_fused;
+        int best_rows = chosen_rows;
+        bool best_fused = true;
+        float best_obs_ms = 3.0e38f;
+        std::vector<int> heights = {chosen_rows};
+        for (int r : {16, 32, 64})
+            if (r != chosen_rows) heights.push_back(r);
+        for (int rows : heights) {
+            if (e2 != hipSuccess) break;
+            c->rows_fused = rows;
+            build_tiles(c, kStripTiles, rows);
+            e2 = upload_tiles(c, kStripTiles);
+            float ms_mode[2] = {0.0f, 0.0f};
+            for (int pass = 0; pass < 3 && e2 == hipSuccess; ++pass) {   // pass 0 warms both up
+                for (int fused = 0; fused < 2 && e2 == hipSuccess; ++fused) {
+                    c->obs_fusion = fused != 0;
+                    void* oc = psi;
+                    e2 = launch_copy(c->prec, red, backup, psi, c->stream);
+                    auto fn = [&](const double* step) { return taylor_step_launches(c, step, order, oc); };
+                    if (e2 == hipSuccess) e2 = hipEventRecord(o0, c->stream);
+                    if (e2 == hipSuccess) e2 = enqueue_chunk(c, 0, obs_reps, 1, rec, rec_stride, &oc, fn, side);
+                    if (e2 == hipSuccess) e2 = hipEventRecord(o1, c->stream);
+                    if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+                    float ms = 0.0f;
+                    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, o0, o1);
+                    if (pass > 0) ms_mode[fused] += ms;
+                }
+            }
+            if (e2 != hipSuccess) break;
+            for (int fused = 1; fused >= 0; --fused) {
+                if (ms_mode[fused] < best_obs_ms) {
+                    best_obs_ms = ms_mode[fused];
+                    best_rows = rows;
+                    best_fused = fused != 0;
+                }
             }
         }
         if (o0) (void)hipEventDestroy(o0);
         if (o1) (void)hipEventDestroy(o1);
-        c->obs_fusion = (e2 == hipSuccess) ? (ms_mode[1] <= ms_mode[0]) : true;
+        c->obs_fusion = (e2 == hipSuccess) ? best_fused : true;
+        c->rows_fused = (e2 == hipSuccess) ? best_rows : chosen_rows;
+        build_tiles(c, kFusedTiles, c->rows_fused);
+        build_tiles(c, kStripTiles, c->rows_fused);
+        if (e2 == hipSuccess) e2 = upload_tiles(c, kFusedTiles);
+        if (e2 == hipSuccess) e2 = upload_tiles(c, kStripTiles);
         if (e2 == hipSuccess) e2 = launch_copy(c->prec, red, backup, psi, c->stream);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
     }
