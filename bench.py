@@ -369,8 +369,8 @@ def main():
     args = parse()
     ARGS = args
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is described, not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
+                                   "(the multi-GPU sharding is described, not implemented)"}))
         sys.exit(2)
     import torch
     import paper_1308_1856_amd as tdse
