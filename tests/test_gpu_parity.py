@@ -487,12 +487,16 @@ def test_autotune_taylor_choice_is_consistent():
     assert np.array_equal(prop.get_state(0), before)           # state restored
     assert k == 0 or 2 <= k <= 8
     assert prop.taylor_fusion_kind in (0, 1)
-    prop.step_taylor(pulse, 5.0, dt, 8, 12)
+    assert prop.obs_fusion in (True, False)     # the tuner's choice of the observables' summation
+    obs_tuned = prop.obs_buffer(12, 1)
+    prop.step_taylor(pulse, 5.0, dt, 8, 12, 1, obs_tuned)
     tuned = prop.get_state(0)
     prop.set_taylor_fusion(0, 16)
     prop.set_state(0, None)
-    prop.step_taylor(pulse, 5.0, dt, 8, 12)
+    obs_plain = prop.obs_buffer(12, 1)
+    prop.step_taylor(pulse, 5.0, dt, 8, 12, 1, obs_plain)
     assert np.array_equal(prop.get_state(0), tuned)
+    assert_records_match(obs_tuned.cpu().numpy(), obs_plain.cpu().numpy(), main_bitwise=False)
     prop.close()
 
 
