@@ -265,22 +265,28 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     int64_t ox = (int64_t)(rho0 + 1 + D) * n, op = (int64_t)(rho0 + D) * n;
     int64_t os = (int64_t)(rho0 - (K - 1)) * n + jc;
 
-    // OBS: sums per lane over the rows, and the previous level-K row as stored
+    // OBS: sums per lane over the rows, and the previous level-K row as stored.
+    // Level K is zero at the rows below l0 (not yet started), so the pair
+    // (l0 - 1, l0) adds exactly zero; only rows from l1 on (the extra
+    // iteration, a short tile's padding) need excluding, and only checked
+    // iterations reach them.  p_ion: |f|^2 times 1 or 0 (exact).
     double oacc[kObsMainQ] = {0.0, 0.0, 0.0, 0.0};
     double2 fprev = zero2();
-    auto obs_row = [&](double2 v, int rk) {
+    const double outer1 = ob.outer ? 1.0 : 0.0;
+    auto obs_row = [&](double2 v, int rk, auto check) {
         if (!OBS) return;
+        constexpr bool CHECK = decltype(check)::value;
         double2 vs = v;
         if (std::is_same<T, float>::value) vs = make_double2((double)(float)v.x, (double)(float)v.y);
-        if (rk > I.l0 && rk <= I.l1) {          // the pair (rk - 1, rk) is the tile's
+        if (!CHECK || rk <= I.l1) {             // the pair (rk - 1, rk) is the tile's
             const double re = fma(fprev.x, vs.x, fprev.y * vs.y) * kq[K];
             oacc[2] = fma(ob.r, re, oacc[2]);
             oacc[3] = fma(re, inv_r2, oacc[3]);
         }
-        if (rk >= I.l0 && rk < I.l1) {          // row rk is the tile's
+        if (!CHECK || rk < I.l1) {              // row rk is the tile's
             const double a2 = fma(vs.x, vs.x, vs.y * vs.y);
             oacc[0] += a2;
-            oacc[1] += ob.outer ? a2 : 0.0;
+            oacc[1] = fma(outer1, a2, oacc[1]);
         }
         fprev = vs;
     };
@@ -316,7 +322,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         // the stored row: in [l0, l1) at every iteration past the warm-up trips
         auto store_row = [&](int rr) { return !CHECK || (rr >= I.l0 && rr < I.l1); };
         if (K == 1 && writes && store_row(rho)) stc(out_i, os, up);
-        if (K == 1) obs_row(up, rho);
+        if (K == 1) obs_row(up, rho, check);
         // levels 2..K from the registers of the level below
 #pragma unroll
         for (int k = 2; k <= K; ++k) {
@@ -331,7 +337,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
             ra[k - 2] = up;
             up = v;
             if (k == K && writes && store_row(rk)) stc(out_i, os, v);
-            if (k == K) obs_row(v, rk);
+            if (k == K) obs_row(v, rk, check);
         }
         // shift the window and the kappa register; fetch kappa for it + 2
 #pragma unroll
@@ -371,9 +377,11 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     if (OBS) {
         // the iteration past the last (slot iters - it < D): level K at row
         // l1 for the last pair, checked so that it stores nothing
+        Slot last = sl[0];
 #pragma unroll
-        for (int u = 0; u < D; ++u)
-            if (it + u == iters) body(iters, sl[u], std::true_type{});
+        for (int u = 1; u < D; ++u)
+            if (it + u == iters) last = sl[u];
+        body(iters, last, std::true_type{});
 #pragma unroll
         for (int q = 0; q < kObsMainQ; ++q) {
             const double sq = wave_sum(writes ? oacc[q] : 0.0);
