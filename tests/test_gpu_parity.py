@@ -586,24 +586,29 @@ def test_observables_in_strip_launch_match_pass(prec, stencil):
     # grids, ragged row blocks (17 rows in blocks of 8), several K, records
     # every step and every third step, with and without graphs.
     t = lib()
+    # (the 65-radius single row and the two-row grid put the row past a
+    # tile, which the launch computes for the last l-coupling, above lmax)
     grids = [t.Grid(2501, 16, 0.1, stencil, prec, 1.0, 60.0), t.Grid(1200, 5, 0.1, stencil, prec, 1.0, 30.0),
-             t.Grid(777, 9, 0.1, stencil, prec, 1.0, 20.0)]
-    pulses = [t.Pulse(0.06, 0.25, 2.0, 0.1, 0.0), t.Pulse(0.03, 0.4, 3.0, 0.0, 0.0), t.Pulse(0.08, 0.3, 2.0, 0.5, 0.0)]
+             t.Grid(777, 9, 0.1, stencil, prec, 1.0, 20.0), t.Grid(65, 0, 0.1, stencil, prec, 1.0, 3.0),
+             t.Grid(300, 1, 0.1, stencil, prec, 1.0, 10.0)]
+    pulses = [t.Pulse(0.06, 0.25, 2.0, 0.1, 0.0), t.Pulse(0.03, 0.4, 3.0, 0.0, 0.0), t.Pulse(0.08, 0.3, 2.0, 0.5, 0.0),
+              t.Pulse(0.05, 0.5, 2.0, 0.0, 0.0), t.Pulse(0.07, 0.2, 2.0, 0.3, 0.0)]
+    ng = len(grids)
     nsteps = 12
     say(f"observables in the strip launch vs their own pass, prec {prec}, stencil {stencil}")
-    for K, rows, every, graphs in ((4, 8, 1, False), (3, 4, 3, True), (8, 16, 1, True)):
+    for K, rows, every, graphs in ((4, 8, 1, False), (3, 4, 3, True), (8, 16, 1, True), (2, 1, 2, False)):
         out = []
         for fused in (True, False):
             prop = t.Propagator(grids, methods=((t.METHOD_TAYLOR, 8),), graphs=graphs)
             prop.set_taylor_fusion(K, rows, 1)
             prop.set_obs_fusion(fused)
             assert prop.obs_fusion == fused
-            dts = [0.5 * t.tdse_taylor_stability_limit(8) / prop.lambda_max_bound(k, 0.1) for k in range(3)]
-            for k in range(3):
+            dts = [0.5 * t.tdse_taylor_stability_limit(8) / prop.lambda_max_bound(k, 0.1) for k in range(ng)]
+            for k in range(ng):
                 prop.set_state(k, None)
             obs = prop.obs_buffer(nsteps, every)
-            prop.step_taylor(pulses, [5.0, 3.0, 1.0], dts, 8, nsteps, every, obs)
-            out.append(([prop.get_state(k) for k in range(3)], obs.cpu().numpy()))
+            prop.step_taylor(pulses, [5.0, 3.0, 1.0, 2.0, 0.5], dts, 8, nsteps, every, obs)
+            out.append(([prop.get_state(k) for k in range(ng)], obs.cpu().numpy()))
             prop.close()
         (sf, rf), (sp, rp) = out
         for a, b in zip(sf, sp):
