@@ -54,6 +54,8 @@ enum {
     TDSE_E_NOMEM = -2,      /* host allocation failed                              */
     TDSE_E_HIP = -3,        /* a HIP runtime call failed                           */
     TDSE_E_UNSTABLE = -4,   /* explicit step would exceed its stability limit      */
+    TDSE_E_BREAKDOWN = -5,  /* information, not a failure: a Lanczos step stopped
+                               early at an invariant subspace (tdse_lanczos_dims) */
     TDSE_E_NONFINITE = -6,  /* a norm came out NaN or Inf                          */
     TDSE_E_WORKSPACE = -7,  /* bound workspace smaller than the method needs       */
     TDSE_E_UNBOUND = -8     /* no device memory bound yet (tdse_bind)              */
@@ -177,14 +179,30 @@ tdse_status tdse_step_rk4(tdse_ctx* ctx, const tdse_pulse* pulses, const double*
                           const double* dt, int32_t nsteps, int32_t obs_every, tdse_obs* d_obs);
 
 /* Lanczos propagator (Sec. 5.2 Lanczos.c, appendix "Lanczos methods"): an
- * m-dimensional Krylov basis of H(t_s + dt/2) from F/||F|| with full
- * re-orthogonalisation (FP64 coefficients), the exponential of the m x m
- * tridiagonal from its eigen-decomposition, and F <- ||F|| Q exp(-i T dt) e1.
- * The process stops early at breakdown (beta_j <= 1e-12 times the
- * Gershgorin bound of H).  m in 1..64.  No stability limit.  Asynchronous. */
+ * m-dimensional Krylov basis of H(t_s + dt/2) from F/||F||, each new
+ * direction orthogonalised against all earlier basis vectors in one
+ * classical Gram-Schmidt pass with FP64 coefficients (this contains the
+ * three-term recurrence), and F <- ||F|| Q exp(-i T dt) e1.  The exponential
+ * of the m x m tridiagonal T is taken by scaling and squaring, in FP64 on
+ * one workgroup per instance: B = T dt / 2^s with ||B||_inf <= 1/2,
+ * exp(-i B) = cos B - i sin B by their Taylor series to degree 17 (remainder
+ * below 1e-21), then s complex squarings (no eigen-decomposition; the
+ * paper's subspace Taylor series alone diverges for the Ritz values of stiff
+ * grids, lambda dt ~ 1e3).  The process stops early at breakdown (beta_j <=
+ * 1e-12 times the Gershgorin bound of the field-free H) and the step is then
+ * exact in the invariant subspace found; since the call is asynchronous,
+ * breakdown is reported afterwards by tdse_lanczos_dims.  m in 1..64.  No
+ * stability limit.  Asynchronous. */
 tdse_status tdse_step_lanczos(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0,
                               const double* dt, int32_t m, int32_t nsteps, int32_t obs_every,
                               tdse_obs* d_obs);
+
+/* Smallest Krylov dimension each instance used over the steps of the last
+ * tdse_step_lanczos call, copied to host_meff[n_inst].  Synchronises the
+ * stream.  Returns TDSE_E_BREAKDOWN (information: the results are valid) if
+ * any instance stopped below the requested m, TDSE_E_INVALID if no Lanczos
+ * step ran since the context was bound. */
+tdse_status tdse_lanczos_dims(tdse_ctx* ctx, int32_t* host_meff);
 
 /* Observables of the bound state at time t[k] (E(t) from pulses[k]) for
  * every instance, copied to host_out[n_inst].  Synchronises the stream.

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libtdse.so")
 
 TDSE_OK = 0
 STATUS = {0: "TDSE_OK", -1: "TDSE_E_INVALID", -2: "TDSE_E_NOMEM", -3: "TDSE_E_HIP",
-          -4: "TDSE_E_UNSTABLE", -6: "TDSE_E_NONFINITE", -7: "TDSE_E_WORKSPACE",
+          -4: "TDSE_E_UNSTABLE", -5: "TDSE_E_BREAKDOWN", -6: "TDSE_E_NONFINITE", -7: "TDSE_E_WORKSPACE",
           -8: "TDSE_E_UNBOUND"}
 FP64, FP32 = 0, 1
 METHOD_TAYLOR, METHOD_RK4, METHOD_LANCZOS, METHOD_TUNE = 0, 1, 2, 3
@@ -36,7 +36,7 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read",
             "tdse_use_graphs", "tdse_set_obs_overlap", "tdse_set_obs_fusion", "tdse_obs_fusion", "tdse_set_rk4_fusion", "tdse_rk4_fusion", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
             "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_taylor_fusion_kind",
-            "tdse_set_taylor_fusion", "tdse_set_sweep_shape")
+            "tdse_set_taylor_fusion", "tdse_set_sweep_shape", "tdse_lanczos_dims")
 
 
 class TdseError(RuntimeError):
@@ -106,6 +106,7 @@ def _load():
         "tdse_taylor_fusion_kind": ([ctxp], i32),
         "tdse_set_taylor_fusion": ([ctxp, i32, i32, i32], i32),
         "tdse_set_sweep_shape": ([ctxp, i32, i32], i32),
+        "tdse_lanczos_dims": ([ctxp, ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -197,6 +198,18 @@ def tdse_observables(ctx, pulses, t) -> np.ndarray:
     out = (Obs * n)()
     _check(ctx, lib.tdse_observables(ctx, _pulses(pulses), _dvec(t, n), out))
     return np.frombuffer(out, dtype=np.float64).reshape(n, OBS_DOUBLES).copy()
+
+
+def tdse_lanczos_dims(ctx):
+    """(Krylov dimension per instance, broke_down): the smallest dimension
+    each instance used in the last Lanczos call; TDSE_E_BREAKDOWN is
+    information, not an error, and comes back as broke_down = True."""
+    n = lib.tdse_num_instances(ctx)
+    out = (ctypes.c_int32 * n)()
+    code = lib.tdse_lanczos_dims(ctx, out)
+    if code not in (TDSE_OK, -5):
+        _check(ctx, code)
+    return list(out), code == -5
 
 
 def tdse_lambda_max_bound(ctx, inst: int, e_max: float) -> float:
@@ -376,6 +389,11 @@ class Propagator:
         tdse_step_lanczos(self.ctx, self._pulse_list(pulses), self._per_inst(t0),
                           self._per_inst(dt), m, nsteps, obs_every, ptr)
         self._leave()
+
+    def lanczos_dims(self):
+        """(smallest Krylov dimension per instance in the last Lanczos call, broke_down)."""
+        self._enter()
+        return tdse_lanczos_dims(self.ctx)
 
     def observables(self, pulses, t) -> np.ndarray:
         self._enter()

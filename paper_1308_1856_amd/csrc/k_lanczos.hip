@@ -296,6 +296,8 @@ k_lz_expm(SweepGeom g, const double* __restrict__ step, LanczosScalars* __restri
     const int m = sc.meff;
     const int mm = m * m;
     const int tid = (int)threadIdx.x;
+    // the dimension the step used, for the breakdown report of the call
+    if (tid == 0) sc.meff_min = min(sc.meff_min, m);
     const double dt = step_value(step, g.n_inst, kDt, inst);
 
     // ||T dt||_inf and the number of squarings (the same in every thread)
@@ -500,6 +502,18 @@ hipError_t launch_lz_finish_b(const SweepGeom& g, int j, const double* partial,
                               LanczosScalars* sc, hipStream_t st)
 {
     hipLaunchKernelGGL(k_lz_finish_b, dim3(g.n_inst), dim3(kBlock), 0, st, g, j, partial, sc);
+    return hipGetLastError();
+}
+
+__global__ void k_lz_reset(int n_inst, int m, LanczosScalars* __restrict__ scs)
+{
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k < n_inst) scs[k].meff_min = m;
+}
+
+hipError_t launch_lz_reset(const SweepGeom& g, int m, LanczosScalars* sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lz_reset, dim3((g.n_inst + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g.n_inst, m, sc);
     return hipGetLastError();
 }
 

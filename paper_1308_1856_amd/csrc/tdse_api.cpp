@@ -84,6 +84,8 @@ struct tdse_ctx {
     bool obs_main_done = false;
     hipStream_t obs_stream = nullptr;
     hipEvent_t obs_fork = nullptr, obs_join = nullptr, obs_done[2] = {nullptr, nullptr};
+    // Krylov dimension requested by the last tdse_step_lanczos call (0: none)
+    int lz_m = 0;
     // captured step graphs, keyed by the launch pattern of a chunk
     bool use_graphs = false;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
@@ -651,6 +653,7 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
     if (work_bytes < c->fixed_bytes)
         return c->fail(TDSE_E_WORKSPACE, "tdse_bind: workspace smaller than the fixed tables");
     c->drop_graphs();
+    c->lz_m = 0;
     c->d_state = static_cast<char*>(d_state);
     c->d_work = static_cast<char*>(d_work);
     c->work_bytes = work_bytes;
@@ -1163,6 +1166,10 @@ extern "C" tdse_status tdse_step_lanczos(tdse_ctx* c, const tdse_pulse* pulses, 
     LanczosScalars* sc = c->d_lz();
     double* part = c->d_partial();
     void* cur = psi;
+    // the breakdown report of this call starts from the requested dimension
+    hipError_t er = launch_lz_reset(g, m, sc, c->stream);
+    if (er != hipSuccess) return c->hip_fail(er, "tdse_step_lanczos reset");
+    c->lz_m = m;
     return run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, 3000 + m, &cur, [&](const double* step) {
         hipError_t e = launch_lz_norm(c->prec, g, psi, part, c->stream);
         if (e == hipSuccess) e = launch_lz_norm_finish(g, part, sc, c->stream);
@@ -1210,6 +1217,25 @@ extern "C" tdse_status tdse_observables(tdse_ctx* c, const tdse_pulse* pulses, c
     if (e != hipSuccess) return c->hip_fail(e, "tdse_observables");
     for (int k = 0; k < c->n_inst; ++k)
         if (!std::isfinite(host_out[k].norm)) return c->fail(TDSE_E_NONFINITE, "tdse_observables: norm is not finite");
+    return TDSE_OK;
+}
+
+extern "C" tdse_status tdse_lanczos_dims(tdse_ctx* c, int32_t* host_meff)
+{
+    if (!c || !host_meff) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_lanczos_dims: not bound");
+    if (c->lz_m <= 0) return c->fail(TDSE_E_INVALID, "tdse_lanczos_dims: no Lanczos step since the context was bound");
+    std::vector<LanczosScalars> sc(c->n_inst);
+    hipError_t e = hipMemcpyAsync(sc.data(), c->d_lz(), sizeof(LanczosScalars) * c->n_inst, hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_lanczos_dims");
+    bool broke = false;
+    for (int k = 0; k < c->n_inst; ++k) {
+        host_meff[k] = sc[k].meff_min;
+        broke = broke || sc[k].meff_min < c->lz_m;
+    }
+    if (broke) return c->fail(TDSE_E_BREAKDOWN, "tdse_lanczos_dims: the Krylov process stopped early (invariant subspace)");
     return TDSE_OK;
 }
 

@@ -61,7 +61,8 @@ struct LanczosScalars {
     double coef[2 * kMaxKrylov];   // recombination weights (re, im), include norm0 and scale
     int32_t meff;                  // Krylov dimension in use (grows; frozen at breakdown)
     int32_t done;                  // breakdown reached
-    int32_t pad_[2];
+    int32_t meff_min;              // smallest Krylov dimension over the steps of the current call
+    int32_t pad_;
 };
 
 // ----------------------------------------------------------------------------
@@ -164,6 +165,8 @@ hipError_t launch_lz_finish_b(const SweepGeom& g, int j, const double* partial,
                               LanczosScalars* sc, hipStream_t st);
 hipError_t launch_lz_expm(const SweepGeom& g, const double* step, LanczosScalars* sc,
                           hipStream_t st);
+// meff_min = m for every instance (before the first step of a call).
+hipError_t launch_lz_reset(const SweepGeom& g, int m, LanczosScalars* sc, hipStream_t st);
 hipError_t launch_lz_recombine(int prec, const SweepGeom& g, int m, void* psi, const void* basis,
                                int64_t vec_stride, const LanczosScalars* sc, hipStream_t st);
 

@@ -249,6 +249,51 @@ def test_lanczos_breakdown_on_eigenstate():
     assert rel_err(got, ref) < 1e-12
 
 
+def test_lanczos_dims_reports_breakdown_as_information():
+    # an eigenvector breaks the Krylov process down after one vector in every
+    # step: tdse_lanczos_dims gives TDSE_E_BREAKDOWN (information) with the
+    # dimension used; a random state keeps the full dimension (TDSE_OK)
+    t = lib()
+    n, lmax, dr = 600, 3, 0.1
+    g = oracle.Grid(n=n, lmax=lmax, dr=dr, stencil=3)
+    e, phi, states = oracle.bound_states(g, 2)
+    prop = make([(n, lmax, dr, 3, 20.0)], [(t.METHOD_LANCZOS, 12)])
+    psi = np.zeros(g.size, dtype=np.complex128)
+    psi[:n] = phi[states.index((1, 0))]
+    prop.set_state(0, psi)
+    prop.step_lanczos(t.Pulse(0.0, 1.0, 1.0, 0.0, 0.0), 0.0, 0.5, 12, 3)
+    dims, broke = prop.lanczos_dims()
+    say(f"lanczos dims on an eigenvector: {dims}, breakdown {broke}")
+    assert broke and dims == [1]
+    prop.set_state(0, workloads.random_state(3, n, lmax))
+    prop.step_lanczos(t.Pulse(0.05, 0.3, 2.0, 0.0, 0.0), 0.0, 1e-3, 12, 2)
+    dims, broke = prop.lanczos_dims()
+    assert not broke and dims == [12]
+    prop.close()
+
+
+def test_fault_paths_nonfinite_and_workspace():
+    # a NaN in the state makes tdse_observables return TDSE_E_NONFINITE; a
+    # Lanczos call with a workspace sized for Taylor returns TDSE_E_WORKSPACE
+    # and enqueues nothing (the state is unchanged)
+    t = lib()
+    n, lmax = 400, 4
+    prop = make([(n, lmax, 0.1, 3, 20.0)], [(t.METHOD_TAYLOR, 8)])
+    psi = workloads.random_state(8, n, lmax)
+    psi[3 * n + 17] = np.nan
+    prop.set_state(0, psi)
+    with pytest.raises(t.TdseError) as e:
+        prop.observables(t.Pulse(0.0, 1.0, 1.0, 0.0, 0.0), 0.0)
+    assert e.value.code == -6
+    prop.set_state(0, None)
+    before = prop.get_state(0)
+    with pytest.raises(t.TdseError) as e:
+        prop.step_lanczos(t.Pulse(0.05, 0.3, 2.0, 0.0, 0.0), 0.0, 1e-3, 20, 4)
+    assert e.value.code == -7
+    assert np.array_equal(prop.get_state(0), before)
+    prop.close()
+
+
 def test_batch_matches_single_instances():
     t = lib()
     grids = [(300, 3, 0.1, 5, 8.0), (777, 10, 0.05, 5, 20.0), (257, 0, 0.2, 5, 10.0)]

@@ -116,3 +116,29 @@ def test_calls_before_bind_fail_cleanly(tdse):
         assert "bound" in tdse.lib.tdse_last_error(ctx).decode()
     finally:
         tdse.tdse_destroy(ctx)
+
+
+def test_bind_rejects_small_workspace_before_touching_the_device(tdse):
+    # a workspace below the fixed tables is refused (TDSE_E_WORKSPACE) before
+    # any HIP call; the pointers are never dereferenced
+    ctx = tdse.tdse_init_grid([tdse.Grid(300, 3, 0.1).desc()])
+    try:
+        need = tdse.lib.tdse_workspace_bytes(ctx, tdse.METHOD_TAYLOR, 8)
+        sb = tdse.lib.tdse_state_bytes(ctx)
+        code = tdse.lib.tdse_bind(ctx, 1 << 20, 1 << 21, need - 3 * sb, None)
+        assert code == -7
+        assert "workspace" in tdse.lib.tdse_last_error(ctx).decode()
+        # misaligned device pointers are refused as invalid
+        assert tdse.lib.tdse_bind(ctx, (1 << 20) + 16, 1 << 21, need, None) == -1
+    finally:
+        tdse.tdse_destroy(ctx)
+
+
+def test_lanczos_dims_needs_a_bound_context(tdse):
+    ctx = tdse.tdse_init_grid([tdse.Grid(100, 2, 0.1).desc()])
+    try:
+        with pytest.raises(tdse.TdseError) as e:
+            tdse.tdse_lanczos_dims(ctx)
+        assert e.value.code == -8
+    finally:
+        tdse.tdse_destroy(ctx)

@@ -113,3 +113,38 @@ def test_batch_recipe_is_deterministic():
     assert all(1e13 <= m.intensity <= 5e14 and 400 <= m.wavelength_nm <= 1600 for m in a)
     total = sum((m.lmax + 1) * m.n for m in a)
     assert total == 104_476_250
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.1])
+def test_p_g_is_the_probability_of_the_initial_state(orc, theta):
+    # eq. p_g read as a probability: for psi = e^{i a} cos(theta) u0 + sin(theta) v
+    # with v orthogonal to u0 (built here by Gram-Schmidt in the grid inner
+    # product dr * sum), p_g = cos^2(theta).  The amplitude |<u0|f_0>| would give
+    # |cos(theta)| instead, and a missing dr or a missing square fails too.
+    g = orc.Grid(n=700, lmax=3, dr=0.1, stencil=5)
+    setup = orc.obs_setup(g, r_ion=30.0)
+    _, u0 = orc.initial_state(g)
+    r = orc.radius(g)
+    w = (r ** 2 * np.exp(-0.5 * r) * (1.0 + 0.3j * np.sin(r))).astype(np.complex128)
+    w -= g.dr * np.vdot(u0, w) * u0
+    w /= math.sqrt(g.dr * np.vdot(w, w).real)
+    assert abs(g.dr * np.vdot(u0, w)) < 1e-14
+    psi = np.zeros(g.size, dtype=np.complex128)
+    psi[:g.n] = np.exp(0.7j) * math.cos(theta) * u0 + math.sin(theta) * w
+    # a component in another partial wave does not enter p_g
+    psi[g.n:2 * g.n] = 0.2 * u0
+    obs = orc.observables(g, orc.Pulse(), 0.0, setup, psi)
+    assert obs[3] == pytest.approx(math.cos(theta) ** 2, abs=1e-13)
+    assert abs(obs[3] - abs(math.cos(theta))) > 0.04     # the two readings differ here
+
+
+def test_initial_state_for_nuclear_charge_two(orc):
+    # Fig. "1sHydroRad" for a hydrogen-like ion of charge Z: the 1s radial
+    # density is 4 Z^3 r^2 exp(-2 Z r); the grid state approaches it.
+    z = 2.0
+    for dr, tol in ((0.02, 2e-3), (0.005, 1.5e-4)):
+        g = orc.Grid(n=int(20 / dr), lmax=1, dr=dr, z=z)
+        psi, _ = orc.initial_state(g)
+        r = orc.radius(g)
+        dens = np.abs(psi[:g.n]) ** 2
+        assert np.max(np.abs(dens - 4 * z ** 3 * r ** 2 * np.exp(-2 * z * r))) < tol

@@ -166,3 +166,35 @@ def test_stark_dipole_and_acceleration(orc):
     assert obs[2] == pytest.approx(1.0, abs=1e-12)
     assert obs[6] == pytest.approx(-4.5 * F - 3555 / 16 * F ** 3, rel=3e-3)
     assert obs[7] == pytest.approx(F, rel=3e-3)
+
+
+def test_hydrogen_like_levels_charge_two(orc):
+    # He+ (Z = 2): 3-point levels approach -Z^2/(2 n^2).  In the scaled radius
+    # Z r the grid spacing is Z dr, so the error is Z^2 times the hydrogen
+    # error at spacing Z dr: below 0.15 Z^4 dr^2, with ratio 4 per halving.
+    z = 2.0
+    errs = {}
+    for dr in (0.05, 0.025):
+        g = orc.Grid(n=int(round(150 / dr)), lmax=2, dr=dr, stencil=3, z=z)
+        e, _, states = orc.bound_states(g, 5)
+        errs[dr] = np.array([abs(ei + z * z * 0.5 / n ** 2) for ei, (n, l) in zip(e, states)])
+        assert np.all(errs[dr] < 0.15 * z ** 4 * dr ** 2), errs[dr]
+    assert 3.8 < errs[0.05][0] / errs[0.025][0] < 4.2
+    # the Z = 1 levels are not the answer (a dropped Z would land there)
+    assert abs(e[0] + 0.5) > 1.0
+
+
+def test_stark_dipole_and_acceleration_charge_two(orc):
+    # He+ 1s in a static field F: polarisability 9/(2 Z^4), so Hellmann-Feynman
+    # gives <z> = -(9/2) F / Z^4; a stationary state feels no net force, so the
+    # acceleration record taken without a pulse, -2 Z sum kappa Re int f* f/r^2
+    # (eq. DipoleAccel for charge Z), must equal +F.  A factor 2 in place of 2Z
+    # would give F/2.
+    z, F = 2.0, 0.02
+    g = orc.Grid(n=1000, lmax=8, dr=0.025, stencil=3, z=z)
+    _, v = _ground_in_field(orc, g, F, sigma=-2.2)
+    psi = v[:, 0].astype(np.complex128) / math.sqrt(g.dr * np.dot(v[:, 0], v[:, 0]))
+    setup = orc.obs_setup(g, r_ion=10.0)
+    obs = orc.observables(g, orc.Pulse(), 0.0, setup, psi)
+    assert obs[6] == pytest.approx(-4.5 * F / z ** 4, rel=3e-3)
+    assert obs[7] == pytest.approx(F, rel=3e-3)
