@@ -28,7 +28,7 @@ TAYLOR, RK4, LANCZOS = 0, 1, 2
 
 def build() -> str:
     """Compile the C oracle with gcc into oracle/liboracle.so."""
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
            "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
@@ -87,6 +87,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int32)
         gp, pp = ctypes.POINTER(_Grid), ctypes.POINTER(_Pulse)
+        L.orc_set_threads.argtypes, L.orc_set_threads.restype = [ctypes.c_int], None
+        L.orc_max_threads.argtypes, L.orc_max_threads.restype = [], ctypes.c_int
         L.orc_radius.argtypes, L.orc_radius.restype = [gp, ctypes.c_int], ctypes.c_double
         L.orc_kappa.argtypes, L.orc_kappa.restype = [ctypes.c_int], ctypes.c_double
         L.orc_field.argtypes, L.orc_field.restype = [pp, ctypes.c_double], ctypes.c_double
@@ -106,6 +108,16 @@ def lib():
         L.orc_propagate.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's element-wise loops (results are
+    bit-identical for every thread count)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _dptr(a: np.ndarray):

@@ -10,8 +10,17 @@
 #include "tdse_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads: the loops over partial waves of H f and the element-wise vector
+ * updates may run on several OpenMP threads (each element is computed by one
+ * thread with the same operations, so the results do not depend on the
+ * thread count); every sum over elements (norms, inner products, observables)
+ * runs on one thread in index order. */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* Sec. 2, grid definition: uniform points, the first one a spacing away from
  * the origin ("Start = 1"), optionally displaced by the "Offset" setting. */
@@ -54,6 +63,7 @@ void orc_apply_h(const orc_grid* g, double efield, const double complex* f, doub
 {
     const int n = g->n;
     const double h2 = g->dr * g->dr;
+#pragma omp parallel for schedule(static)
     for (int l = 0; l <= g->lmax; ++l) {
         const double complex* fl = f + (size_t)l * n;
         const double complex* flm = (l > 0) ? f + (size_t)(l - 1) * n : NULL;
@@ -115,6 +125,7 @@ void orc_taylor_step(const orc_grid* g, double efield, double dt, int order, dou
     for (int p = 0; p < order; ++p) {
         orc_apply_h(g, efield, term, next);
         const double complex factor = -I * dt / (double)(p + 1);
+#pragma omp parallel for schedule(static)
         for (size_t k = 0; k < len; ++k) {
             term[k] = factor * next[k];
             psi[k] += term[k];
@@ -140,11 +151,16 @@ static void rk4_step_fields(const orc_grid* g, double e_start, double e_mid, dou
     memcpy(acc, psi, len * sizeof *acc);
     memcpy(y, psi, len * sizeof *y);
     for (int s = 0; s < 4; ++s) {
-        if (s > 0)
+        if (s > 0) {
+#pragma omp parallel for schedule(static)
             for (size_t j = 0; j < len; ++j) y[j] = psi[j] + a[s] * dt * k[j];
+        }
         orc_apply_h(g, e[s], y, k);
-        for (size_t j = 0; j < len; ++j) k[j] = -I * k[j];
-        for (size_t j = 0; j < len; ++j) acc[j] += b[s] * dt * k[j];
+#pragma omp parallel for schedule(static)
+        for (size_t j = 0; j < len; ++j) {
+            k[j] = -I * k[j];
+            acc[j] += b[s] * dt * k[j];
+        }
     }
     memcpy(psi, acc, len * sizeof *acc);
     free(k);
@@ -240,10 +256,9 @@ int orc_lanczos_step(const orc_grid* g, double efield, double dt, int m, double 
             for (size_t k = 0; k < len; ++k) dot += conj(qi[k]) * w[k];
             h[i] = dot;
         }
-        for (int i = 0; i <= j; ++i) {
-            const double complex* qi = q + (size_t)i * len;
-            for (size_t k = 0; k < len; ++k) w[k] -= h[i] * qi[k];
-        }
+#pragma omp parallel for schedule(static)
+        for (size_t k = 0; k < len; ++k)
+            for (int i = 0; i <= j; ++i) w[k] -= h[i] * q[(size_t)i * len + k];
         alpha[j] = creal(h[j]);
         double b2 = 0.0;
         for (size_t k = 0; k < len; ++k) b2 += creal(w[k]) * creal(w[k]) + cimag(w[k]) * cimag(w[k]);
@@ -252,6 +267,7 @@ int orc_lanczos_step(const orc_grid* g, double efield, double dt, int m, double 
         if (j == m - 1) break;
         if (beta[j] <= breakdown) break; /* invariant subspace found */
         double complex* qn = q + (size_t)(j + 1) * len;
+#pragma omp parallel for schedule(static)
         for (size_t k = 0; k < len; ++k) qn[k] = w[k] / beta[j];
     }
 
@@ -275,6 +291,7 @@ int orc_lanczos_step(const orc_grid* g, double efield, double dt, int m, double 
         }
         c[k] = acc;
     }
+#pragma omp parallel for schedule(static)
     for (size_t k = 0; k < len; ++k) {
         double complex acc = 0.0;
         for (int j = 0; j < meff; ++j) acc += c[j] * q[(size_t)j * len + k];

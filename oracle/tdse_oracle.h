@@ -55,6 +55,11 @@ double orc_field(const orc_pulse* p, double t);
 
 double orc_h_bound(const orc_grid* g, double efield);
 
+/* OpenMP threads of the element-wise loops (results do not depend on it:
+ * every sum over elements runs on one thread, in index order). */
+void orc_set_threads(int n);
+int orc_max_threads(void);
+
 void orc_apply_h(const orc_grid* g, double efield,
                  const double complex* f, double complex* hf);
 
