@@ -159,3 +159,22 @@ def test_jacobi_matches_lapack(orc):
     w, v = orc.jacobi_eig(t)
     ref = np.linalg.eigvalsh(t)
     assert np.allclose(np.sort(w), ref, rtol=1e-13, atol=1e-9)
+
+
+def test_thread_count_does_not_change_results(orc):
+    # the element-wise loops may run on several threads; every element is
+    # computed by one thread with the same operations and every sum runs on
+    # one thread in index order, so the results are bit-identical
+    g = orc.Grid(n=900, lmax=9, dr=0.1, stencil=5)
+    p = orc.Pulse(0.06, 0.3, 2.0, 0.1, 0.0)
+    setup = orc.obs_setup(g, r_ion=20.0)
+    psi0 = smooth_state(g, 17)
+    out = []
+    for th in (1, 4):
+        orc.set_threads(th)
+        runs = [orc.propagate(g, p, code, order, 0.3, dt, 6, 2, setup, psi0)
+                for code, order, dt in ((orc.TAYLOR, 8, 2e-4), (orc.RK4, 4, 2e-4), (orc.LANCZOS, 10, 0.01))]
+        out.append(runs)
+    orc.set_threads(orc.max_threads())
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
