@@ -26,10 +26,12 @@
  *   tdse_state_offset(ctx, k) (a multiple of 64 elements).  Within an
  *   instance, element (l, i) sits at offset + l*N + i.  An element is an
  *   interleaved complex number: 16 bytes (re, im as double) for
- *   TDSE_FP64, 8 bytes (re, im as float) for TDSE_FP32.  In TDSE_FP32 mode
- *   every sweep reads and writes FP32 values but computes in FP64, and all
- *   reductions (norms, inner products, observables, Lanczos coefficients,
- *   the tridiagonal eigen-decomposition) are FP64.
+ *   TDSE_FP64, 8 bytes (re, im as float) for TDSE_FP32; TDSE_FP48 splits
+ *   the vector into two planes (see tdse_precision).  In the TDSE_FP32 and
+ *   TDSE_FP48 modes every sweep reads and writes values of that storage
+ *   precision but computes in FP64, and all reductions (norms, inner
+ *   products, observables, Lanczos coefficients, the tridiagonal
+ *   exponential) are FP64.
  *
  * Errors
  *   Every function returning tdse_status returns TDSE_OK (0) or a negative
@@ -61,7 +63,19 @@ enum {
     TDSE_E_UNBOUND = -8     /* no device memory bound yet (tdse_bind)              */
 };
 
-typedef enum { TDSE_FP64 = 0, TDSE_FP32 = 1 } tdse_precision;
+/* Storage precision of state-shaped vectors (arithmetic and reductions are
+ * FP64 in all three).  TDSE_FP48: each FP64 component rounded to nearest at
+ * 36 mantissa bits (relative rounding error <= 2^-37, against 2^-24 for
+ * FP32), 12 bytes per complex element, stored in two planes: plane h holds
+ * the upper 32-bit words of (re, im) of every element (8 bytes per element),
+ * plane l, from byte 8 * P of the vector on, the next 16 bits of re (low
+ * half) and im (high half) of every element (4 bytes), with P the element
+ * count rounded up to a multiple of 64.  Rounding an FP32 state once per
+ * step drifts coherently at the small steps explicit methods need on these
+ * grids (the state changes by a few FP32 ulp per step); the 48-bit state
+ * keeps that drift 2^13 times smaller.  The two-radii sweeps and the
+ * LDS-ring fused kernel are FP64/FP32 only. */
+typedef enum { TDSE_FP64 = 0, TDSE_FP32 = 1, TDSE_FP48 = 2 } tdse_precision;
 /* TDSE_METHOD_TUNE only sizes the workspace the autotuners need (four
  * state-shaped vectors). */
 typedef enum { TDSE_METHOD_TAYLOR = 0, TDSE_METHOD_RK4 = 1, TDSE_METHOD_LANCZOS = 2,
@@ -73,7 +87,7 @@ typedef struct {
     int32_t n_r;        /* radial points N, >= 8                                  */
     int32_t lmax;       /* highest partial wave, 0..1023                          */
     int32_t stencil;    /* 3 or 5                                                 */
-    int32_t precision;  /* tdse_precision                                         */
+    int32_t precision;  /* tdse_precision (TDSE_FP64, TDSE_FP32 or TDSE_FP48)     */
     double dr;          /* grid spacing (au), > 0                                 */
     double z_nuc;       /* nuclear charge Z (> 0)                                 */
     double r_ion;       /* ionisation radius r_b (au) for p_ion                   */

@@ -23,7 +23,7 @@ TDSE_OK = 0
 STATUS = {0: "TDSE_OK", -1: "TDSE_E_INVALID", -2: "TDSE_E_NOMEM", -3: "TDSE_E_HIP",
           -4: "TDSE_E_UNSTABLE", -5: "TDSE_E_BREAKDOWN", -6: "TDSE_E_NONFINITE", -7: "TDSE_E_WORKSPACE",
           -8: "TDSE_E_UNBOUND"}
-FP64, FP32 = 0, 1
+FP64, FP32, FP48 = 0, 1, 2
 METHOD_TAYLOR, METHOD_RK4, METHOD_LANCZOS, METHOD_TUNE = 0, 1, 2, 3
 MAX_STATES = 15
 OBS_FIELDS = ("t", "e_field", "norm", "p_g", "p_bound", "p_ion", "dipole", "accel")
@@ -318,7 +318,7 @@ class Propagator:
         tdse_bind(self.ctx, self.state.data_ptr(), self.work.data_ptr(), wbytes,
                   self.stream.cuda_stream)
         self.offsets = [lib.tdse_state_offset(self.ctx, k) for k in range(self.n_inst)]
-        self.elem = 16 if self.grids[0].precision == FP64 else 8
+        self.elem = {FP64: 16, FP32: 8, FP48: 12}[self.grids[0].precision]
         self.fusion_rows = 16   # rows of the fused tiles (the library's default until set or tuned)
         if graphs:
             tdse_use_graphs(self.ctx, True)

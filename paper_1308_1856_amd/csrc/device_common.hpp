@@ -6,9 +6,73 @@
 
 namespace tdse {
 
+// Storage precisions: T = double (16 B per complex element), float (8 B) or
+// s48 (12 B).  s48 keeps each FP64 component rounded to 36 mantissa bits
+// (relative rounding error at most 2^-37): the upper 32-bit word of the FP64
+// bit pattern in plane h (8 B per element: re, im) and the next 16 bits in
+// plane l (4 B per element: re in the low half, im in the high half).  A
+// state-shaped vector of s48 storage is [plane h | plane l], plane l starting
+// 8 * plane bytes after plane h (SweepGeom::plane elements per plane).
+struct s48 {};
+struct c48 {
+    unsigned hx, hy, l;
+};
+struct P48 {
+    uint2* h;
+    unsigned* l;
+    __host__ __device__ __forceinline__ P48 operator+(int64_t k) const { return P48{h + k, l + k}; }
+    __host__ __device__ __forceinline__ P48 operator-(int64_t k) const { return P48{h - k, l - k}; }
+    __device__ __forceinline__ c48 operator[](int64_t k) const
+    {
+        const uint2 a = h[k];
+        return c48{a.x, a.y, l[k]};
+    }
+};
+
 template <typename T> struct Cplx;
 template <> struct Cplx<double> { using type = double2; };
 template <> struct Cplx<float> { using type = float2; };
+template <> struct Cplx<s48> { using type = c48; };
+
+// Kernel-argument types of state-shaped vectors and their construction from
+// the launchers' untyped pointers (the s48 planes from one base address, or,
+// for a run of vectors stored plane by plane, from the two plane bases).
+template <typename T> struct Stor {
+    using C = typename Cplx<T>::type;
+    using cptr = const C* __restrict__;
+    using ptr = C* __restrict__;
+    using aptr = C*;          // may alias another argument
+    using captr = const C*;   // read-only, may alias another argument
+    static const C* cmake(const void* p, int64_t) { return static_cast<const C*>(p); }
+    static C* make(void* p, int64_t) { return static_cast<C*>(p); }
+};
+template <> struct Stor<s48> {
+    using C = c48;
+    using cptr = P48;
+    using ptr = P48;
+    using aptr = P48;
+    using captr = P48;
+    static P48 cmake(const void* p, int64_t plane)
+    {
+        char* b = static_cast<char*>(const_cast<void*>(p));
+        return P48{reinterpret_cast<uint2*>(b), reinterpret_cast<unsigned*>(b + 8 * plane)};
+    }
+    static P48 make(void* p, int64_t plane) { return cmake(p, plane); }
+};
+
+// s48 conversions: the FP64 value from its stored words, and the stored words
+// of an FP64 value rounded to nearest (ties away from zero) at bit 16.
+__device__ __forceinline__ double2 widen48(c48 v)
+{
+    const unsigned lox = v.l << 16, loy = v.l & 0xffff0000u;
+    return make_double2(__hiloint2double((int)v.hx, (int)lox), __hiloint2double((int)v.hy, (int)loy));
+}
+__device__ __forceinline__ c48 narrow48(double2 v)
+{
+    const unsigned long long a = (unsigned long long)__double_as_longlong(v.x) + 0x8000ull;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v.y) + 0x8000ull;
+    return c48{(unsigned)(a >> 32), (unsigned)(b >> 32), ((unsigned)a >> 16) | ((unsigned)b & 0xffff0000u)};
+}
 
 __device__ __forceinline__ double2 ldc(const double2* p, int64_t k) { return p[k]; }
 __device__ __forceinline__ double2 ldc(const float2* p, int64_t k)
@@ -33,6 +97,23 @@ __device__ __forceinline__ void stc(float2* p, int64_t k, double2 v)
     const fvec2_t w = {(float)v.x, (float)v.y};
     __builtin_nontemporal_store(w, reinterpret_cast<fvec2_t*>(p + k));
 }
+__device__ __forceinline__ double2 ldc(P48 p, int64_t k) { return widen48(p[k]); }
+typedef unsigned uvec2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void stc(P48 p, int64_t k, double2 v)
+{
+    const c48 c = narrow48(v);
+    const uvec2_t w = {c.hx, c.hy};
+    __builtin_nontemporal_store(w, reinterpret_cast<uvec2_t*>(p.h + k));
+    __builtin_nontemporal_store(c.l, p.l + k);
+}
+// The value a store of v keeps, as FP64.
+template <typename T> __device__ __forceinline__ double2 stored_value(double2 v);
+template <> __device__ __forceinline__ double2 stored_value<double>(double2 v) { return v; }
+template <> __device__ __forceinline__ double2 stored_value<float>(double2 v)
+{
+    return make_double2((double)(float)v.x, (double)(float)v.y);
+}
+template <> __device__ __forceinline__ double2 stored_value<s48>(double2 v) { return widen48(narrow48(v)); }
 // Ordinary stores, for vectors read again while still cache-resident (the
 // Lanczos w and basis vectors, reread by the next sweep; measured 2.6% more
 // steps per second than with streaming stores).
@@ -40,6 +121,12 @@ __device__ __forceinline__ void stc_keep(double2* p, int64_t k, double2 v) { p[k
 __device__ __forceinline__ void stc_keep(float2* p, int64_t k, double2 v)
 {
     p[k] = make_float2((float)v.x, (float)v.y);
+}
+__device__ __forceinline__ void stc_keep(P48 p, int64_t k, double2 v)
+{
+    const c48 c = narrow48(v);
+    p.h[k] = make_uint2(c.hx, c.hy);
+    p.l[k] = c.l;
 }
 
 __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
@@ -245,10 +332,11 @@ __device__ __forceinline__ double2 horner_update(double2 psi, double2 h, double 
 }
 
 // Radial neighbours of element i of a row (zero outside [0, n)).
-template <int S, typename C>
+template <int S>
 struct Neighbours {
     double2 m1, p1, m2, p2;
-    __device__ __forceinline__ void load(const C* row, int i, int n)
+    template <typename P>
+    __device__ __forceinline__ void load(P row, int i, int n)
     {
         m1 = (i >= 1) ? ldc(row, i - 1) : zero2();
         p1 = (i + 1 < n) ? ldc(row, i + 1) : zero2();

@@ -37,7 +37,6 @@ k_horner_fused(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
                const typename Cplx<T>::type* __restrict__ psi, typename Cplx<T>::type* __restrict__ out,
                const double* __restrict__ step, int first_term)
 {
-    using C = typename Cplx<T>::type;
     constexpr int kSlotsPerLevel = 4;
     // LDS: levels 1..K-1, four rows of 256 complex FP64 each
     __shared__ double2 ring[(K > 1 ? K - 1 : 1) * kSlotsPerLevel * kBlock];
@@ -86,7 +85,7 @@ k_horner_fused(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
             pr[0] = load_psi(rho);
             double2 v = zero2();
             if (inside && rho >= 0 && rho <= lmax) {
-                Neighbours<S, C> nb;
+                Neighbours<S> nb;
                 nb.load(in + base + (int64_t)rho * n, jc, n);
                 const double vpot = row_potential(rho, inv_r2, z_over_r);
                 const double2 h = h_point<S>(in_cur, nb.m1, nb.p1, nb.m2, nb.p2, in_prev, in_next,
@@ -174,6 +173,7 @@ hipError_t launch_horner_fused(int prec, int S, int K, const SweepGeom& g, const
 {
     if (prec == 0) return S == 1 ? fused_k<1, double>(K, g, in, psi, out, step, first_term, st)
                                  : fused_k<2, double>(K, g, in, psi, out, step, first_term, st);
+    if (prec != 1) return hipErrorInvalidValue;   // LDS-ring kernel: FP64 and FP32 storage only
     return S == 1 ? fused_k<1, float>(K, g, in, psi, out, step, first_term, st)
                   : fused_k<2, float>(K, g, in, psi, out, step, first_term, st);
 }

@@ -15,19 +15,27 @@
 // Basis vectors are stored unnormalised (FP64 or FP32) and scaled on load by
 // FP64 factors; q_0 is the state buffer itself.  All inner products, norms
 // and coefficients are FP64.
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace tdse {
 
-template <typename C>
-__device__ __forceinline__ const C* basis_vec(const C* psi, const C* basis, int64_t stride, int j)
+// Vector j of the basis: the state for j = 0, else stored vector j at
+// basis + (j - 1) stride elements (with s48 storage the basis vectors are
+// stored plane by plane: their h planes one after another, then their l
+// planes, so the same element arithmetic reaches both).
+template <typename P>
+__device__ __forceinline__ P basis_vec(P psi, P basis, int64_t stride, int j)
 {
     return (j == 0) ? psi : basis + (int64_t)(j - 1) * stride;
 }
+template <typename C> __device__ __forceinline__ const C* cview(const C* p) { return p; }
+__device__ __forceinline__ P48 cview(P48 p) { return p; }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_lz_norm(SweepGeom g, const typename Cplx<T>::type* __restrict__ psi, double* __restrict__ partial)
+k_lz_norm(SweepGeom g, typename Stor<T>::cptr psi, double* __restrict__ partial)
 {
     __shared__ double lds[kBlock / 64];
     const int t = my_tile_index(g);
@@ -102,12 +110,10 @@ k_lz_norm_finish(SweepGeom g, const double* __restrict__ partial, LanczosScalars
 // wrote, eight basis vectors at a time).
 template <int S, typename T>
 __global__ void __launch_bounds__(kBlock)
-k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
-             const typename Cplx<T>::type* basis, int64_t stride, typename Cplx<T>::type* w,
-             const double* __restrict__ step, const LanczosScalars* __restrict__ scs,
+k_lz_sweep_a(SweepGeom g, int j, int m, typename Stor<T>::captr psi, typename Stor<T>::captr basis, int64_t stride,
+             typename Stor<T>::aptr w, const double* __restrict__ step, const LanczosScalars* __restrict__ scs,
              double* __restrict__ partial)
 {
-    using C = typename Cplx<T>::type;
     constexpr int JB = 8;
     __shared__ double lds[(kBlock / 64) * 2 * JB];
     const int t = my_tile_index(g);
@@ -118,7 +124,7 @@ k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
     const int n = I.n;
     const int i = tile.r0 + (int)threadIdx.x;
     const bool active = i < n;
-    const C* qj = basis_vec(psi, basis, stride, j);
+    const auto qj = basis_vec(psi, basis, stride, j);
     const double sj = sc.scale[j];
 
     if (active) {
@@ -130,7 +136,7 @@ k_lz_sweep_a(SweepGeom g, int j, int m, const typename Cplx<T>::type* psi,
         for (int l = tile.l0; l < tile.l1; ++l) {
             const int64_t row = base + (int64_t)l * n;
             const double2 next = (l < I.lmax) ? ldc(qj, row + n + i) : zero2();
-            Neighbours<S, C> nb;
+            Neighbours<S> nb;
             nb.load(qj + row, i, n);
             const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
             double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
@@ -197,9 +203,8 @@ k_lz_finish_a(SweepGeom g, int j, int m, const double* __restrict__ partial,
 // q_{j+1} (stored unnormalised) = w - sum_{i<=j} h_i q_i, and ||.||^2 partials.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_lz_sweep_b(SweepGeom g, int j, const typename Cplx<T>::type* psi, typename Cplx<T>::type* basis,
-             int64_t stride, const typename Cplx<T>::type* __restrict__ w,
-             const LanczosScalars* __restrict__ scs, double* __restrict__ partial)
+k_lz_sweep_b(SweepGeom g, int j, typename Stor<T>::captr psi, typename Stor<T>::aptr basis, int64_t stride,
+             typename Stor<T>::cptr w, const LanczosScalars* __restrict__ scs, double* __restrict__ partial)
 {
     __shared__ double lds[kBlock / 64];
     const int t = my_tile_index(g);
@@ -208,7 +213,7 @@ k_lz_sweep_b(SweepGeom g, int j, const typename Cplx<T>::type* psi, typename Cpl
     const LanczosScalars& sc = scs[tile.inst];
     if (sc.done) return;
     const int i = tile.r0 + (int)threadIdx.x;
-    typename Cplx<T>::type* out = basis + (int64_t)j * stride;  // vector j+1
+    const auto out = basis + (int64_t)j * stride;  // vector j+1
     double acc[1] = {0.0};
     if (i < I.n) {
         for (int l = tile.l0; l < tile.l1; ++l) {
@@ -217,7 +222,7 @@ k_lz_sweep_b(SweepGeom g, int j, const typename Cplx<T>::type* psi, typename Cpl
             for (int q = 0; q <= j; ++q) {
                 const double s = sc.scale[q];
                 const double hr = s * sc.h[2 * q], hi = s * sc.h[2 * q + 1];
-                const double2 b = ldc(basis_vec(psi, (const typename Cplx<T>::type*)basis, stride, q), k);
+                const double2 b = ldc(basis_vec(psi, cview(basis), stride, q), k);
                 v.x = fma(-hr, b.x, fma(hi, b.y, v.x));
                 v.y = fma(-hr, b.y, fma(-hi, b.x, v.y));
             }
@@ -408,8 +413,8 @@ k_lz_expm(SweepGeom g, const double* __restrict__ step, LanczosScalars* __restri
 // F <- sum_k coef_k stored_k  (stored_0 is F itself: read before written).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_lz_recombine(SweepGeom g, typename Cplx<T>::type* psi, const typename Cplx<T>::type* __restrict__ basis,
-               int64_t stride, const LanczosScalars* __restrict__ scs)
+k_lz_recombine(SweepGeom g, typename Stor<T>::aptr psi, typename Stor<T>::cptr basis, int64_t stride,
+               const LanczosScalars* __restrict__ scs)
 {
     const Tile I = my_tile(g);
     const Tile& tile = I;
@@ -422,7 +427,7 @@ k_lz_recombine(SweepGeom g, typename Cplx<T>::type* psi, const typename Cplx<T>:
         double2 v = zero2();
         for (int q = 0; q < m; ++q) {
             const double cr = sc.coef[2 * q], ci = sc.coef[2 * q + 1];
-            const double2 b = ldc(basis_vec((const typename Cplx<T>::type*)psi, basis, stride, q), k);
+            const double2 b = ldc(basis_vec(cview(psi), basis, stride, q), k);
             v.x = fma(cr, b.x, fma(-ci, b.y, v.x));
             v.y = fma(cr, b.y, fma(ci, b.x, v.y));
         }
@@ -431,16 +436,34 @@ k_lz_recombine(SweepGeom g, typename Cplx<T>::type* psi, const typename Cplx<T>:
 }
 
 // ---------------------------------------------------------------------------
+// Launchers.  The basis vectors 1..m-1 start at `basis`, vec_stride elements
+// apart (with s48 storage, vec_stride is the plane length and the m - 1
+// vectors are stored plane by plane, see basis_vec).
+template <typename T>
+static typename Stor<T>::aptr basis_ptr(const SweepGeom& g, const void* basis, int64_t vec_stride, int m)
+{
+    if constexpr (std::is_same<T, s48>::value) {
+        char* b = static_cast<char*>(const_cast<void*>(basis));
+        return P48{reinterpret_cast<uint2*>(b), reinterpret_cast<unsigned*>(b + 8 * vec_stride * (int64_t)max(m - 1, 0))};
+    } else {
+        (void)g, (void)vec_stride, (void)m;
+        return static_cast<typename Cplx<T>::type*>(const_cast<void*>(basis));
+    }
+}
+
+template <typename T>
+static hipError_t lz_norm_t(const SweepGeom& g, const void* psi, double* partial, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_lz_norm<T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(psi, g.plane),
+                       partial);
+    return hipGetLastError();
+}
 hipError_t launch_lz_norm(int prec, const SweepGeom& g, const void* psi, double* partial,
                           hipStream_t st)
 {
-    if (prec == 0)
-        hipLaunchKernelGGL((k_lz_norm<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const double2*>(psi), partial);
-    else
-        hipLaunchKernelGGL((k_lz_norm<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const float2*>(psi), partial);
-    return hipGetLastError();
+    if (prec == 0) return lz_norm_t<double>(g, psi, partial, st);
+    if (prec == 2) return lz_norm_t<s48>(g, psi, partial, st);
+    return lz_norm_t<float>(g, psi, partial, st);
 }
 
 hipError_t launch_lz_norm_finish(const SweepGeom& g, const double* partial, LanczosScalars* sc,
@@ -455,10 +478,9 @@ static hipError_t sweep_a_t(const SweepGeom& g, int j, int m, const void* psi, c
                             int64_t stride, void* w, const double* step, const LanczosScalars* sc,
                             double* partial, hipStream_t st)
 {
-    using C = typename Cplx<T>::type;
     hipLaunchKernelGGL((k_lz_sweep_a<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j, m,
-                       static_cast<const C*>(psi), static_cast<const C*>(basis), stride,
-                       static_cast<C*>(w), step, sc, partial);
+                       Stor<T>::cmake(psi, g.plane), basis_ptr<T>(g, basis, stride, m), stride,
+                       Stor<T>::make(w, g.plane), step, sc, partial);
     return hipGetLastError();
 }
 
@@ -469,6 +491,9 @@ hipError_t launch_lz_sweep_a(int prec, int S, const SweepGeom& g, int j, int m, 
     if (prec == 0)
         return S == 1 ? sweep_a_t<1, double>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st)
                       : sweep_a_t<2, double>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st);
+    if (prec == 2)
+        return S == 1 ? sweep_a_t<1, s48>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st)
+                      : sweep_a_t<2, s48>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st);
     return S == 1 ? sweep_a_t<1, float>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st)
                   : sweep_a_t<2, float>(g, j, m, psi, basis, vec_stride, w, step, sc, partial, st);
 }
@@ -481,21 +506,21 @@ hipError_t launch_lz_finish_a(const SweepGeom& g, int j, int m, const double* pa
     return hipGetLastError();
 }
 
-hipError_t launch_lz_sweep_b(int prec, const SweepGeom& g, int j, const void* psi,
+template <typename T>
+static hipError_t sweep_b_t(const SweepGeom& g, int j, int m, const void* psi, const void* basis, int64_t stride,
+                            const void* w, const LanczosScalars* sc, double* partial, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_lz_sweep_b<T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j, Stor<T>::cmake(psi, g.plane),
+                       basis_ptr<T>(g, basis, stride, m), stride, Stor<T>::cmake(w, g.plane), sc, partial);
+    return hipGetLastError();
+}
+hipError_t launch_lz_sweep_b(int prec, const SweepGeom& g, int j, int m, const void* psi,
                              const void* basis, int64_t vec_stride, const void* w,
                              const LanczosScalars* sc, double* partial, hipStream_t st)
 {
-    if (prec == 0)
-        hipLaunchKernelGGL((k_lz_sweep_b<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j,
-                           static_cast<const double2*>(psi),
-                           static_cast<double2*>(const_cast<void*>(basis)), vec_stride,
-                           static_cast<const double2*>(w), sc, partial);
-    else
-        hipLaunchKernelGGL((k_lz_sweep_b<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j,
-                           static_cast<const float2*>(psi),
-                           static_cast<float2*>(const_cast<void*>(basis)), vec_stride,
-                           static_cast<const float2*>(w), sc, partial);
-    return hipGetLastError();
+    if (prec == 0) return sweep_b_t<double>(g, j, m, psi, basis, vec_stride, w, sc, partial, st);
+    if (prec == 2) return sweep_b_t<s48>(g, j, m, psi, basis, vec_stride, w, sc, partial, st);
+    return sweep_b_t<float>(g, j, m, psi, basis, vec_stride, w, sc, partial, st);
 }
 
 hipError_t launch_lz_finish_b(const SweepGeom& g, int j, const double* partial,
@@ -524,19 +549,20 @@ hipError_t launch_lz_expm(const SweepGeom& g, const double* step, LanczosScalars
     return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t recombine_t(const SweepGeom& g, int m, void* psi, const void* basis, int64_t stride,
+                              const LanczosScalars* sc, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_lz_recombine<T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::make(psi, g.plane),
+                       basis_ptr<T>(g, basis, stride, m), stride, sc);
+    return hipGetLastError();
+}
 hipError_t launch_lz_recombine(int prec, const SweepGeom& g, int m, void* psi, const void* basis,
                                int64_t vec_stride, const LanczosScalars* sc, hipStream_t st)
 {
-    (void)m;
-    if (prec == 0)
-        hipLaunchKernelGGL((k_lz_recombine<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<double2*>(psi), static_cast<const double2*>(basis),
-                           vec_stride, sc);
-    else
-        hipLaunchKernelGGL((k_lz_recombine<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<float2*>(psi), static_cast<const float2*>(basis), vec_stride,
-                           sc);
-    return hipGetLastError();
+    if (prec == 0) return recombine_t<double>(g, m, psi, basis, vec_stride, sc, st);
+    if (prec == 2) return recombine_t<s48>(g, m, psi, basis, vec_stride, sc, st);
+    return recombine_t<float>(g, m, psi, basis, vec_stride, sc, st);
 }
 
 }  // namespace tdse

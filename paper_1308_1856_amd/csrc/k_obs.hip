@@ -12,7 +12,7 @@
 namespace tdse {
 
 template <typename T>
-__device__ __forceinline__ void obs_main(const SweepGeom& g, int t, const typename Cplx<T>::type* __restrict__ psi,
+__device__ __forceinline__ void obs_main(const SweepGeom& g, int t, typename Stor<T>::cptr psi,
                                          double* __restrict__ partial, double* lds)
 {
     const Tile I = g.tiles[t];
@@ -51,8 +51,7 @@ __device__ __forceinline__ void obs_main(const SweepGeom& g, int t, const typena
 
 template <typename T>
 __device__ __forceinline__ void obs_pop(const SweepGeom& g, int t, const double* __restrict__ radial,
-                                        const typename Cplx<T>::type* __restrict__ psi,
-                                        double* __restrict__ partial, double* lds)
+                                        typename Stor<T>::cptr psi, double* __restrict__ partial, double* lds)
 {
     const Tile I = g.tiles[t];
     const int n = I.n;
@@ -85,7 +84,7 @@ __device__ __forceinline__ void obs_pop(const SweepGeom& g, int t, const double*
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_obs_partial(SweepGeom red, SweepGeom pop, const double* __restrict__ radial,
-              const typename Cplx<T>::type* __restrict__ psi, double* __restrict__ partial_main,
+              typename Stor<T>::cptr psi, double* __restrict__ partial_main,
               double* __restrict__ partial_pop)
 {
     __shared__ double lds[(kBlock / 64) * kObsPopQ];
@@ -166,18 +165,23 @@ k_obs_finish(SweepGeom red, SweepGeom pop, const double* __restrict__ pmain,
     }
 }
 
+template <typename T>
+static hipError_t obs_partial_t(const SweepGeom& red, const SweepGeom& pop, const double* radial_tab,
+                                const void* psi, double* partial_main, double* partial_pop, hipStream_t st)
+{
+    const dim3 grid(red.n_tiles + pop.n_tiles);
+    hipLaunchKernelGGL((k_obs_partial<T>), grid, dim3(kBlock), 0, st, red, pop, radial_tab,
+                       Stor<T>::cmake(psi, red.plane), partial_main, partial_pop);
+    return hipGetLastError();
+}
+
 hipError_t launch_obs_partial(int prec, const SweepGeom& red, const SweepGeom& pop,
                               const double* radial_tab, const void* psi, double* partial_main,
                               double* partial_pop, hipStream_t st)
 {
-    const dim3 grid(red.n_tiles + pop.n_tiles);
-    if (prec == 0)
-        hipLaunchKernelGGL((k_obs_partial<double>), grid, dim3(kBlock), 0, st, red, pop, radial_tab,
-                           static_cast<const double2*>(psi), partial_main, partial_pop);
-    else
-        hipLaunchKernelGGL((k_obs_partial<float>), grid, dim3(kBlock), 0, st, red, pop, radial_tab,
-                           static_cast<const float2*>(psi), partial_main, partial_pop);
-    return hipGetLastError();
+    if (prec == 0) return obs_partial_t<double>(red, pop, radial_tab, psi, partial_main, partial_pop, st);
+    if (prec == 2) return obs_partial_t<s48>(red, pop, radial_tab, psi, partial_main, partial_pop, st);
+    return obs_partial_t<float>(red, pop, radial_tab, psi, partial_main, partial_pop, st);
 }
 
 hipError_t launch_obs_finish(const SweepGeom& red, const SweepGeom& pop, const double* partial_main,

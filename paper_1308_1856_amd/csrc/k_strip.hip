@@ -36,8 +36,21 @@ namespace tdse {
 template <typename C> __device__ __forceinline__ C zero_c();
 template <> __device__ __forceinline__ float2 zero_c<float2>() { return make_float2(0.f, 0.f); }
 template <> __device__ __forceinline__ double2 zero_c<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ __forceinline__ c48 zero_c<c48>() { return c48{0u, 0u, 0u}; }
 __device__ __forceinline__ double2 widen(float2 v) { return make_double2((double)v.x, (double)v.y); }
 __device__ __forceinline__ double2 widen(double2 v) { return v; }
+__device__ __forceinline__ double2 widen(c48 v) { return widen48(v); }
+// The all-zero row (at least max N complex FP64 values) as a row of storage
+// type T.
+template <typename T> __device__ __forceinline__ auto zero_rowt(const SweepGeom& g)
+{
+    if constexpr (std::is_same<T, s48>::value) {
+        void* z = const_cast<void*>(g.zero_row);
+        return P48{static_cast<uint2*>(z), static_cast<unsigned*>(z)};
+    } else {
+        return static_cast<const typename Cplx<T>::type*>(g.zero_row);
+    }
+}
 __device__ __forceinline__ double2 pick2(bool c, double2 a, double2 b)
 {
     return make_double2(c ? a.x : b.x, c ? a.y : b.y);
@@ -98,6 +111,14 @@ __device__ __forceinline__ float2 take(float2 v)
     asm volatile("v_mov_b32 %0, %1" : "=&v"(r.y) : "v"(v.y) : "memory");
     return r;
 }
+__device__ __forceinline__ c48 take(c48 v)
+{
+    c48 r;
+    asm volatile("v_mov_b32 %0, %1" : "=&v"(r.hx) : "v"(v.hx) : "memory");
+    asm volatile("v_mov_b32 %0, %1" : "=&v"(r.hy) : "v"(v.hy) : "memory");
+    asm volatile("v_mov_b32 %0, %1" : "=&v"(r.l) : "v"(v.l) : "memory");
+    return r;
+}
 // value of lane - d / lane + d (d = 1 or 2)
 __device__ __forceinline__ double2 lane_below(double2 v, int d)
 {
@@ -154,8 +175,8 @@ struct StripEdge {
 // iteration computes it (the same bits) without storing it.
 template <int S, typename T, int K, bool MASKED, bool APPLY = false, bool ALIGNED = false, int D = kStripDepth,
           bool OBS = false>
-__device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, const typename Cplx<T>::type* in_i,
-                                           const typename Cplx<T>::type* psi_i, typename Cplx<T>::type* out_i,
+__device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, typename Stor<T>::cptr in_i,
+                                           typename Stor<T>::cptr psi_i, typename Stor<T>::ptr out_i,
                                            int jc, bool inside, bool writes, double er, double inv_r2,
                                            double z_over_r, const double (&coef)[K], StripEdge edge = {},
                                            StripObs ob = {})
@@ -164,8 +185,9 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     static_assert(!(APPLY || ALIGNED) || K == 1, "the plain sweep and the aligned strips have one level");
     using C = typename Cplx<T>::type;
     const int n = I.n, lmax = I.lmax;
-    const C* zrow = static_cast<const C*>(g.zero_row);
-    auto rowp = [&](const C* base, int rr) -> const C* {
+    const auto zrow = zero_rowt<T>(g);
+    using RowP = decltype(zrow + 0);
+    auto rowp = [&](RowP base, int rr) -> RowP {
         return (rr >= 0 && rr <= lmax) ? base + (int64_t)rr * n : zrow;
     };
     auto widen_lane = [&](C raw) -> double2 {
@@ -232,15 +254,15 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     const int iters = max((I.l1 - I.l0) + 2 * K - 2, warm_trips_end);
     const int xhi = min(lmax, rho0 + iters + (OBS ? 1 : 0));
     const int phi = min(lmax, rho0 + iters - 1 + (OBS ? 1 : 0));
-    auto rowp_x = [&](int rr) -> const C* { return (unsigned)rr <= (unsigned)xhi ? in_i + (int64_t)rr * n : zrow; };
-    auto rowp_p = [&](int rr) -> const C* { return (unsigned)rr <= (unsigned)phi ? psi_i + (int64_t)rr * n : zrow; };
+    auto rowp_x = [&](int rr) -> RowP { return (unsigned)rr <= (unsigned)xhi ? in_i + (int64_t)rr * n : zrow; };
+    auto rowp_p = [&](int rr) -> RowP { return (unsigned)rr <= (unsigned)phi ? psi_i + (int64_t)rr * n : zrow; };
     struct Slot {
         C x, p, x1, x2;   // x1, x2: row rho+1 beyond the wave ends (ALIGNED)
     };
     Slot sl[D];
 #pragma unroll
     for (int u = 0; u < D; ++u) {
-        const C* xr = rowp_x(rho0 + 1 + u);
+        const RowP xr = rowp_x(rho0 + 1 + u);
         sl[u] = Slot{xr[jc], APPLY ? zero_c<C>() : rowp_p(rho0 + u)[jc], ALIGNED ? xr[edge.e1] : zero_c<C>(),
                      ALIGNED && S == 2 ? xr[edge.e2] : zero_c<C>()};
     }
@@ -276,8 +298,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
     auto obs_row = [&](double2 v, int rk, auto check) {
         if (!OBS) return;
         constexpr bool CHECK = decltype(check)::value;
-        double2 vs = v;
-        if (std::is_same<T, float>::value) vs = make_double2((double)(float)v.x, (double)(float)v.y);
+        const double2 vs = stored_value<T>(v);
         if (!CHECK || rk <= I.l1) {             // the pair (rk - 1, rk) is the tile's
             const double re = fma(fprev.x, vs.x, fprev.y * vs.y) * kq[K];
             oacc[2] = fma(ob.r, re, oacc[2]);
@@ -300,7 +321,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
         const C po = APPLY ? zero_c<C>() : take(sl.p);
         const C xo1 = ALIGNED ? take(sl.x1) : zero_c<C>();
         const C xo2 = ALIGNED && S == 2 ? take(sl.x2) : zero_c<C>();
-        const C* xr = (unsigned)(rho + 1 + D) <= (unsigned)xhi ? in_i + ox : zrow;
+        const RowP xr = (unsigned)(rho + 1 + D) <= (unsigned)xhi ? in_i + ox : zrow;
         sl.x = xr[jc];
         if (!APPLY) sl.p = ((unsigned)(rho + D) <= (unsigned)phi ? psi_i + op : zrow)[jc];
         if (ALIGNED) sl.x1 = xr[edge.e1];
@@ -392,8 +413,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, co
 
 template <int S, typename T, int K, bool OBS>
 __global__ void __launch_bounds__(kBlock)
-k_horner_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
-               const typename Cplx<T>::type* __restrict__ psi, typename Cplx<T>::type* __restrict__ out,
+k_horner_strip(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typename Stor<T>::ptr out,
                const double* __restrict__ step, int first_term, double* __restrict__ obs_partial)
 {
     const int halo = g.variant * S;             // >= K * S: lanes lost per side after K levels
@@ -418,9 +438,9 @@ k_horner_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
 #pragma unroll
     for (int k = 0; k < K; ++k) coef[k] = wave_uniform(dt / (double)(first_term - k));
 
-    const auto* in_i = in + I.off;
-    const auto* psi_i = psi + I.off;
-    auto* out_i = out + I.off;
+    const auto in_i = in + I.off;
+    const auto psi_i = psi + I.off;
+    const auto out_i = out + I.off;
     StripObs ob;
     if (OBS) {
         ob.partial = obs_partial;
@@ -442,14 +462,13 @@ template <int S, typename T, int K>
 static hipError_t strip_t(const SweepGeom& g, const void* in, const void* psi, void* out,
                           const double* step, int first_term, double* obs_partial, hipStream_t st)
 {
-    using C = typename Cplx<T>::type;
     if (obs_partial)
         hipLaunchKernelGGL((k_horner_strip<S, T, K, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                           Stor<T>::cmake(in, g.plane), Stor<T>::cmake(psi, g.plane), Stor<T>::make(out, g.plane),
                            step, first_term, obs_partial);
     else
         hipLaunchKernelGGL((k_horner_strip<S, T, K, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                           Stor<T>::cmake(in, g.plane), Stor<T>::cmake(psi, g.plane), Stor<T>::make(out, g.plane),
                            step, first_term, obs_partial);
     return hipGetLastError();
 }
@@ -477,6 +496,8 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
 {
     if (prec == 0) return S == 1 ? strip_k<1, double>(K, g, in, psi, out, step, first_term, obs_partial, st)
                                  : strip_k<2, double>(K, g, in, psi, out, step, first_term, obs_partial, st);
+    if (prec == 2) return S == 1 ? strip_k<1, s48>(K, g, in, psi, out, step, first_term, obs_partial, st)
+                                 : strip_k<2, s48>(K, g, in, psi, out, step, first_term, obs_partial, st);
     return S == 1 ? strip_k<1, float>(K, g, in, psi, out, step, first_term, obs_partial, st)
                   : strip_k<2, float>(K, g, in, psi, out, step, first_term, obs_partial, st);
 }
@@ -489,8 +510,7 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
 // those of the workgroup sweeps of k_sweep.hip, bit for bit.
 template <int S, typename T, bool APPLY>
 __global__ void __launch_bounds__(kBlock)
-k_sweep_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
-              const typename Cplx<T>::type* __restrict__ psi, typename Cplx<T>::type* __restrict__ out,
+k_sweep_strip(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typename Stor<T>::ptr out,
               const double* __restrict__ step, int term)
 {
     const Tile I = my_tile(g);
@@ -517,9 +537,9 @@ k_sweep_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
     const double z_over_r = I.z * inv_r;
     const double er = step_value(step, g.n_inst, kEMid, I.inst) * r;
     const double coef[1] = {APPLY ? 0.0 : wave_uniform(step_value(step, g.n_inst, kDt, I.inst) / (double)term)};
-    const auto* in_i = in + I.off;
-    const auto* psi_i = psi + I.off;
-    auto* out_i = out + I.off;
+    const auto in_i = in + I.off;
+    const auto psi_i = psi + I.off;
+    const auto out_i = out + I.off;
     if (j0 - S >= 0 && j0 + 63 + S < n)   // wave-uniform: every value the wave reads is inside
         strip_loop<S, T, 1, false, APPLY, true>(g, I, in_i, psi_i, out_i, jc, inside, inside, er, inv_r2, z_over_r,
                                                 coef, edge);
@@ -532,13 +552,14 @@ template <int S, typename T>
 static hipError_t sweep_strip_t(const SweepGeom& g, const void* in, const void* psi, void* out, const double* step,
                                 int term, hipStream_t st)
 {
-    using C = typename Cplx<T>::type;
     if (term == 0)
         hipLaunchKernelGGL((k_sweep_strip<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const C*>(in), static_cast<const C*>(in), static_cast<C*>(out), step, term);
+                           Stor<T>::cmake(in, g.plane), Stor<T>::cmake(in, g.plane), Stor<T>::make(out, g.plane), step,
+                           term);
     else
         hipLaunchKernelGGL((k_sweep_strip<S, T, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out), step, term);
+                           Stor<T>::cmake(in, g.plane), Stor<T>::cmake(psi, g.plane), Stor<T>::make(out, g.plane), step,
+                           term);
     return hipGetLastError();
 }
 
@@ -548,6 +569,8 @@ hipError_t launch_strip_sweep(int prec, int S, const SweepGeom& g, const void* i
     if (g.variant != 1 || term < 0) return hipErrorInvalidValue;   // aligned tiles of one level
     if (prec == 0) return S == 1 ? sweep_strip_t<1, double>(g, in, psi, out, step, term, st)
                                  : sweep_strip_t<2, double>(g, in, psi, out, step, term, st);
+    if (prec == 2) return S == 1 ? sweep_strip_t<1, s48>(g, in, psi, out, step, term, st)
+                                 : sweep_strip_t<2, s48>(g, in, psi, out, step, term, st);
     return S == 1 ? sweep_strip_t<1, float>(g, in, psi, out, step, term, st)
                   : sweep_strip_t<2, float>(g, in, psi, out, step, term, st);
 }
@@ -569,15 +592,16 @@ hipError_t launch_strip_sweep(int prec, int S, const SweepGeom& g, const void* i
 // FP32 storage g and acc stay FP64 between stages.  HBM traffic per unknown
 // and step: read psi, write psi' (2c, against 16c for the stage launches).
 template <int S, typename T, bool MASKED>
-__device__ __forceinline__ void rk4_strip_loop(const SweepGeom& g, const Tile& I, const typename Cplx<T>::type* in_i,
-                                               typename Cplx<T>::type* out_i, int jc, bool inside, bool writes,
+__device__ __forceinline__ void rk4_strip_loop(const SweepGeom& g, const Tile& I, typename Stor<T>::cptr in_i,
+                                               typename Stor<T>::ptr out_i, int jc, bool inside, bool writes,
                                                const double (&er)[4], double inv_r2, double z_over_r, double dt)
 {
     using C = typename Cplx<T>::type;
     constexpr int K = 4;
     const int n = I.n, lmax = I.lmax;
-    const C* zrow = static_cast<const C*>(g.zero_row);
-    auto rowp = [&](const C* base, int rr) -> const C* {
+    const auto zrow = zero_rowt<T>(g);
+    using RowP = decltype(zrow + 0);
+    auto rowp = [&](RowP base, int rr) -> RowP {
         return (rr >= 0 && rr <= lmax) ? base + (int64_t)rr * n : zrow;
     };
     auto widen_lane = [&](C raw) -> double2 {
@@ -697,8 +721,7 @@ __device__ __forceinline__ void rk4_strip_loop(const SweepGeom& g, const Tile& I
 
 template <int S, typename T>
 __global__ void __launch_bounds__(kBlock)
-k_rk4_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in, typename Cplx<T>::type* __restrict__ out,
-            const double* __restrict__ step)
+k_rk4_strip(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::ptr out, const double* __restrict__ step)
 {
     const int halo = g.variant * S;             // = 4 S: lanes lost per side after the four stages
     const int valid = 64 - 2 * halo;
@@ -721,34 +744,29 @@ k_rk4_strip(SweepGeom g, const typename Cplx<T>::type* __restrict__ in, typename
                           step_value(step, g.n_inst, kEEnd, I.inst) * r};
     const double dt = step_value(step, g.n_inst, kDt, I.inst);
 
-    const auto* in_i = in + I.off;
-    auto* out_i = out + I.off;
+    const auto in_i = in + I.off;
+    const auto out_i = out + I.off;
     if (j0 >= 0 && j0 + 63 < n)   // wave-uniform
         rk4_strip_loop<S, T, false>(g, I, in_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, dt);
     else
         rk4_strip_loop<S, T, true>(g, I, in_i, out_i, jc, inside, writes, er, inv_r2, z_over_r, dt);
 }
 
+template <int S, typename T>
+static hipError_t rk4_strip_t(const SweepGeom& g, const void* in, void* out, const double* step, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rk4_strip<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(in, g.plane),
+                       Stor<T>::make(out, g.plane), step);
+    return hipGetLastError();
+}
+
 hipError_t launch_rk4_strip(int prec, int S, const SweepGeom& g, const void* in, void* out, const double* step,
                             hipStream_t st)
 {
     if (g.variant != 4) return hipErrorInvalidValue;   // tiles built for the four stages
-    if (prec == 0) {
-        if (S == 1)
-            hipLaunchKernelGGL((k_rk4_strip<1, double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                               static_cast<const double2*>(in), static_cast<double2*>(out), step);
-        else
-            hipLaunchKernelGGL((k_rk4_strip<2, double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                               static_cast<const double2*>(in), static_cast<double2*>(out), step);
-    } else {
-        if (S == 1)
-            hipLaunchKernelGGL((k_rk4_strip<1, float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                               static_cast<const float2*>(in), static_cast<float2*>(out), step);
-        else
-            hipLaunchKernelGGL((k_rk4_strip<2, float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                               static_cast<const float2*>(in), static_cast<float2*>(out), step);
-    }
-    return hipGetLastError();
+    if (prec == 0) return S == 1 ? rk4_strip_t<1, double>(g, in, out, step, st) : rk4_strip_t<2, double>(g, in, out, step, st);
+    if (prec == 2) return S == 1 ? rk4_strip_t<1, s48>(g, in, out, step, st) : rk4_strip_t<2, s48>(g, in, out, step, st);
+    return S == 1 ? rk4_strip_t<1, float>(g, in, out, step, st) : rk4_strip_t<2, float>(g, in, out, step, st);
 }
 
 }  // namespace tdse

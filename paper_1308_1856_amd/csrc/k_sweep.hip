@@ -22,17 +22,17 @@
 //                  to keep the register count (and so the occupancy) up.
 // Both evaluate H through h_point and the term through horner_update, so
 // they agree bit for bit.
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace tdse {
 
 template <int S, typename T>
 __global__ void __launch_bounds__(kBlock)
-k_hsweep(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
-         const typename Cplx<T>::type* __restrict__ psi, typename Cplx<T>::type* __restrict__ out,
+k_hsweep(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typename Stor<T>::ptr out,
          const double* __restrict__ step, int term)
 {
-    using C = typename Cplx<T>::type;
     const Tile I = my_tile(g);
     const int n = I.n;
     const int i = I.r0 + (int)threadIdx.x;
@@ -46,7 +46,7 @@ k_hsweep(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
     for (int l = I.l0; l < I.l1; ++l) {
         const int64_t row = base + (int64_t)l * n;
         const double2 next = (l < I.lmax) ? ldc(in, row + n + i) : zero2();
-        Neighbours<S, C> nb;
+        Neighbours<S> nb;
         nb.load(in + row, i, n);
         const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
         const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
@@ -198,11 +198,9 @@ k_hsweep_pair(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
 // H is taken at t_n (stage 0), t_n + dt/2 (stages 1, 2) and t_n + dt (stage 3).
 template <int S, typename T, int STAGE>
 __global__ void __launch_bounds__(kBlock)
-k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
-            typename Cplx<T>::type* psi, typename Cplx<T>::type* acc,
-            typename Cplx<T>::type* __restrict__ gout, const double* __restrict__ step)
+k_rk4_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::aptr psi, typename Stor<T>::aptr acc,
+            typename Stor<T>::ptr gout, const double* __restrict__ step)
 {
-    using C = typename Cplx<T>::type;
     const Tile I = my_tile(g);
     const int n = I.n;
     const int i = I.r0 + (int)threadIdx.x;
@@ -220,11 +218,11 @@ k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
     // software pipeline: row l + 1's loads go out before row l
     // is stored (acc and psi are read and written only at a thread's own
     // elements, one row apart)
-    const C* row0 = gin + base + (int64_t)I.l0 * n;
+    const auto row0 = gin + base + (int64_t)I.l0 * n;
     double2 prev = (I.l0 > 0) ? ldc(row0 - n, i) : zero2();
     double2 cur = ldc(row0, i);
     double2 next = (I.l0 < I.lmax) ? ldc(row0 + n, i) : zero2();
-    Neighbours<S, C> nb;
+    Neighbours<S> nb;
     nb.load(row0, i, n);
     double2 a = kReadAcc ? ldc(acc, base + (int64_t)I.l0 * n + i) : zero2();
     double2 p = kReadPsi ? ldc(psi, base + (int64_t)I.l0 * n + i) : zero2();
@@ -232,7 +230,7 @@ k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
         const int64_t row = base + (int64_t)l * n;
         const bool more = l + 1 < I.l1;
         const double2 next2 = (l + 2 <= I.lmax) ? ldc(gin, row + 2 * n + i) : zero2();
-        Neighbours<S, C> nb_next;
+        Neighbours<S> nb_next;
         if (more) nb_next.load(gin + row + n, i, n);
         const double2 a_next = (kReadAcc && more) ? ldc(acc, row + n + i) : zero2();
         const double2 p_next = (kReadPsi && more) ? ldc(psi, row + n + i) : zero2();
@@ -259,16 +257,24 @@ k_rk4_stage(SweepGeom g, const typename Cplx<T>::type* __restrict__ gin,
     }
 }
 
+__device__ __forceinline__ void copy_elem(const double2* src, double2* dst, int64_t k) { dst[k] = src[k]; }
+__device__ __forceinline__ void copy_elem(const float2* src, float2* dst, int64_t k) { dst[k] = src[k]; }
+__device__ __forceinline__ void copy_elem(P48 src, P48 dst, int64_t k)
+{
+    dst.h[k] = src.h[k];
+    dst.l[k] = src.l[k];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_copy(SweepGeom g, const typename Cplx<T>::type* __restrict__ src, typename Cplx<T>::type* __restrict__ dst)
+k_copy(SweepGeom g, typename Stor<T>::cptr src, typename Stor<T>::ptr dst)
 {
     const Tile I = my_tile(g);
     const int i = I.r0 + (int)threadIdx.x;
     if (i >= I.n) return;
     for (int l = I.l0; l < I.l1; ++l) {
         const int64_t k = I.off + (int64_t)l * I.n + i;
-        dst[k] = src[k];
+        copy_elem(src, dst, k);
     }
 }
 
@@ -281,12 +287,12 @@ __device__ __forceinline__ bool bits_differ(float2 a, float2 b)
 {
     return __float_as_uint(a.x) != __float_as_uint(b.x) || __float_as_uint(a.y) != __float_as_uint(b.y);
 }
+__device__ __forceinline__ bool bits_differ(c48 a, c48 b) { return a.hx != b.hx || a.hy != b.hy || a.l != b.l; }
 
 // Counts elements (over the tiles of g) whose stored values differ bit for bit.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_count_diff(SweepGeom g, const typename Cplx<T>::type* __restrict__ a,
-             const typename Cplx<T>::type* __restrict__ b, unsigned int* __restrict__ count)
+k_count_diff(SweepGeom g, typename Stor<T>::cptr a, typename Stor<T>::cptr b, unsigned int* __restrict__ count)
 {
     const Tile I = my_tile(g);
     const int i = I.r0 + (int)threadIdx.x;
@@ -302,8 +308,7 @@ k_count_diff(SweepGeom g, const typename Cplx<T>::type* __restrict__ a,
 // out[0] += sum |a - b|^2, out[1] += sum |b|^2 over the tiles of g (FP64).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_diff_norm(SweepGeom g, const typename Cplx<T>::type* __restrict__ a,
-            const typename Cplx<T>::type* __restrict__ b, double* __restrict__ out)
+k_diff_norm(SweepGeom g, typename Stor<T>::cptr a, typename Stor<T>::cptr b, double* __restrict__ out)
 {
     __shared__ double lds[(kBlock / 64) * 2];
     const Tile I = my_tile(g);
@@ -330,18 +335,21 @@ static hipError_t hsweep_t(const SweepGeom& g, const void* in, const void* psi, 
                            const double* step, int term, hipStream_t st)
 {
     using C = typename Cplx<T>::type;
-    if (g.variant == 1 && term > 0)
-        hipLaunchKernelGGL((k_hsweep_pair<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
-                           step, term);
-    else if (g.variant == 1)
-        hipLaunchKernelGGL((k_hsweep_pair<S, T, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
-                           step, term);
-    else
-        hipLaunchKernelGGL((k_hsweep<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
-                           step, term);
+    if constexpr (std::is_same<T, s48>::value) {
+        if (g.variant == 1) return hipErrorInvalidValue;   // two-radii sweeps: FP64 and FP32 storage only
+    } else {
+        if (g.variant == 1 && term > 0)
+            hipLaunchKernelGGL((k_hsweep_pair<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                               step, term);
+        else if (g.variant == 1)
+            hipLaunchKernelGGL((k_hsweep_pair<S, T, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                               static_cast<const C*>(in), static_cast<const C*>(psi), static_cast<C*>(out),
+                               step, term);
+        if (g.variant == 1) return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_hsweep<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(in, g.plane),
+                       Stor<T>::cmake(psi, g.plane), Stor<T>::make(out, g.plane), step, term);
     return hipGetLastError();
 }
 
@@ -351,6 +359,8 @@ hipError_t launch_hsweep(int prec, int S, const SweepGeom& g, const void* in, co
     if (g.set == kApplyTiles) return launch_strip_sweep(prec, S, g, in, psi, out, step, term, st);
     if (prec == 0) return S == 1 ? hsweep_t<1, double>(g, in, psi, out, step, term, st)
                                  : hsweep_t<2, double>(g, in, psi, out, step, term, st);
+    if (prec == 2) return S == 1 ? hsweep_t<1, s48>(g, in, psi, out, step, term, st)
+                                 : hsweep_t<2, s48>(g, in, psi, out, step, term, st);
     return S == 1 ? hsweep_t<1, float>(g, in, psi, out, step, term, st)
                   : hsweep_t<2, float>(g, in, psi, out, step, term, st);
 }
@@ -359,10 +369,9 @@ template <int S, typename T, int STAGE>
 static hipError_t rk4_t(const SweepGeom& g, const void* gin, const void* psi, void* acc, void* gout,
                         const double* step, hipStream_t st)
 {
-    using C = typename Cplx<T>::type;
     hipLaunchKernelGGL((k_rk4_stage<S, T, STAGE>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                       static_cast<const C*>(gin), static_cast<C*>(const_cast<void*>(psi)),
-                       static_cast<C*>(acc), static_cast<C*>(gout), step);
+                       Stor<T>::cmake(gin, g.plane), Stor<T>::make(const_cast<void*>(psi), g.plane),
+                       Stor<T>::make(acc, g.plane), Stor<T>::make(gout, g.plane), step);
     return hipGetLastError();
 }
 
@@ -384,43 +393,55 @@ hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, cons
 {
     if (prec == 0) return S == 1 ? rk4_s<1, double>(g, stage, gin, psi, acc, gout, step, st)
                                  : rk4_s<2, double>(g, stage, gin, psi, acc, gout, step, st);
+    if (prec == 2) return S == 1 ? rk4_s<1, s48>(g, stage, gin, psi, acc, gout, step, st)
+                                 : rk4_s<2, s48>(g, stage, gin, psi, acc, gout, step, st);
     return S == 1 ? rk4_s<1, float>(g, stage, gin, psi, acc, gout, step, st)
                   : rk4_s<2, float>(g, stage, gin, psi, acc, gout, step, st);
 }
 
+template <typename T>
+static hipError_t count_diff_t(const SweepGeom& g, const void* a, const void* b, unsigned int* count,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL((k_count_diff<T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(a, g.plane),
+                       Stor<T>::cmake(b, g.plane), count);
+    return hipGetLastError();
+}
 hipError_t launch_count_diff(int prec, const SweepGeom& g, const void* a, const void* b,
                              unsigned int* count, hipStream_t st)
 {
-    if (prec == 0)
-        hipLaunchKernelGGL((k_count_diff<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const double2*>(a), static_cast<const double2*>(b), count);
-    else
-        hipLaunchKernelGGL((k_count_diff<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const float2*>(a), static_cast<const float2*>(b), count);
-    return hipGetLastError();
+    if (prec == 0) return count_diff_t<double>(g, a, b, count, st);
+    if (prec == 2) return count_diff_t<s48>(g, a, b, count, st);
+    return count_diff_t<float>(g, a, b, count, st);
 }
 
+template <typename T>
+static hipError_t diff_norm_t(const SweepGeom& g, const void* a, const void* b, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_diff_norm<T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(a, g.plane),
+                       Stor<T>::cmake(b, g.plane), out);
+    return hipGetLastError();
+}
 hipError_t launch_diff_norm(int prec, const SweepGeom& g, const void* a, const void* b, double* out,
                             hipStream_t st)
 {
-    if (prec == 0)
-        hipLaunchKernelGGL((k_diff_norm<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const double2*>(a), static_cast<const double2*>(b), out);
-    else
-        hipLaunchKernelGGL((k_diff_norm<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const float2*>(a), static_cast<const float2*>(b), out);
-    return hipGetLastError();
+    if (prec == 0) return diff_norm_t<double>(g, a, b, out, st);
+    if (prec == 2) return diff_norm_t<s48>(g, a, b, out, st);
+    return diff_norm_t<float>(g, a, b, out, st);
 }
 
+template <typename T>
+static hipError_t copy_t(const SweepGeom& g, const void* src, void* dst, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_copy<T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(src, g.plane),
+                       Stor<T>::make(dst, g.plane));
+    return hipGetLastError();
+}
 hipError_t launch_copy(int prec, const SweepGeom& g, const void* src, void* dst, hipStream_t st)
 {
-    if (prec == 0)
-        hipLaunchKernelGGL((k_copy<double>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const double2*>(src), static_cast<double2*>(dst));
-    else
-        hipLaunchKernelGGL((k_copy<float>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                           static_cast<const float2*>(src), static_cast<float2*>(dst));
-    return hipGetLastError();
+    if (prec == 0) return copy_t<double>(g, src, dst, st);
+    if (prec == 2) return copy_t<s48>(g, src, dst, st);
+    return copy_t<float>(g, src, dst, st);
 }
 
 }  // namespace tdse

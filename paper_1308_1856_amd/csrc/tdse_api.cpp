@@ -127,6 +127,7 @@ struct tdse_ctx {
         g.set = set;
         g.variant = 0;
         g.order = 0;
+        g.plane = plane();
         return g;
     }
     // geometry of the H sweeps (apply_H, Taylor terms) in the tuned shape
@@ -145,7 +146,14 @@ struct tdse_ctx {
     double* d_radial() const { return reinterpret_cast<double*>(d_work + off_radial); }
     LanczosScalars* d_lz() const { return reinterpret_cast<LanczosScalars*>(d_work + off_lz); }
     char* d_vec(int k) const { return d_work + off_vecs + (size_t)k * state_bytes(); }
-    size_t state_bytes() const { return align_up((size_t)state_elems * elem, kAlign); }
+    // elements per plane of a state-shaped vector with 48-bit storage (its
+    // plane h then takes 8 * plane bytes, a multiple of 256, plane l 4 * plane)
+    int64_t plane() const { return (int64_t)align_up((size_t)state_elems, 64); }
+    size_t state_bytes() const
+    {
+        if (prec == TDSE_FP48) return 12 * (size_t)plane();
+        return align_up((size_t)state_elems * elem, kAlign);
+    }
     size_t vecs_needed(int method, int order_or_m) const
     {
         if (method == TDSE_METHOD_TAYLOR) return 2;
@@ -431,14 +439,14 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     for (int k = 0; k < n_inst; ++k) {
         const tdse_grid_desc& g = grids[k];
         if (g.n_r < 8 || g.n_r > (1 << 26) || g.lmax < 0 || g.lmax > 1023 ||
-            (g.stencil != 3 && g.stencil != 5) || (g.precision != TDSE_FP64 && g.precision != TDSE_FP32) ||
+            (g.stencil != 3 && g.stencil != 5) || (g.precision != TDSE_FP64 && g.precision != TDSE_FP32 && g.precision != TDSE_FP48) ||
             !(g.dr > 0.0) || !(g.z_nuc > 0.0) || !std::isfinite(g.r_ion) || g.stencil != c->stencil ||
             g.precision != c->prec) {
             delete c;
             return TDSE_E_INVALID;
         }
     }
-    c->elem = (c->prec == TDSE_FP64) ? 16 : 8;
+    c->elem = (c->prec == TDSE_FP64) ? 16 : (c->prec == TDSE_FP48) ? 12 : 8;
     // instance table, offsets aligned to 64 elements
     int lmax_all = 0;
     int64_t off = 0, tab = 0;
@@ -714,6 +722,24 @@ extern "C" tdse_status tdse_set_state(tdse_ctx* c, int32_t k, const double* host
     char* dst = c->d_state + (size_t)I.off * c->elem;
     if (c->prec == TDSE_FP64) {
         e = hipMemcpyAsync(dst, host, cnt * 16, hipMemcpyHostToDevice, c->stream);
+    } else if (c->prec == TDSE_FP48) {
+        // plane h: upper words of (re, im); plane l: the next 16 bits of
+        // each, rounded to nearest (ties away from zero) as the kernels store
+        std::vector<uint32_t> h(2 * cnt), l(cnt);
+        for (size_t j = 0; j < cnt; ++j) {
+            uint64_t a, b;
+            std::memcpy(&a, host + 2 * j, 8);
+            std::memcpy(&b, host + 2 * j + 1, 8);
+            a += 0x8000u;
+            b += 0x8000u;
+            h[2 * j] = (uint32_t)(a >> 32);
+            h[2 * j + 1] = (uint32_t)(b >> 32);
+            l[j] = ((uint32_t)a >> 16) | ((uint32_t)b & 0xffff0000u);
+        }
+        char* dl = c->d_state + 8 * (size_t)c->plane() + 4 * (size_t)I.off;
+        e = hipMemcpyAsync(c->d_state + 8 * (size_t)I.off, h.data(), cnt * 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dl, l.data(), cnt * 4, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     } else {
         std::vector<float> f(2 * cnt);
         for (size_t j = 0; j < 2 * cnt; ++j) f[j] = (float)host[j];
@@ -736,6 +762,19 @@ extern "C" tdse_status tdse_get_state(tdse_ctx* c, int32_t k, double* host)
     if (c->prec == TDSE_FP64) {
         e = hipMemcpyAsync(host, src, cnt * 16, hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    } else if (c->prec == TDSE_FP48) {
+        std::vector<uint32_t> h(2 * cnt), l(cnt);
+        e = hipMemcpyAsync(h.data(), c->d_state + 8 * (size_t)I.off, cnt * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(l.data(), c->d_state + 8 * (size_t)c->plane() + 4 * (size_t)I.off, cnt * 4,
+                               hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        for (size_t j = 0; j < cnt; ++j) {
+            const uint64_t a = ((uint64_t)h[2 * j] << 32) | (uint64_t)(l[j] << 16);
+            const uint64_t b = ((uint64_t)h[2 * j + 1] << 32) | (uint64_t)(l[j] & 0xffff0000u);
+            std::memcpy(host + 2 * j, &a, 8);
+            std::memcpy(host + 2 * j + 1, &b, 8);
+        }
     } else {
         std::vector<float> f(2 * cnt);
         e = hipMemcpyAsync(f.data(), src, cnt * 8, hipMemcpyDeviceToHost, c->stream);
@@ -1063,7 +1102,7 @@ extern "C" tdse_status tdse_apply_H(tdse_ctx* c, const double* e_field, const vo
     if (!e_field || !d_in || !d_out) return c->fail(TDSE_E_INVALID, "tdse_apply_H: null argument");
     const char* a = static_cast<const char*>(d_in);
     const char* b = static_cast<const char*>(d_out);
-    const size_t nb = (size_t)c->state_elems * c->elem;
+    const size_t nb = c->state_bytes();
     if (a < b + nb && b < a + nb) return c->fail(TDSE_E_INVALID, "tdse_apply_H: in and out overlap");
     std::vector<tdse_pulse> none(c->n_inst);
     std::vector<double> zero(c->n_inst, 0.0), one(c->n_inst, 1.0);
@@ -1162,7 +1201,9 @@ extern "C" tdse_status tdse_step_lanczos(tdse_ctx* c, const tdse_pulse* pulses, 
     void* psi = c->d_state;
     void* w = c->d_vec(0);
     void* basis = c->d_vec(1);  // vectors 1..m-1
-    const int64_t stride = (int64_t)(c->state_bytes() / c->elem);
+    // element distance of consecutive basis vectors (48-bit storage: the
+    // basis vectors are stored plane by plane, one plane length apart)
+    const int64_t stride = (c->prec == TDSE_FP48) ? c->plane() : (int64_t)(c->state_bytes() / c->elem);
     LanczosScalars* sc = c->d_lz();
     double* part = c->d_partial();
     void* cur = psi;
@@ -1180,7 +1221,7 @@ extern "C" tdse_status tdse_step_lanczos(tdse_ctx* c, const tdse_pulse* pulses, 
             }
             if (e == hipSuccess) e = launch_lz_finish_a(g, j, m, part, sc, c->stream);
             if (j + 1 < m) {
-                if (e == hipSuccess) e = launch_lz_sweep_b(c->prec, g, j, psi, basis, stride, w, sc, part, c->stream);
+                if (e == hipSuccess) e = launch_lz_sweep_b(c->prec, g, j, m, psi, basis, stride, w, sc, part, c->stream);
                 if (e == hipSuccess) e = launch_lz_finish_b(g, j, part, sc, c->stream);
             }
         }
@@ -1283,6 +1324,7 @@ extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
         const int variant = variants[cand / 6];
         if (e != hipSuccess) break;
         if (rows != 1 && c->total_cols / rows < 64) continue;
+        if (c->prec == TDSE_FP48 && (variant & 5) == 1) continue;   // two-radii sweeps: FP64/FP32 storage only
         c->sweep_variant = variant;
         const int set = (variant & 4) ? kApplyTiles : (variant & 1) ? kPairTiles : kSweepTiles;
         build_tiles(c, set, rows);
@@ -1391,7 +1433,8 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     struct Cand { int k, rows, kind; };
     std::vector<Cand> cands = {{0, 0, 0}};
     for (int K = 2; K <= std::min(order, (int)kMaxFused); ++K) {
-        for (int rows : {8, 16, 32}) cands.push_back({K, rows, 0});
+        if (c->prec != TDSE_FP48)   // the LDS-ring kernel has no 48-bit form
+            for (int rows : {8, 16, 32}) cands.push_back({K, rows, 0});
         for (int rows : {8, 16, 32, 64}) cands.push_back({K, rows, 1});
     }
     double best_ms = 1e300;
@@ -1416,7 +1459,10 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) break;
         const double rel = std::sqrt(h_acc[0] / std::max(h_acc[1], 1e-300));
-        const double tol = (c->prec == TDSE_FP64) ? 0.0 : 1e-6;
+        // FP64: bit for bit; otherwise the per-term step rounds every
+        // intermediate level to the storage precision, the fused launches
+        // only their outputs
+        const double tol = (c->prec == TDSE_FP64) ? 0.0 : (c->prec == TDSE_FP48) ? 1e-9 : 1e-6;
         if (!(rel <= tol)) {
             bad += " K=" + std::to_string(cd.k) + "/rows=" + std::to_string(cd.rows) + "/kind=" +
                    std::to_string(cd.kind) + ": " + std::to_string(rel);
@@ -1541,6 +1587,8 @@ extern "C" tdse_status tdse_set_taylor_fusion(tdse_ctx* c, int32_t k, int32_t ro
     if (!c) return TDSE_E_INVALID;
     if (k < 0 || k > kMaxFused || (k > 0 && (rows < 1 || rows > 64)) || kind < 0 || kind > 1)
         return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: k must be 0..8, rows 1..64, kind 0 or 1");
+    if (c->prec == TDSE_FP48 && k > 0 && kind == 0)
+        return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: the LDS-ring kernel (kind 0) has no 48-bit form");
     if (c->bound) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "tdse_set_taylor_fusion sync");
@@ -1566,6 +1614,8 @@ extern "C" tdse_status tdse_set_sweep_shape(tdse_ctx* c, int32_t rows, int32_t v
     if (!c) return TDSE_E_INVALID;
     if (rows < 1 || rows > kTileRows || variant < 0 || variant > 7)
         return c->fail(TDSE_E_INVALID, "tdse_set_sweep_shape: rows must be 1..32 and variant 0..7");
+    if (c->prec == TDSE_FP48 && (variant & 5) == 1)
+        return c->fail(TDSE_E_INVALID, "tdse_set_sweep_shape: two-radii sweeps have no 48-bit form");
     if (c->bound) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "tdse_set_sweep_shape sync");

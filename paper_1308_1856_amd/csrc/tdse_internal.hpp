@@ -66,8 +66,10 @@ struct LanczosScalars {
 };
 
 // ----------------------------------------------------------------------------
-// Launchers (defined next to their kernels).  `T` is double (FP64 storage) or
-// float (FP32 storage); `S` is the stencil half-width (1 or 2).
+// Launchers (defined next to their kernels).  `prec` is the storage precision
+// (0: FP64, 1: FP32, 2: 48-bit, see device_common.hpp); `S` is the stencil
+// half-width (1 or 2).  Launchers of kernels without a 48-bit form return
+// hipErrorInvalidValue for prec 2.
 // ----------------------------------------------------------------------------
 struct SweepGeom {
     const Inst* inst;      // device instance table
@@ -80,6 +82,7 @@ struct SweepGeom {
                            // strip sets: the level count the tiles were built for
     int32_t order;         // block -> tile map: 0 identity, 1 XCD-contiguous runs, 2 short runs dealt round the XCDs
     const void* zero_row;  // device zeros, at least max N complex FP64 values
+    int64_t plane;         // s48 storage: elements per plane of a state-shaped vector
 };
 
 // Per-step scalars, FP64, laid out [slot][instance] with these slots:
@@ -148,7 +151,8 @@ hipError_t launch_obs_finish(const SweepGeom& red, const SweepGeom& pop, const d
                              int64_t main_stride = -1);
 
 // Lanczos pieces (basis vector j >= 1 lives at basis + (j-1)*vec_stride
-// elements; vector 0 is the state itself).
+// elements; vector 0 is the state itself; with 48-bit storage vec_stride is
+// the plane length and the m - 1 basis vectors are stored plane by plane).
 hipError_t launch_lz_norm(int prec, const SweepGeom& g, const void* psi, double* partial,
                           hipStream_t st);
 hipError_t launch_lz_norm_finish(const SweepGeom& g, const double* partial, LanczosScalars* sc,
@@ -158,7 +162,7 @@ hipError_t launch_lz_sweep_a(int prec, int S, const SweepGeom& g, int j, int m, 
                              const LanczosScalars* sc, double* partial, hipStream_t st);
 hipError_t launch_lz_finish_a(const SweepGeom& g, int j, int m, const double* partial,
                               LanczosScalars* sc, hipStream_t st);
-hipError_t launch_lz_sweep_b(int prec, const SweepGeom& g, int j, const void* psi,
+hipError_t launch_lz_sweep_b(int prec, const SweepGeom& g, int j, int m, const void* psi,
                              const void* basis, int64_t vec_stride, const void* w,
                              const LanczosScalars* sc, double* partial, hipStream_t st);
 hipError_t launch_lz_finish_b(const SweepGeom& g, int j, const double* partial,

@@ -27,6 +27,17 @@ def read_vector(prop, buf, inst: int) -> np.ndarray:
     import torch
     g = prop.grids[inst]
     cnt = (g.lmax + 1) * g.n
+    if prop.elem == 12:
+        # 48-bit storage: plane h (upper words of re, im), then plane l (the
+        # next 16 bits of re in the low half, of im in the high half)
+        words = buf.view(torch.int32).cpu().numpy().view(np.uint32)
+        plane = (words.size * 4) // 12
+        off = prop.offsets[inst]
+        h = words[2 * off:2 * (off + cnt)].astype(np.uint64)
+        lo = words[2 * plane + off:2 * plane + off + cnt].astype(np.uint64)
+        re = (h[0::2] << np.uint64(32)) | ((lo & np.uint64(0xFFFF)) << np.uint64(16))
+        im = (h[1::2] << np.uint64(32)) | (lo & np.uint64(0xFFFF0000))
+        return re.view(np.float64) + 1j * im.view(np.float64)
     dt = torch.float64 if prop.elem == 16 else torch.float32
     flat = buf.view(dt)
     off = prop.offsets[inst] * 2
@@ -44,6 +55,15 @@ def orc_pulse(p) -> oracle.Pulse:
 
 def to_fp32(v: np.ndarray) -> np.ndarray:
     return v.astype(np.complex64).astype(np.complex128)
+
+
+def to_fp48(v: np.ndarray) -> np.ndarray:
+    """The value 48-bit storage keeps: each FP64 component rounded to nearest
+    (ties away from zero) at 36 mantissa bits."""
+    def r(x):
+        b = np.ascontiguousarray(x, dtype=np.float64).view(np.uint64) + np.uint64(0x8000)
+        return (b & ~np.uint64(0xFFFF)).view(np.float64)
+    return r(v.real) + 1j * r(v.imag)
 
 
 def rel_err(a: np.ndarray, b: np.ndarray) -> float:

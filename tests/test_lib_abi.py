@@ -76,7 +76,7 @@ def test_rejects_bad_descriptors(tdse):
     bad = [tdse.GridDesc(4, 2, 3, 0, 0.1, 1.0, 10.0),        # n < 8
            tdse.GridDesc(100, 2, 4, 0, 0.1, 1.0, 10.0),      # stencil
            tdse.GridDesc(100, -1, 3, 0, 0.1, 1.0, 10.0),     # lmax
-           tdse.GridDesc(100, 2, 3, 2, 0.1, 1.0, 10.0),      # precision
+           tdse.GridDesc(100, 2, 3, 3, 0.1, 1.0, 10.0),      # precision
            tdse.GridDesc(100, 2, 3, 0, 0.0, 1.0, 10.0),      # dr
            tdse.GridDesc(100, 2, 3, 0, 0.1, 0.0, 10.0)]      # z
     for d in bad:
@@ -103,6 +103,22 @@ def test_sizes_and_offsets(tdse):
         wl = tdse.lib.tdse_workspace_bytes(ctx, tdse.METHOD_LANCZOS, 20)
         assert wr - wt == sb and wl - wt == 18 * sb
         assert tdse.lib.tdse_state_offset(ctx, 3) == -1
+    finally:
+        tdse.tdse_destroy(ctx)
+
+
+def test_fp48_state_is_two_planes(tdse):
+    # 48-bit storage: plane h (8 B per element) and plane l (4 B per element)
+    # of P elements each, P the element count rounded up to 64: 12 P bytes,
+    # plane l starting 256-byte aligned
+    grids = [tdse.Grid(1000, 4, 0.1, 3, tdse.FP48), tdse.Grid(777, 9, 0.1, 3, tdse.FP48)]
+    ctx = tdse.tdse_init_grid([g.desc() for g in grids])
+    try:
+        offs = [tdse.lib.tdse_state_offset(ctx, k) for k in range(2)]
+        total = offs[1] + 10 * 777
+        plane = (total + 63) // 64 * 64
+        assert tdse.lib.tdse_state_bytes(ctx) == 12 * plane
+        assert (8 * plane) % 256 == 0
     finally:
         tdse.tdse_destroy(ctx)
 

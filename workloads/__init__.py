@@ -159,3 +159,23 @@ def random_state(seed: int, n: int, lmax: int, smooth: bool = False) -> np.ndarr
     else:
         v = rng.standard_normal((lmax + 1, n)) + 1j * rng.standard_normal((lmax + 1, n))
     return np.ascontiguousarray(v.reshape(-1))
+
+
+def mixed_state(seed: int, n: int, lmax: int, dr: float) -> np.ndarray:
+    """Seeded smooth complex128 state of shape [(lmax+1)*n] (unnormalised)
+    that carries bound, excited and outgoing parts at once: hydrogen-like
+    radial shapes r e^{-r} (l = 0), r^2 e^{-r/2} (l = 1) and r^3 e^{-r/3}
+    (l = 2) with seeded complex amplitudes, plus 0.3 times a smooth seeded
+    wave in every partial wave (random_state(seed, smooth=True), scaled to
+    unit grid norm), whose sin^2 envelope over the box puts weight far out."""
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal((3, 2))
+    amp = c[:, 0] + 1j * c[:, 1]
+    r = (np.arange(n) + 1.0) * dr
+    v = 0.3 * random_state(seed + 1, n, lmax, smooth=True)
+    v /= math.sqrt(dr * float(np.vdot(v, v).real))
+    shapes = (r * np.exp(-r), r ** 2 * np.exp(-r / 2.0), r ** 3 * np.exp(-r / 3.0))
+    for l, (a, f) in enumerate(zip(amp, shapes)):
+        if l <= lmax:
+            v[l * n:(l + 1) * n] += a * f / math.sqrt(dr * float(np.dot(f, f)))
+    return v
