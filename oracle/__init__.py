@@ -99,6 +99,8 @@ def lib():
         L.orc_lanczos_step.argtypes = [gp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
         L.orc_lanczos_step.restype = ctypes.c_int
         L.orc_jacobi_eig.argtypes = [ctypes.c_int, dp, dp]
+        L.orc_imag_step.argtypes, L.orc_imag_step.restype = [gp, ctypes.c_double, ctypes.c_int, dp], ctypes.c_double
+        L.orc_imag_propagate.argtypes = [gp, ctypes.c_double, ctypes.c_int, ctypes.c_int64, dp, dp]
         L.orc_initial_state.argtypes = [gp, dp, dp]
         L.orc_observables.argtypes = [gp, pp, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int,
                                       ip, dp, dp, dp]
@@ -246,9 +248,20 @@ def propagate(g: Grid, p: Pulse, method: int, order_or_m: int, t0: float, dt: fl
     return psi, obs[:n_obs], used
 
 
+def imag_propagate(g: Grid, dtau: float, order: int, nsteps: int, psi):
+    """Diffusion (imaginary-time) ground-state search (Sec. 4): normalises psi,
+    runs nsteps field-free steps of the order-P Taylor polynomial of
+    exp(-dtau H) with renormalisation; returns (state, energy per step)."""
+    psi = _state(g, psi).copy()
+    energy = np.zeros(max(int(nsteps), 1))
+    gc = g.c()
+    lib().orc_imag_propagate(ctypes.byref(gc), float(dtau), int(order), int(nsteps), _dptr(psi), _dptr(energy))
+    return psi, energy[:nsteps]
+
+
 from .eigen import bound_states, obs_setup  # noqa: E402  (needs Grid)
 
 __all__ = ["Grid", "Pulse", "ObsSetup", "build", "lib", "radius", "kappa", "field", "h_bound", "apply_h",
            "taylor_step", "rk4_step", "lanczos_step", "jacobi_eig", "initial_state",
-           "observables", "propagate", "bound_states", "obs_setup", "TAYLOR", "RK4", "LANCZOS",
+           "observables", "propagate", "imag_propagate", "bound_states", "obs_setup", "TAYLOR", "RK4", "LANCZOS",
            "OBS_FIXED", "OBS_NAMES"]

@@ -19,8 +19,17 @@
  * thread with the same operations, so the results do not depend on the
  * thread count); every sum over elements (norms, inner products, observables)
  * runs on one thread in index order. */
+static int default_threads = 1;
+/* At load: remember the OpenMP default (OMP_NUM_THREADS, else the cores) and
+ * run on one thread until told otherwise (the tests call the oracle on small
+ * grids, where thread start-up costs more than the loops). */
+__attribute__((constructor)) static void orc_threads_init(void)
+{
+    default_threads = omp_get_max_threads();
+    omp_set_num_threads(1);
+}
 void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
-int orc_max_threads(void) { return omp_get_max_threads(); }
+int orc_max_threads(void) { return default_threads; }
 
 /* Sec. 2, grid definition: uniform points, the first one a spacing away from
  * the origin ("Start = 1"), optionally displaced by the "Offset" setting. */
@@ -306,6 +315,54 @@ int orc_lanczos_step(const orc_grid* g, double efield, double dt, int m, double 
     free(alpha);
     free(beta);
     return meff;
+}
+
+/* Sec. 4 "Ground state calculation": the diffusion equation, i.e. the TDSE
+ * with the time derivative taken in imaginary time (the factor -i of the
+ * propagator replaced, read here as dF/dtau = -H F), field free, propagated by
+ * the Taylor series of eq. Taylor with that factor:
+ *   F_{n+1} = sum_{p=0..P} F^(p),  F^(0) = F_n,  F^(p+1) = (-dtau/(p+1)) H F^(p),
+ * the partial waves renormalised after every step.  For a normalised F_n the
+ * loss of unitarity gives the energy, eq. e_g read with the factor 2 of a
+ * squared norm: E = -ln <F_{n+1}|F_{n+1}> / (2 dtau).  Returns E and leaves the
+ * renormalised F_{n+1} in psi (the input is assumed normalised). */
+double orc_imag_step(const orc_grid* g, double dtau, int order, double complex* psi)
+{
+    const size_t len = state_len(g);
+    double complex* term = malloc(len * sizeof *term);
+    double complex* next = malloc(len * sizeof *next);
+    memcpy(term, psi, len * sizeof *term);
+    for (int p = 0; p < order; ++p) {
+        orc_apply_h(g, 0.0, term, next);
+        const double factor = -dtau / (double)(p + 1);
+#pragma omp parallel for schedule(static)
+        for (size_t k = 0; k < len; ++k) {
+            term[k] = factor * next[k];
+            psi[k] += term[k];
+        }
+    }
+    double n2 = 0.0;
+    for (size_t k = 0; k < len; ++k) n2 += creal(psi[k]) * creal(psi[k]) + cimag(psi[k]) * cimag(psi[k]);
+    n2 *= g->dr;
+    const double scale = 1.0 / sqrt(n2);
+#pragma omp parallel for schedule(static)
+    for (size_t k = 0; k < len; ++k) psi[k] *= scale;
+    free(term);
+    free(next);
+    return -log(n2) / (2.0 * dtau);
+}
+
+/* nsteps diffusion steps from psi, normalised first; energy[s] receives the
+ * estimate of step s. */
+void orc_imag_propagate(const orc_grid* g, double dtau, int order, int64_t nsteps, double complex* psi,
+                        double* energy)
+{
+    const size_t len = state_len(g);
+    double n2 = 0.0;
+    for (size_t k = 0; k < len; ++k) n2 += creal(psi[k]) * creal(psi[k]) + cimag(psi[k]) * cimag(psi[k]);
+    const double scale = 1.0 / sqrt(g->dr * n2);
+    for (size_t k = 0; k < len; ++k) psi[k] *= scale;
+    for (int64_t s = 0; s < nsteps; ++s) energy[s] = orc_imag_step(g, dtau, order, psi);
 }
 
 /* Initial state: the hydrogenic 1s radial function u(r) ~ r exp(-z r)

@@ -56,7 +56,9 @@ double orc_field(const orc_pulse* p, double t);
 double orc_h_bound(const orc_grid* g, double efield);
 
 /* OpenMP threads of the element-wise loops (results do not depend on it:
- * every sum over elements runs on one thread, in index order). */
+ * every sum over elements runs on one thread, in index order).  One thread
+ * after loading; orc_max_threads gives the OpenMP default of the process
+ * (OMP_NUM_THREADS, else the cores). */
 void orc_set_threads(int n);
 int orc_max_threads(void);
 
@@ -70,6 +72,14 @@ void orc_rk4_step(const orc_grid* g, const orc_pulse* p, double t, double dt,
 /* returns the Krylov dimension actually used (smaller than m on breakdown) */
 int orc_lanczos_step(const orc_grid* g, double efield, double dt, int m,
                      double complex* psi);
+
+/* Diffusion (imaginary-time) step of the ground-state search: order-P
+ * Taylor polynomial of exp(-dtau H) with E = 0, renormalised; returns the
+ * energy estimate -ln||F'||^2 / (2 dtau) (input assumed normalised). */
+double orc_imag_step(const orc_grid* g, double dtau, int order, double complex* psi);
+/* normalises psi, then nsteps steps; energy[s] per step */
+void orc_imag_propagate(const orc_grid* g, double dtau, int order, int64_t nsteps,
+                        double complex* psi, double* energy);
 
 /* Eigen-decomposition of a dense real symmetric m x m matrix (row-major) by
  * cyclic Jacobi rotations: on return a holds the eigenvalues on its diagonal

@@ -175,6 +175,6 @@ def test_thread_count_does_not_change_results(orc):
         runs = [orc.propagate(g, p, code, order, 0.3, dt, 6, 2, setup, psi0)
                 for code, order, dt in ((orc.TAYLOR, 8, 2e-4), (orc.RK4, 4, 2e-4), (orc.LANCZOS, 10, 0.01))]
         out.append(runs)
-    orc.set_threads(orc.max_threads())
+    orc.set_threads(1)
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
