@@ -24,6 +24,8 @@ OBS_FIXED = 8
 OBS_NAMES = ("t", "e_field", "norm", "p_g", "p_bound", "p_ion", "dipole", "accel")
 
 TAYLOR, RK4, LANCZOS = 0, 1, 2
+RK_EULER, RK_CLASSIC4, RK_FEHLBERG45, RK_CASHKARP, RK_DORMANDPRINCE, RK_MERSON = range(6)
+RK_MAX = 8
 
 
 def build() -> str:
@@ -99,6 +101,12 @@ def lib():
         L.orc_lanczos_step.argtypes = [gp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
         L.orc_lanczos_step.restype = ctypes.c_int
         L.orc_jacobi_eig.argtypes = [ctypes.c_int, dp, dp]
+        L.orc_rk_tableau.argtypes, L.orc_rk_tableau.restype = [ctypes.c_int, dp, dp, dp, dp], ctypes.c_int
+        L.orc_rk_step.argtypes, L.orc_rk_step.restype = [gp, pp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                         dp], ctypes.c_double
+        L.orc_propagate_rk.argtypes = [gp, pp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_double, dp, ctypes.c_int, ip, dp, dp, dp]
+        L.orc_propagate_rk.restype = ctypes.c_double
         L.orc_imag_step.argtypes, L.orc_imag_step.restype = [gp, ctypes.c_double, ctypes.c_int, dp], ctypes.c_double
         L.orc_imag_propagate.argtypes = [gp, ctypes.c_double, ctypes.c_int, ctypes.c_int64, dp, dp]
         L.orc_initial_state.argtypes = [gp, dp, dp]
@@ -248,6 +256,38 @@ def propagate(g: Grid, p: Pulse, method: int, order_or_m: int, t0: float, dt: fl
     return psi, obs[:n_obs], used
 
 
+def rk_tableau(method: int):
+    """(c, a, b, bhat, stages) of an explicit Runge-Kutta method (appendix)."""
+    c, b, bh = np.zeros(RK_MAX), np.zeros(RK_MAX), np.zeros(RK_MAX)
+    a = np.zeros((RK_MAX, RK_MAX))
+    s = lib().orc_rk_tableau(int(method), _dptr(c), _dptr(a), _dptr(b), _dptr(bh))
+    return c[:s], a[:s, :s], b[:s], bh[:s], s
+
+
+def rk_step(g: Grid, p: Pulse, method: int, t: float, dt: float, psi):
+    """One step; returns (state, sigma_n)."""
+    psi = _state(g, psi).copy()
+    gc, pc = g.c(), p.c()
+    sig = lib().orc_rk_step(ctypes.byref(gc), ctypes.byref(pc), int(method), float(t), float(dt), _dptr(psi))
+    return psi, sig
+
+
+def propagate_rk(g: Grid, p: Pulse, method: int, t0: float, dt: float, nsteps: int, obs_every: int,
+                 setup: "ObsSetup", psi):
+    """Runs nsteps steps; returns (state, observables [n_obs, record], sigma = sum of sigma_n)."""
+    psi = _state(g, psi).copy()
+    n_obs = nsteps // obs_every if obs_every > 0 else 0
+    obs = np.zeros((max(n_obs, 1), setup.record))
+    gc, pc = g.c(), p.c()
+    phi = np.ascontiguousarray(setup.phi, dtype=np.float64)
+    sl = np.ascontiguousarray(setup.state_l, dtype=np.int32)
+    sigma = lib().orc_propagate_rk(ctypes.byref(gc), ctypes.byref(pc), int(method), float(t0), float(dt),
+                                   int(nsteps), int(obs_every), float(setup.r_ion),
+                                   _dptr(np.ascontiguousarray(setup.u0)), len(sl), _iptr(sl), _dptr(phi),
+                                   _dptr(psi), _dptr(obs))
+    return psi, obs[:n_obs], sigma
+
+
 def imag_propagate(g: Grid, dtau: float, order: int, nsteps: int, psi):
     """Diffusion (imaginary-time) ground-state search (Sec. 4): normalises psi,
     runs nsteps field-free steps of the order-P Taylor polynomial of
@@ -263,5 +303,5 @@ from .eigen import bound_states, obs_setup  # noqa: E402  (needs Grid)
 
 __all__ = ["Grid", "Pulse", "ObsSetup", "build", "lib", "radius", "kappa", "field", "h_bound", "apply_h",
            "taylor_step", "rk4_step", "lanczos_step", "jacobi_eig", "initial_state",
-           "observables", "propagate", "imag_propagate", "bound_states", "obs_setup", "TAYLOR", "RK4", "LANCZOS",
+           "observables", "propagate", "imag_propagate", "rk_tableau", "rk_step", "propagate_rk", "bound_states", "obs_setup", "TAYLOR", "RK4", "LANCZOS",
            "OBS_FIXED", "OBS_NAMES"]

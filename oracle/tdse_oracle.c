@@ -182,6 +182,150 @@ void orc_rk4_step(const orc_grid* g, const orc_pulse* p, double t, double dt, do
     rk4_step_fields(g, orc_field(p, t), orc_field(p, t + 0.5 * dt), orc_field(p, t + dt), dt, psi);
 }
 
+/* Appendix "Runge-Kutta" and Sec. 5.2 (RungeKutta.c, eq. RKDeriv): explicit
+ * Runge-Kutta methods given by their Butcher tableaux, the published ones:
+ * Euler; the classic fourth-order method; Fehlberg's 4(5) pair; the
+ * Cash-Karp 5(4) pair; the Dormand-Prince 5(4) pair; Merson's 4(3) method.
+ * b: the weights of the solution carried forward (the higher order of a
+ * pair); bhat: the weights of the embedded solution of the other order
+ * (zero rows for the methods without one). */
+int orc_rk_tableau(int method, double* c, double* a /* [ORC_RK_MAX][ORC_RK_MAX] */, double* b, double* bhat)
+{
+    const int M = ORC_RK_MAX;
+    for (int i = 0; i < M; ++i) {
+        c[i] = b[i] = bhat[i] = 0.0;
+        for (int j = 0; j < M; ++j) a[i * M + j] = 0.0;
+    }
+#define A_(i, j, v) a[(i) * M + (j)] = (v)
+    switch (method) {
+    case ORC_RK_EULER:
+        b[0] = 1.0;
+        return 1;
+    case ORC_RK_CLASSIC4:
+        c[1] = 0.5; c[2] = 0.5; c[3] = 1.0;
+        A_(1, 0, 0.5); A_(2, 1, 0.5); A_(3, 2, 1.0);
+        b[0] = 1.0 / 6.0; b[1] = 1.0 / 3.0; b[2] = 1.0 / 3.0; b[3] = 1.0 / 6.0;
+        return 4;
+    case ORC_RK_FEHLBERG45:
+        c[1] = 1.0 / 4.0; c[2] = 3.0 / 8.0; c[3] = 12.0 / 13.0; c[4] = 1.0; c[5] = 1.0 / 2.0;
+        A_(1, 0, 1.0 / 4.0);
+        A_(2, 0, 3.0 / 32.0); A_(2, 1, 9.0 / 32.0);
+        A_(3, 0, 1932.0 / 2197.0); A_(3, 1, -7200.0 / 2197.0); A_(3, 2, 7296.0 / 2197.0);
+        A_(4, 0, 439.0 / 216.0); A_(4, 1, -8.0); A_(4, 2, 3680.0 / 513.0); A_(4, 3, -845.0 / 4104.0);
+        A_(5, 0, -8.0 / 27.0); A_(5, 1, 2.0); A_(5, 2, -3544.0 / 2565.0); A_(5, 3, 1859.0 / 4104.0);
+        A_(5, 4, -11.0 / 40.0);
+        b[0] = 16.0 / 135.0; b[2] = 6656.0 / 12825.0; b[3] = 28561.0 / 56430.0; b[4] = -9.0 / 50.0;
+        b[5] = 2.0 / 55.0;
+        bhat[0] = 25.0 / 216.0; bhat[2] = 1408.0 / 2565.0; bhat[3] = 2197.0 / 4104.0; bhat[4] = -1.0 / 5.0;
+        return 6;
+    case ORC_RK_CASHKARP:
+        c[1] = 1.0 / 5.0; c[2] = 3.0 / 10.0; c[3] = 3.0 / 5.0; c[4] = 1.0; c[5] = 7.0 / 8.0;
+        A_(1, 0, 1.0 / 5.0);
+        A_(2, 0, 3.0 / 40.0); A_(2, 1, 9.0 / 40.0);
+        A_(3, 0, 3.0 / 10.0); A_(3, 1, -9.0 / 10.0); A_(3, 2, 6.0 / 5.0);
+        A_(4, 0, -11.0 / 54.0); A_(4, 1, 5.0 / 2.0); A_(4, 2, -70.0 / 27.0); A_(4, 3, 35.0 / 27.0);
+        A_(5, 0, 1631.0 / 55296.0); A_(5, 1, 175.0 / 512.0); A_(5, 2, 575.0 / 13824.0);
+        A_(5, 3, 44275.0 / 110592.0); A_(5, 4, 253.0 / 4096.0);
+        b[0] = 37.0 / 378.0; b[2] = 250.0 / 621.0; b[3] = 125.0 / 594.0; b[5] = 512.0 / 1771.0;
+        bhat[0] = 2825.0 / 27648.0; bhat[2] = 18575.0 / 48384.0; bhat[3] = 13525.0 / 55296.0;
+        bhat[4] = 277.0 / 14336.0; bhat[5] = 1.0 / 4.0;
+        return 6;
+    case ORC_RK_DORMANDPRINCE:
+        c[1] = 1.0 / 5.0; c[2] = 3.0 / 10.0; c[3] = 4.0 / 5.0; c[4] = 8.0 / 9.0; c[5] = 1.0; c[6] = 1.0;
+        A_(1, 0, 1.0 / 5.0);
+        A_(2, 0, 3.0 / 40.0); A_(2, 1, 9.0 / 40.0);
+        A_(3, 0, 44.0 / 45.0); A_(3, 1, -56.0 / 15.0); A_(3, 2, 32.0 / 9.0);
+        A_(4, 0, 19372.0 / 6561.0); A_(4, 1, -25360.0 / 2187.0); A_(4, 2, 64448.0 / 6561.0);
+        A_(4, 3, -212.0 / 729.0);
+        A_(5, 0, 9017.0 / 3168.0); A_(5, 1, -355.0 / 33.0); A_(5, 2, 46732.0 / 5247.0); A_(5, 3, 49.0 / 176.0);
+        A_(5, 4, -5103.0 / 18656.0);
+        A_(6, 0, 35.0 / 384.0); A_(6, 2, 500.0 / 1113.0); A_(6, 3, 125.0 / 192.0); A_(6, 4, -2187.0 / 6784.0);
+        A_(6, 5, 11.0 / 84.0);
+        b[0] = 35.0 / 384.0; b[2] = 500.0 / 1113.0; b[3] = 125.0 / 192.0; b[4] = -2187.0 / 6784.0;
+        b[5] = 11.0 / 84.0;
+        bhat[0] = 5179.0 / 57600.0; bhat[2] = 7571.0 / 16695.0; bhat[3] = 393.0 / 640.0;
+        bhat[4] = -92097.0 / 339200.0; bhat[5] = 187.0 / 2100.0; bhat[6] = 1.0 / 40.0;
+        return 7;
+    case ORC_RK_MERSON:
+        c[1] = 1.0 / 3.0; c[2] = 1.0 / 3.0; c[3] = 1.0 / 2.0; c[4] = 1.0;
+        A_(1, 0, 1.0 / 3.0);
+        A_(2, 0, 1.0 / 6.0); A_(2, 1, 1.0 / 6.0);
+        A_(3, 0, 1.0 / 8.0); A_(3, 2, 3.0 / 8.0);
+        A_(4, 0, 1.0 / 2.0); A_(4, 2, -3.0 / 2.0); A_(4, 3, 2.0);
+        b[0] = 1.0 / 6.0; b[3] = 2.0 / 3.0; b[4] = 1.0 / 6.0;
+        bhat[0] = 1.0 / 10.0; bhat[2] = 3.0 / 10.0; bhat[3] = 2.0 / 5.0; bhat[4] = 1.0 / 5.0;
+        return 5;
+    default:
+        return 0;
+    }
+#undef A_
+}
+
+/* One step of the method from psi at t: k_i = -i H(t + c_i dt) g_i with
+ * g_i = F_n + dt sum_{j<i} a_ij k_j; F_{n+1} = F_n + dt sum_i b_i k_i.  For a
+ * pair, the local deviation Delta = dt sum_i (b_i - bhat_i) k_i gives
+ * sigma_n = sqrt(sum_e |Delta_e|^2 / U) over the U elements of the state (the
+ * root mean square over the solution vector); returned (0 without a pair). */
+double orc_rk_step(const orc_grid* g, const orc_pulse* p, int method, double t, double dt,
+                   double complex* psi)
+{
+    const int M = ORC_RK_MAX;
+    double c[ORC_RK_MAX], a[ORC_RK_MAX * ORC_RK_MAX], b[ORC_RK_MAX], bh[ORC_RK_MAX];
+    const int stages = orc_rk_tableau(method, c, a, b, bh);
+    const size_t len = state_len(g);
+    double complex* k = malloc((size_t)stages * len * sizeof *k);
+    double complex* y = malloc(len * sizeof *y);
+    for (int i = 0; i < stages; ++i) {
+#pragma omp parallel for schedule(static)
+        for (size_t e = 0; e < len; ++e) {
+            double complex acc = 0.0;
+            for (int j = 0; j < i; ++j) acc += a[i * M + j] * k[(size_t)j * len + e];
+            y[e] = psi[e] + dt * acc;
+        }
+        double complex* ki = k + (size_t)i * len;
+        orc_apply_h(g, orc_field(p, t + c[i] * dt), y, ki);
+#pragma omp parallel for schedule(static)
+        for (size_t e = 0; e < len; ++e) ki[e] = -I * ki[e];
+    }
+    double d2 = 0.0;
+    for (size_t e = 0; e < len; ++e) {
+        double complex acc = 0.0, dev = 0.0;
+        for (int i = 0; i < stages; ++i) {
+            acc += b[i] * k[(size_t)i * len + e];
+            dev += (b[i] - bh[i]) * k[(size_t)i * len + e];
+        }
+        psi[e] += dt * acc;
+        dev *= dt;
+        d2 += creal(dev) * creal(dev) + cimag(dev) * cimag(dev);
+    }
+    free(k);
+    free(y);
+    int pair = 0;
+    for (int i = 0; i < stages; ++i) pair = pair || (bh[i] != 0.0);
+    return pair ? sqrt(d2 / (double)len) : 0.0;
+}
+
+/* nsteps steps of method from t0 with observables every obs_every steps (as
+ * orc_propagate); returns sigma = sum_n sigma_n, the passive global
+ * truncation estimate of the appendix. */
+double orc_propagate_rk(const orc_grid* g, const orc_pulse* p, int method, double t0, double dt,
+                        int64_t nsteps, int64_t obs_every, double r_ion, const double* u0, int n_states,
+                        const int32_t* state_l, const double* phi, double complex* psi, double* obs_out)
+{
+    const int rec = ORC_OBS_FIXED + n_states;
+    int64_t n_obs = 0;
+    double sigma = 0.0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        sigma += orc_rk_step(g, p, method, t0 + (double)s * dt, dt, psi);
+        if (obs_every > 0 && (s + 1) % obs_every == 0 && obs_out) {
+            orc_observables(g, p, t0 + (double)(s + 1) * dt, r_ion, u0, n_states, state_l, phi, psi,
+                            obs_out + (size_t)n_obs * rec);
+            ++n_obs;
+        }
+    }
+    return sigma;
+}
+
 /* Cyclic-by-row Jacobi method for a dense symmetric matrix (the rotation of
  * Golub & Van Loan, Matrix Computations, Sec. 8.5).  Each rotation zeroes one
  * off-diagonal pair; sweeps repeat until the off-diagonal part vanishes. */

@@ -81,6 +81,22 @@ double orc_imag_step(const orc_grid* g, double dtau, int order, double complex* 
 void orc_imag_propagate(const orc_grid* g, double dtau, int order, int64_t nsteps,
                         double complex* psi, double* energy);
 
+/* Explicit Runge-Kutta methods of the appendix "Runge-Kutta" (tableaux). */
+#define ORC_RK_MAX 8
+enum { ORC_RK_EULER = 0, ORC_RK_CLASSIC4 = 1, ORC_RK_FEHLBERG45 = 2, ORC_RK_CASHKARP = 3,
+       ORC_RK_DORMANDPRINCE = 4, ORC_RK_MERSON = 5 };
+/* fills c[ORC_RK_MAX], a[ORC_RK_MAX][ORC_RK_MAX] (row-major), b, bhat;
+ * returns the number of stages (0: unknown method) */
+int orc_rk_tableau(int method, double* c, double* a, double* b, double* bhat);
+/* one step; returns sigma_n (0 for methods without an embedded pair) */
+double orc_rk_step(const orc_grid* g, const orc_pulse* p, int method, double t, double dt,
+                   double complex* psi);
+/* returns sigma = sum of sigma_n over the steps */
+double orc_propagate_rk(const orc_grid* g, const orc_pulse* p, int method, double t0, double dt,
+                        int64_t nsteps, int64_t obs_every, double r_ion, const double* u0,
+                        int n_states, const int32_t* state_l, const double* phi,
+                        double complex* psi, double* obs_out);
+
 /* Eigen-decomposition of a dense real symmetric m x m matrix (row-major) by
  * cyclic Jacobi rotations: on return a holds the eigenvalues on its diagonal
  * and v (row-major) the eigenvectors as columns. */
