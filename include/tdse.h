@@ -77,9 +77,17 @@ enum {
  * LDS-ring fused kernel are FP64/FP32 only. */
 typedef enum { TDSE_FP64 = 0, TDSE_FP32 = 1, TDSE_FP48 = 2 } tdse_precision;
 /* TDSE_METHOD_TUNE only sizes the workspace the autotuners need (four
- * state-shaped vectors). */
+ * state-shaped vectors); TDSE_METHOD_RK_TABLEAU sizes tdse_step_rk's (its
+ * order_or_m argument is the tdse_rk_method: stages + 1 vectors). */
 typedef enum { TDSE_METHOD_TAYLOR = 0, TDSE_METHOD_RK4 = 1, TDSE_METHOD_LANCZOS = 2,
-               TDSE_METHOD_TUNE = 3 } tdse_method;
+               TDSE_METHOD_TUNE = 3, TDSE_METHOD_RK_TABLEAU = 4 } tdse_method;
+/* Explicit Runge-Kutta methods of tdse_step_rk (appendix "Runge-Kutta"): the
+ * published tableaux of Euler (1 stage, order 1), the classic fourth-order
+ * method (4, 4), Fehlberg's pair (6 stages, orders 5 and 4), the Cash-Karp
+ * pair (6; 5, 4), the Dormand-Prince pair (7; 5, 4) and Merson's method
+ * (5; 4, 3).  The solution carried forward is the higher order of a pair. */
+typedef enum { TDSE_RK_EULER = 0, TDSE_RK_CLASSIC4 = 1, TDSE_RK_FEHLBERG45 = 2, TDSE_RK_CASHKARP = 3,
+               TDSE_RK_DORMANDPRINCE = 4, TDSE_RK_MERSON = 5 } tdse_rk_method;
 
 /* One instance (one radial grid and partial-wave set).  All instances of a
  * context must share stencil and precision. */
@@ -192,6 +200,25 @@ tdse_status tdse_step_taylor(tdse_ctx* ctx, const tdse_pulse* pulses, const doub
 tdse_status tdse_step_rk4(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0,
                           const double* dt, int32_t nsteps, int32_t obs_every, tdse_obs* d_obs);
 
+/* Explicit Runge-Kutta propagator of the appendix "Runge-Kutta" (eq.
+ * RKDeriv) with the tableau of `method` (tdse_rk_method): per step
+ *   k_i = -i H(t_s + c_i dt) (F + dt sum_{j<i} a_ij k_j),  F <- F + dt sum_i b_i k_i,
+ * one launch per stage.  For the embedded pairs and d_sigma != NULL (device
+ * memory, n_inst FP64 values), the passive truncation estimate of the
+ * appendix is accumulated: d_sigma[k] += sigma_n for every step, sigma_n =
+ * sqrt(sum_e |Delta_e|^2 / U_k) the root mean square over the U_k elements of
+ * instance k of the pair's difference Delta = dt sum_i (b_i - bhat_i) k_i (the
+ * caller zeroes d_sigma to start a sum).  Arguments, observables and errors as
+ * tdse_step_taylor; TDSE_E_UNSTABLE if dt[k] tdse_lambda_max_bound(k, |e0|)
+ * exceeds tdse_rk_stability_limit(method).  Needs the TDSE_METHOD_RK_TABLEAU
+ * workspace of the method.  Asynchronous. */
+tdse_status tdse_step_rk(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0, const double* dt,
+                         int32_t method, int32_t nsteps, int32_t obs_every, tdse_obs* d_obs, double* d_sigma);
+/* Imaginary-axis stability limit of the method's stability polynomial
+ * R(z) = 1 + sum_k (b^T A^(k-1) 1) z^k: the largest y with |R(i y')| <=
+ * 1 + 1e-12 for all y' <= y (0 for an unknown method). */
+double tdse_rk_stability_limit(int32_t method);
+
 /* Lanczos propagator (Sec. 5.2 Lanczos.c, appendix "Lanczos methods"): an
  * m-dimensional Krylov basis of H(t_s + dt/2) from F/||F||, each new
  * direction orthogonalised against all earlier basis vectors in one
@@ -210,6 +237,23 @@ tdse_status tdse_step_rk4(tdse_ctx* ctx, const tdse_pulse* pulses, const double*
 tdse_status tdse_step_lanczos(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0,
                               const double* dt, int32_t m, int32_t nsteps, int32_t obs_every,
                               tdse_obs* d_obs);
+
+/* Ground-state search by the diffusion equation (Sec. 4, "Ground state
+ * calculation"; eq. e_g): the TDSE in imaginary time, dF/dtau = -H F with no
+ * field, advanced by nsteps steps of dtau[k] from the bound state of every
+ * instance.  The state is first normalised; each step then applies the
+ * order-P Taylor polynomial of exp(-dtau H) in Horner form,
+ *   w_P = F - (dtau/P) H F, ..., w_1 = F - dtau H w_2,
+ * takes n2 = ||w_1||^2 (FP64, dr * sum |w|^2), records the energy estimate
+ * E = -ln(n2) / (2 dtau) (the loss of norm of a normalised state over one
+ * step; the factor 2 of a squared norm) at d_energy[k * nsteps + s] (device
+ * memory, FP64; may be NULL), and stores F = w_1 / sqrt(n2).  Repeated steps
+ * converge to the lowest state of the discrete H within the symmetry of the
+ * start (no field couples partial waves).  Returns TDSE_E_UNSTABLE (and
+ * enqueues nothing) if dtau[k] times tdse_lambda_max_bound(k, 0) exceeds
+ * tdse_taylor_real_stability_limit(order).  Needs the Taylor workspace of
+ * the same order.  Asynchronous. */
+tdse_status tdse_step_imag(tdse_ctx* ctx, const double* dtau, int32_t order, int32_t nsteps, double* d_energy);
 
 /* Smallest Krylov dimension each instance used over the steps of the last
  * tdse_step_lanczos call, copied to host_meff[n_inst].  Synchronises the
@@ -231,6 +275,10 @@ double tdse_lambda_max_bound(const tdse_ctx* ctx, int32_t inst, double e_max);
 /* Imaginary-axis stability limit y_P of the degree-P Taylor polynomial: the
  * largest y with |sum_{k<=P} (i y')^k / k!| <= 1 + 1e-12 for all y' <= y. */
 double tdse_taylor_stability_limit(int32_t order);
+
+/* Real-axis stability limit x_P of the diffusion step's polynomial: the
+ * largest x with |sum_{k<=P} (-x')^k / k!| <= 1 + 1e-12 for all 0 <= x' <= x. */
+double tdse_taylor_real_stability_limit(int32_t order);
 
 /* Autotuner for the sweep kernels (H.psi, Horner terms; RK4 stages take the
  * row count): times a Horner-term sweep of the bound state for each tile

@@ -24,7 +24,8 @@ STATUS = {0: "TDSE_OK", -1: "TDSE_E_INVALID", -2: "TDSE_E_NOMEM", -3: "TDSE_E_HI
           -4: "TDSE_E_UNSTABLE", -5: "TDSE_E_BREAKDOWN", -6: "TDSE_E_NONFINITE", -7: "TDSE_E_WORKSPACE",
           -8: "TDSE_E_UNBOUND"}
 FP64, FP32, FP48 = 0, 1, 2
-METHOD_TAYLOR, METHOD_RK4, METHOD_LANCZOS, METHOD_TUNE = 0, 1, 2, 3
+METHOD_TAYLOR, METHOD_RK4, METHOD_LANCZOS, METHOD_TUNE, METHOD_RK_TABLEAU = 0, 1, 2, 3, 4
+RK_EULER, RK_CLASSIC4, RK_FEHLBERG45, RK_CASHKARP, RK_DORMANDPRINCE, RK_MERSON = range(6)
 MAX_STATES = 15
 OBS_FIELDS = ("t", "e_field", "norm", "p_g", "p_bound", "p_ion", "dipole", "accel")
 OBS_DOUBLES = len(OBS_FIELDS) + MAX_STATES
@@ -36,7 +37,9 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_taylor_stability_limit", "tdse_timing_enable", "tdse_timing_read",
             "tdse_use_graphs", "tdse_set_obs_overlap", "tdse_set_obs_fusion", "tdse_obs_fusion", "tdse_set_rk4_fusion", "tdse_rk4_fusion", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
             "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_taylor_fusion_kind",
-            "tdse_set_taylor_fusion", "tdse_set_sweep_shape", "tdse_lanczos_dims")
+            "tdse_set_taylor_fusion", "tdse_set_sweep_shape", "tdse_lanczos_dims",
+            "tdse_step_imag", "tdse_taylor_real_stability_limit",
+            "tdse_step_rk", "tdse_rk_stability_limit")
 
 
 class TdseError(RuntimeError):
@@ -90,6 +93,10 @@ def _load():
         "tdse_observables": ([ctxp, ctypes.POINTER(Pulse), dp, ctypes.POINTER(Obs)], i32),
         "tdse_lambda_max_bound": ([ctxp, i32, ctypes.c_double], ctypes.c_double),
         "tdse_taylor_stability_limit": ([i32], ctypes.c_double),
+        "tdse_taylor_real_stability_limit": ([i32], ctypes.c_double),
+        "tdse_step_imag": ([ctxp, dp, i32, i32, vp], i32),
+        "tdse_step_rk": ([ctxp, ctypes.POINTER(Pulse), dp, dp, i32, i32, i32, vp, vp], i32),
+        "tdse_rk_stability_limit": ([i32], ctypes.c_double),
         "tdse_timing_enable": ([ctxp, i32], i32),
         "tdse_timing_read": ([ctxp, ctypes.c_char_p, ctypes.POINTER(i64), dp], i32),
         "tdse_use_graphs": ([ctxp, i32], i32),
@@ -191,6 +198,25 @@ def tdse_step_lanczos(ctx, pulses, t0, dt, m, nsteps, obs_every, d_obs):
     n = lib.tdse_num_instances(ctx)
     _check(ctx, lib.tdse_step_lanczos(ctx, _pulses(pulses), _dvec(t0, n), _dvec(dt, n), m,
                                       nsteps, obs_every, d_obs))
+
+
+def tdse_step_rk(ctx, pulses, t0, dt, method, nsteps, obs_every, d_obs, d_sigma=None):
+    n = lib.tdse_num_instances(ctx)
+    _check(ctx, lib.tdse_step_rk(ctx, _pulses(pulses), _dvec(t0, n), _dvec(dt, n), method, nsteps,
+                                 obs_every, d_obs, d_sigma))
+
+
+def tdse_rk_stability_limit(method: int) -> float:
+    return lib.tdse_rk_stability_limit(int(method))
+
+
+def tdse_step_imag(ctx, dtau, order, nsteps, d_energy):
+    n = lib.tdse_num_instances(ctx)
+    _check(ctx, lib.tdse_step_imag(ctx, _dvec(dtau, n), order, nsteps, d_energy))
+
+
+def tdse_taylor_real_stability_limit(order: int) -> float:
+    return lib.tdse_taylor_real_stability_limit(int(order))
 
 
 def tdse_observables(ctx, pulses, t) -> np.ndarray:
@@ -388,6 +414,24 @@ class Propagator:
         self._enter()
         tdse_step_lanczos(self.ctx, self._pulse_list(pulses), self._per_inst(t0),
                           self._per_inst(dt), m, nsteps, obs_every, ptr)
+        self._leave()
+
+    def step_rk(self, pulses, t0, dt, method, nsteps, obs_every=0, obs=None, sigma=None):
+        """Tableau Runge-Kutta steps; `sigma` a float64 device tensor of n_inst
+        values the passive truncation estimate is added to (or None)."""
+        ptr = obs.data_ptr() if obs is not None else None
+        sptr = sigma.data_ptr() if sigma is not None else None
+        self._enter()
+        tdse_step_rk(self.ctx, self._pulse_list(pulses), self._per_inst(t0), self._per_inst(dt), method, nsteps,
+                     obs_every, ptr, sptr)
+        self._leave()
+
+    def step_imag(self, dtau, order, nsteps, energy=None):
+        """Diffusion (imaginary-time) steps; `energy` a float64 device tensor of
+        n_inst * nsteps values (or None)."""
+        ptr = energy.data_ptr() if energy is not None else None
+        self._enter()
+        tdse_step_imag(self.ctx, self._per_inst(dtau), order, nsteps, ptr)
         self._leave()
 
     def lanczos_dims(self):

@@ -331,6 +331,12 @@ __device__ __forceinline__ double2 horner_update(double2 psi, double2 h, double 
     return make_double2(fma(c, h.y, psi.x), fma(-c, h.x, psi.y));
 }
 
+// The diffusion step's Horner term: psi - c h.
+__device__ __forceinline__ double2 horner_update_imag(double2 psi, double2 h, double c)
+{
+    return make_double2(fma(-c, h.x, psi.x), fma(-c, h.y, psi.y));
+}
+
 // Radial neighbours of element i of a row (zero outside [0, n)).
 template <int S>
 struct Neighbours {

@@ -436,6 +436,66 @@ k_lz_recombine(SweepGeom g, typename Stor<T>::aptr psi, typename Stor<T>::cptr b
 }
 
 // ---------------------------------------------------------------------------
+// The diffusion (imaginary-time) step's renormalisation (Sec. 4, ground state
+// calculation; eq. e_g): the norm of the step's output from the lz_norm
+// partials, the energy estimate -ln(n2) / (2 dtau), and the scale 1/sqrt(n2).
+__global__ void __launch_bounds__(kBlock)
+k_imag_finish(SweepGeom g, const double* __restrict__ partial, const double* __restrict__ step, int record,
+              double* __restrict__ energy, int64_t e_stride, int64_t e_index, LanczosScalars* __restrict__ scs)
+{
+    __shared__ double lds[kBlock / 64];
+    const int k = blockIdx.x;
+    const Inst& I = g.inst[k];
+    const double s = instance_sum<1>(I, partial, 1, 1, lds);
+    if (threadIdx.x == 0) {
+        const double n2 = I.dr * s;
+        scs[k].norm0 = 1.0 / sqrt(n2);
+        if (record && energy)
+            energy[(int64_t)k * e_stride + e_index] = -log(n2) / (2.0 * step_value(step, g.n_inst, kDt, k));
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_imag_scale(SweepGeom g, typename Stor<T>::cptr src, typename Stor<T>::ptr dst, const LanczosScalars* __restrict__ scs)
+{
+    const Tile I = my_tile(g);
+    const int i = I.r0 + (int)threadIdx.x;
+    if (i >= I.n) return;
+    const double f = scs[I.inst].norm0;
+    for (int l = I.l0; l < I.l1; ++l) {
+        const int64_t k = I.off + (int64_t)l * I.n + i;
+        const double2 v = ldc(src, k);
+        stc(dst, k, make_double2(f * v.x, f * v.y));
+    }
+}
+
+hipError_t launch_imag_finish(const SweepGeom& g, const double* partial, const double* step, int record,
+                              double* energy, int64_t e_stride, int64_t e_index, LanczosScalars* sc,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_imag_finish, dim3(g.n_inst), dim3(kBlock), 0, st, g, partial, step, record, energy,
+                       e_stride, e_index, sc);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t imag_scale_t(const SweepGeom& g, const void* src, void* dst, const LanczosScalars* sc,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL((k_imag_scale<T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(src, g.plane),
+                       Stor<T>::make(dst, g.plane), sc);
+    return hipGetLastError();
+}
+hipError_t launch_imag_scale(int prec, const SweepGeom& g, const void* src, void* dst, const LanczosScalars* sc,
+                             hipStream_t st)
+{
+    if (prec == 0) return imag_scale_t<double>(g, src, dst, sc, st);
+    if (prec == 2) return imag_scale_t<s48>(g, src, dst, sc, st);
+    return imag_scale_t<float>(g, src, dst, sc, st);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers.  The basis vectors 1..m-1 start at `basis`, vec_stride elements
 // apart (with s48 storage, vec_stride is the plane length and the m - 1
 // vectors are stored plane by plane, see basis_vec).

@@ -28,7 +28,10 @@
 
 namespace tdse {
 
-template <int S, typename T>
+// IMAG (term < 0): the Horner term of the diffusion (imaginary-time) step,
+// out = psi - (dtau / |term|) H in (the factor -i of the Taylor step replaced
+// by -1; Sec. 4, ground state calculation).
+template <int S, typename T, bool IMAG = false>
 __global__ void __launch_bounds__(kBlock)
 k_hsweep(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typename Stor<T>::ptr out,
          const double* __restrict__ step, int term)
@@ -39,7 +42,8 @@ k_hsweep(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typ
     if (i >= n) return;
     const RadialPoint rp = radial_point(I, i);
     const double er = step_value(step, g.n_inst, kEMid, I.inst) * rp.r;
-    const double c = (term > 0) ? step_value(step, g.n_inst, kDt, I.inst) / (double)term : 0.0;
+    const double c = IMAG ? step_value(step, g.n_inst, kDt, I.inst) / (double)(-term)
+                          : (term > 0) ? step_value(step, g.n_inst, kDt, I.inst) / (double)term : 0.0;
     const int64_t base = I.off;
     double2 prev = (I.l0 > 0) ? ldc(in, base + (int64_t)(I.l0 - 1) * n + i) : zero2();
     double2 cur = ldc(in, base + (int64_t)I.l0 * n + i);
@@ -51,7 +55,9 @@ k_hsweep(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typ
         const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
         const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
                                      g.kappa[l], g.kappa[l + 1]);
-        if (term > 0)
+        if (IMAG)
+            stc(out, row + i, horner_update_imag(ldc(psi, row + i), h, c));
+        else if (term > 0)
             stc(out, row + i, horner_update(ldc(psi, row + i), h, c));
         else
             stc(out, row + i, h);
@@ -265,6 +271,80 @@ __device__ __forceinline__ void copy_elem(P48 src, P48 dst, int64_t k)
     dst.l[k] = src.l[k];
 }
 
+// Stage i of an explicit Runge-Kutta step given by its tableau (see
+// launch_rk_stage): H at the stage's time on g_i, k_i = -i H g_i, then the
+// combination of the stage weights in stage order, j = 0..i.
+template <int S, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_rk_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::cptr psi, typename Stor<T>::aptr kv,
+           int64_t kstride, typename Stor<T>::ptr next, const double* __restrict__ step, RkStage A,
+           double* __restrict__ err_partial)
+{
+    __shared__ double lds[kBlock / 64];
+    const int t = my_tile_index(g);
+    const Tile I = g.tiles[t];
+    const int n = I.n;
+    const int i = I.r0 + (int)threadIdx.x;
+    double acc[1] = {0.0};
+    if (i < n) {
+        const RadialPoint rp = radial_point(I, i);
+        const double er = step_value(step, g.n_inst, A.slot, I.inst) * rp.r;
+        const double dt = step_value(step, g.n_inst, kDt, I.inst);
+        const int64_t base = I.off;
+        double2 prev = (I.l0 > 0) ? ldc(gin, base + (int64_t)(I.l0 - 1) * n + i) : zero2();
+        double2 cur = ldc(gin, base + (int64_t)I.l0 * n + i);
+        for (int l = I.l0; l < I.l1; ++l) {
+            const int64_t row = base + (int64_t)l * n;
+            const double2 nx = (l < I.lmax) ? ldc(gin, row + n + i) : zero2();
+            Neighbours<S> nb;
+            nb.load(gin + row, i, n);
+            const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
+            const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, nx, I.inv_dr2, v, er,
+                                         g.kappa[l], g.kappa[l + 1]);
+            const double2 ki = make_double2(h.y, -h.x);      // -i h
+            if (!A.last) stc(kv + (int64_t)A.stage * kstride, row + i, ki);
+            double2 sum = zero2(), dev = zero2();
+#pragma unroll
+            for (int j = 0; j < kRkMax; ++j) {
+                if (j < A.stage) {
+                    const double2 kj = ldc(kv + (int64_t)j * kstride, row + i);
+                    sum = make_double2(fma(A.w[j], kj.x, sum.x), fma(A.w[j], kj.y, sum.y));
+                    if (A.err) dev = make_double2(fma(A.we[j], kj.x, dev.x), fma(A.we[j], kj.y, dev.y));
+                }
+            }
+            sum = make_double2(fma(A.w[A.stage], ki.x, sum.x), fma(A.w[A.stage], ki.y, sum.y));
+            const double2 p = ldc(psi, row + i);
+            stc(next, row + i, make_double2(fma(dt, sum.x, p.x), fma(dt, sum.y, p.y)));
+            if (A.err) {
+                dev = make_double2(fma(A.we[A.stage], ki.x, dev.x), fma(A.we[A.stage], ki.y, dev.y));
+                const double dx = dt * dev.x, dy = dt * dev.y;
+                acc[0] = fma(dx, dx, fma(dy, dy, acc[0]));
+            }
+            prev = cur;
+            cur = nx;
+        }
+    }
+    if (A.err) {   // uniform over the launch
+        const double s = block_sum<1>(acc, lds);
+        if (threadIdx.x == 0) err_partial[t] = s;
+    }
+}
+
+// One workgroup per instance: sigma[k] += sqrt(sum_t partial[t] / U_k) over
+// the instance's sweep tiles (each thread adds its tiles in order, then the
+// fixed block tree).
+__global__ void __launch_bounds__(kBlock)
+k_rk_sigma(SweepGeom g, const double* __restrict__ partial, double* __restrict__ sigma)
+{
+    __shared__ double lds[kBlock / 64];
+    const int k = blockIdx.x;
+    const Inst& I = g.inst[k];
+    double acc[1] = {0.0};
+    for (int t = I.tbegin[kSweepTiles] + (int)threadIdx.x; t < I.tend[kSweepTiles]; t += kBlock) acc[0] += partial[t];
+    const double s = block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) sigma[k] += sqrt(s / ((double)(I.lmax + 1) * (double)I.n));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_copy(SweepGeom g, typename Stor<T>::cptr src, typename Stor<T>::ptr dst)
@@ -335,6 +415,12 @@ static hipError_t hsweep_t(const SweepGeom& g, const void* in, const void* psi, 
                            const double* step, int term, hipStream_t st)
 {
     using C = typename Cplx<T>::type;
+    if (term < 0) {   // the diffusion step's Horner terms: one radius per thread
+        if (g.variant != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_hsweep<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(in, g.plane),
+                           Stor<T>::cmake(psi, g.plane), Stor<T>::make(out, g.plane), step, term);
+        return hipGetLastError();
+    }
     if constexpr (std::is_same<T, s48>::value) {
         if (g.variant == 1) return hipErrorInvalidValue;   // two-radii sweeps: FP64 and FP32 storage only
     } else {
@@ -397,6 +483,41 @@ hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, cons
                                  : rk4_s<2, s48>(g, stage, gin, psi, acc, gout, step, st);
     return S == 1 ? rk4_s<1, float>(g, stage, gin, psi, acc, gout, step, st)
                   : rk4_s<2, float>(g, stage, gin, psi, acc, gout, step, st);
+}
+
+template <int S, typename T>
+static hipError_t rk_stage_t(const SweepGeom& g, const void* gin, const void* psi, void* kv, int64_t kstride, int nk,
+                             void* next, const double* step, const RkStage& a, double* err_partial, hipStream_t st)
+{
+    typename Stor<T>::aptr k;
+    if constexpr (std::is_same<T, s48>::value) {
+        char* b = static_cast<char*>(kv);
+        k = P48{reinterpret_cast<uint2*>(b), reinterpret_cast<unsigned*>(b + 8 * kstride * (int64_t)max(nk, 0))};
+    } else {
+        k = static_cast<typename Cplx<T>::type*>(kv);
+    }
+    hipLaunchKernelGGL((k_rk_stage<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(gin, g.plane),
+                       Stor<T>::cmake(psi, g.plane), k, kstride, Stor<T>::make(next, g.plane), step, a, err_partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk_stage(int prec, int S, const SweepGeom& g, const void* gin, const void* psi, void* kv,
+                           int64_t kstride, int nk, void* next, const double* step, const RkStage& a,
+                           double* err_partial, hipStream_t st)
+{
+    if (g.variant != 0 || a.stage < 0 || a.stage >= kRkMax) return hipErrorInvalidValue;
+    if (prec == 0) return S == 1 ? rk_stage_t<1, double>(g, gin, psi, kv, kstride, nk, next, step, a, err_partial, st)
+                                 : rk_stage_t<2, double>(g, gin, psi, kv, kstride, nk, next, step, a, err_partial, st);
+    if (prec == 2) return S == 1 ? rk_stage_t<1, s48>(g, gin, psi, kv, kstride, nk, next, step, a, err_partial, st)
+                                 : rk_stage_t<2, s48>(g, gin, psi, kv, kstride, nk, next, step, a, err_partial, st);
+    return S == 1 ? rk_stage_t<1, float>(g, gin, psi, kv, kstride, nk, next, step, a, err_partial, st)
+                  : rk_stage_t<2, float>(g, gin, psi, kv, kstride, nk, next, step, a, err_partial, st);
+}
+
+hipError_t launch_rk_sigma(const SweepGeom& g, const double* err_partial, double* sigma, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rk_sigma, dim3(g.n_inst), dim3(kBlock), 0, st, g, err_partial, sigma);
+    return hipGetLastError();
 }
 
 template <typename T>

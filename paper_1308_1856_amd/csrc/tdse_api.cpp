@@ -36,6 +36,68 @@ constexpr int kNumTimed = 7;
 
 }  // namespace
 
+namespace {
+
+// Butcher tableaux of the explicit Runge-Kutta methods of the appendix
+// "Runge-Kutta" (the published ones): b are the weights of the solution
+// carried forward (the higher order of a pair), bhat those of the embedded
+// solution (all zero without one).
+struct RkTableau {
+    int stages;
+    double c[kRkMax];
+    double a[kRkMax][kRkMax];
+    double b[kRkMax];
+    double bhat[kRkMax];
+};
+const RkTableau* rk_tableau(int method)
+{
+    static const RkTableau tabs[] = {
+        // Euler
+        {1, {0}, {{0}}, {1.0}, {0}},
+        // classic fourth order
+        {4, {0, 0.5, 0.5, 1.0},
+         {{0}, {0.5}, {0, 0.5}, {0, 0, 1.0}},
+         {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6}, {0}},
+        // Fehlberg 4(5): b of order 5, bhat of order 4
+        {6, {0, 1.0 / 4, 3.0 / 8, 12.0 / 13, 1.0, 1.0 / 2},
+         {{0}, {1.0 / 4}, {3.0 / 32, 9.0 / 32}, {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197},
+          {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104},
+          {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40}},
+         {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55},
+         {25.0 / 216, 0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0}},
+        // Cash-Karp 5(4)
+        {6, {0, 1.0 / 5, 3.0 / 10, 3.0 / 5, 1.0, 7.0 / 8},
+         {{0}, {1.0 / 5}, {3.0 / 40, 9.0 / 40}, {3.0 / 10, -9.0 / 10, 6.0 / 5},
+          {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27},
+          {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592, 253.0 / 4096}},
+         {37.0 / 378, 0, 250.0 / 621, 125.0 / 594, 0, 512.0 / 1771},
+         {2825.0 / 27648, 0, 18575.0 / 48384, 13525.0 / 55296, 277.0 / 14336, 1.0 / 4}},
+        // Dormand-Prince 5(4)
+        {7, {0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0},
+         {{0}, {1.0 / 5}, {3.0 / 40, 9.0 / 40}, {44.0 / 45, -56.0 / 15, 32.0 / 9},
+          {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729},
+          {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656},
+          {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}},
+         {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0},
+         {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200, 187.0 / 2100, 1.0 / 40}},
+        // Merson 4(3)
+        {5, {0, 1.0 / 3, 1.0 / 3, 1.0 / 2, 1.0},
+         {{0}, {1.0 / 3}, {1.0 / 6, 1.0 / 6}, {1.0 / 8, 0, 3.0 / 8}, {1.0 / 2, 0, -3.0 / 2, 2.0}},
+         {1.0 / 6, 0, 0, 2.0 / 3, 1.0 / 6},
+         {1.0 / 10, 0, 3.0 / 10, 2.0 / 5, 1.0 / 5}},
+    };
+    if (method < 0 || method >= (int)(sizeof tabs / sizeof tabs[0])) return nullptr;
+    return &tabs[method];
+}
+// state-shaped work vectors of a tableau step: k_0..k_{S-2} and two g buffers
+int rk_vecs(int method)
+{
+    const RkTableau* T = rk_tableau(method);
+    return T ? T->stages + 1 : 0;
+}
+
+}  // namespace
+
 struct tdse_ctx {
     std::string err;
     int n_inst = 0, stencil = 3, prec = 0;
@@ -86,6 +148,10 @@ struct tdse_ctx {
     hipEvent_t obs_fork = nullptr, obs_join = nullptr, obs_done[2] = {nullptr, nullptr};
     // Krylov dimension requested by the last tdse_step_lanczos call (0: none)
     int lz_m = 0;
+    // the Runge-Kutta tableau whose stage times upload_steps fills in
+    // (kEStage0 + i: E(t_n + c_i dt)); 0 stages for the other methods
+    int rk_stages = 0;
+    double rk_c[kRkMax] = {};
     // captured step graphs, keyed by the launch pattern of a chunk
     bool use_graphs = false;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
@@ -160,6 +226,7 @@ struct tdse_ctx {
         if (method == TDSE_METHOD_RK4) return 3;
         if (method == TDSE_METHOD_LANCZOS) return (size_t)std::max(1, order_or_m);
         if (method == TDSE_METHOD_TUNE) return 4;
+        if (method == TDSE_METHOD_RK_TABLEAU) return (size_t)rk_vecs(order_or_m);
         return 0;
     }
 };
@@ -213,7 +280,39 @@ double taylor_poly_abs(int order, double y)
     return std::abs(sum);
 }
 
+// |sum_{k<=P} (-x)^k / k!|: the diffusion step's polynomial of exp(-x)
+double taylor_real_poly_abs(int order, double x)
+{
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k <= order; ++k) {
+        term *= -x / (double)k;
+        sum += term;
+    }
+    return std::fabs(sum);
+}
+
 }  // namespace
+
+extern "C" double tdse_taylor_real_stability_limit(int32_t order)
+{
+    static std::mutex mu;
+    static std::map<int, double> cache;
+    if (order < 1 || order > 16) return 0.0;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(order);
+    if (it != cache.end()) return it->second;
+    const double tol = 1.0 + 1e-12;
+    double x = 0.0;
+    const double h = 1e-4;
+    while (x < 20.0 && taylor_real_poly_abs(order, x + h) <= tol) x += h;
+    double a = x, b = x + h;
+    for (int i = 0; i < 60; ++i) {
+        const double mid = 0.5 * (a + b);
+        if (taylor_real_poly_abs(order, mid) <= tol) a = mid; else b = mid;
+    }
+    cache[order] = a;
+    return a;
+}
 
 extern "C" double tdse_taylor_stability_limit(int32_t order)
 {
@@ -594,7 +693,9 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->off_lz = take(sizeof(LanczosScalars) * n_inst);
     // Lanczos dots; the observables pass; or the strips' main partials (two
     // sets, by step parity) and the population tiles
-    c->partial_doubles = std::max({(size_t)c->tiles[kReduceTiles].size() * 2 * kMaxKrylov,
+    // (and the Runge-Kutta stages' deviation partials, one per sweep tile:
+    // at most total_cols, the one-row tiling)
+    c->partial_doubles = std::max({(size_t)c->total_cols, (size_t)c->tiles[kReduceTiles].size() * 2 * kMaxKrylov,
                                    (size_t)c->tiles[kObsTiles].size() * kObsMainQ +
                                        (size_t)c->tiles[kPopTiles].size() * kObsPopQ,
                                    2 * c->strip_units_cap * kObsMainQ +
@@ -825,6 +926,9 @@ tdse_status upload_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0
             row[kDt * n + k] = dt[k];
             const int64_t done = s0 + s + 1;
             row[kRec * n + k] = (obs_every > 0 && done % obs_every == 0) ? (double)(done / obs_every - 1) : -1.0;
+            for (int i = 0; i < kRkMax; ++i)
+                row[(kEStage0 + i) * n + k] =
+                    (pulses && i < c->rk_stages) ? field_at(pulses[k], t0[k] + (step + c->rk_c[i]) * dt[k]) : 0.0;
         }
     }
     hipError_t e = hipMemcpyAsync(c->d_step(), h, sizeof(double) * kSlots * n * (size_t)count,
@@ -1138,6 +1242,69 @@ extern "C" tdse_status tdse_step_taylor(tdse_ctx* c, const tdse_pulse* pulses, c
                      [&](const double* step) { return taylor_step_launches(c, step, order, cur); }, true);
 }
 
+// Sec. 4 "Ground state calculation": field-free diffusion steps (imaginary
+// time), each the order-P Taylor polynomial of exp(-dtau H) in Horner form (one
+// launch per term, one radius per thread), then the norm of the result, the
+// energy estimate -ln(n2)/(2 dtau) and the renormalisation into the state.
+extern "C" tdse_status tdse_step_imag(tdse_ctx* c, const double* dtau, int32_t order, int32_t nsteps,
+                                      double* d_energy)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_step_imag: not bound");
+    if (!dtau) return c->fail(TDSE_E_INVALID, "tdse_step_imag: null argument");
+    if (order < 1 || order > 16) return c->fail(TDSE_E_INVALID, "tdse_step_imag: order must be 1..16");
+    if (nsteps < 0) return c->fail(TDSE_E_INVALID, "tdse_step_imag: nsteps < 0");
+    const size_t need = tdse_workspace_bytes(c, TDSE_METHOD_TAYLOR, order);
+    if (c->work_bytes < need)
+        return c->fail(TDSE_E_WORKSPACE, "tdse_step_imag: workspace too small (" + std::to_string(need) +
+                                             " bytes needed)");
+    const double xp = tdse_taylor_real_stability_limit(order);
+    for (int k = 0; k < c->n_inst; ++k) {
+        if (!(dtau[k] > 0.0) || !std::isfinite(dtau[k])) return c->fail(TDSE_E_INVALID, "tdse_step_imag: dtau must be > 0");
+        const double lam = cached_bound(c, k, 0.0);
+        if (dtau[k] * lam > xp) {
+            char buf[256];
+            std::snprintf(buf, sizeof buf,
+                          "instance %d: dtau*lambda_max = %.4g exceeds the order-%d real-axis limit %.4g", k,
+                          dtau[k] * lam, order, xp);
+            return c->fail(TDSE_E_UNSTABLE, buf);
+        }
+    }
+    c->drop_graphs();
+    // one table of step scalars serves every step: no field, dt = dtau
+    std::vector<double> zero(c->n_inst, 0.0);
+    tdse_status st = upload_steps(c, nullptr, zero.data(), dtau, 0, 1, 0);
+    if (st != TDSE_OK) return st;
+    const int S = c->stencil == 3 ? 1 : 2;
+    const SweepGeom gs = c->geom(kSweepTiles);   // one radius per thread (variant 0)
+    const SweepGeom red = c->geom(kReduceTiles);
+    const double* step = c->d_step();
+    double* part = c->d_partial();
+    LanczosScalars* sc = c->d_lz();
+    void* psi = c->d_state;
+    void* v0 = c->d_vec(0);
+    void* v1 = c->d_vec(1);
+    // the input normalised first (no energy recorded)
+    hipError_t e = launch_lz_norm(c->prec, red, psi, part, c->stream);
+    if (e == hipSuccess) e = launch_imag_finish(red, part, step, 0, nullptr, 0, 0, sc, c->stream);
+    if (e == hipSuccess) e = launch_imag_scale(c->prec, red, psi, v0, sc, c->stream);
+    if (e == hipSuccess) e = launch_copy(c->prec, red, v0, psi, c->stream);
+    for (int32_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+        // w_P = psi - dtau/P H psi, ..., w_1 = psi - dtau H w_2, alternating v0 / v1
+        const void* in = psi;
+        void* out = v0;
+        for (int k = order; k >= 1 && e == hipSuccess; --k) {
+            e = launch_hsweep(c->prec, S, gs, in, psi, out, step, -k, c->stream);
+            in = out;
+            out = (out == v0) ? v1 : v0;
+        }
+        if (e == hipSuccess) e = launch_lz_norm(c->prec, red, in, part, c->stream);
+        if (e == hipSuccess) e = launch_imag_finish(red, part, step, 1, d_energy, nsteps, s, sc, c->stream);
+        if (e == hipSuccess) e = launch_imag_scale(c->prec, red, in, psi, sc, c->stream);
+    }
+    return (e == hipSuccess) ? TDSE_OK : c->hip_fail(e, "tdse_step_imag");
+}
+
 extern "C" tdse_status tdse_step_rk4(tdse_ctx* c, const tdse_pulse* pulses, const double* t0,
                                      const double* dt, int32_t nsteps, int32_t obs_every,
                                      tdse_obs* d_obs)
@@ -1186,6 +1353,125 @@ extern "C" tdse_status tdse_step_rk4(tdse_ctx* c, const tdse_pulse* pulses, cons
         }
         return hipSuccess;
     });
+}
+
+extern "C" double tdse_rk_stability_limit(int32_t method)
+{
+    const RkTableau* T = rk_tableau(method);
+    if (!T) return 0.0;
+    // R(z) = 1 + sum_k gamma_k z^k, gamma_k = b^T A^(k-1) 1: the step's factor
+    // on dy/dt = lambda y; the largest y with |R(i y')| <= 1 + 1e-12 up to y
+    double gamma[kRkMax + 1] = {1.0};
+    double v[kRkMax];
+    for (int i = 0; i < T->stages; ++i) v[i] = 1.0;
+    for (int k = 1; k <= T->stages; ++k) {
+        double g = 0.0;
+        for (int i = 0; i < T->stages; ++i) g += T->b[i] * v[i];
+        gamma[k] = g;
+        double w[kRkMax];
+        for (int i = 0; i < T->stages; ++i) {
+            w[i] = 0.0;
+            for (int j = 0; j < T->stages; ++j) w[i] += T->a[i][j] * v[j];
+        }
+        for (int i = 0; i < T->stages; ++i) v[i] = w[i];
+    }
+    auto mag = [&](double y) {
+        std::complex<double> z(0.0, y), zk(1.0, 0.0), r(1.0, 0.0);
+        for (int k = 1; k <= T->stages; ++k) {
+            zk *= z;
+            r += gamma[k] * zk;
+        }
+        return std::abs(r);
+    };
+    const double tol = 1.0 + 1e-12;
+    double y = 0.0;
+    const double h = 1e-4;
+    while (y < 10.0 && mag(y + h) <= tol) y += h;
+    double a = y, b = y + h;
+    for (int i = 0; i < 60; ++i) {
+        const double mid = 0.5 * (a + b);
+        if (mag(mid) <= tol) a = mid; else b = mid;
+    }
+    return a;
+}
+
+// Appendix "Runge-Kutta" (eq. RKDeriv): one launch per stage over the sweep
+// tiles; psi rotates through the state and work vectors 0 and 1 as in the
+// Taylor path (stage 0 reads psi, stage i reads g_i from one of the two other
+// buffers and writes g_{i+1} to the other; the last stage writes the new psi
+// there), the stage derivatives k_0..k_{S-2} sit in work vectors 2..S.
+extern "C" tdse_status tdse_step_rk(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, const double* dt,
+                                    int32_t method, int32_t nsteps, int32_t obs_every, tdse_obs* d_obs,
+                                    double* d_sigma)
+{
+    if (!c) return TDSE_E_INVALID;
+    const RkTableau* T = rk_tableau(method);
+    if (!T) return c->fail(TDSE_E_INVALID, "tdse_step_rk: unknown method");
+    tdse_status st = check_common(c, pulses, t0, dt, nsteps, obs_every, d_obs, TDSE_METHOD_RK_TABLEAU, method);
+    if (st != TDSE_OK) return st;
+    const double y = tdse_rk_stability_limit(method);
+    for (int k = 0; k < c->n_inst; ++k) {
+        const double lam = cached_bound(c, k, pulses[k].e0);
+        if (dt[k] * lam > y) {
+            char buf[256];
+            std::snprintf(buf, sizeof buf,
+                          "instance %d: dt*lambda_max = %.4g exceeds the method's stability limit %.4g", k,
+                          dt[k] * lam, y);
+            return c->fail(TDSE_E_UNSTABLE, buf);
+        }
+    }
+    bool pair = false;
+    for (int i = 0; i < T->stages; ++i) pair = pair || T->bhat[i] != 0.0;
+    const bool err = pair && d_sigma != nullptr;
+    // the stage times the step table carries (captured graphs depend on them
+    // only through the uploaded values)
+    c->rk_stages = T->stages;
+    for (int i = 0; i < kRkMax; ++i) c->rk_c[i] = (i < T->stages) ? T->c[i] : 0.0;
+    const int S = c->stencil == 3 ? 1 : 2;
+    const SweepGeom g = c->geom();
+    void* kv = c->d_vec(2);
+    const int nk = T->stages - 1;
+    // k vectors: one state-shaped vector apart (48-bit: plane by plane)
+    const int64_t kstride = (c->prec == TDSE_FP48) ? c->plane() : (int64_t)(c->state_bytes() / c->elem);
+    double* part = c->d_partial();
+    void* cur = c->d_state;
+    const int64_t key = 4000 + 10 * method + (err ? 1 : 0) + (int64_t)reinterpret_cast<uintptr_t>(d_sigma) * 100;
+    st = run_steps(c, pulses, t0, dt, nsteps, obs_every, d_obs, key, &cur, [&](const double* step) {
+        void* bufs[2];
+        int nb = 0;
+        for (void* b : {static_cast<void*>(c->d_state), static_cast<void*>(c->d_vec(0)), static_cast<void*>(c->d_vec(1))})
+            if (b != cur && nb < 2) bufs[nb++] = b;
+        const void* gin = cur;
+        void* out = nullptr;
+        for (int i = 0; i < T->stages; ++i) {
+            RkStage a{};
+            a.stage = i;
+            a.last = (i == T->stages - 1) ? 1 : 0;
+            a.err = (a.last && err) ? 1 : 0;
+            a.slot = kEStage0 + i;
+            for (int j = 0; j <= i; ++j) {
+                // g_{i+1} = psi + dt sum_j a_{i+1,j} k_j, or the new state
+                a.w[j] = a.last ? T->b[j] : T->a[i + 1][j];
+                a.we[j] = T->b[j] - T->bhat[j];
+            }
+            out = bufs[i & 1];
+            hipError_t e;
+            {
+                TimedLaunch tl(c, 1);
+                e = launch_rk_stage(c->prec, S, g, gin, cur, kv, kstride, nk, out, step, a, part, c->stream);
+            }
+            if (e != hipSuccess) return e;
+            gin = out;
+        }
+        if (err) {
+            hipError_t e = launch_rk_sigma(g, part, d_sigma, c->stream);
+            if (e != hipSuccess) return e;
+        }
+        cur = out;
+        return hipSuccess;
+    });
+    c->rk_stages = 0;
+    return st;
 }
 
 extern "C" tdse_status tdse_step_lanczos(tdse_ctx* c, const tdse_pulse* pulses, const double* t0,

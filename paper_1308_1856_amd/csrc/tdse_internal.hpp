@@ -87,7 +87,11 @@ struct SweepGeom {
 
 // Per-step scalars, FP64, laid out [slot][instance] with these slots:
 // kRec: index of the observable record written after this step (-1: none).
-enum StepSlot { kEStart = 0, kEMid = 1, kEEnd = 2, kTEnd = 3, kDt = 4, kRec = 5, kSlots = 6 };
+// kEStage0 + i: the field at t_n + c_i dt for stage i of an explicit
+// Runge-Kutta method given by its tableau (zero for other methods).
+constexpr int kRkMax = 8;           // most stages of a tableau
+enum StepSlot { kEStart = 0, kEMid = 1, kEEnd = 2, kTEnd = 3, kDt = 4, kRec = 5, kEStage0 = 6,
+                kSlots = kEStage0 + kRkMax };
 __host__ __device__ inline double step_value(const double* st, int n_inst, int slot, int inst)
 {
     return st[slot * n_inst + inst];
@@ -95,6 +99,8 @@ __host__ __device__ inline double step_value(const double* st, int n_inst, int s
 
 // out = H(E_mid) in                              (term == 0)
 // out = psi + (-i dt / term) H(E_mid) in         (term >= 1: one Horner term)
+// out = psi - (dt / |term|) H(E_mid) in          (term <= -1: a Horner term of the
+//                                                 diffusion step; g.variant 0 only)
 // `out` must not overlap `in` or `psi` (`in` may equal `psi`).
 hipError_t launch_hsweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi,
                          void* out, const double* step, int term, hipStream_t st);
@@ -128,6 +134,26 @@ hipError_t launch_rk4_strip(int prec, int S, const SweepGeom& g, const void* in,
 hipError_t launch_rk4_stage(int prec, int S, const SweepGeom& g, int stage, const void* gin,
                             const void* psi, void* acc, void* gout, const double* step,
                             hipStream_t st);
+
+// Stage i of an explicit Runge-Kutta step (appendix "Runge-Kutta", eq.
+// RKDeriv) over the sweep tiles (one radius per thread, g.variant 0):
+//   k_i = -i H(t_n + c_i dt) g_i            (g_i read from gin; E from slot)
+//   next = psi + dt sum_{j<=i} w_j k_j      (g_{i+1}, or the new state when last)
+// k_i is stored at kv + i kstride unless last (k_0..k_{i-1} are read there);
+// with err, the last stage also adds dt sum_j we_j k_j (the pair's deviation)
+// as |.|^2 to a per-tile partial, err_partial[tile].  With 48-bit storage the
+// nk stored k vectors are laid out plane by plane (kstride = plane length).
+struct RkStage {
+    int32_t stage, last, err, slot;
+    double w[kRkMax];
+    double we[kRkMax];
+};
+hipError_t launch_rk_stage(int prec, int S, const SweepGeom& g, const void* gin, const void* psi, void* kv,
+                           int64_t kstride, int nk, void* next, const double* step, const RkStage& a,
+                           double* err_partial, hipStream_t st);
+// sigma[k] += sqrt(sum of instance k's err partials (sweep tiles) / U_k),
+// U_k = (lmax + 1) N: the root mean square deviation of the step.
+hipError_t launch_rk_sigma(const SweepGeom& g, const double* err_partial, double* sigma, hipStream_t st);
 
 // Observables: per-tile partial sums of norm, p_ion, dipole and acceleration
 // over the reduce tiles (kObsMainQ per tile, stored [q][tile]) and of p_g and
@@ -173,6 +199,17 @@ hipError_t launch_lz_expm(const SweepGeom& g, const double* step, LanczosScalars
 hipError_t launch_lz_reset(const SweepGeom& g, int m, LanczosScalars* sc, hipStream_t st);
 hipError_t launch_lz_recombine(int prec, const SweepGeom& g, int m, void* psi, const void* basis,
                                int64_t vec_stride, const LanczosScalars* sc, hipStream_t st);
+
+// The diffusion (imaginary-time) step's renormalisation, over the reduce
+// tiles.  finish: per instance, n2 = dr * (sum of the lz_norm partials);
+// scale_k = 1 / sqrt(n2) kept in sc[k].norm0; with energy != nullptr also
+// energy[k * e_stride + e_index] = -ln(n2) / (2 dtau) (dtau from the step
+// table) when `record` is set.  scale: dst = scale_k * src.
+hipError_t launch_imag_finish(const SweepGeom& g, const double* partial, const double* step, int record,
+                              double* energy, int64_t e_stride, int64_t e_index, LanczosScalars* sc,
+                              hipStream_t st);
+hipError_t launch_imag_scale(int prec, const SweepGeom& g, const void* src, void* dst, const LanczosScalars* sc,
+                             hipStream_t st);
 
 // Number of elements whose stored values differ bit for bit, added to *count.
 hipError_t launch_count_diff(int prec, const SweepGeom& g, const void* a, const void* b,

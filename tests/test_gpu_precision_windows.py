@@ -112,3 +112,22 @@ def test_large_grid_window_200_steps():
     say("large-grid window: 25.7M unknowns, 200 Taylor-8 steps, FP64 / FP48 / FP32")
     compare("25.7M grid 200 steps", grids_of, "taylor", 8, p, 0.5 * wl.pulse.duration, wl.dt, 200, 1, [psi],
             (4, 32, 1))
+
+
+def test_lanczos_window_2000_steps():
+    # N = 2e4, dr = 0.05, lmax = 64, 5-point, Lanczos m = 20 (4-cycle 800 nm
+    # 1e14 W/cm^2 pulse), 2000 steps from mid-pulse at dt = 1e-4, where the
+    # FP64 step reproduces itself to round-off (at dt = 0.01 a relative 1e-15
+    # perturbation of the start grows to 1% of the state in 200 steps, in any
+    # precision)
+    t = lib()
+    wl = workloads.WORKLOADS["hydrogen_n20000_l64_fp32_lanczos20"]
+    p = t.Pulse(wl.pulse.e0, wl.pulse.omega, wl.pulse.n_cycles, wl.pulse.cep, wl.pulse.t_on)
+    psi = mixed_state(wl.n, wl.lmax, wl.dr, 78)
+
+    def grids_of(prec):
+        return [t.Grid(wl.n, wl.lmax, wl.dr, wl.stencil, prec, 1.0, wl.r_ion)]
+
+    say("Lanczos window: 1.3M unknowns, m = 20, 2000 steps of 1e-4 au, FP64 / FP48 / FP32")
+    compare("Lanczos 2000 steps", grids_of, "lanczos", 20, p, 0.5 * wl.pulse.duration - 0.1, 1e-4, 2000, 20,
+            [psi])

@@ -58,6 +58,40 @@ def test_stability_limits(tdse):
     assert tdse.tdse_taylor_stability_limit(0) == 0.0
 
 
+def test_real_axis_stability_limits(tdse):
+    # the diffusion step's polynomial sum (-x)^k/k!: |p| <= 1 on [0, 2] for
+    # P = 1, 2 (|1 - x| and 1 - x + x^2/2 reach 1 at x = 2), the classical
+    # 2.785 of RK4 for P = 4, and at each limit the next x leaves the interval
+    p = lambda x, P: abs(sum((-x) ** k / math.factorial(k) for k in range(P + 1)))
+    assert tdse.tdse_taylor_real_stability_limit(1) == pytest.approx(2.0, abs=1e-9)
+    assert tdse.tdse_taylor_real_stability_limit(2) == pytest.approx(2.0, abs=1e-9)
+    assert tdse.tdse_taylor_real_stability_limit(4) == pytest.approx(2.785293563, abs=1e-6)
+    for P in (3, 6, 8, 12):
+        x = tdse.tdse_taylor_real_stability_limit(P)
+        assert p(x, P) <= 1 + 2e-12 and p(x + 1e-6, P) > 1 + 1e-12
+        assert all(p(y, P) <= 1 + 2e-12 for y in np.linspace(0, x, 2001))
+
+
+def test_rk_stability_limits_from_the_oracle_tableaux(tdse, orc):
+    # the library's limit for each tableau equals the one found from the
+    # oracle's copy of the tableau: |R(iy)| <= 1 with R(z) = 1 + sum_k
+    # (b^T A^(k-1) 1) z^k; RK4 gives the Taylor-4 value 2 sqrt(2)
+    assert tdse.tdse_rk_stability_limit(1) == pytest.approx(2 * math.sqrt(2), abs=1e-9)
+    assert tdse.tdse_rk_stability_limit(0) < 2e-6                     # Euler: none
+    assert tdse.tdse_rk_stability_limit(6) == 0.0                     # unknown method
+    for m in range(6):
+        c, a, b, bh, s = orc.rk_tableau(m)
+        gam = [1.0]
+        v = np.ones(s)
+        for _ in range(s):
+            gam.append(float(b @ v))
+            v = a @ v
+        R = lambda y: abs(sum(gk * (1j * y) ** k for k, gk in enumerate(gam)))
+        y = tdse.tdse_rk_stability_limit(m)
+        assert R(y) <= 1 + 2e-12 and R(y + 1e-6) > 1 + 1e-12
+        assert all(R(x) <= 1 + 2e-12 for x in np.linspace(0, y, 1001))
+
+
 @pytest.mark.parametrize("stencil,lmax,dr", [(3, 8, 0.1), (5, 12, 0.05)])
 def test_lambda_bound_against_oracle_and_spectrum(tdse, orc, stencil, lmax, dr):
     g = tdse.Grid(600, lmax, dr, stencil)
