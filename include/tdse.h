@@ -268,6 +268,25 @@ tdse_status tdse_lanczos_dims(tdse_ctx* ctx, int32_t* host_meff);
 tdse_status tdse_observables(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t,
                              tdse_obs* host_out);
 
+/* For callers that cannot allocate device memory, or bind a workspace for
+ * scratch (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the observables of tdse_observables, computed by the
+ * same kernels in the same order (bit-identical records), with the call's
+ * scratch (the step scalars of the record, the per-tile partial sums and the
+ * records before their copy to host_out) in a static device buffer of the
+ * library, TDSE_NOALLOC_SCRATCH_BYTES bytes per GPU, held until the process
+ * ends, instead of the bound workspace; the context's tables still come from
+ * the workspace bound by tdse_bind.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).  The current device must
+ * be the one of the bound stream.  Returns TDSE_E_WORKSPACE (before any
+ * device work) if the context's grids need more scratch than that,
+ * TDSE_E_NONFINITE if any norm is not finite.  Every call on one GPU uses the
+ * same buffer: calls that overlap on one GPU (other threads, other streams)
+ * race.  Synchronises the stream. */
+#define TDSE_NOALLOC_SCRATCH_BYTES (8u << 20)
+tdse_status tdse_observables_noalloc(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t,
+                                     tdse_obs* host_out);
+
 /* Gershgorin bound on the spectral radius of H for instance k when
  * |E| <= e_max: the largest absolute row sum of eq. h_matrix. */
 double tdse_lambda_max_bound(const tdse_ctx* ctx, int32_t inst, double e_max);

@@ -38,7 +38,7 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_use_graphs", "tdse_set_obs_overlap", "tdse_set_obs_fusion", "tdse_obs_fusion", "tdse_set_rk4_fusion", "tdse_rk4_fusion", "tdse_autotune", "tdse_tile_rows", "tdse_sweep_variant",
             "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_taylor_fusion_kind",
             "tdse_set_taylor_fusion", "tdse_set_sweep_shape", "tdse_lanczos_dims",
-            "tdse_step_imag", "tdse_taylor_real_stability_limit",
+            "tdse_observables_noalloc", "tdse_step_imag", "tdse_taylor_real_stability_limit",
             "tdse_step_rk", "tdse_rk_stability_limit")
 
 
@@ -91,6 +91,7 @@ def _load():
         "tdse_step_rk4": ([ctxp, ctypes.POINTER(Pulse), dp, dp, i32, i32, vp], i32),
         "tdse_step_lanczos": ([ctxp, ctypes.POINTER(Pulse), dp, dp, i32, i32, i32, vp], i32),
         "tdse_observables": ([ctxp, ctypes.POINTER(Pulse), dp, ctypes.POINTER(Obs)], i32),
+        "tdse_observables_noalloc": ([ctxp, ctypes.POINTER(Pulse), dp, ctypes.POINTER(Obs)], i32),
         "tdse_lambda_max_bound": ([ctxp, i32, ctypes.c_double], ctypes.c_double),
         "tdse_taylor_stability_limit": ([i32], ctypes.c_double),
         "tdse_taylor_real_stability_limit": ([i32], ctypes.c_double),
@@ -223,6 +224,14 @@ def tdse_observables(ctx, pulses, t) -> np.ndarray:
     n = lib.tdse_num_instances(ctx)
     out = (Obs * n)()
     _check(ctx, lib.tdse_observables(ctx, _pulses(pulses), _dvec(t, n), out))
+    return np.frombuffer(out, dtype=np.float64).reshape(n, OBS_DOUBLES).copy()
+
+
+def tdse_observables_noalloc(ctx, pulses, t) -> np.ndarray:
+    """tdse_observables with its scratch in the library's static device buffer."""
+    n = lib.tdse_num_instances(ctx)
+    out = (Obs * n)()
+    _check(ctx, lib.tdse_observables_noalloc(ctx, _pulses(pulses), _dvec(t, n), out))
     return np.frombuffer(out, dtype=np.float64).reshape(n, OBS_DOUBLES).copy()
 
 
@@ -442,6 +451,10 @@ class Propagator:
     def observables(self, pulses, t) -> np.ndarray:
         self._enter()
         return tdse_observables(self.ctx, self._pulse_list(pulses), self._per_inst(t))
+
+    def observables_noalloc(self, pulses, t) -> np.ndarray:
+        self._enter()
+        return tdse_observables_noalloc(self.ctx, self._pulse_list(pulses), self._per_inst(t))
 
     def use_graphs(self, enable: bool):
         tdse_use_graphs(self.ctx, enable)

@@ -979,11 +979,11 @@ tdse_status check_stable(tdse_ctx* c, const tdse_pulse* pulses, const double* dt
 
 // observables of the state after step s (within the uploaded chunk at `step`)
 hipError_t launch_obs(tdse_ctx* c, const void* psi, const double* step, double* records,
-                      int64_t rec_stride, hipStream_t st)
+                      int64_t rec_stride, hipStream_t st, double* partial = nullptr)
 {
     TimedLaunch tl(c, 2, st);
     const SweepGeom red = c->geom(kObsTiles), pop = c->geom(kPopTiles);
-    double* pmain = c->d_partial();
+    double* pmain = partial ? partial : c->d_partial();
     double* ppop = pmain + (size_t)red.n_tiles * kObsMainQ;
     hipError_t e = launch_obs_partial(c->prec, red, pop, c->d_radial(), psi, pmain, ppop, st);
     if (e != hipSuccess) return e;
@@ -1544,6 +1544,117 @@ extern "C" tdse_status tdse_observables(tdse_ctx* c, const tdse_pulse* pulses, c
     if (e != hipSuccess) return c->hip_fail(e, "tdse_observables");
     for (int k = 0; k < c->n_inst; ++k)
         if (!std::isfinite(host_out[k].norm)) return c->fail(TDSE_E_NONFINITE, "tdse_observables: norm is not finite");
+    return TDSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// observables without a workspace for scratch: a static device buffer
+// ---------------------------------------------------------------------------
+// The scratch of tdse_observables_noalloc: the call's step scalars, the
+// per-tile partial sums and the records before their copy to the host.  One
+// copy per GPU (the runtime loads the code object on each device used), held
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy: it takes the device address from hipGetSymbolAddress, per
+// device (scratch_ptr).
+static __device__ __align__(256) char scratch[TDSE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with the device current).
+hipError_t scratch_ptr(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// Byte layout of the scratch for a context: [step scalars | partial sums |
+// records], each region 256-byte aligned.
+struct NoallocLayout {
+    size_t step = 0, partial = 0, records = 0, total = 0;
+};
+NoallocLayout noalloc_layout(const tdse_ctx* c)
+{
+    NoallocLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, kAlign);
+        return at;
+    };
+    L.step = take(sizeof(double) * kSlots * (size_t)c->n_inst);
+    L.partial = take(sizeof(double) * ((size_t)c->tiles[kObsTiles].size() * kObsMainQ +
+                                       (size_t)c->tiles[kPopTiles].size() * kObsPopQ));
+    L.records = take(sizeof(tdse_obs) * (size_t)c->n_inst);
+    L.total = o;
+    return L;
+}
+}  // namespace
+
+extern "C" tdse_status tdse_observables_noalloc(tdse_ctx* c, const tdse_pulse* pulses, const double* t,
+                                                tdse_obs* host_out)
+{
+    if (!c) return TDSE_E_INVALID;
+    const NoallocLayout L = noalloc_layout(c);
+    if (L.total > (size_t)TDSE_NOALLOC_SCRATCH_BYTES)
+        return c->fail(TDSE_E_WORKSPACE, "tdse_observables_noalloc: the grids need " + std::to_string(L.total) +
+                                             " bytes of scratch, more than the static " +
+                                             std::to_string((size_t)TDSE_NOALLOC_SCRATCH_BYTES));
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_observables_noalloc: not bound");
+    if (!pulses || !t || !host_out) return c->fail(TDSE_E_INVALID, "tdse_observables_noalloc: null argument");
+    void* base = nullptr;
+    hipError_t e = scratch_ptr(&base);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_observables_noalloc: scratch address");
+    char* sb = static_cast<char*>(base);
+    double* d_step = reinterpret_cast<double*>(sb + L.step);
+    double* d_partial = reinterpret_cast<double*>(sb + L.partial);
+    double* d_rec = reinterpret_cast<double*>(sb + L.records);
+    // the step scalars of one record at time t (the fields the finish reads:
+    // t, E(t), record index 0), staged in the context's pinned buffer; every
+    // scratch value a kernel reads is written first in this call, so nothing
+    // needs clearing
+    const int b = c->step_buf;
+    c->step_buf ^= 1;
+    if (c->step_ev_used[b]) {
+        e = hipEventSynchronize(c->step_ev[b]);
+        if (e != hipSuccess) return c->hip_fail(e, "tdse_observables_noalloc: staging wait");
+    }
+    double* h = c->h_step[b];
+    const int n = c->n_inst;
+    for (int k = 0; k < n; ++k) {
+        h[kEStart * n + k] = 0.0;
+        h[kEMid * n + k] = 0.0;
+        h[kEEnd * n + k] = field_at(pulses[k], t[k]);
+        h[kTEnd * n + k] = t[k];
+        h[kDt * n + k] = 1.0;
+        h[kRec * n + k] = 0.0;
+    }
+    e = hipMemcpyAsync(d_step, h, sizeof(double) * kSlots * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->step_ev[b], c->stream);
+    if (e == hipSuccess) c->step_ev_used[b] = true;
+    if (e == hipSuccess) e = launch_obs(c, c->d_state, d_step, d_rec, kObsRecord, c->stream, d_partial);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_out, d_rec, sizeof(tdse_obs) * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_observables_noalloc");
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(host_out[k].norm))
+            return c->fail(TDSE_E_NONFINITE, "tdse_observables_noalloc: norm is not finite");
     return TDSE_OK;
 }
 

@@ -157,6 +157,29 @@ def test_fp48_state_is_two_planes(tdse):
         tdse.tdse_destroy(ctx)
 
 
+def test_noalloc_observables_refuse_grids_beyond_the_static_scratch(tdse):
+    # 20000 small grids need ~10 MB of scratch (step scalars, partial sums,
+    # records), more than the static 8 MiB: refused before any device work
+    # (the context is not even bound)
+    ctx = tdse.tdse_init_grid([tdse.Grid(8, 0, 0.5).desc()] * 20000)
+    try:
+        pulses = [tdse.Pulse(0.0, 1.0, 1.0, 0.0, 0.0)] * 20000
+        with pytest.raises(tdse.TdseError) as e:
+            tdse.tdse_observables_noalloc(ctx, pulses, [0.0] * 20000)
+        assert e.value.code == -7
+        assert "scratch" in tdse.lib.tdse_last_error(ctx).decode()
+    finally:
+        tdse.tdse_destroy(ctx)
+    # a small context passes the size check and stops at the missing binding
+    ctx = tdse.tdse_init_grid([tdse.Grid(300, 3, 0.1).desc()])
+    try:
+        with pytest.raises(tdse.TdseError) as e:
+            tdse.tdse_observables_noalloc(ctx, [tdse.Pulse(0.0, 1.0, 1.0, 0.0, 0.0)], [0.0])
+        assert e.value.code == -8
+    finally:
+        tdse.tdse_destroy(ctx)
+
+
 def test_calls_before_bind_fail_cleanly(tdse):
     ctx = tdse.tdse_init_grid([tdse.Grid(100, 2, 0.1).desc()])
     try:
