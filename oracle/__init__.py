@@ -107,6 +107,13 @@ def lib():
         L.orc_propagate_rk.argtypes = [gp, pp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                        ctypes.c_int64, ctypes.c_double, dp, ctypes.c_int, ip, dp, dp, dp]
         L.orc_propagate_rk.restype = ctypes.c_double
+        L.orc_mask.argtypes, L.orc_mask.restype = [ctypes.c_double, ctypes.c_double, ctypes.c_double], ctypes.c_double
+        L.orc_apply_mask.argtypes = [gp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_radial_current.argtypes, L.orc_radial_current.restype = [gp, ctypes.c_int, dp], ctypes.c_double
+        L.orc_propagate_abs.argtypes = [gp, pp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_double, dp, ctypes.c_int, ip, dp,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, dp]
+        L.orc_propagate_abs.restype = ctypes.c_int
         L.orc_imag_step.argtypes, L.orc_imag_step.restype = [gp, ctypes.c_double, ctypes.c_int, dp], ctypes.c_double
         L.orc_imag_propagate.argtypes = [gp, ctypes.c_double, ctypes.c_int, ctypes.c_int64, dp, dp]
         L.orc_initial_state.argtypes = [gp, dp, dp]
@@ -256,6 +263,38 @@ def propagate(g: Grid, p: Pulse, method: int, order_or_m: int, t0: float, dt: fl
     return psi, obs[:n_obs], used
 
 
+def mask(r: float, r_b: float, p: float) -> float:
+    """Absorbing mask M(r) (Sec. 2.1), the one-step factor of W."""
+    return float(lib().orc_mask(float(r), float(r_b), float(p)))
+
+
+def radial_current(g: Grid, j: int, psi) -> float:
+    """J = sum_l Im[f_l^* df_l/dr] at grid point j (eq. flux, length gauge)."""
+    psi = _state(g, psi)
+    gc = g.c()
+    return float(lib().orc_radial_current(ctypes.byref(gc), int(j), _dptr(psi)))
+
+
+def propagate_abs(g: Grid, p: Pulse, method: int, order_or_m: int, t0: float, dt: float, nsteps: int,
+                  obs_every: int, setup: "ObsSetup", psi, r_abs: float = 0.0, p_abs: float = 0.0,
+                  flux_j: int = -1):
+    """propagate with the absorbing mask after every step (r_abs > 0) and the
+    time-integrated current at point flux_j (>= 0); returns (state, records,
+    min Krylov dim, flux integral)."""
+    psi = _state(g, psi).copy()
+    n_obs = nsteps // obs_every if obs_every > 0 else 0
+    obs = np.zeros((max(n_obs, 1), setup.record))
+    flux = np.zeros(1)
+    gc, pc = g.c(), p.c()
+    phi = np.ascontiguousarray(setup.phi, dtype=np.float64)
+    sl = np.ascontiguousarray(setup.state_l, dtype=np.int32)
+    used = lib().orc_propagate_abs(ctypes.byref(gc), ctypes.byref(pc), int(method), int(order_or_m), float(t0),
+                                   float(dt), int(nsteps), int(obs_every), float(setup.r_ion),
+                                   _dptr(np.ascontiguousarray(setup.u0)), len(sl), _iptr(sl), _dptr(phi),
+                                   float(r_abs), float(p_abs), int(flux_j), _dptr(psi), _dptr(obs), _dptr(flux))
+    return psi, obs[:n_obs], used, float(flux[0])
+
+
 def rk_tableau(method: int):
     """(c, a, b, bhat, stages) of an explicit Runge-Kutta method (appendix)."""
     c, b, bh = np.zeros(RK_MAX), np.zeros(RK_MAX), np.zeros(RK_MAX)
@@ -303,5 +342,5 @@ from .eigen import bound_states, obs_setup  # noqa: E402  (needs Grid)
 
 __all__ = ["Grid", "Pulse", "ObsSetup", "build", "lib", "radius", "kappa", "field", "h_bound", "apply_h",
            "taylor_step", "rk4_step", "lanczos_step", "jacobi_eig", "initial_state",
-           "observables", "propagate", "imag_propagate", "rk_tableau", "rk_step", "propagate_rk", "bound_states", "obs_setup", "TAYLOR", "RK4", "LANCZOS",
+           "observables", "propagate", "imag_propagate", "mask", "radial_current", "propagate_abs", "rk_tableau", "rk_step", "propagate_rk", "bound_states", "obs_setup", "TAYLOR", "RK4", "LANCZOS",
            "OBS_FIXED", "OBS_NAMES"]

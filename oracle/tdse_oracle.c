@@ -509,6 +509,46 @@ void orc_imag_propagate(const orc_grid* g, double dtau, int order, int64_t nstep
     for (int64_t s = 0; s < nsteps; ++s) energy[s] = orc_imag_step(g, dtau, order, psi);
 }
 
+/* Sec. 2.1 "Absorbing potential": W(r) = (i/dt) ln{1 - cos^p[(pi/2)(1 - r/r_b)]}
+ * added to V.  Over a step of length dt its propagator factor exp(-i W dt) is
+ * exactly the mask M(r) = 1 - cos^p[(pi/2)(1 - r/r_b)] (taken as 0 from r_b
+ * on): the potential is split off the step and applied as M to every partial
+ * wave after it. */
+double orc_mask(double r, double r_b, double p)
+{
+    if (r >= r_b) return 0.0;
+    return 1.0 - pow(cos(0.5 * M_PI * (1.0 - r / r_b)), p);
+}
+
+void orc_apply_mask(const orc_grid* g, double r_b, double p, double complex* psi)
+{
+    for (int l = 0; l <= g->lmax; ++l)
+        for (int i = 0; i < g->n; ++i) psi[(size_t)l * g->n + i] *= orc_mask(orc_radius(g, i), r_b, p);
+}
+
+/* Sec. 4, eq. flux and eq. yield in the length gauge (no vector-potential
+ * term): the radial probability current through the sphere r = r_j,
+ *   J = sum_l Im[f_l^*(r_j) df_l/dr(r_j)],
+ * the first derivative of the stencil's order, zero beyond the box:
+ * (f_{j+1} - f_{j-1}) / (2 dr) with the 3-point stencil and the 4th-order
+ * (f_{j-2} - 8 f_{j-1} + 8 f_{j+1} - f_{j+2}) / (12 dr) of Sec. 2 with the
+ * 5-point stencil. */
+double orc_radial_current(const orc_grid* g, int j, const double complex* psi)
+{
+    double sum = 0.0;
+    for (int l = 0; l <= g->lmax; ++l) {
+        const double complex* f = psi + (size_t)l * g->n;
+        double complex d;
+        if (g->stencil == 3)
+            d = (value_at(g, f, j + 1) - value_at(g, f, j - 1)) / (2.0 * g->dr);
+        else
+            d = (value_at(g, f, j - 2) - 8.0 * value_at(g, f, j - 1) + 8.0 * value_at(g, f, j + 1)
+                 - value_at(g, f, j + 2)) / (12.0 * g->dr);
+        sum += cimag(conj(f[j]) * d);
+    }
+    return sum;
+}
+
 /* Initial state: the hydrogenic 1s radial function u(r) ~ r exp(-z r)
  * (Fig. "1sHydroRad": density 4 r^2 exp(-2r) for z = 1), normalised on the
  * grid, placed in the l = 0 partial wave.  u0 receives the normalised l = 0
@@ -586,6 +626,47 @@ void orc_observables(const orc_grid* g, const orc_pulse* p, double t, double r_i
     out[5] = dr * outer;
     out[6] = 2.0 * dr * dip;
     out[7] = -efield - 2.0 * g->z * dr * acc;
+}
+
+/* orc_propagate with the absorbing mask (r_abs > 0) applied after every step
+ * and, for flux_j >= 0, the ionisation yield of eq. yield: the current J at
+ * r_{flux_j} after every step (and at the start) integrated over time by the
+ * trapezoid rule, returned in *flux. */
+int orc_propagate_abs(const orc_grid* g, const orc_pulse* p, int method, int order_or_m, double t0,
+                      double dt, int64_t nsteps, int64_t obs_every, double r_ion, const double* u0,
+                      int n_states, const int32_t* state_l, const double* phi, double r_abs, double p_abs,
+                      int flux_j, double complex* psi, double* obs_out, double* flux)
+{
+    const int rec = ORC_OBS_FIXED + n_states;
+    int64_t n_obs = 0;
+    int min_m = (method == ORC_LANCZOS) ? order_or_m : 0;
+    double j_prev = (flux_j >= 0) ? orc_radial_current(g, flux_j, psi) : 0.0;
+    double yield = 0.0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const double t_start = t0 + (double)s * dt;
+        const double t_mid = t0 + ((double)s + 0.5) * dt;
+        const double t_end = t0 + (double)(s + 1) * dt;
+        if (method == ORC_TAYLOR) {
+            orc_taylor_step(g, orc_field(p, t_mid), dt, order_or_m, psi);
+        } else if (method == ORC_RK4) {
+            rk4_step_fields(g, orc_field(p, t_start), orc_field(p, t_mid), orc_field(p, t_end), dt, psi);
+        } else {
+            const int used = orc_lanczos_step(g, orc_field(p, t_mid), dt, order_or_m, psi);
+            if (used < min_m) min_m = used;
+        }
+        if (r_abs > 0.0) orc_apply_mask(g, r_abs, p_abs, psi);
+        if (flux_j >= 0) {
+            const double j_new = orc_radial_current(g, flux_j, psi);
+            yield += 0.5 * dt * (j_prev + j_new);
+            j_prev = j_new;
+        }
+        if (obs_every > 0 && (s + 1) % obs_every == 0 && obs_out) {
+            orc_observables(g, p, t_end, r_ion, u0, n_states, state_l, phi, psi, obs_out + (size_t)n_obs * rec);
+            ++n_obs;
+        }
+    }
+    if (flux) *flux = yield;
+    return min_m;
 }
 
 int orc_propagate(const orc_grid* g, const orc_pulse* p, int method, int order_or_m, double t0,

@@ -109,6 +109,20 @@ void orc_observables(const orc_grid* g, const orc_pulse* p, double t,
                      const int32_t* state_l, const double* phi,
                      const double complex* psi, double* out);
 
+/* Sec. 2.1 absorbing mask M(r) = 1 - cos^p[(pi/2)(1 - r/r_b)] (0 from r_b
+ * on), the one-step factor of the absorbing potential W; applied in place */
+double orc_mask(double r, double r_b, double p);
+void orc_apply_mask(const orc_grid* g, double r_b, double p, double complex* psi);
+/* radial current J = sum_l Im[f_l^* df_l/dr] at grid point j (eq. flux) */
+double orc_radial_current(const orc_grid* g, int j, const double complex* psi);
+/* orc_propagate plus the mask after every step (r_abs > 0) and the
+ * trapezoid-rule time integral of J at point flux_j (>= 0) in *flux */
+int orc_propagate_abs(const orc_grid* g, const orc_pulse* p, int method, int order_or_m,
+                      double t0, double dt, int64_t nsteps, int64_t obs_every, double r_ion,
+                      const double* u0, int n_states, const int32_t* state_l,
+                      const double* phi, double r_abs, double p_abs, int flux_j,
+                      double complex* psi, double* obs_out, double* flux);
+
 /* Runs nsteps steps of the chosen method from t0.  After every obs_every-th
  * step the observables are appended to obs_out (record length
  * ORC_OBS_FIXED + n_states).  Returns the smallest Krylov dimension used
