@@ -24,6 +24,8 @@ OBS_FIXED = 8
 OBS_NAMES = ("t", "e_field", "norm", "p_g", "p_bound", "p_ion", "dipole", "accel")
 
 TAYLOR, RK4, LANCZOS = 0, 1, 2
+LENGTH, VELOCITY = 0, 1
+SINE_SQR_E, SINE_SQR_A = 0, 1
 RK_EULER, RK_CLASSIC4, RK_FEHLBERG45, RK_CASHKARP, RK_DORMANDPRINCE, RK_MERSON = range(6)
 RK_MAX = 8
 
@@ -39,13 +41,14 @@ def build() -> str:
 
 class _Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("lmax", ctypes.c_int32), ("stencil", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("dr", ctypes.c_double), ("z", ctypes.c_double),
+                ("gauge", ctypes.c_int32), ("dr", ctypes.c_double), ("z", ctypes.c_double),
                 ("r_shift", ctypes.c_double)]
 
 
 class _Pulse(ctypes.Structure):
     _fields_ = [("e0", ctypes.c_double), ("omega", ctypes.c_double), ("n_cycles", ctypes.c_double),
-                ("cep", ctypes.c_double), ("t_on", ctypes.c_double)]
+                ("cep", ctypes.c_double), ("t_on", ctypes.c_double), ("shape", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -56,13 +59,14 @@ class Grid:
     stencil: int = 3
     z: float = 1.0
     r_shift: float = 0.0
+    gauge: int = 0          # LENGTH or VELOCITY
 
     @property
     def size(self) -> int:
         return (self.lmax + 1) * self.n
 
     def c(self) -> _Grid:
-        return _Grid(self.n, self.lmax, self.stencil, 0, self.dr, self.z, self.r_shift)
+        return _Grid(self.n, self.lmax, self.stencil, int(self.gauge), self.dr, self.z, self.r_shift)
 
 
 @dataclass(frozen=True)
@@ -72,9 +76,10 @@ class Pulse:
     n_cycles: float = 1.0
     cep: float = 0.0
     t_on: float = 0.0
+    shape: int = 0          # SINE_SQR_E or SINE_SQR_A
 
     def c(self) -> _Pulse:
-        return _Pulse(self.e0, self.omega, self.n_cycles, self.cep, self.t_on)
+        return _Pulse(self.e0, self.omega, self.n_cycles, self.cep, self.t_on, int(self.shape), 0)
 
 
 _lib = None
@@ -95,6 +100,12 @@ def lib():
         L.orc_kappa.argtypes, L.orc_kappa.restype = [ctypes.c_int], ctypes.c_double
         L.orc_field.argtypes, L.orc_field.restype = [pp, ctypes.c_double], ctypes.c_double
         L.orc_apply_h.argtypes = [gp, ctypes.c_double, dp, dp]
+        L.orc_vector_potential_step.argtypes = [pp, ctypes.c_double, ctypes.c_double]
+        L.orc_vector_potential_step.restype = ctypes.c_double
+        L.orc_vector_potential_at.argtypes = [pp, ctypes.c_double, ctypes.c_double]
+        L.orc_vector_potential_at.restype = ctypes.c_double
+        L.orc_radial_current_vel.argtypes = [gp, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_radial_current_vel.restype = ctypes.c_double
         L.orc_h_bound.argtypes, L.orc_h_bound.restype = [gp, ctypes.c_double], ctypes.c_double
         L.orc_taylor_step.argtypes = [gp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
         L.orc_rk4_step.argtypes = [gp, pp, ctypes.c_double, ctypes.c_double, dp]
@@ -168,8 +179,20 @@ def field(p: Pulse, t: float) -> float:
     return lib().orc_field(ctypes.byref(pc), float(t))
 
 
+def vector_potential_step(p: Pulse, t: float, h: float) -> float:
+    """-int_t^{t+h} E by 5-point Gauss-Legendre (the increment of A/c)."""
+    pc = p.c()
+    return lib().orc_vector_potential_step(ctypes.byref(pc), float(t), float(h))
+
+
+def vector_potential_at(p: Pulse, t0: float, dt: float) -> float:
+    """A/c at t0 from t_on by the same rule over ceil((t0 - t_on)/dt) equal pieces."""
+    pc = p.c()
+    return lib().orc_vector_potential_at(ctypes.byref(pc), float(t0), float(dt))
+
+
 def h_bound(g: Grid, efield: float) -> float:
-    """Gershgorin bound on the spectral radius of H(E)."""
+    """Gershgorin bound on the spectral radius of H(E) (H(A/c) in the velocity gauge)."""
     gc = g.c()
     return lib().orc_h_bound(ctypes.byref(gc), float(efield))
 
@@ -273,6 +296,13 @@ def radial_current(g: Grid, j: int, psi) -> float:
     psi = _state(g, psi)
     gc = g.c()
     return float(lib().orc_radial_current(ctypes.byref(gc), int(j), _dptr(psi)))
+
+
+def radial_current_vel(g: Grid, j: int, a_tilde: float, psi) -> float:
+    """The velocity-gauge current: radial_current plus 2 A~ sum_l kappa_{l+1} Re[f_l^* f_{l+1}]."""
+    psi = _state(g, psi)
+    gc = g.c()
+    return float(lib().orc_radial_current_vel(ctypes.byref(gc), int(j), float(a_tilde), _dptr(psi)))
 
 
 def propagate_abs(g: Grid, p: Pulse, method: int, order_or_m: int, t0: float, dt: float, nsteps: int,

@@ -45,14 +45,57 @@ double orc_kappa(int l)
 }
 
 /* Sec. 3, field with the Hann (sine-squared) envelope: E0 f(tau) cos(w tau +
- * phi), f = sin^2(pi tau / T), T = 2 pi n_c / w, zero outside the pulse. */
+ * phi), f = sin^2(pi tau / T), T = 2 pi n_c / w, zero outside the pulse.
+ * Shape 1 ("SineA" of Sec. 3, eq. VecSinSinCosE): the envelope sits on the
+ * vector potential, A/c = -E0 sin^2(W tau) sin(w tau + phi) with W = pi / T,
+ * and E = -d(A/c)/dt = E0 sin(W tau) [w sin(W tau) cos(w tau + phi)
+ * + 2 W cos(W tau) sin(w tau + phi)]. */
 double orc_field(const orc_pulse* p, double t)
 {
     double tau = t - p->t_on;
     double period = 2.0 * M_PI * p->n_cycles / p->omega;
     if (!(tau >= 0.0 && tau <= period)) return 0.0;
     double s = sin(M_PI * tau / period);
+    if (p->shape == 1) {
+        const double w_env = M_PI / period;
+        const double c = cos(M_PI * tau / period);
+        return p->e0 * s * (p->omega * s * cos(p->omega * tau + p->cep) + 2.0 * w_env * c * sin(p->omega * tau + p->cep));
+    }
     return p->e0 * s * s * cos(p->omega * tau + p->cep);
+}
+
+/* 5-point Gauss-Legendre rule on [-1, 1] (nodes: 0 and the roots
+ * +-(1/3) sqrt(5 -+ 2 sqrt(10/7)) of P_5; weights 128/225 and
+ * (322 +- 13 sqrt(70)) / 900), nodes in increasing order. */
+static void gauss_legendre5(double x[5], double w[5])
+{
+    const double a = sqrt(5.0 - 2.0 * sqrt(10.0 / 7.0)) / 3.0;
+    const double b = sqrt(5.0 + 2.0 * sqrt(10.0 / 7.0)) / 3.0;
+    const double wa = (322.0 + 13.0 * sqrt(70.0)) / 900.0;
+    const double wb = (322.0 - 13.0 * sqrt(70.0)) / 900.0;
+    x[0] = -b; x[1] = -a; x[2] = 0.0; x[3] = a; x[4] = b;
+    w[0] = wb; w[1] = wa; w[2] = 128.0 / 225.0; w[3] = wa; w[4] = wb;
+}
+
+double orc_vector_potential_step(const orc_pulse* p, double t, double h)
+{
+    double x[5], w[5];
+    gauss_legendre5(x, w);
+    double sum = 0.0;
+    for (int j = 0; j < 5; ++j) sum += w[j] * orc_field(p, t + 0.5 * h * (1.0 + x[j]));
+    return -0.5 * h * sum;
+}
+
+double orc_vector_potential_at(const orc_pulse* p, double t0, double dt)
+{
+    if (!(t0 > p->t_on)) return 0.0;
+    const double span = t0 - p->t_on;
+    int64_t m = (int64_t)ceil(span / dt - 1e-9);
+    if (m < 1) m = 1;
+    const double piece = span / (double)m;
+    double a = 0.0;
+    for (int64_t q = 0; q < m; ++q) a += orc_vector_potential_step(p, p->t_on + (double)q * piece, piece);
+    return a;
 }
 
 static double complex value_at(const orc_grid* g, const double complex* row, int i)
@@ -62,12 +105,29 @@ static double complex value_at(const orc_grid* g, const double complex* row, int
     return row[i];
 }
 
-/* H(t) f for the length gauge (Sec. 2, radial TDSE in the L gauge, with the
- * field-free block h_l and the matrix layout of eq. h_matrix):
- *   (H f)_l = -1/2 D2 f_l + [l(l+1)/(2 r^2) - z/r] f_l
- *             + E r [kappa_l f_{l-1} + kappa_{l+1} f_{l+1}]
- * D2 is the 3-point second difference or the 5-point fourth-order formula of
- * Sec. 2. */
+/* First radial derivative of a row at point i, of the stencil's order: the
+ * central difference (f_{i+1} - f_{i-1}) / (2 dr) with the 3-point Laplacian,
+ * the fourth-order (f_{i-2} - 8 f_{i-1} + 8 f_{i+1} - f_{i+2}) / (12 dr) of
+ * Sec. 2 with the 5-point one (its printed 1/(12 h^2) read as 1/(12 h)). */
+static double complex first_derivative(const orc_grid* g, const double complex* f, int i)
+{
+    if (g->stencil == 3) return (value_at(g, f, i + 1) - value_at(g, f, i - 1)) / (2.0 * g->dr);
+    return (value_at(g, f, i - 2) - 8.0 * value_at(g, f, i - 1) + 8.0 * value_at(g, f, i + 1)
+            - value_at(g, f, i + 2)) / (12.0 * g->dr);
+}
+
+/* H(t) f (Sec. 2, radial TDSE in the L and V gauges, with the field-free
+ * block h_l and the matrix layout of eq. h_matrix):
+ *   (H f)_l = -1/2 D2 f_l + [l(l+1)/(2 r^2) - z/r] f_l + coupling,
+ * length gauge (g->gauge 0, `field` = E):
+ *   coupling = E r [kappa_l f_{l-1} + kappa_{l+1} f_{l+1}],
+ * velocity gauge (g->gauge 1, `field` = A~ = A/c):
+ *   coupling = -i A~ [kappa_l (d/dr - l/r) f_{l-1}
+ *                     + kappa_{l+1} (d/dr + (l+1)/r) f_{l+1}],
+ * the partial-wave form of A~ p_z on f_l / r (the signs of the l/r terms as
+ * p_z acting on (f/r) Y_l0 gives them; the paper prints them the other way
+ * round).  D2 is the 3-point second difference or the 5-point fourth-order
+ * formula of Sec. 2, d/dr the first derivative of the same order. */
 void orc_apply_h(const orc_grid* g, double efield, const double complex* f, double complex* hf)
 {
     const int n = g->n;
@@ -92,28 +152,39 @@ void orc_apply_h(const orc_grid* g, double efield, const double complex* f, doub
             const double r = orc_radius(g, i);
             const double v = centrifugal / (r * r) - g->z / r;
             double complex coupling = 0.0;
-            if (flm) coupling += kl * flm[i];
-            if (flp) coupling += klp * flp[i];
-            hf[(size_t)l * n + i] = -0.5 * d2 + v * fl[i] + efield * r * coupling;
+            if (g->gauge == 1) {
+                if (flm) coupling += kl * (first_derivative(g, flm, i) - ((double)l / r) * flm[i]);
+                if (flp) coupling += klp * (first_derivative(g, flp, i) + ((double)(l + 1) / r) * flp[i]);
+                hf[(size_t)l * n + i] = -0.5 * d2 + v * fl[i] + (-I * efield) * coupling;
+            } else {
+                if (flm) coupling += kl * flm[i];
+                if (flp) coupling += klp * flp[i];
+                hf[(size_t)l * n + i] = -0.5 * d2 + v * fl[i] + efield * r * coupling;
+            }
         }
     }
 }
 
-/* Gershgorin bound on the spectral radius of H(E): the largest absolute
- * row sum of the matrix of eq. h_matrix.  Used as the scale of the Lanczos
- * breakdown test and of the explicit-step stability limit. */
+/* Gershgorin bound on the spectral radius of H(E) (length gauge; H(A~) in
+ * the velocity gauge): the largest absolute row sum of the matrix of eq.
+ * h_matrix.  Used as the scale of the Lanczos breakdown test and of the
+ * explicit-step stability limit. */
 double orc_h_bound(const orc_grid* g, double efield)
 {
     const double h2 = g->dr * g->dr;
     const double diag_kin = (g->stencil == 3) ? 1.0 / h2 : 30.0 / (24.0 * h2);
     const double off_kin = (g->stencil == 3) ? 1.0 / h2 : (32.0 + 2.0) / (24.0 * h2);
+    const double d1 = (g->stencil == 3) ? 1.0 / g->dr : 18.0 / (12.0 * g->dr);   /* sum |first-derivative weights| */
     double bound = 0.0;
     for (int l = 0; l <= g->lmax; ++l) {
-        const double coup = orc_kappa(l) + ((l < g->lmax) ? orc_kappa(l + 1) : 0.0);
+        const double klm = orc_kappa(l), klp = (l < g->lmax) ? orc_kappa(l + 1) : 0.0;
+        const double coup = klm + klp;
         for (int i = 0; i < g->n; ++i) {
             const double r = orc_radius(g, i);
             const double d = diag_kin + 0.5 * (double)l * (double)(l + 1) / (r * r) - g->z / r;
-            const double row = fabs(d) + off_kin + fabs(efield) * r * coup;
+            const double cpl = (g->gauge == 1) ? fabs(efield) * (klm * (d1 + (double)l / r) + klp * (d1 + (double)(l + 1) / r))
+                                               : fabs(efield) * r * coup;
+            const double row = fabs(d) + off_kin + cpl;
             if (row > bound) bound = row;
         }
     }
@@ -177,9 +248,28 @@ static void rk4_step_fields(const orc_grid* g, double e_start, double e_mid, dou
     free(acc);
 }
 
+/* The coupling scalar of the gauge at time t_n + frac dt inside the step
+ * starting at t_n: E(t_lg) in the length gauge (t_lg that time as the caller
+ * forms it), A~(t_n) - int_{t_n}^{t_n + frac dt} E in the velocity gauge
+ * (a_n = A~(t_n); eq. VectorStep applied from the step start to each stage
+ * time, as the appendix describes for the Runge-Kutta stages). */
+static double coupling_at(const orc_grid* g, const orc_pulse* p, double t_n, double a_n, double frac, double dt,
+                          double t_lg)
+{
+    if (g->gauge == 1) return a_n + orc_vector_potential_step(p, t_n, frac * dt);
+    return orc_field(p, t_lg);
+}
+
+static double start_potential(const orc_grid* g, const orc_pulse* p, double t0, double dt)
+{
+    return (g->gauge == 1) ? orc_vector_potential_at(p, t0, dt) : 0.0;
+}
+
 void orc_rk4_step(const orc_grid* g, const orc_pulse* p, double t, double dt, double complex* psi)
 {
-    rk4_step_fields(g, orc_field(p, t), orc_field(p, t + 0.5 * dt), orc_field(p, t + dt), dt, psi);
+    const double a = start_potential(g, p, t, dt);
+    rk4_step_fields(g, coupling_at(g, p, t, a, 0.0, dt, t), coupling_at(g, p, t, a, 0.5, dt, t + 0.5 * dt),
+                    coupling_at(g, p, t, a, 1.0, dt, t + dt), dt, psi);
 }
 
 /* Appendix "Runge-Kutta" and Sec. 5.2 (RungeKutta.c, eq. RKDeriv): explicit
@@ -266,8 +356,8 @@ int orc_rk_tableau(int method, double* c, double* a /* [ORC_RK_MAX][ORC_RK_MAX] 
  * pair, the local deviation Delta = dt sum_i (b_i - bhat_i) k_i gives
  * sigma_n = sqrt(sum_e |Delta_e|^2 / U) over the U elements of the state (the
  * root mean square over the solution vector); returned (0 without a pair). */
-double orc_rk_step(const orc_grid* g, const orc_pulse* p, int method, double t, double dt,
-                   double complex* psi)
+static double rk_step_a(const orc_grid* g, const orc_pulse* p, int method, double t, double dt, double a_n,
+                        double complex* psi)
 {
     const int M = ORC_RK_MAX;
     double c[ORC_RK_MAX], a[ORC_RK_MAX * ORC_RK_MAX], b[ORC_RK_MAX], bh[ORC_RK_MAX];
@@ -283,7 +373,7 @@ double orc_rk_step(const orc_grid* g, const orc_pulse* p, int method, double t, 
             y[e] = psi[e] + dt * acc;
         }
         double complex* ki = k + (size_t)i * len;
-        orc_apply_h(g, orc_field(p, t + c[i] * dt), y, ki);
+        orc_apply_h(g, coupling_at(g, p, t, a_n, c[i], dt, t + c[i] * dt), y, ki);
 #pragma omp parallel for schedule(static)
         for (size_t e = 0; e < len; ++e) ki[e] = -I * ki[e];
     }
@@ -305,6 +395,12 @@ double orc_rk_step(const orc_grid* g, const orc_pulse* p, int method, double t, 
     return pair ? sqrt(d2 / (double)len) : 0.0;
 }
 
+double orc_rk_step(const orc_grid* g, const orc_pulse* p, int method, double t, double dt,
+                   double complex* psi)
+{
+    return rk_step_a(g, p, method, t, dt, start_potential(g, p, t, dt), psi);
+}
+
 /* nsteps steps of method from t0 with observables every obs_every steps (as
  * orc_propagate); returns sigma = sum_n sigma_n, the passive global
  * truncation estimate of the appendix. */
@@ -315,8 +411,11 @@ double orc_propagate_rk(const orc_grid* g, const orc_pulse* p, int method, doubl
     const int rec = ORC_OBS_FIXED + n_states;
     int64_t n_obs = 0;
     double sigma = 0.0;
+    double a_n = start_potential(g, p, t0, dt);
     for (int64_t s = 0; s < nsteps; ++s) {
-        sigma += orc_rk_step(g, p, method, t0 + (double)s * dt, dt, psi);
+        const double t_n = t0 + (double)s * dt;
+        sigma += rk_step_a(g, p, method, t_n, dt, a_n, psi);
+        if (g->gauge == 1) a_n += orc_vector_potential_step(p, t_n, dt);
         if (obs_every > 0 && (s + 1) % obs_every == 0 && obs_out) {
             orc_observables(g, p, t0 + (double)(s + 1) * dt, r_ion, u0, n_states, state_l, phi, psi,
                             obs_out + (size_t)n_obs * rec);
@@ -538,15 +637,21 @@ double orc_radial_current(const orc_grid* g, int j, const double complex* psi)
     double sum = 0.0;
     for (int l = 0; l <= g->lmax; ++l) {
         const double complex* f = psi + (size_t)l * g->n;
-        double complex d;
-        if (g->stencil == 3)
-            d = (value_at(g, f, j + 1) - value_at(g, f, j - 1)) / (2.0 * g->dr);
-        else
-            d = (value_at(g, f, j - 2) - 8.0 * value_at(g, f, j - 1) + 8.0 * value_at(g, f, j + 1)
-                 - value_at(g, f, j + 2)) / (12.0 * g->dr);
-        sum += cimag(conj(f[j]) * d);
+        sum += cimag(conj(f[j]) * first_derivative(g, f, j));
     }
     return sum;
+}
+
+/* The velocity-gauge current (Sec. 4, eq. yield with its vector-potential
+ * term): J + 2 A~ sum_l kappa_{l+1} Re[f_l^*(r_j) f_{l+1}(r_j)], the flux of
+ * Re{psi^* (p + A/c) psi} through the sphere; equal to the length-gauge
+ * current of the gauge-transformed state. */
+double orc_radial_current_vel(const orc_grid* g, int j, double a_tilde, const double complex* psi)
+{
+    double extra = 0.0;
+    for (int l = 0; l < g->lmax; ++l)
+        extra += orc_kappa(l + 1) * creal(conj(psi[(size_t)l * g->n + j]) * psi[(size_t)(l + 1) * g->n + j]);
+    return orc_radial_current(g, j, psi) + 2.0 * a_tilde * extra;
 }
 
 /* Initial state: the hydrogenic 1s radial function u(r) ~ r exp(-z r)
@@ -640,23 +745,27 @@ int orc_propagate_abs(const orc_grid* g, const orc_pulse* p, int method, int ord
     const int rec = ORC_OBS_FIXED + n_states;
     int64_t n_obs = 0;
     int min_m = (method == ORC_LANCZOS) ? order_or_m : 0;
-    double j_prev = (flux_j >= 0) ? orc_radial_current(g, flux_j, psi) : 0.0;
+    double a_n = start_potential(g, p, t0, dt);
+    double j_prev = (flux_j >= 0) ? orc_radial_current_vel(g, flux_j, a_n, psi) : 0.0;
     double yield = 0.0;
     for (int64_t s = 0; s < nsteps; ++s) {
         const double t_start = t0 + (double)s * dt;
         const double t_mid = t0 + ((double)s + 0.5) * dt;
         const double t_end = t0 + (double)(s + 1) * dt;
+        const double c_mid = coupling_at(g, p, t_start, a_n, 0.5, dt, t_mid);
         if (method == ORC_TAYLOR) {
-            orc_taylor_step(g, orc_field(p, t_mid), dt, order_or_m, psi);
+            orc_taylor_step(g, c_mid, dt, order_or_m, psi);
         } else if (method == ORC_RK4) {
-            rk4_step_fields(g, orc_field(p, t_start), orc_field(p, t_mid), orc_field(p, t_end), dt, psi);
+            rk4_step_fields(g, coupling_at(g, p, t_start, a_n, 0.0, dt, t_start), c_mid,
+                            coupling_at(g, p, t_start, a_n, 1.0, dt, t_end), dt, psi);
         } else {
-            const int used = orc_lanczos_step(g, orc_field(p, t_mid), dt, order_or_m, psi);
+            const int used = orc_lanczos_step(g, c_mid, dt, order_or_m, psi);
             if (used < min_m) min_m = used;
         }
+        if (g->gauge == 1) a_n += orc_vector_potential_step(p, t_start, dt);
         if (r_abs > 0.0) orc_apply_mask(g, r_abs, p_abs, psi);
         if (flux_j >= 0) {
-            const double j_new = orc_radial_current(g, flux_j, psi);
+            const double j_new = orc_radial_current_vel(g, flux_j, a_n, psi);
             yield += 0.5 * dt * (j_prev + j_new);
             j_prev = j_new;
         }
@@ -677,18 +786,22 @@ int orc_propagate(const orc_grid* g, const orc_pulse* p, int method, int order_o
     const int rec = ORC_OBS_FIXED + n_states;
     int64_t n_obs = 0;
     int min_m = (method == ORC_LANCZOS) ? order_or_m : 0;
+    double a_n = start_potential(g, p, t0, dt);
     for (int64_t s = 0; s < nsteps; ++s) {
         const double t_start = t0 + (double)s * dt;
         const double t_mid = t0 + ((double)s + 0.5) * dt;
         const double t_end = t0 + (double)(s + 1) * dt;
+        const double c_mid = coupling_at(g, p, t_start, a_n, 0.5, dt, t_mid);
         if (method == ORC_TAYLOR) {
-            orc_taylor_step(g, orc_field(p, t_mid), dt, order_or_m, psi);
+            orc_taylor_step(g, c_mid, dt, order_or_m, psi);
         } else if (method == ORC_RK4) {
-            rk4_step_fields(g, orc_field(p, t_start), orc_field(p, t_mid), orc_field(p, t_end), dt, psi);
+            rk4_step_fields(g, coupling_at(g, p, t_start, a_n, 0.0, dt, t_start), c_mid,
+                            coupling_at(g, p, t_start, a_n, 1.0, dt, t_end), dt, psi);
         } else {
-            const int used = orc_lanczos_step(g, orc_field(p, t_mid), dt, order_or_m, psi);
+            const int used = orc_lanczos_step(g, c_mid, dt, order_or_m, psi);
             if (used < min_m) min_m = used;
         }
+        if (g->gauge == 1) a_n += orc_vector_potential_step(p, t_start, dt);
         if (obs_every > 0 && (s + 1) % obs_every == 0 && obs_out) {
             orc_observables(g, p, t_end, r_ion, u0, n_states, state_l, phi, psi,
                             obs_out + (size_t)n_obs * rec);

@@ -7,7 +7,7 @@
  * the CPU-baseline leg of the benchmark load it.  It shares no source with the
  * GPU library.
  *
- * Conventions (each a reading of the paper, listed in the design doc):
+ * Conventions (each a reading of the paper where it is silent):
  *   state      psi[l*n + i] = f_l(r_i), l = 0..lmax, i = 0..n-1, complex128
  *   grid       r_i = (i+1)*dr + r_shift   (Sec. 2 grid, "Start"/"Offset" of
  *              the FD settings group); f = 0 outside [0, n)  (Sec. 2.1: the FD
@@ -28,7 +28,7 @@ typedef struct {
     int32_t n;        /* radial points per partial wave                    */
     int32_t lmax;     /* highest partial wave                              */
     int32_t stencil;  /* 3 (2nd order) or 5 (4th order, Sec. 2)            */
-    int32_t pad_;
+    int32_t gauge;    /* 0 length, 1 velocity (Sec. 2, the two forms of d) */
     double dr;        /* grid spacing (au)                                 */
     double z;         /* nuclear charge, V(r) = -z/r                       */
     double r_shift;   /* grid offset added to every radius (normally 0)    */
@@ -40,6 +40,8 @@ typedef struct {
     double n_cycles;  /* number of carrier cycles under the envelope       */
     double cep;       /* carrier-envelope phase                            */
     double t_on;      /* pulse start time (au)                             */
+    int32_t shape;    /* 0 sin^2 envelope on E, 1 on A/c (Sec. 3, "SineA") */
+    int32_t pad_;
 } orc_pulse;
 
 /* Observable record, in this order (all FP64):
@@ -52,6 +54,14 @@ enum { ORC_TAYLOR = 0, ORC_RK4 = 1, ORC_LANCZOS = 2 };
 double orc_radius(const orc_grid* g, int i);
 double orc_kappa(int l);
 double orc_field(const orc_pulse* p, double t);
+
+/* Sec. 3, eq. VectorStep with A~ = A/c: -int_t^{t+h} E by the 5-point
+ * Gauss-Legendre rule, the increment of A~ over [t, t + h]. */
+double orc_vector_potential_step(const orc_pulse* p, double t, double h);
+/* A~(t0) = -int_{t_on}^{t0} E (0 for t0 <= t_on) by the same rule over
+ * M = ceil((t0 - t_on)/dt) equal pieces, summed in time order: the value the
+ * per-step increments reach when the steps start at t_on. */
+double orc_vector_potential_at(const orc_pulse* p, double t0, double dt);
 
 double orc_h_bound(const orc_grid* g, double efield);
 
@@ -115,6 +125,9 @@ double orc_mask(double r, double r_b, double p);
 void orc_apply_mask(const orc_grid* g, double r_b, double p, double complex* psi);
 /* radial current J = sum_l Im[f_l^* df_l/dr] at grid point j (eq. flux) */
 double orc_radial_current(const orc_grid* g, int j, const double complex* psi);
+/* The velocity-gauge current: orc_radial_current plus the vector-potential
+ * term of eq. yield, 2 A~ sum_l kappa_{l+1} Re[f_l^* f_{l+1}] at r_j. */
+double orc_radial_current_vel(const orc_grid* g, int j, double a_tilde, const double complex* psi);
 /* orc_propagate plus the mask after every step (r_abs > 0) and the
  * trapezoid-rule time integral of J at point flux_j (>= 0) in *flux */
 int orc_propagate_abs(const orc_grid* g, const orc_pulse* p, int method, int order_or_m,
