@@ -101,13 +101,22 @@ typedef struct {
     double r_ion;       /* ionisation radius r_b (au) for p_ion                   */
 } tdse_grid_desc;
 
-/* Sec. 3 pulse (eq. EField with the Hann envelope). */
+/* Sec. 3 pulse with the Hann (sine-squared) envelope over T = 2 pi n_c / w
+ * from t_on (tau = t - t_on, zero outside [0, T]), in one of two shapes:
+ *   TDSE_PULSE_SINE2_E  E = E0 sin^2(pi tau / T) cos(w tau + phi)  (eq. EField)
+ *   TDSE_PULSE_SINE2_A  A/c = -E0 sin^2(W tau) sin(w tau + phi), W = pi / T,
+ *                       E = -d(A/c)/dt  (the "SineA" form, eq. VecSinSinCosE;
+ *                       A(T) = 0, so the gauges agree after the pulse) */
+#define TDSE_PULSE_SINE2_E 0
+#define TDSE_PULSE_SINE2_A 1
 typedef struct {
-    double e0;          /* peak field (au)                                        */
+    double e0;          /* field amplitude E0 (au)                                */
     double omega;       /* carrier angular frequency (au), > 0                    */
     double n_cycles;    /* carrier cycles under the envelope, > 0                 */
     double cep;         /* carrier-envelope phase (a sine carrier is -pi/2)       */
     double t_on;        /* start of the pulse (au)                                */
+    int32_t shape;      /* TDSE_PULSE_SINE2_E or TDSE_PULSE_SINE2_A               */
+    int32_t pad_;
 } tdse_pulse;
 
 #define TDSE_MAX_STATES 15
@@ -168,7 +177,8 @@ tdse_status tdse_set_state(tdse_ctx* ctx, int32_t inst, const double* host_c128)
 tdse_status tdse_get_state(tdse_ctx* ctx, int32_t inst, double* host_c128);
 
 /* d_out = H(E) d_in for every instance, with e_field[k] the field of
- * instance k (Sec. 2, eq. h_matrix).  d_in and d_out are caller-owned
+ * instance k (Sec. 2, eq. h_matrix; A/c in the velocity gauge, see
+ * tdse_set_gauge).  d_in and d_out are caller-owned
  * state-shaped device vectors in the context's precision; they must not
  * overlap.  Asynchronous. */
 tdse_status tdse_apply_H(tdse_ctx* ctx, const double* e_field, const void* d_in, void* d_out);
@@ -184,8 +194,11 @@ tdse_status tdse_apply_H(tdse_ctx* ctx, const double* e_field, const void* d_in,
  * spans [t0 + s dt, t0 + (s+1) dt].  If obs_every > 0 and d_obs != NULL the
  * observables after every obs_every-th step are written to d_obs (device
  * memory, [n_inst][nsteps / obs_every] records).  Returns TDSE_E_UNSTABLE
- * (and enqueues nothing) if dt[k] times tdse_lambda_max_bound(k, |e0|)
- * exceeds the imaginary-axis stability limit of the order-P polynomial.
+ * (and enqueues nothing) if dt[k] times tdse_lambda_max_bound(k, c_k)
+ * exceeds the imaginary-axis stability limit of the order-P polynomial, with
+ * c_k the pulse's bound on the coupling scalar of the gauge (length gauge:
+ * |E0|, or |E0| (w + w / (2 n_c)) for TDSE_PULSE_SINE2_A; velocity gauge:
+ * see tdse_set_gauge).  Returns TDSE_E_INVALID for an unknown pulse shape.
  * Asynchronous. */
 tdse_status tdse_step_taylor(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0,
                              const double* dt, int32_t order, int32_t nsteps, int32_t obs_every,
@@ -209,7 +222,7 @@ tdse_status tdse_step_rk4(tdse_ctx* ctx, const tdse_pulse* pulses, const double*
  * sqrt(sum_e |Delta_e|^2 / U_k) the root mean square over the U_k elements of
  * instance k of the pair's difference Delta = dt sum_i (b_i - bhat_i) k_i (the
  * caller zeroes d_sigma to start a sum).  Arguments, observables and errors as
- * tdse_step_taylor; TDSE_E_UNSTABLE if dt[k] tdse_lambda_max_bound(k, |e0|)
+ * tdse_step_taylor; TDSE_E_UNSTABLE if dt[k] tdse_lambda_max_bound(k, c_k)
  * exceeds tdse_rk_stability_limit(method).  Needs the TDSE_METHOD_RK_TABLEAU
  * workspace of the method.  Asynchronous. */
 tdse_status tdse_step_rk(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t0, const double* dt,
@@ -255,6 +268,72 @@ tdse_status tdse_step_lanczos(tdse_ctx* ctx, const tdse_pulse* pulses, const dou
  * the same order.  Asynchronous. */
 tdse_status tdse_step_imag(tdse_ctx* ctx, const double* dtau, int32_t order, int32_t nsteps, double* d_energy);
 
+/* Gauge of the atom-field coupling (Sec. 2, the L and V forms of the radial
+ * TDSE in the dipole approximation):
+ *   length    (H f)_l += E r [kappa_l f_{l-1} + kappa_{l+1} f_{l+1}]
+ *   velocity  (H f)_l += -i (A/c) [kappa_l (d/dr - l/r) f_{l-1}
+ *                                  + kappa_{l+1} (d/dr + (l+1)/r) f_{l+1}]
+ * with d/dr the first derivative of the stencil's order ((f_{i+1} -
+ * f_{i-1}) / (2 dr), or the fourth-order 5-point formula of Sec. 2 whose
+ * printed 1/(12 h^2) is read as 1/(12 h)) and the l/r signs of p_z acting
+ * on (f/r) Y_l0 (printed the other way round in the paper).  In the velocity
+ * gauge A/c = -int_{t_on}^t E comes from eq. VectorStep (Sec. 3): A/c at the
+ * start of a step call is the 5-point Gauss-Legendre quadrature of -E over
+ * ceil((t0 - t_on) / dt) equal pieces from t_on (0 for t0 <= t_on), then each
+ * step adds the quadrature over its own span, and every stage (midpoint,
+ * Runge-Kutta stage times t_n + c_i dt) takes A/c(t_n) plus the quadrature
+ * from t_n to its time.  The steps then run the workgroup sweeps (one launch
+ * per Horner term; RK4 in four stage launches; the fusion settings are kept
+ * for the length gauge), tdse_apply_H takes A/c in place of E, and
+ * tdse_lambda_max_bound takes a bound on |A/c| (the step calls bound it by
+ * |E0| for TDSE_PULSE_SINE2_A, by 3 |E0| / w for TDSE_PULSE_SINE2_E).  The
+ * observables are the same sums (the norm, p_ion, dipole and acceleration
+ * do not depend on the gauge; the populations agree once A = 0), and the
+ * flux current gains its A term.  The diffusion steps have no field.  The
+ * autotuners time the length-gauge kernels (the context is in the length
+ * gauge while they run).  Returns TDSE_E_INVALID for another value. */
+#define TDSE_GAUGE_LENGTH 0
+#define TDSE_GAUGE_VELOCITY 1
+tdse_status tdse_set_gauge(tdse_ctx* ctx, int32_t gauge);
+int32_t tdse_gauge(const tdse_ctx* ctx);
+
+/* Absorbing boundary (Sec. 2, "Absorbing potential"): the imaginary
+ * potential W(r) of that subsection, split off every real-time step
+ * (tdse_step_taylor, _rk4, _rk, _lanczos; not the diffusion steps) and
+ * applied after it as its exact one-step factor, the mask
+ *   M(r) = 1 - cos^p[(pi/2)(1 - r/r_b)]   (0 from r_b on),
+ * multiplying every partial wave at radius r.  r_abs[k] is r_b of instance
+ * k (au; <= 0: no absorber), p_abs[k] its exponent p (> 0 where r_abs[k] >
+ * 0); host arrays of n_inst, copied.  The mask is 1 to FP64 precision well
+ * inside r_b for the usual large p, so the loss of norm it causes measures
+ * the probability that reached the absorber.  While any instance absorbs,
+ * the Taylor path sums its observables in their own pass (after the mask)
+ * instead of in the step's last launch.  Returns TDSE_E_UNBOUND before
+ * tdse_bind, TDSE_E_INVALID for a non-finite r_abs or a p_abs <= 0 where
+ * r_abs > 0 (nothing changed).  Synchronises the stream. */
+tdse_status tdse_set_absorber(tdse_ctx* ctx, const double* r_abs, const double* p_abs);
+
+/* Ionisation yield by the radial probability current (Sec. 4, "Ionisation
+ * yield and angular distribution"; eq. yield): for each instance with
+ * i_flux[k] >= 0, after every real-time step (after the absorbing mask)
+ *   J = sum_l Im[f_l^*(r_j) df_l/dr(r_j)],   r_j = (i_flux[k] + 1) dr,
+ * plus, in the velocity gauge, the vector-potential term
+ * 2 (A/c) sum_l kappa_{l+1} Re[f_l^*(r_j) f_{l+1}(r_j)] (A/c at the state's time),
+ * with the first derivative of the stencil's order ((f_{j+1} - f_{j-1}) /
+ * (2 dr) with the 3-point Laplacian, the 4th-order 5-point derivative with
+ * the 5-point one; values beyond the box are 0), integrated over time by the
+ * trapezoid rule from the current of the state each step call starts from.
+ * The yields accumulate on the device across step calls; this call sets
+ * the flux points (host array of n_inst, -1: none) and resets every yield
+ * to 0.  Returns TDSE_E_UNBOUND before tdse_bind, TDSE_E_INVALID for an
+ * index outside [-1, n_r) (nothing changed).  Asynchronous, except for the
+ * table upload. */
+tdse_status tdse_set_flux(tdse_ctx* ctx, const int32_t* i_flux);
+
+/* The accumulated flux yields, copied to host_yield[n_inst] (0 for the
+ * instances without a flux point).  Synchronises the stream. */
+tdse_status tdse_get_flux(tdse_ctx* ctx, double* host_yield);
+
 /* Smallest Krylov dimension each instance used over the steps of the last
  * tdse_step_lanczos call, copied to host_meff[n_inst].  Synchronises the
  * stream.  Returns TDSE_E_BREAKDOWN (information: the results are valid) if
@@ -287,8 +366,10 @@ tdse_status tdse_observables(tdse_ctx* ctx, const tdse_pulse* pulses, const doub
 tdse_status tdse_observables_noalloc(tdse_ctx* ctx, const tdse_pulse* pulses, const double* t,
                                      tdse_obs* host_out);
 
-/* Gershgorin bound on the spectral radius of H for instance k when
- * |E| <= e_max: the largest absolute row sum of eq. h_matrix. */
+/* Gershgorin bound on the spectral radius of H for instance k when the
+ * coupling scalar of the context's gauge is at most e_max in magnitude (|E|
+ * in the length gauge, |A/c| in the velocity gauge): the largest absolute
+ * row sum of eq. h_matrix. */
 double tdse_lambda_max_bound(const tdse_ctx* ctx, int32_t inst, double e_max);
 
 /* Imaginary-axis stability limit y_P of the degree-P Taylor polynomial: the

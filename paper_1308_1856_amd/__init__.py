@@ -26,6 +26,8 @@ STATUS = {0: "TDSE_OK", -1: "TDSE_E_INVALID", -2: "TDSE_E_NOMEM", -3: "TDSE_E_HI
 FP64, FP32, FP48 = 0, 1, 2
 METHOD_TAYLOR, METHOD_RK4, METHOD_LANCZOS, METHOD_TUNE, METHOD_RK_TABLEAU = 0, 1, 2, 3, 4
 RK_EULER, RK_CLASSIC4, RK_FEHLBERG45, RK_CASHKARP, RK_DORMANDPRINCE, RK_MERSON = range(6)
+GAUGE_LENGTH, GAUGE_VELOCITY = 0, 1
+PULSE_SINE2_E, PULSE_SINE2_A = 0, 1
 MAX_STATES = 15
 OBS_FIELDS = ("t", "e_field", "norm", "p_g", "p_bound", "p_ion", "dipole", "accel")
 OBS_DOUBLES = len(OBS_FIELDS) + MAX_STATES
@@ -39,7 +41,8 @@ EXPORTED = ("tdse_init_grid", "tdse_destroy", "tdse_last_error", "tdse_num_insta
             "tdse_autotune_taylor", "tdse_taylor_fusion", "tdse_taylor_fusion_kind",
             "tdse_set_taylor_fusion", "tdse_set_sweep_shape", "tdse_lanczos_dims",
             "tdse_observables_noalloc", "tdse_step_imag", "tdse_taylor_real_stability_limit",
-            "tdse_step_rk", "tdse_rk_stability_limit")
+            "tdse_step_rk", "tdse_rk_stability_limit", "tdse_set_absorber", "tdse_set_flux", "tdse_get_flux",
+            "tdse_set_gauge", "tdse_gauge")
 
 
 class TdseError(RuntimeError):
@@ -56,7 +59,8 @@ class GridDesc(ctypes.Structure):
 
 class Pulse(ctypes.Structure):
     _fields_ = [("e0", ctypes.c_double), ("omega", ctypes.c_double), ("n_cycles", ctypes.c_double),
-                ("cep", ctypes.c_double), ("t_on", ctypes.c_double)]
+                ("cep", ctypes.c_double), ("t_on", ctypes.c_double), ("shape", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class Obs(ctypes.Structure):
@@ -98,6 +102,11 @@ def _load():
         "tdse_step_imag": ([ctxp, dp, i32, i32, vp], i32),
         "tdse_step_rk": ([ctxp, ctypes.POINTER(Pulse), dp, dp, i32, i32, i32, vp, vp], i32),
         "tdse_rk_stability_limit": ([i32], ctypes.c_double),
+        "tdse_set_absorber": ([ctxp, dp, dp], i32),
+        "tdse_set_gauge": ([ctxp, i32], i32),
+        "tdse_gauge": ([ctxp], i32),
+        "tdse_set_flux": ([ctxp, ctypes.POINTER(i32)], i32),
+        "tdse_get_flux": ([ctxp, dp], i32),
         "tdse_timing_enable": ([ctxp, i32], i32),
         "tdse_timing_read": ([ctxp, ctypes.c_char_p, ctypes.POINTER(i64), dp], i32),
         "tdse_use_graphs": ([ctxp, i32], i32),
@@ -139,7 +148,8 @@ def _dvec(values, n: int):
 def _pulses(pulses: Sequence) -> ctypes.Array:
     arr = (Pulse * len(pulses))()
     for k, p in enumerate(pulses):
-        arr[k] = Pulse(float(p.e0), float(p.omega), float(p.n_cycles), float(p.cep), float(p.t_on))
+        arr[k] = Pulse(float(p.e0), float(p.omega), float(p.n_cycles), float(p.cep), float(p.t_on),
+                       int(getattr(p, "shape", 0)))
     return arr
 
 
@@ -214,6 +224,27 @@ def tdse_rk_stability_limit(method: int) -> float:
 def tdse_step_imag(ctx, dtau, order, nsteps, d_energy):
     n = lib.tdse_num_instances(ctx)
     _check(ctx, lib.tdse_step_imag(ctx, _dvec(dtau, n), order, nsteps, d_energy))
+
+
+def tdse_set_gauge(ctx, gauge: int):
+    _check(ctx, lib.tdse_set_gauge(ctx, int(gauge)))
+
+
+def tdse_set_absorber(ctx, r_abs, p_abs):
+    n = lib.tdse_num_instances(ctx)
+    _check(ctx, lib.tdse_set_absorber(ctx, _dvec(r_abs, n), _dvec(p_abs, n)))
+
+
+def tdse_set_flux(ctx, i_flux):
+    n = lib.tdse_num_instances(ctx)
+    _check(ctx, lib.tdse_set_flux(ctx, (ctypes.c_int32 * n)(*[int(i) for i in i_flux])))
+
+
+def tdse_get_flux(ctx) -> np.ndarray:
+    n = lib.tdse_num_instances(ctx)
+    out = (ctypes.c_double * n)()
+    _check(ctx, lib.tdse_get_flux(ctx, out))
+    return np.frombuffer(out, dtype=np.float64).copy()
 
 
 def tdse_taylor_real_stability_limit(order: int) -> float:
@@ -442,6 +473,32 @@ class Propagator:
         self._enter()
         tdse_step_imag(self.ctx, self._per_inst(dtau), order, nsteps, ptr)
         self._leave()
+
+    def set_gauge(self, gauge: int):
+        """GAUGE_LENGTH or GAUGE_VELOCITY for the following steps."""
+        tdse_set_gauge(self.ctx, gauge)
+
+    @property
+    def gauge(self) -> int:
+        return lib.tdse_gauge(self.ctx)
+
+    def set_absorber(self, r_abs, p_abs):
+        """Absorbing mask after every real-time step (r_abs <= 0: none)."""
+        self._enter()
+        tdse_set_absorber(self.ctx, self._per_inst(r_abs), self._per_inst(p_abs))
+        self._leave()
+
+    def set_flux(self, i_flux):
+        """Flux points (radial index, -1: none); resets the accumulated yields."""
+        self._enter()
+        tdse_set_flux(self.ctx, self._per_inst(i_flux))
+        self._leave()
+
+    def flux_yield(self) -> np.ndarray:
+        self._enter()
+        out = tdse_get_flux(self.ctx)
+        self._leave()
+        return out
 
     def lanczos_dims(self):
         """(smallest Krylov dimension per instance in the last Lanczos call, broke_down)."""

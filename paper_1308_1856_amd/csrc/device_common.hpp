@@ -278,15 +278,15 @@ template <> struct Kin<2> {
 
 // Per-thread radial constants.
 struct RadialPoint {
-    double r, inv_r2, z_over_r;
+    double r, inv_r, inv_r2, z_over_r;
 };
 __device__ __forceinline__ RadialPoint radial_point(const Tile& I, int i)
 {
     RadialPoint p;
     p.r = (double)(i + 1) * I.dr;
-    const double inv_r = 1.0 / p.r;
-    p.inv_r2 = inv_r * inv_r;
-    p.z_over_r = I.z * inv_r;
+    p.inv_r = 1.0 / p.r;
+    p.inv_r2 = p.inv_r * p.inv_r;
+    p.z_over_r = I.z * p.inv_r;
     return p;
 }
 
@@ -341,6 +341,7 @@ __device__ __forceinline__ double2 horner_update_imag(double2 psi, double2 h, do
 template <int S>
 struct Neighbours {
     double2 m1, p1, m2, p2;
+    __device__ __forceinline__ void zero() { m1 = p1 = m2 = p2 = zero2(); }
     template <typename P>
     __device__ __forceinline__ void load(P row, int i, int n)
     {
@@ -354,5 +355,39 @@ struct Neighbours {
         }
     }
 };
+
+// First radial derivative of a row at the point whose neighbours are nb, of
+// the stencil's order (Sec. 2): (f_{i+1} - f_{i-1}) / (2 dr), or the
+// fourth-order (f_{i-2} - 8 f_{i-1} + 8 f_{i+1} - f_{i+2}) / (12 dr).
+template <int S>
+__device__ __forceinline__ double2 first_derivative(const Neighbours<S>& nb, double inv_dr)
+{
+    if (S == 1) {
+        const double s = 0.5 * inv_dr;
+        return make_double2((nb.p1.x - nb.m1.x) * s, (nb.p1.y - nb.m1.y) * s);
+    }
+    const double s = inv_dr * (1.0 / 12.0);
+    return make_double2(fma(8.0, nb.p1.x - nb.m1.x, nb.m2.x - nb.p2.x) * s,
+                        fma(8.0, nb.p1.y - nb.m1.y, nb.m2.y - nb.p2.y) * s);
+}
+
+// Velocity-gauge coupling of row l (Sec. 2, the V form of the radial TDSE:
+// A/c p_z in partial waves):
+//   -i a [kappa_l (d/dr - l/r) f_{l-1} + kappa_{l+1} (d/dr + (l+1)/r) f_{l+1}]
+// from the values fm, fp of rows l - 1, l + 1 at this radius and their
+// radial neighbours (zeros for rows outside [0, lmax]); a = A/c.
+template <int S>
+__device__ __forceinline__ double2 vel_coupling(double2 fm, const Neighbours<S>& nbm, double2 fp,
+                                                const Neighbours<S>& nbp, int l, double inv_r, double inv_dr,
+                                                double a, double kl, double klp)
+{
+    const double2 dm = first_derivative<S>(nbm, inv_dr);
+    const double2 dp = first_derivative<S>(nbp, inv_dr);
+    const double cm = (double)l * inv_r, cp = (double)(l + 1) * inv_r;
+    double cx = kl * fma(-cm, fm.x, dm.x), cy = kl * fma(-cm, fm.y, dm.y);
+    cx = fma(klp, fma(cp, fp.x, dp.x), cx);
+    cy = fma(klp, fma(cp, fp.y, dp.y), cy);
+    return make_double2(a * cy, -(a * cx));   // -i a (cx + i cy)
+}
 
 }  // namespace tdse

@@ -171,6 +171,7 @@ hipError_t launch_horner_fused(int prec, int S, int K, const SweepGeom& g, const
                                const void* psi, void* out, const double* step, int first_term,
                                hipStream_t st)
 {
+    if (g.gauge != 0) return hipErrorInvalidValue;   // length gauge only
     if (prec == 0) return S == 1 ? fused_k<1, double>(K, g, in, psi, out, step, first_term, st)
                                  : fused_k<2, double>(K, g, in, psi, out, step, first_term, st);
     if (prec != 1) return hipErrorInvalidValue;   // LDS-ring kernel: FP64 and FP32 storage only

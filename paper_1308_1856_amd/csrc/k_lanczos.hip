@@ -108,7 +108,7 @@ k_lz_norm_finish(SweepGeom g, const double* __restrict__ partial, LanczosScalars
 // Sweep A for iteration j: w = H q_j over the tile rows, then the partial
 // sums of <q_i, w> for i <= j (w re-read from the lines this thread just
 // wrote, eight basis vectors at a time).
-template <int S, typename T>
+template <int S, typename T, bool VG = false>
 __global__ void __launch_bounds__(kBlock)
 k_lz_sweep_a(SweepGeom g, int j, int m, typename Stor<T>::captr psi, typename Stor<T>::captr basis, int64_t stride,
              typename Stor<T>::aptr w, const double* __restrict__ step, const LanczosScalars* __restrict__ scs,
@@ -129,18 +129,39 @@ k_lz_sweep_a(SweepGeom g, int j, int m, typename Stor<T>::captr psi, typename St
 
     if (active) {
         const RadialPoint rp = radial_point(I, i);
-        const double er = step_value(step, g.n_inst, kEMid, tile.inst) * rp.r;
+        const double fld = step_value(step, g.n_inst, kEMid, tile.inst);
+        const double er = VG ? 0.0 : fld * rp.r;
+        const double inv_dr = 1.0 / I.dr;
         const int64_t base = I.off;
         double2 prev = (tile.l0 > 0) ? ldc(qj, base + (int64_t)(tile.l0 - 1) * n + i) : zero2();
         double2 cur = ldc(qj, base + (int64_t)tile.l0 * n + i);
+        Neighbours<S> nbm, nb;   // rows l - 1 and l (velocity gauge)
+        if (VG) {
+            nbm.zero();
+            if (tile.l0 > 0) nbm.load(qj + (base + (int64_t)(tile.l0 - 1) * n), i, n);
+            nb.load(qj + (base + (int64_t)tile.l0 * n), i, n);
+        }
         for (int l = tile.l0; l < tile.l1; ++l) {
             const int64_t row = base + (int64_t)l * n;
             const double2 next = (l < I.lmax) ? ldc(qj, row + n + i) : zero2();
-            Neighbours<S> nb;
-            nb.load(qj + row, i, n);
+            Neighbours<S> nbp;
+            if (VG) {
+                nbp.zero();
+                if (l < I.lmax) nbp.load(qj + (row + n), i, n);
+            } else {
+                nb.load(qj + row, i, n);
+            }
             const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
             double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
                                    g.kappa[l], g.kappa[l + 1]);
+            if (VG) {
+                const double2 w = vel_coupling<S>(prev, nbm, next, nbp, l, rp.inv_r, inv_dr, fld, g.kappa[l],
+                                                  g.kappa[l + 1]);
+                h.x += w.x;
+                h.y += w.y;
+                nbm = nb;
+                nb = nbp;
+            }
             h.x *= sj;
             h.y *= sj;
             stc_keep(w, row + i, h);
@@ -538,9 +559,14 @@ static hipError_t sweep_a_t(const SweepGeom& g, int j, int m, const void* psi, c
                             int64_t stride, void* w, const double* step, const LanczosScalars* sc,
                             double* partial, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_lz_sweep_a<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j, m,
-                       Stor<T>::cmake(psi, g.plane), basis_ptr<T>(g, basis, stride, m), stride,
-                       Stor<T>::make(w, g.plane), step, sc, partial);
+    if (g.gauge != 0)
+        hipLaunchKernelGGL((k_lz_sweep_a<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j, m,
+                           Stor<T>::cmake(psi, g.plane), basis_ptr<T>(g, basis, stride, m), stride,
+                           Stor<T>::make(w, g.plane), step, sc, partial);
+    else
+        hipLaunchKernelGGL((k_lz_sweep_a<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, j, m,
+                           Stor<T>::cmake(psi, g.plane), basis_ptr<T>(g, basis, stride, m), stride,
+                           Stor<T>::make(w, g.plane), step, sc, partial);
     return hipGetLastError();
 }
 

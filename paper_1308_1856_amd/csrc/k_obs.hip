@@ -110,7 +110,7 @@ k_obs_finish(SweepGeom red, SweepGeom pop, const double* __restrict__ pmain,
     const Inst& I = red.inst[k];
     // the step scalars of the record, loaded now rather than after the sums
     const double t_end = step_value(step, red.n_inst, kTEnd, k);
-    const double e = step_value(step, red.n_inst, kEEnd, k);
+    const double e = step_value(step, red.n_inst, kEObs, k);
     const int64_t ridx = (int64_t)step_value(step, red.n_inst, kRec, k);
     double acc[Q];
 #pragma unroll
@@ -182,6 +182,107 @@ hipError_t launch_obs_partial(int prec, const SweepGeom& red, const SweepGeom& p
     if (prec == 0) return obs_partial_t<double>(red, pop, radial_tab, psi, partial_main, partial_pop, st);
     if (prec == 2) return obs_partial_t<s48>(red, pop, radial_tab, psi, partial_main, partial_pop, st);
     return obs_partial_t<float>(red, pop, radial_tab, psi, partial_main, partial_pop, st);
+}
+
+// ---------------------------------------------------------------------------
+// absorbing mask (Sec. 2.1) and radial current (Sec. 4, eq. flux)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_mask(SweepGeom g, typename Stor<T>::aptr psi)
+{
+    const Tile I = my_tile(g);
+    const Inst& J = g.inst[I.inst];
+    const double rb = J.r_abs;
+    if (!(rb > 0.0)) return;   // uniform over the workgroup
+    const int i = I.r0 + (int)threadIdx.x;
+    if (i >= I.n) return;
+    const double r = (double)(i + 1) * I.dr;
+    const double m = (r >= rb) ? 0.0 : 1.0 - pow(cos(0.5 * M_PI * (1.0 - r / rb)), J.p_abs);
+    for (int l = I.l0; l < I.l1; ++l) {
+        const int64_t k = I.off + (int64_t)l * I.n + i;
+        const double2 v = ldc(psi, k);
+        stc(psi, k, make_double2(m * v.x, m * v.y));
+    }
+}
+
+template <typename T>
+static hipError_t mask_t(const SweepGeom& g, void* psi, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_mask<T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::make(psi, g.plane));
+    return hipGetLastError();
+}
+hipError_t launch_mask(int prec, const SweepGeom& g, void* psi, hipStream_t st)
+{
+    if (prec == 0) return mask_t<double>(g, psi, st);
+    if (prec == 2) return mask_t<s48>(g, psi, st);
+    return mask_t<float>(g, psi, st);
+}
+
+template <int S, typename T, bool VG>
+__global__ void __launch_bounds__(kBlock)
+k_flux(SweepGeom g, typename Stor<T>::cptr psi, const double* __restrict__ step, int init,
+       double* __restrict__ j_prev, double* __restrict__ yield)
+{
+    __shared__ double lds[kBlock / 64];
+    const int k = blockIdx.x;
+    const Inst& I = g.inst[k];
+    const int j = I.i_flux;
+    if (j < 0) return;   // uniform over the workgroup
+    // velocity gauge: A/c at the state's time (the step's start for the
+    // first point of the trapezoid, its end after the step)
+    const double a = VG ? step_value(step, g.n_inst, init ? kEStart : kEEnd, k) : 0.0;
+    double acc[1] = {0.0};
+    for (int l = (int)threadIdx.x; l <= I.lmax; l += kBlock) {
+        const int64_t row = I.off + (int64_t)l * I.n;
+        auto at = [&](int i) { return (i >= 0 && i < I.n) ? ldc(psi, row + i) : zero2(); };
+        auto at_row = [&](int r) { return ldc(psi, I.off + (int64_t)r * I.n + j); };
+        const double2 f = at(j);
+        double2 d;
+        if (S == 1) {
+            const double2 a = at(j + 1), b = at(j - 1);
+            const double s = 1.0 / (2.0 * I.dr);
+            d = make_double2((a.x - b.x) * s, (a.y - b.y) * s);
+        } else {
+            const double2 m2 = at(j - 2), m1 = at(j - 1), p1 = at(j + 1), p2 = at(j + 2);
+            const double s = 1.0 / (12.0 * I.dr);
+            d = make_double2((m2.x - 8.0 * m1.x + 8.0 * p1.x - p2.x) * s, (m2.y - 8.0 * m1.y + 8.0 * p1.y - p2.y) * s);
+        }
+        acc[0] += fma(f.x, d.y, -(f.y * d.x));   // Im(conj(f) d)
+        if (VG && l < I.lmax) {
+            // + 2 (A/c) kappa_{l+1} Re(conj(f_l) f_{l+1})
+            const double2 fp = at_row(l + 1);
+            acc[0] += 2.0 * a * g.kappa[l + 1] * fma(f.x, fp.x, f.y * fp.y);
+        }
+    }
+    const double cur = block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) {
+        if (!init) yield[k] += 0.5 * step_value(step, g.n_inst, kDt, k) * (j_prev[k] + cur);
+        j_prev[k] = cur;
+    }
+}
+
+template <int S, typename T>
+static hipError_t flux_t(const SweepGeom& g, const void* psi, const double* step, int init, double* j_prev,
+                         double* yield, hipStream_t st)
+{
+    if (g.gauge != 0)
+        hipLaunchKernelGGL((k_flux<S, T, true>), dim3(g.n_inst), dim3(kBlock), 0, st, g,
+                           Stor<T>::cmake(psi, g.plane), step, init, j_prev, yield);
+    else
+        hipLaunchKernelGGL((k_flux<S, T, false>), dim3(g.n_inst), dim3(kBlock), 0, st, g,
+                           Stor<T>::cmake(psi, g.plane), step, init, j_prev, yield);
+    return hipGetLastError();
+}
+hipError_t launch_flux(int prec, int S, const SweepGeom& g, const void* psi, const double* step, int init,
+                       double* j_prev, double* yield, hipStream_t st)
+{
+    if (prec == 0) return S == 1 ? flux_t<1, double>(g, psi, step, init, j_prev, yield, st)
+                                 : flux_t<2, double>(g, psi, step, init, j_prev, yield, st);
+    if (prec == 2) return S == 1 ? flux_t<1, s48>(g, psi, step, init, j_prev, yield, st)
+                                 : flux_t<2, s48>(g, psi, step, init, j_prev, yield, st);
+    return S == 1 ? flux_t<1, float>(g, psi, step, init, j_prev, yield, st)
+                  : flux_t<2, float>(g, psi, step, init, j_prev, yield, st);
 }
 
 hipError_t launch_obs_finish(const SweepGeom& red, const SweepGeom& pop, const double* partial_main,

@@ -494,6 +494,7 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
                                const void* psi, void* out, const double* step, int first_term,
                                hipStream_t st, double* obs_partial)
 {
+    if (g.gauge != 0) return hipErrorInvalidValue;   // length gauge only
     if (prec == 0) return S == 1 ? strip_k<1, double>(K, g, in, psi, out, step, first_term, obs_partial, st)
                                  : strip_k<2, double>(K, g, in, psi, out, step, first_term, obs_partial, st);
     if (prec == 2) return S == 1 ? strip_k<1, s48>(K, g, in, psi, out, step, first_term, obs_partial, st)
@@ -566,6 +567,7 @@ static hipError_t sweep_strip_t(const SweepGeom& g, const void* in, const void* 
 hipError_t launch_strip_sweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi, void* out,
                               const double* step, int term, hipStream_t st)
 {
+    if (g.gauge != 0) return hipErrorInvalidValue;   // length gauge only
     if (g.variant != 1 || term < 0) return hipErrorInvalidValue;   // aligned tiles of one level
     if (prec == 0) return S == 1 ? sweep_strip_t<1, double>(g, in, psi, out, step, term, st)
                                  : sweep_strip_t<2, double>(g, in, psi, out, step, term, st);
@@ -763,6 +765,7 @@ static hipError_t rk4_strip_t(const SweepGeom& g, const void* in, void* out, con
 hipError_t launch_rk4_strip(int prec, int S, const SweepGeom& g, const void* in, void* out, const double* step,
                             hipStream_t st)
 {
+    if (g.gauge != 0) return hipErrorInvalidValue;   // length gauge only
     if (g.variant != 4) return hipErrorInvalidValue;   // tiles built for the four stages
     if (prec == 0) return S == 1 ? rk4_strip_t<1, double>(g, in, out, step, st) : rk4_strip_t<2, double>(g, in, out, step, st);
     if (prec == 2) return S == 1 ? rk4_strip_t<1, s48>(g, in, out, step, st) : rk4_strip_t<2, s48>(g, in, out, step, st);

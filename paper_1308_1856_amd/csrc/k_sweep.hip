@@ -31,7 +31,9 @@ namespace tdse {
 // IMAG (term < 0): the Horner term of the diffusion (imaginary-time) step,
 // out = psi - (dtau / |term|) H in (the factor -i of the Taylor step replaced
 // by -1; Sec. 4, ground state calculation).
-template <int S, typename T, bool IMAG = false>
+// VG: the velocity gauge (the kEMid slot holds A/c; the coupling takes the
+// radial neighbours of rows l -+ 1, kept from the rows before and after).
+template <int S, typename T, bool IMAG = false, bool VG = false>
 __global__ void __launch_bounds__(kBlock)
 k_hsweep(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typename Stor<T>::ptr out,
          const double* __restrict__ step, int term)
@@ -41,20 +43,41 @@ k_hsweep(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typ
     const int i = I.r0 + (int)threadIdx.x;
     if (i >= n) return;
     const RadialPoint rp = radial_point(I, i);
-    const double er = step_value(step, g.n_inst, kEMid, I.inst) * rp.r;
+    const double fld = step_value(step, g.n_inst, kEMid, I.inst);
+    const double er = VG ? 0.0 : fld * rp.r;
+    const double inv_dr = 1.0 / I.dr;
     const double c = IMAG ? step_value(step, g.n_inst, kDt, I.inst) / (double)(-term)
                           : (term > 0) ? step_value(step, g.n_inst, kDt, I.inst) / (double)term : 0.0;
     const int64_t base = I.off;
     double2 prev = (I.l0 > 0) ? ldc(in, base + (int64_t)(I.l0 - 1) * n + i) : zero2();
     double2 cur = ldc(in, base + (int64_t)I.l0 * n + i);
+    Neighbours<S> nbm, nb;   // rows l - 1 and l (velocity gauge)
+    if (VG) {
+        nbm.zero();
+        if (I.l0 > 0) nbm.load(in + (base + (int64_t)(I.l0 - 1) * n), i, n);
+        nb.load(in + (base + (int64_t)I.l0 * n), i, n);
+    }
     for (int l = I.l0; l < I.l1; ++l) {
         const int64_t row = base + (int64_t)l * n;
         const double2 next = (l < I.lmax) ? ldc(in, row + n + i) : zero2();
-        Neighbours<S> nb;
-        nb.load(in + row, i, n);
+        Neighbours<S> nbp;
+        if (VG) {
+            nbp.zero();
+            if (l < I.lmax) nbp.load(in + (row + n), i, n);
+        } else {
+            nb.load(in + row, i, n);
+        }
         const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
-        const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
-                                     g.kappa[l], g.kappa[l + 1]);
+        double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
+                               g.kappa[l], g.kappa[l + 1]);
+        if (VG) {
+            const double2 w = vel_coupling<S>(prev, nbm, next, nbp, l, rp.inv_r, inv_dr, fld, g.kappa[l],
+                                              g.kappa[l + 1]);
+            h.x += w.x;
+            h.y += w.y;
+            nbm = nb;
+            nb = nbp;
+        }
         if (IMAG)
             stc(out, row + i, horner_update_imag(ldc(psi, row + i), h, c));
         else if (term > 0)
@@ -202,7 +225,7 @@ k_hsweep_pair(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
 //   stage 2: g = gin                 acc += dt/3 k,       gout = psi + dt k
 //   stage 3: g = gin                 psi  = acc + dt/6 k
 // H is taken at t_n (stage 0), t_n + dt/2 (stages 1, 2) and t_n + dt (stage 3).
-template <int S, typename T, int STAGE>
+template <int S, typename T, int STAGE, bool VG = false>
 __global__ void __launch_bounds__(kBlock)
 k_rk4_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::aptr psi, typename Stor<T>::aptr acc,
             typename Stor<T>::ptr gout, const double* __restrict__ step)
@@ -213,7 +236,9 @@ k_rk4_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::aptr psi,
     if (i >= n) return;
     const RadialPoint rp = radial_point(I, i);
     const int slot = (STAGE == 0) ? kEStart : (STAGE == 3 ? kEEnd : kEMid);
-    const double er = step_value(step, g.n_inst, slot, I.inst) * rp.r;
+    const double fld = step_value(step, g.n_inst, slot, I.inst);
+    const double er = VG ? 0.0 : fld * rp.r;
+    const double inv_dr = 1.0 / I.dr;
     const double dt = step_value(step, g.n_inst, kDt, I.inst);
     const double bw = (STAGE == 0 || STAGE == 3) ? dt / 6.0 : dt / 3.0;
     const double aw = (STAGE == 2) ? dt : 0.5 * dt;
@@ -228,8 +253,12 @@ k_rk4_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::aptr psi,
     double2 prev = (I.l0 > 0) ? ldc(row0 - n, i) : zero2();
     double2 cur = ldc(row0, i);
     double2 next = (I.l0 < I.lmax) ? ldc(row0 + n, i) : zero2();
-    Neighbours<S> nb;
+    Neighbours<S> nb, nbm;   // rows l and (velocity gauge) l - 1
     nb.load(row0, i, n);
+    if (VG) {
+        nbm.zero();
+        if (I.l0 > 0) nbm.load(row0 - n, i, n);
+    }
     double2 a = kReadAcc ? ldc(acc, base + (int64_t)I.l0 * n + i) : zero2();
     double2 p = kReadPsi ? ldc(psi, base + (int64_t)I.l0 * n + i) : zero2();
     for (int l = I.l0; l < I.l1; ++l) {
@@ -237,13 +266,23 @@ k_rk4_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::aptr psi,
         const bool more = l + 1 < I.l1;
         const double2 next2 = (l + 2 <= I.lmax) ? ldc(gin, row + 2 * n + i) : zero2();
         Neighbours<S> nb_next;
-        if (more) nb_next.load(gin + row + n, i, n);
+        // the velocity gauge needs row l + 1's neighbours also past the tile
+        const bool want_next = VG ? (l + 1 <= I.lmax) : more;
+        if (VG) nb_next.zero();
+        if (want_next) nb_next.load(gin + row + n, i, n);
         const double2 a_next = (kReadAcc && more) ? ldc(acc, row + n + i) : zero2();
         const double2 p_next = (kReadPsi && more) ? ldc(psi, row + n + i) : zero2();
 
         const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
-        const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
-                                     g.kappa[l], g.kappa[l + 1]);
+        double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
+                               g.kappa[l], g.kappa[l + 1]);
+        if (VG) {
+            const double2 w = vel_coupling<S>(prev, nbm, next, nb_next, l, rp.inv_r, inv_dr, fld, g.kappa[l],
+                                              g.kappa[l + 1]);
+            h.x += w.x;
+            h.y += w.y;
+            nbm = nb;
+        }
         // x + w k with k = -i h
         if (STAGE == 0) {
             stc(acc, row + i, horner_update(cur, h, bw));
@@ -274,7 +313,7 @@ __device__ __forceinline__ void copy_elem(P48 src, P48 dst, int64_t k)
 // Stage i of an explicit Runge-Kutta step given by its tableau (see
 // launch_rk_stage): H at the stage's time on g_i, k_i = -i H g_i, then the
 // combination of the stage weights in stage order, j = 0..i.
-template <int S, typename T>
+template <int S, typename T, bool VG = false>
 __global__ void __launch_bounds__(kBlock)
 k_rk_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::cptr psi, typename Stor<T>::aptr kv,
            int64_t kstride, typename Stor<T>::ptr next, const double* __restrict__ step, RkStage A,
@@ -288,19 +327,40 @@ k_rk_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::cptr psi, 
     double acc[1] = {0.0};
     if (i < n) {
         const RadialPoint rp = radial_point(I, i);
-        const double er = step_value(step, g.n_inst, A.slot, I.inst) * rp.r;
+        const double fld = step_value(step, g.n_inst, A.slot, I.inst);
+        const double er = VG ? 0.0 : fld * rp.r;
+        const double inv_dr = 1.0 / I.dr;
         const double dt = step_value(step, g.n_inst, kDt, I.inst);
         const int64_t base = I.off;
         double2 prev = (I.l0 > 0) ? ldc(gin, base + (int64_t)(I.l0 - 1) * n + i) : zero2();
         double2 cur = ldc(gin, base + (int64_t)I.l0 * n + i);
+        Neighbours<S> nbm, nb;   // rows l - 1 and l (velocity gauge)
+        if (VG) {
+            nbm.zero();
+            if (I.l0 > 0) nbm.load(gin + (base + (int64_t)(I.l0 - 1) * n), i, n);
+            nb.load(gin + (base + (int64_t)I.l0 * n), i, n);
+        }
         for (int l = I.l0; l < I.l1; ++l) {
             const int64_t row = base + (int64_t)l * n;
             const double2 nx = (l < I.lmax) ? ldc(gin, row + n + i) : zero2();
-            Neighbours<S> nb;
-            nb.load(gin + row, i, n);
+            Neighbours<S> nbp;
+            if (VG) {
+                nbp.zero();
+                if (l < I.lmax) nbp.load(gin + (row + n), i, n);
+            } else {
+                nb.load(gin + row, i, n);
+            }
             const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
-            const double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, nx, I.inv_dr2, v, er,
-                                         g.kappa[l], g.kappa[l + 1]);
+            double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, nx, I.inv_dr2, v, er,
+                                   g.kappa[l], g.kappa[l + 1]);
+            if (VG) {
+                const double2 w = vel_coupling<S>(prev, nbm, nx, nbp, l, rp.inv_r, inv_dr, fld, g.kappa[l],
+                                                  g.kappa[l + 1]);
+                h.x += w.x;
+                h.y += w.y;
+                nbm = nb;
+                nb = nbp;
+            }
             const double2 ki = make_double2(h.y, -h.x);      // -i h
             if (!A.last) stc(kv + (int64_t)A.stage * kstride, row + i, ki);
             double2 sum = zero2(), dev = zero2();
@@ -415,6 +475,13 @@ static hipError_t hsweep_t(const SweepGeom& g, const void* in, const void* psi, 
                            const double* step, int term, hipStream_t st)
 {
     using C = typename Cplx<T>::type;
+    if (g.gauge != 0) {   // velocity gauge: one radius per thread, real-time terms and H only
+        if (g.variant != 0 || term < 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_hsweep<S, T, false, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           Stor<T>::cmake(in, g.plane), Stor<T>::cmake(psi, g.plane), Stor<T>::make(out, g.plane),
+                           step, term);
+        return hipGetLastError();
+    }
     if (term < 0) {   // the diffusion step's Horner terms: one radius per thread
         if (g.variant != 0) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_hsweep<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(in, g.plane),
@@ -442,6 +509,7 @@ static hipError_t hsweep_t(const SweepGeom& g, const void* in, const void* psi, 
 hipError_t launch_hsweep(int prec, int S, const SweepGeom& g, const void* in, const void* psi,
                          void* out, const double* step, int term, hipStream_t st)
 {
+    if (g.set == kApplyTiles && g.gauge != 0) return hipErrorInvalidValue;
     if (g.set == kApplyTiles) return launch_strip_sweep(prec, S, g, in, psi, out, step, term, st);
     if (prec == 0) return S == 1 ? hsweep_t<1, double>(g, in, psi, out, step, term, st)
                                  : hsweep_t<2, double>(g, in, psi, out, step, term, st);
@@ -455,9 +523,14 @@ template <int S, typename T, int STAGE>
 static hipError_t rk4_t(const SweepGeom& g, const void* gin, const void* psi, void* acc, void* gout,
                         const double* step, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_rk4_stage<S, T, STAGE>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
-                       Stor<T>::cmake(gin, g.plane), Stor<T>::make(const_cast<void*>(psi), g.plane),
-                       Stor<T>::make(acc, g.plane), Stor<T>::make(gout, g.plane), step);
+    if (g.gauge != 0)
+        hipLaunchKernelGGL((k_rk4_stage<S, T, STAGE, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           Stor<T>::cmake(gin, g.plane), Stor<T>::make(const_cast<void*>(psi), g.plane),
+                           Stor<T>::make(acc, g.plane), Stor<T>::make(gout, g.plane), step);
+    else
+        hipLaunchKernelGGL((k_rk4_stage<S, T, STAGE>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           Stor<T>::cmake(gin, g.plane), Stor<T>::make(const_cast<void*>(psi), g.plane),
+                           Stor<T>::make(acc, g.plane), Stor<T>::make(gout, g.plane), step);
     return hipGetLastError();
 }
 
@@ -496,8 +569,14 @@ static hipError_t rk_stage_t(const SweepGeom& g, const void* gin, const void* ps
     } else {
         k = static_cast<typename Cplx<T>::type*>(kv);
     }
-    hipLaunchKernelGGL((k_rk_stage<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(gin, g.plane),
-                       Stor<T>::cmake(psi, g.plane), k, kstride, Stor<T>::make(next, g.plane), step, a, err_partial);
+    if (g.gauge != 0)
+        hipLaunchKernelGGL((k_rk_stage<S, T, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
+                           Stor<T>::cmake(gin, g.plane), Stor<T>::cmake(psi, g.plane), k, kstride,
+                           Stor<T>::make(next, g.plane), step, a, err_partial);
+    else
+        hipLaunchKernelGGL((k_rk_stage<S, T>), dim3(g.n_tiles), dim3(kBlock), 0, st, g, Stor<T>::cmake(gin, g.plane),
+                           Stor<T>::cmake(psi, g.plane), k, kstride, Stor<T>::make(next, g.plane), step, a,
+                           err_partial);
     return hipGetLastError();
 }
 

@@ -152,6 +152,17 @@ struct tdse_ctx {
     // (kEStage0 + i: E(t_n + c_i dt)); 0 stages for the other methods
     int rk_stages = 0;
     double rk_c[kRkMax] = {};
+    // the absorbing mask (Sec. 2.1) and the flux yield (Sec. 4) after every
+    // real-time step, once set for some instance (tdse_set_absorber,
+    // tdse_set_flux); off_flux: the current at the last step, then the
+    // accumulated yield, n_inst doubles each
+    bool absorber_on = false, flux_on = false;
+    size_t off_flux = 0;
+    // Sec. 2 gauge of the coupling (0 length, 1 velocity: the step tables
+    // carry A/c, the steps run the workgroup sweeps); a_run: A/c of each
+    // instance at the start of the next step of the running call
+    int gauge = 0;
+    std::vector<double> a_run;
     // captured step graphs, keyed by the launch pattern of a chunk
     bool use_graphs = false;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
@@ -164,7 +175,7 @@ struct tdse_ctx {
     }
     // Gershgorin bounds already computed, keyed by (instance, |E|): the bound
     // costs one pass over the grid, too much to repeat on every step call
-    mutable std::map<std::pair<int, double>, double> bound_cache;
+    mutable std::map<std::tuple<int, int, double>, double> bound_cache;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -194,11 +205,14 @@ struct tdse_ctx {
         g.variant = 0;
         g.order = 0;
         g.plane = plane();
+        g.gauge = gauge;
+        g.pad_ = 0;
         return g;
     }
     // geometry of the H sweeps (apply_H, Taylor terms) in the tuned shape
     SweepGeom hgeom() const
     {
+        if (gauge != 0) return geom(kSweepTiles);   // the velocity gauge: one radius per thread
         const bool strip = (sweep_variant & 4) != 0;
         SweepGeom g = geom(strip ? kApplyTiles : (sweep_variant & 1) ? kPairTiles : kSweepTiles);
         g.variant = strip ? 1 : (sweep_variant & 1);
@@ -211,6 +225,8 @@ struct tdse_ctx {
     double* d_partial() const { return reinterpret_cast<double*>(d_work + off_partial); }
     double* d_radial() const { return reinterpret_cast<double*>(d_work + off_radial); }
     LanczosScalars* d_lz() const { return reinterpret_cast<LanczosScalars*>(d_work + off_lz); }
+    double* d_jprev() const { return reinterpret_cast<double*>(d_work + off_flux); }
+    double* d_yield() const { return d_jprev() + n_inst; }
     char* d_vec(int k) const { return d_work + off_vecs + (size_t)k * state_bytes(); }
     // elements per plane of a state-shaped vector with 48-bit storage (its
     // plane h then takes 8 * plane bytes, a multiple of 256, plane l 4 * plane)
@@ -339,11 +355,16 @@ extern "C" double tdse_taylor_stability_limit(int32_t order)
 // ---------------------------------------------------------------------------
 // context creation
 // ---------------------------------------------------------------------------
-static double gershgorin_bound(const tdse_grid_desc& g, double e_max)
+// Largest absolute row sum of H (eq. h_matrix) with the coupling scalar of
+// the gauge bounded by e_max: |E| (length gauge: e_max r kappa per coupled
+// row) or |A/c| (velocity gauge: e_max kappa (sum |first-derivative
+// weights| + l/r) per coupled row).
+static double gershgorin_bound(const tdse_grid_desc& g, double e_max, int gauge = 0)
 {
     const double h2 = g.dr * g.dr;
     const double dk = (g.stencil == 3) ? 1.0 / h2 : 30.0 / (24.0 * h2);
     const double ok = (g.stencil == 3) ? 1.0 / h2 : 34.0 / (24.0 * h2);
+    const double d1 = (g.stencil == 3) ? 1.0 / g.dr : 1.5 / g.dr;
     double best = 0.0;
     for (int l = 0; l <= g.lmax; ++l) {
         const double kl = (l > 0) ? std::sqrt((double)l * l / (4.0 * l * l - 1.0)) : 0.0;
@@ -351,7 +372,9 @@ static double gershgorin_bound(const tdse_grid_desc& g, double e_max)
         for (int i = 0; i < g.n_r; ++i) {
             const double r = (double)(i + 1) * g.dr;
             const double d = dk + 0.5 * (double)l * (l + 1) / (r * r) - g.z_nuc / r;
-            best = std::max(best, std::fabs(d) + ok + std::fabs(e_max) * r * (kl + kp));
+            const double cpl = (gauge != 0) ? std::fabs(e_max) * (kl * (d1 + (double)l / r) + kp * (d1 + (double)(l + 1) / r))
+                                            : std::fabs(e_max) * r * (kl + kp);
+            best = std::max(best, std::fabs(d) + ok + cpl);
         }
     }
     return best;
@@ -359,12 +382,24 @@ static double gershgorin_bound(const tdse_grid_desc& g, double e_max)
 
 static double cached_bound(const tdse_ctx* c, int k, double e_max)
 {
-    const std::pair<int, double> key(k, std::fabs(e_max));
+    const std::tuple<int, int, double> key(k, c->gauge, std::fabs(e_max));
     auto it = c->bound_cache.find(key);
     if (it != c->bound_cache.end()) return it->second;
-    const double b = gershgorin_bound(c->grids[k], key.second);
+    const double b = gershgorin_bound(c->grids[k], std::fabs(e_max), c->gauge);
     c->bound_cache.emplace(key, b);
     return b;
+}
+
+// Bound on the coupling scalar of the gauge over a whole pulse (Sec. 3):
+// length gauge |E| <= |E0| (sin^2 envelope on E) or |E0| (w + W) (on A/c,
+// W = w / (2 n_c)); velocity gauge |A/c| <= |E0| (envelope on A/c) or
+// 3 |E0| / w (on E: integrating sin^2(W tau) cos(w tau + phi) by parts
+// leaves the envelope's value plus its total variation 2, over w).
+static double coupling_bound(const tdse_ctx* c, const tdse_pulse& p)
+{
+    const double e = std::fabs(p.e0);
+    if (c->gauge == 0) return (p.shape == 1) ? e * (p.omega + p.omega / (2.0 * p.n_cycles)) : e;
+    return (p.shape == 1) ? e : 3.0 * e / p.omega;
 }
 
 static int states_for(int lmax)
@@ -565,7 +600,8 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         while (i_ion < g.n_r && (double)(i_ion + 1) * g.dr <= g.r_ion) ++i_ion;
         I.i_ion = i_ion;
         I.tab_off = tab;
-        I.breakdown = 1e-12 * gershgorin_bound(g, 0.0);
+        I.breakdown = 1e-12 * gershgorin_bound(g, 0.0, 0);
+        I.i_flux = -1;
         tab += (int64_t)(1 + I.n_states) * g.n_r;
         off += ((int64_t)(g.lmax + 1) * g.n_r + 63) / 64 * 64;
         lmax_all = std::max(lmax_all, g.lmax);
@@ -691,6 +727,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->off_step = take(sizeof(double) * kSlots * (size_t)n_inst * kEtabSteps);
     c->off_obs_tmp = take(sizeof(tdse_obs) * n_inst);
     c->off_lz = take(sizeof(LanczosScalars) * n_inst);
+    c->off_flux = take(sizeof(double) * 2 * (size_t)n_inst);
     // Lanczos dots; the observables pass; or the strips' main partials (two
     // sets, by step parity) and the population tiles
     // (and the Runge-Kutta stages' deviation partials, one per sweep tile:
@@ -800,6 +837,8 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
     }
     hipError_t e = hipMemsetAsync(c->d_work + c->off_zero, 0, c->zero_bytes, c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "tdse_bind zero row");
+    e = hipMemsetAsync(c->d_work + c->off_flux, 0, sizeof(double) * 2 * (size_t)c->n_inst, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_bind flux");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "tdse_bind sync");
     c->bound = true;
@@ -896,7 +935,46 @@ double field_at(const tdse_pulse& p, double t)
     const double period = 2.0 * M_PI * p.n_cycles / p.omega;
     if (!(tau >= 0.0 && tau <= period)) return 0.0;
     const double s = std::sin(M_PI * tau / period);
+    if (p.shape == 1) {
+        // sin^2 envelope on A/c = -E0 sin^2(W tau) sin(w tau + phi), W = pi / T:
+        // E = -d(A/c)/dt
+        const double w_env = M_PI / period;
+        const double cs = std::cos(M_PI * tau / period);
+        return p.e0 * s * (p.omega * s * std::cos(p.omega * tau + p.cep) +
+                           2.0 * w_env * cs * std::sin(p.omega * tau + p.cep));
+    }
     return p.e0 * s * s * std::cos(p.omega * tau + p.cep);
+}
+
+// Sec. 3, eq. VectorStep with A/c in place of A: the change of A/c over
+// [t, t + h], -int E, by the 5-point Gauss-Legendre rule (the roots 0,
+// +-sqrt(5 -+ 2 sqrt(10/7)) / 3 of the Legendre polynomial P_5, weights
+// 128/225 and (322 +- 13 sqrt(70)) / 900), nodes taken in increasing order.
+double vp_increment(const tdse_pulse& p, double t, double h)
+{
+    const double xa = std::sqrt(5.0 - 2.0 * std::sqrt(10.0 / 7.0)) / 3.0;
+    const double xb = std::sqrt(5.0 + 2.0 * std::sqrt(10.0 / 7.0)) / 3.0;
+    const double wa = (322.0 + 13.0 * std::sqrt(70.0)) / 900.0;
+    const double wb = (322.0 - 13.0 * std::sqrt(70.0)) / 900.0;
+    const double x[5] = {-xb, -xa, 0.0, xa, xb};
+    const double w[5] = {wb, wa, 128.0 / 225.0, wa, wb};
+    double sum = 0.0;
+    for (int j = 0; j < 5; ++j) sum += w[j] * field_at(p, t + 0.5 * h * (1.0 + x[j]));
+    return -0.5 * h * sum;
+}
+
+// A/c at t0, -int_{t_on}^{t0} E, by the same rule over ceil((t0 - t_on) / dt)
+// equal pieces in time order (the increments of steps of dt from t_on).
+double vp_at(const tdse_pulse& p, double t0, double dt)
+{
+    if (!(t0 > p.t_on)) return 0.0;
+    const double span = t0 - p.t_on;
+    int64_t m = (int64_t)std::ceil(span / dt - 1e-9);
+    if (m < 1) m = 1;
+    const double piece = span / (double)m;
+    double a = 0.0;
+    for (int64_t q = 0; q < m; ++q) a += vp_increment(p, p.t_on + (double)q * piece, piece);
+    return a;
 }
 
 // Fills and uploads the scalars of steps [s0, s0 + count) (count <= kEtabSteps)
@@ -912,6 +990,11 @@ tdse_status upload_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0
     }
     double* h = c->h_step[b];
     const int n = c->n_inst;
+    const bool vel = c->gauge != 0 && pulses != nullptr;
+    if (vel && s0 == 0) {
+        c->a_run.assign(n, 0.0);
+        for (int k = 0; k < n; ++k) c->a_run[k] = vp_at(pulses[k], t0[k], dt[k]);
+    }
     for (int s = 0; s < count; ++s) {
         double* row = h + (size_t)s * kSlots * n;
         for (int k = 0; k < n; ++k) {
@@ -919,16 +1002,30 @@ tdse_status upload_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0
             const double ts = t0[k] + step * dt[k];
             const double tm = t0[k] + (step + 0.5) * dt[k];
             const double te = t0[k] + (step + 1.0) * dt[k];
-            row[kEStart * n + k] = pulses ? field_at(pulses[k], ts) : 0.0;
-            row[kEMid * n + k] = pulses ? field_at(pulses[k], tm) : 0.0;
-            row[kEEnd * n + k] = pulses ? field_at(pulses[k], te) : 0.0;
+            const double e_end = pulses ? field_at(pulses[k], te) : 0.0;
+            if (vel) {
+                // A/c at the stage times: A/c(t_n) plus the quadrature from t_n
+                const tdse_pulse& p = pulses[k];
+                const double a = c->a_run[k];
+                row[kEStart * n + k] = a + vp_increment(p, ts, 0.0 * dt[k]);
+                row[kEMid * n + k] = a + vp_increment(p, ts, 0.5 * dt[k]);
+                row[kEEnd * n + k] = a + vp_increment(p, ts, 1.0 * dt[k]);
+                for (int i = 0; i < kRkMax; ++i)
+                    row[(kEStage0 + i) * n + k] = (i < c->rk_stages) ? a + vp_increment(p, ts, c->rk_c[i] * dt[k]) : 0.0;
+                c->a_run[k] = a + vp_increment(p, ts, dt[k]);
+            } else {
+                row[kEStart * n + k] = pulses ? field_at(pulses[k], ts) : 0.0;
+                row[kEMid * n + k] = pulses ? field_at(pulses[k], tm) : 0.0;
+                row[kEEnd * n + k] = e_end;
+                for (int i = 0; i < kRkMax; ++i)
+                    row[(kEStage0 + i) * n + k] =
+                        (pulses && i < c->rk_stages) ? field_at(pulses[k], t0[k] + (step + c->rk_c[i]) * dt[k]) : 0.0;
+            }
+            row[kEObs * n + k] = e_end;
             row[kTEnd * n + k] = te;
             row[kDt * n + k] = dt[k];
             const int64_t done = s0 + s + 1;
             row[kRec * n + k] = (obs_every > 0 && done % obs_every == 0) ? (double)(done / obs_every - 1) : -1.0;
-            for (int i = 0; i < kRkMax; ++i)
-                row[(kEStage0 + i) * n + k] =
-                    (pulses && i < c->rk_stages) ? field_at(pulses[k], t0[k] + (step + c->rk_c[i]) * dt[k]) : 0.0;
         }
     }
     hipError_t e = hipMemcpyAsync(c->d_step(), h, sizeof(double) * kSlots * n * (size_t)count,
@@ -953,6 +1050,8 @@ tdse_status check_common(tdse_ctx* c, const tdse_pulse* pulses, const double* t0
             return c->fail(TDSE_E_INVALID, "step: t0 must be finite and dt > 0");
         if (!(pulses[k].omega > 0.0) || !(pulses[k].n_cycles > 0.0) || !std::isfinite(pulses[k].e0))
             return c->fail(TDSE_E_INVALID, "step: pulse needs omega > 0, n_cycles > 0, finite e0");
+        if (pulses[k].shape != TDSE_PULSE_SINE2_E && pulses[k].shape != TDSE_PULSE_SINE2_A)
+            return c->fail(TDSE_E_INVALID, "step: unknown pulse shape");
     }
     const size_t need = tdse_workspace_bytes(c, method, order);
     if (c->work_bytes < need)
@@ -965,7 +1064,7 @@ tdse_status check_stable(tdse_ctx* c, const tdse_pulse* pulses, const double* dt
 {
     const double y = tdse_taylor_stability_limit(order);
     for (int k = 0; k < c->n_inst; ++k) {
-        const double lam = cached_bound(c, k, pulses[k].e0);
+        const double lam = cached_bound(c, k, coupling_bound(c, pulses[k]));
         if (dt[k] * lam > y) {
             char buf[256];
             std::snprintf(buf, sizeof buf,
@@ -1026,10 +1125,15 @@ static hipError_t ensure_obs_stream(tdse_ctx* c)
 // second stream runs them in order (they share the partial-sum buffer) and
 // rejoins the main stream at the end of the chunk, so a chunk (and its
 // captured graph) leaves nothing running on it.
+//
+// hooks: after each step, the absorbing mask (in place on psi; the
+// observables then run their own pass) and the flux yield, where set.
 template <typename StepFn>
 hipError_t enqueue_chunk(tdse_ctx* c, int64_t s0, int count, int32_t obs_every, tdse_obs* d_obs,
-                         int64_t rec_stride, void** cur, StepFn& step_fn, bool side)
+                         int64_t rec_stride, void** cur, StepFn& step_fn, bool side, bool hooks)
 {
+    const bool absorb = hooks && c->absorber_on;
+    const bool flux = hooks && c->flux_on;
     auto obs_at = [&](int s) { return obs_every > 0 && s >= 0 && (s0 + s + 1) % obs_every == 0; };
     bool forked = false;
     for (int s = 0; s < count; ++s) {
@@ -1040,10 +1144,14 @@ hipError_t enqueue_chunk(tdse_ctx* c, int64_t s0, int count, int32_t obs_every, 
         // launch does so into the partial set of this step's parity (the
         // step two later, which reuses it, waits for these observables)
         double* pstrip = c->d_partial() + (size_t)(s & 1) * c->strip_units_cap * kObsMainQ;
-        c->obs_req = (c->obs_fusion && obs_at(s)) ? pstrip : nullptr;
+        c->obs_req = (c->obs_fusion && !absorb && obs_at(s)) ? pstrip : nullptr;
         c->obs_main_done = false;
         if (e == hipSuccess) e = step_fn(step);
         c->obs_req = nullptr;
+        if (e == hipSuccess && absorb) e = launch_mask(c->prec, c->geom(kReduceTiles), *cur, c->stream);
+        if (e == hipSuccess && flux)
+            e = launch_flux(c->prec, c->stencil == 3 ? 1 : 2, c->geom(kReduceTiles), *cur, step, 0, c->d_jprev(),
+                            c->d_yield(), c->stream);
         if (e != hipSuccess) return e;
         if (!obs_at(s)) continue;
         const bool fused = c->obs_main_done;
@@ -1092,8 +1200,15 @@ tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, c
         const int count = (int)std::min<int64_t>(kEtabSteps, nsteps - s0);
         tdse_status st = upload_steps(c, pulses, t0, dt, s0, count, obs_every);
         if (st != TDSE_OK) return st;
+        if (c->flux_on && s0 == 0) {
+            // the current of the state the steps start from (the trapezoid's
+            // first point; the velocity gauge takes A/c at the first step's start)
+            hipError_t e = launch_flux(c->prec, c->stencil == 3 ? 1 : 2, c->geom(kReduceTiles), *cur, c->d_step(), 1,
+                                       c->d_jprev(), c->d_yield(), c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "flux start");
+        }
         if (!graphs) {
-            hipError_t e = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn, side);
+            hipError_t e = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn, side, true);
             if (e != hipSuccess) return c->hip_fail(e, "step launch");
             continue;
         }
@@ -1101,12 +1216,13 @@ tdse_status run_steps(tdse_ctx* c, const tdse_pulse* pulses, const double* t0, c
         const std::vector<int64_t> key = {method_key, count, obs_every,
                                           obs_every > 0 ? s0 % obs_every : 0,
                                           (int64_t)reinterpret_cast<uintptr_t>(d_obs), rec_stride,
-                                          (int64_t)reinterpret_cast<uintptr_t>(cur_start)};
+                                          (int64_t)reinterpret_cast<uintptr_t>(cur_start),
+                                          (c->absorber_on ? 1 : 0) + (c->flux_on ? 2 : 0)};
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return c->hip_fail(e, "hipStreamBeginCapture");
-            hipError_t el = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn, side);
+            hipError_t el = enqueue_chunk(c, s0, count, obs_every, d_obs, rec_stride, cur, step_fn, side, true);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(c->stream, &graph);
             if (el != hipSuccess) {
@@ -1152,7 +1268,7 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
     const void* psi = cur;
     const void* in = cur;
     void* out = nullptr;
-    const int K = c->fuse_k;
+    const int K = (c->gauge != 0) ? 0 : c->fuse_k;   // the fused kernels couple in the length gauge only
     if (K > 0) {
         const bool strips = c->fuse_kind == 1;
         SweepGeom gf = c->geom(strips ? kStripTiles : kFusedTiles);
@@ -1276,7 +1392,8 @@ extern "C" tdse_status tdse_step_imag(tdse_ctx* c, const double* dtau, int32_t o
     tdse_status st = upload_steps(c, nullptr, zero.data(), dtau, 0, 1, 0);
     if (st != TDSE_OK) return st;
     const int S = c->stencil == 3 ? 1 : 2;
-    const SweepGeom gs = c->geom(kSweepTiles);   // one radius per thread (variant 0)
+    SweepGeom gs = c->geom(kSweepTiles);   // one radius per thread (variant 0)
+    gs.gauge = 0;                          // no field: the gauge does not enter
     const SweepGeom red = c->geom(kReduceTiles);
     const double* step = c->d_step();
     double* part = c->d_partial();
@@ -1315,7 +1432,7 @@ extern "C" tdse_status tdse_step_rk4(tdse_ctx* c, const tdse_pulse* pulses, cons
     st = check_stable(c, pulses, dt, 4);
     if (st != TDSE_OK) return st;
     const int S = c->stencil == 3 ? 1 : 2;
-    if (c->rk4_fused) {
+    if (c->rk4_fused && c->gauge == 0) {
         // one strip launch per step; psi rotates through the state and work
         // vectors 0 and 1 (a launch writes a buffer it does not read, and the
         // buffer holding psi(s) is first overwritten in step s+2), so the
@@ -1411,7 +1528,7 @@ extern "C" tdse_status tdse_step_rk(tdse_ctx* c, const tdse_pulse* pulses, const
     if (st != TDSE_OK) return st;
     const double y = tdse_rk_stability_limit(method);
     for (int k = 0; k < c->n_inst; ++k) {
-        const double lam = cached_bound(c, k, pulses[k].e0);
+        const double lam = cached_bound(c, k, coupling_bound(c, pulses[k]));
         if (dt[k] * lam > y) {
             char buf[256];
             std::snprintf(buf, sizeof buf,
@@ -1535,7 +1652,7 @@ extern "C" tdse_status tdse_observables(tdse_ctx* c, const tdse_pulse* pulses, c
     std::vector<double> ee(c->n_inst);
     for (int k = 0; k < c->n_inst; ++k) ee[k] = field_at(pulses[k], t[k]);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->d_step() + kEEnd * c->n_inst, ee.data(), sizeof(double) * c->n_inst,
+        e = hipMemcpyAsync(c->d_step() + kEObs * c->n_inst, ee.data(), sizeof(double) * c->n_inst,
                            hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_obs(c, c->d_state, c->d_step(), tmp, kObsRecord, c->stream);
     if (e == hipSuccess)
@@ -1639,7 +1756,8 @@ extern "C" tdse_status tdse_observables_noalloc(tdse_ctx* c, const tdse_pulse* p
     for (int k = 0; k < n; ++k) {
         h[kEStart * n + k] = 0.0;
         h[kEMid * n + k] = 0.0;
-        h[kEEnd * n + k] = field_at(pulses[k], t[k]);
+        h[kEEnd * n + k] = 0.0;
+        h[kEObs * n + k] = field_at(pulses[k], t[k]);
         h[kTEnd * n + k] = t[k];
         h[kDt * n + k] = 1.0;
         h[kRec * n + k] = 0.0;
@@ -1656,6 +1774,78 @@ extern "C" tdse_status tdse_observables_noalloc(tdse_ctx* c, const tdse_pulse* p
         if (!std::isfinite(host_out[k].norm))
             return c->fail(TDSE_E_NONFINITE, "tdse_observables_noalloc: norm is not finite");
     return TDSE_OK;
+}
+
+extern "C" tdse_status tdse_set_gauge(tdse_ctx* c, int32_t gauge)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (gauge != TDSE_GAUGE_LENGTH && gauge != TDSE_GAUGE_VELOCITY)
+        return c->fail(TDSE_E_INVALID, "tdse_set_gauge: gauge must be TDSE_GAUGE_LENGTH or TDSE_GAUGE_VELOCITY");
+    if (gauge != c->gauge) c->drop_graphs();
+    c->gauge = gauge;
+    return TDSE_OK;
+}
+
+extern "C" int32_t tdse_gauge(const tdse_ctx* c) { return c ? c->gauge : 0; }
+
+static tdse_status upload_inst(tdse_ctx* c, const char* what)
+{
+    c->drop_graphs();
+    hipError_t e = hipMemcpyAsync(c->d_work + c->off_inst, c->inst.data(), sizeof(Inst) * c->inst.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return (e == hipSuccess) ? TDSE_OK : c->hip_fail(e, what);
+}
+
+extern "C" tdse_status tdse_set_absorber(tdse_ctx* c, const double* r_abs, const double* p_abs)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_set_absorber: not bound");
+    if (!r_abs || !p_abs) return c->fail(TDSE_E_INVALID, "tdse_set_absorber: null argument");
+    for (int k = 0; k < c->n_inst; ++k)
+        if (!std::isfinite(r_abs[k]) || (r_abs[k] > 0.0 && !(p_abs[k] > 0.0 && std::isfinite(p_abs[k]))))
+            return c->fail(TDSE_E_INVALID, "tdse_set_absorber: instance " + std::to_string(k) +
+                                               ": r_abs must be finite, p_abs finite and > 0 where r_abs > 0");
+    bool on = false;
+    for (int k = 0; k < c->n_inst; ++k) {
+        const bool a = r_abs[k] > 0.0;
+        c->inst[k].r_abs = a ? r_abs[k] : 0.0;
+        c->inst[k].p_abs = a ? p_abs[k] : 0.0;
+        on = on || a;
+    }
+    c->absorber_on = on;
+    return upload_inst(c, "tdse_set_absorber");
+}
+
+extern "C" tdse_status tdse_set_flux(tdse_ctx* c, const int32_t* i_flux)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_set_flux: not bound");
+    if (!i_flux) return c->fail(TDSE_E_INVALID, "tdse_set_flux: null argument");
+    for (int k = 0; k < c->n_inst; ++k)
+        if (i_flux[k] < -1 || i_flux[k] >= c->inst[k].n)
+            return c->fail(TDSE_E_INVALID, "tdse_set_flux: instance " + std::to_string(k) +
+                                               ": i_flux must be -1 or a radial index of the grid");
+    bool on = false;
+    for (int k = 0; k < c->n_inst; ++k) {
+        c->inst[k].i_flux = i_flux[k];
+        on = on || i_flux[k] >= 0;
+    }
+    c->flux_on = on;
+    hipError_t e = hipMemsetAsync(c->d_jprev(), 0, sizeof(double) * 2 * (size_t)c->n_inst, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_set_flux");
+    return upload_inst(c, "tdse_set_flux");
+}
+
+extern "C" tdse_status tdse_get_flux(tdse_ctx* c, double* host_yield)
+{
+    if (!c) return TDSE_E_INVALID;
+    if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_get_flux: not bound");
+    if (!host_yield) return c->fail(TDSE_E_INVALID, "tdse_get_flux: null argument");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(host_yield, c->d_yield(), sizeof(double) * (size_t)c->n_inst, hipMemcpyDeviceToHost);
+    return (e == hipSuccess) ? TDSE_OK : c->hip_fail(e, "tdse_get_flux");
 }
 
 extern "C" tdse_status tdse_lanczos_dims(tdse_ctx* c, int32_t* host_meff)
@@ -1689,9 +1879,24 @@ static hipError_t upload_tiles(tdse_ctx* c, int set)
     return e;
 }
 
+// The autotuners time the length-gauge kernels (the velocity gauge runs the
+// workgroup sweeps in a fixed shape): the context is in the length gauge
+// while they run.
+struct LengthGaugeScope {
+    tdse_ctx* c;
+    int saved;
+    explicit LengthGaugeScope(tdse_ctx* ctx) : c(ctx), saved(ctx->gauge) { c->gauge = 0; }
+    ~LengthGaugeScope()
+    {
+        if (saved != 0) c->drop_graphs();
+        c->gauge = saved;
+    }
+};
+
 extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
 {
     if (!c) return TDSE_E_INVALID;
+    LengthGaugeScope lgs(c);
     if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_autotune: not bound");
     if (c->work_bytes < tdse_workspace_bytes(c, TDSE_METHOD_TAYLOR, 2))
         return c->fail(TDSE_E_WORKSPACE, "tdse_autotune: needs the Taylor workspace (two vectors)");
@@ -1785,6 +1990,7 @@ extern "C" tdse_status tdse_autotune(tdse_ctx* c, int32_t* rows_out)
 extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t* k_out, int32_t* rows_out)
 {
     if (!c) return TDSE_E_INVALID;
+    LengthGaugeScope lgs(c);
     if (!c->bound) return c->fail(TDSE_E_UNBOUND, "tdse_autotune_taylor: not bound");
     if (order < 1 || order > 16) return c->fail(TDSE_E_INVALID, "tdse_autotune_taylor: order must be 1..16");
     if (c->work_bytes < tdse_workspace_bytes(c, TDSE_METHOD_TUNE, 0))
@@ -1937,7 +2143,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
                     e2 = launch_copy(c->prec, red, backup, psi, c->stream);
                     auto fn = [&](const double* step) { return taylor_step_launches(c, step, order, oc); };
                     if (e2 == hipSuccess) e2 = hipEventRecord(o0, c->stream);
-                    if (e2 == hipSuccess) e2 = enqueue_chunk(c, 0, obs_reps, 1, rec, rec_stride, &oc, fn, side);
+                    if (e2 == hipSuccess) e2 = enqueue_chunk(c, 0, obs_reps, 1, rec, rec_stride, &oc, fn, side, false);
                     if (e2 == hipSuccess) e2 = hipEventRecord(o1, c->stream);
                     if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
                     float ms = 0.0f;

@@ -38,6 +38,10 @@ struct Inst {
     double inv_dr2;     // 1 / dr^2
     double z;
     double breakdown;   // Lanczos breakdown threshold: 1e-12 * Gershgorin bound of H
+    double r_abs;       // absorbing mask reaching 0 at r_abs (<= 0: none)
+    double p_abs;       // its exponent
+    int32_t i_flux;     // grid point of the flux sphere (-1: none)
+    int32_t pad_;
 };
 
 // A workgroup's share of a sweep: radial points [r0, r0 + kBlock) of rows
@@ -83,14 +87,19 @@ struct SweepGeom {
     int32_t order;         // block -> tile map: 0 identity, 1 XCD-contiguous runs, 2 short runs dealt round the XCDs
     const void* zero_row;  // device zeros, at least max N complex FP64 values
     int64_t plane;         // s48 storage: elements per plane of a state-shaped vector
+    int32_t gauge;         // 0 length (the field slots hold E), 1 velocity (they hold A/c)
+    int32_t pad_;
 };
 
 // Per-step scalars, FP64, laid out [slot][instance] with these slots:
+// kEStart, kEMid, kEEnd: the coupling scalar of the gauge at t_n, t_n + dt/2
+// and t_n + dt (E in the length gauge, A/c in the velocity gauge).
 // kRec: index of the observable record written after this step (-1: none).
-// kEStage0 + i: the field at t_n + c_i dt for stage i of an explicit
-// Runge-Kutta method given by its tableau (zero for other methods).
+// kEObs: the field E at t_n + dt (the observables' record, both gauges).
+// kEStage0 + i: the coupling scalar at t_n + c_i dt for stage i of an
+// explicit Runge-Kutta method given by its tableau (zero for other methods).
 constexpr int kRkMax = 8;           // most stages of a tableau
-enum StepSlot { kEStart = 0, kEMid = 1, kEEnd = 2, kTEnd = 3, kDt = 4, kRec = 5, kEStage0 = 6,
+enum StepSlot { kEStart = 0, kEMid = 1, kEEnd = 2, kTEnd = 3, kDt = 4, kRec = 5, kEObs = 6, kEStage0 = 7,
                 kSlots = kEStage0 + kRkMax };
 __host__ __device__ inline double step_value(const double* st, int n_inst, int slot, int inst)
 {
@@ -154,6 +163,17 @@ hipError_t launch_rk_stage(int prec, int S, const SweepGeom& g, const void* gin,
 // sigma[k] += sqrt(sum of instance k's err partials (sweep tiles) / U_k),
 // U_k = (lmax + 1) N: the root mean square deviation of the step.
 hipError_t launch_rk_sigma(const SweepGeom& g, const double* err_partial, double* sigma, hipStream_t st);
+
+// Sec. 2.1 absorbing potential as its one-step factor: psi *= M(r) =
+// 1 - cos^p[(pi/2)(1 - r/r_abs)] (0 from r_abs on) for the instances with
+// r_abs > 0, in place, over the reduce tiles.
+hipError_t launch_mask(int prec, const SweepGeom& g, void* psi, hipStream_t st);
+// Sec. 4 eq. flux / eq. yield: one workgroup per instance with i_flux >= 0,
+// J = sum_l Im[f_l^* df_l/dr] at point i_flux (the stencil's first
+// derivative).  init: j_prev[k] = J; else yield[k] += dt (j_prev[k] + J) / 2
+// and j_prev[k] = J (dt from the step table).
+hipError_t launch_flux(int prec, int S, const SweepGeom& g, const void* psi, const double* step, int init,
+                       double* j_prev, double* yield, hipStream_t st);
 
 // Observables: per-tile partial sums of norm, p_ion, dipole and acceleration
 // over the reduce tiles (kObsMainQ per tile, stored [q][tile]) and of p_g and

@@ -1,8 +1,9 @@
 """Test helper: the matrix of the oracle's apply_h, recovered by probing.
 
-A column (l, i) of H touches rows (l, i +- k) for k <= s and (l +- 1, i).  Two
-columns with equal l mod 3 and equal i mod (2s+1) never touch a common row,
-so 3(2s+1) probe vectors recover every entry of H.
+A column (l, i) of H touches rows (l, i +- k) for k <= s and (l +- 1, i) (the
+velocity gauge: (l +- 1, i +- k) as well).  Two columns with equal l mod 3 and
+equal i mod (2s+1) never touch a common row, so 3(2s+1) probe vectors recover
+every entry of H.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -21,7 +22,9 @@ def sparse_h(orc, g, efield):
         out = orc.apply_h(g, efield, probe)
         for dl in (-1, 0, 1):
             for di in range(-s, s + 1):
-                if dl != 0 and di != 0:
+                # the length gauge couples rows l +- 1 at the same radius only;
+                # the velocity gauge through the radial derivative as well
+                if dl != 0 and di != 0 and getattr(g, "gauge", 0) == 0:
                     continue
                 # rows r = (l+dl, i+di) of the probed columns (l, i)
                 col = np.nonzero(probe)[0]

@@ -215,3 +215,44 @@ def test_lanczos_dims_needs_a_bound_context(tdse):
         assert e.value.code == -8
     finally:
         tdse.tdse_destroy(ctx)
+
+
+def test_pulse_marshalling_keeps_the_shape(tdse):
+    arr = tdse._pulses([tdse.Pulse(0.1, 0.5, 2.0, 0.3, 1.0, tdse.PULSE_SINE2_A), tdse.Pulse(0.2, 0.4, 3.0, 0.0, 0.0)])
+    assert arr[0].shape == tdse.PULSE_SINE2_A and arr[1].shape == tdse.PULSE_SINE2_E
+    assert (arr[0].e0, arr[0].omega, arr[0].n_cycles, arr[0].cep, arr[0].t_on) == (0.1, 0.5, 2.0, 0.3, 1.0)
+
+
+@pytest.mark.parametrize("stencil,lmax", [(3, 4), (5, 6)])
+def test_velocity_gauge_lambda_bound(tdse, orc, stencil, lmax):
+    # tdse_lambda_max_bound in the velocity gauge takes a bound on |A/c| and
+    # agrees with the oracle's Gershgorin bound; it covers the spectrum of H
+    g = tdse.Grid(300, lmax, 0.1, stencil)
+    ctx = tdse.tdse_init_grid([g.desc()])
+    try:
+        with pytest.raises(tdse.TdseError):
+            tdse.tdse_set_gauge(ctx, 2)
+        tdse.tdse_set_gauge(ctx, tdse.GAUGE_VELOCITY)
+        assert tdse.lib.tdse_gauge(ctx) == tdse.GAUGE_VELOCITY
+        b = tdse.tdse_lambda_max_bound(ctx, 0, 0.7)
+        og = orc.Grid(n=300, lmax=lmax, dr=0.1, stencil=stencil, gauge=orc.VELOCITY)
+        assert b == pytest.approx(orc.h_bound(og, 0.7), rel=1e-14)
+        lam = eigsh(sparse_h(orc, og, 0.7), k=1, which="LM", return_eigenvectors=False)[0]
+        assert abs(lam) <= b
+        tdse.tdse_set_gauge(ctx, tdse.GAUGE_LENGTH)
+        og = orc.Grid(n=300, lmax=lmax, dr=0.1, stencil=stencil)
+        assert tdse.tdse_lambda_max_bound(ctx, 0, 0.7) == pytest.approx(orc.h_bound(og, 0.7), rel=1e-14)
+    finally:
+        tdse.tdse_destroy(ctx)
+
+
+def test_absorber_and_flux_need_a_bound_context(tdse):
+    ctx = tdse.tdse_init_grid([tdse.Grid(100, 2, 0.1).desc()])
+    try:
+        for call in (lambda: tdse.tdse_set_absorber(ctx, [50.0], [100.0]), lambda: tdse.tdse_set_flux(ctx, [10]),
+                     lambda: tdse.tdse_get_flux(ctx)):
+            with pytest.raises(tdse.TdseError) as e:
+                call()
+            assert e.value.code == -8
+    finally:
+        tdse.tdse_destroy(ctx)

@@ -179,3 +179,24 @@ def mixed_state(seed: int, n: int, lmax: int, dr: float) -> np.ndarray:
         if l <= lmax:
             v[l * n:(l + 1) * n] += a * f / math.sqrt(dr * float(np.dot(f, f)))
     return v
+
+
+def outgoing_packet(seed: int, n: int, lmax: int, dr: float, r0: float = 20.0, sigma: float = 3.0,
+                    k: float = 1.5) -> np.ndarray:
+    """Seeded complex128 state of shape [(lmax+1)*n], normalised on the grid:
+    a Gaussian packet exp(-(r - r0)^2 / (2 sigma^2)) moving outward with
+    momentum k (au) in every partial wave, each wave with a seeded complex
+    amplitude, plus the l = 0 bound-like shape r e^{-r} with weight 1/2, so
+    the packet carries probability through a flux sphere beyond r0 into an
+    absorber while part of the state stays near the origin."""
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal((lmax + 1, 2))
+    r = (np.arange(n) + 1.0) * dr
+    f = np.exp(-((r - r0) ** 2) / (2.0 * sigma ** 2)) * np.exp(1j * k * r)
+    v = np.zeros((lmax + 1) * n, dtype=np.complex128)
+    for l in range(lmax + 1):
+        v[l * n:(l + 1) * n] = (c[l, 0] + 1j * c[l, 1]) * f
+    v /= math.sqrt(dr * float(np.vdot(v, v).real))
+    b = r * np.exp(-r)
+    v[:n] += 0.5 * b / math.sqrt(dr * float(np.dot(b, b)))
+    return v / math.sqrt(dr * float(np.vdot(v, v).real))
