@@ -403,7 +403,9 @@ tdse_status tdse_autotune(tdse_ctx* ctx, int32_t* rows_out);
  * launch (ceil(order/K) launches per step), for both fused kernels (kind 0: workgroup tiles of 256
  * radii with the intermediate levels in LDS rings, 8, 16 or 32 rows; kind 1:
  * independent 64-radius wave strips with the intermediate levels in
- * registers, 8, 16, 32 or 64 rows), verifies each candidate's step against
+ * registers, 8, 16, 32 or 64 rows; kind 2: 128-radius pair strips, two
+ * adjacent radii per lane, the psi rows of the levels in an LDS ring, 8, 16,
+ * 32 or 64 rows), verifies each candidate's step against
  * the one-launch-per-term step (bit for bit in FP64; relative 2-norm
  * difference <= 1e-6 with FP32 storage, where the fused launches keep their
  * intermediates in FP64), and keeps the fastest for later tdse_step_taylor
@@ -417,7 +419,7 @@ tdse_status tdse_autotune(tdse_ctx* ctx, int32_t* rows_out);
  * the choice; tdse_taylor_fusion_kind gives the kernel.  Synchronises. */
 tdse_status tdse_autotune_taylor(tdse_ctx* ctx, int32_t order, int32_t* fuse_k_out, int32_t* rows_out);
 /* Horner terms per fused Taylor launch in use (0: one launch per term), the
- * fused kernel in use (0 LDS rings, 1 wave strips), and an explicit choice:
+ * fused kernel in use (0 LDS rings, 1 wave strips, 2 pair strips), and an explicit choice:
  * k = 0 (one launch per term) or 1..8 terms per fused launch of kernel
  * `kind` on tiles of `rows` rows (1..64); tdse_step_taylor then makes
  * ceil(order/k) launches per step, the last one with the remaining terms.

@@ -290,24 +290,36 @@ __device__ __forceinline__ RadialPoint radial_point(const Tile& I, int i)
     return p;
 }
 
-// Diagonal potential of row l: l(l+1)/(2 r^2) - Z/r.  l(l+1)/2 is formed in
-// integers (exact; scalar unit when l is wave-uniform) and converted once.
-__device__ __forceinline__ double row_potential(int l, double inv_r2, double z_over_r)
+// The diagonal of H on row l at one radius, kinetic centre weight included:
+//   d0 = l(l+1)/(2 r^2) + (c0 / dr^2 - Z/r),
+// as fma(L, 1/r^2, base) with L = l(l+1)/2 (formed in integers, exact; the
+// scalar unit when l is wave-uniform, then one conversion) and base =
+// fma(c0, 1/dr^2, -Z/r), formed once per radius.
+__device__ __forceinline__ double half_ll(int l) { return (double)((l * (l + 1)) >> 1); }
+template <int S>
+__device__ __forceinline__ double diag_base(double kin_scale, double z_over_r);
+__device__ __forceinline__ double row_diag(double half_ll_l, double inv_r2, double base)
 {
-    return fma((double)((l * (l + 1)) >> 1), inv_r2, -z_over_r);
+    return fma(half_ll_l, inv_r2, base);
+}
+
+template <int S>
+__device__ __forceinline__ double diag_base(double kin_scale, double z_over_r)
+{
+    return fma(Kin<S>::c0, kin_scale, -z_over_r);
 }
 
 // (H f)_{l,i} from the centre value, its radial neighbours (already zero
-// outside the box) and the values of rows l-1, l+1 at the same radius.
-// Every multiply-add is an explicit fma in a fixed order (the library is
-// built without implicit contraction), so every kernel that evaluates H
-// through this function rounds identically, whatever its loop shape.
+// outside the box), the values of rows l-1, l+1 at the same radius and the
+// diagonal d0 of row l (row_diag).  Every multiply-add is an explicit fma in
+// a fixed order (the library is built without implicit contraction), so
+// every kernel that evaluates H through this function rounds identically,
+// whatever its loop shape.
 template <int S>
 __device__ __forceinline__ double2 h_point(double2 cur, double2 m1, double2 p1, double2 m2, double2 p2,
-                                           double2 lm, double2 lp, double kin_scale, double v,
+                                           double2 lm, double2 lp, double kin_scale, double d0,
                                            double er, double kl, double klp)
 {
-    const double d0 = fma(Kin<S>::c0, kin_scale, v);
     const double d1 = Kin<S>::c1 * kin_scale;
     const double d2 = Kin<S>::c2 * kin_scale;
     const double ekl = er * kl, eklp = er * klp;

@@ -87,9 +87,9 @@ k_horner_fused(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
             if (inside && rho >= 0 && rho <= lmax) {
                 Neighbours<S> nb;
                 nb.load(in + base + (int64_t)rho * n, jc, n);
-                const double vpot = row_potential(rho, inv_r2, z_over_r);
+                const double d0 = row_diag(half_ll(rho), inv_r2, diag_base<S>(I.inv_dr2, z_over_r));
                 const double2 h = h_point<S>(in_cur, nb.m1, nb.p1, nb.m2, nb.p2, in_prev, in_next,
-                                             I.inv_dr2, vpot, er, g.kappa[rho], g.kappa[rho + 1]);
+                                             I.inv_dr2, d0, er, g.kappa[rho], g.kappa[rho + 1]);
                 v = horner_update(pr[0], h, dt / (double)first_term);
             }
             in_prev = in_cur;
@@ -125,8 +125,8 @@ k_horner_fused(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
                     m2 = (tid >= 2) ? row0[tid - 2] : zero2();
                     p2 = (tid + 2 < kBlock) ? row0[tid + 2] : zero2();
                 }
-                const double vpot = row_potential(rho, inv_r2, z_over_r);
-                const double2 h = h_point<S>(cur, m1, p1, m2, p2, lm, lp, I.inv_dr2, vpot, er,
+                const double d0 = row_diag(half_ll(rho), inv_r2, diag_base<S>(I.inv_dr2, z_over_r));
+                const double2 h = h_point<S>(cur, m1, p1, m2, p2, lm, lp, I.inv_dr2, d0, er,
                                              g.kappa[rho], g.kappa[rho + 1]);
                 v = horner_update(pr[k - 1], h, dt / (double)(first_term - k + 1));
             }

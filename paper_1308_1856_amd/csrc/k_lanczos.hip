@@ -151,8 +151,8 @@ k_lz_sweep_a(SweepGeom g, int j, int m, typename Stor<T>::captr psi, typename St
             } else {
                 nb.load(qj + row, i, n);
             }
-            const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
-            double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
+            const double d0 = row_diag(half_ll(l), rp.inv_r2, diag_base<S>(I.inv_dr2, rp.z_over_r));
+            double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, d0, er,
                                    g.kappa[l], g.kappa[l + 1]);
             if (VG) {
                 const double2 w = vel_coupling<S>(prev, nbm, next, nbp, l, rp.inv_r, inv_dr, fld, g.kappa[l],

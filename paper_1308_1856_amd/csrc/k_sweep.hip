@@ -67,8 +67,8 @@ k_hsweep(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typ
         } else {
             nb.load(in + row, i, n);
         }
-        const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
-        double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
+        const double d0 = row_diag(half_ll(l), rp.inv_r2, diag_base<S>(I.inv_dr2, rp.z_over_r));
+        double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, d0, er,
                                g.kappa[l], g.kappa[l + 1]);
         if (VG) {
             const double2 w = vel_coupling<S>(prev, nbm, next, nbp, l, rp.inv_r, inv_dr, fld, g.kappa[l],
@@ -202,9 +202,9 @@ k_hsweep_pair(SweepGeom g, const typename Cplx<T>::type* __restrict__ in,
         }
         const double kl = g.kappa[l], klp = g.kappa[l + 1];
         const double2 ha = h_point<S>(ca, xm1, cb, xm2, xp2, P.da(), N.da(), I.inv_dr2,
-                                      row_potential(l, ira2, zra), ef * ra, kl, klp);
+                                      row_diag(half_ll(l), ira2, diag_base<S>(I.inv_dr2, zra)), ef * ra, kl, klp);
         const double2 hb = h_point<S>(cb, ca, xp2, xm1, xp3, P.db(), N.db(), I.inv_dr2,
-                                      row_potential(l, irb2, zrb), ef * rb, kl, klp);
+                                      row_diag(half_ll(l), irb2, diag_base<S>(I.inv_dr2, zrb)), ef * rb, kl, klp);
         const double2 oa = TERM ? horner_update(Q.da(), ha, c) : ha;
         const double2 ob = TERM ? horner_update(Q.db(), hb, c) : hb;
         if (full)
@@ -273,8 +273,8 @@ k_rk4_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::aptr psi,
         const double2 a_next = (kReadAcc && more) ? ldc(acc, row + n + i) : zero2();
         const double2 p_next = (kReadPsi && more) ? ldc(psi, row + n + i) : zero2();
 
-        const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
-        double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, v, er,
+        const double d0 = row_diag(half_ll(l), rp.inv_r2, diag_base<S>(I.inv_dr2, rp.z_over_r));
+        double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, next, I.inv_dr2, d0, er,
                                g.kappa[l], g.kappa[l + 1]);
         if (VG) {
             const double2 w = vel_coupling<S>(prev, nbm, next, nb_next, l, rp.inv_r, inv_dr, fld, g.kappa[l],
@@ -350,8 +350,8 @@ k_rk_stage(SweepGeom g, typename Stor<T>::cptr gin, typename Stor<T>::cptr psi, 
             } else {
                 nb.load(gin + row, i, n);
             }
-            const double v = row_potential(l, rp.inv_r2, rp.z_over_r);
-            double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, nx, I.inv_dr2, v, er,
+            const double d0 = row_diag(half_ll(l), rp.inv_r2, diag_base<S>(I.inv_dr2, rp.z_over_r));
+            double2 h = h_point<S>(cur, nb.m1, nb.p1, nb.m2, nb.p2, prev, nx, I.inv_dr2, d0, er,
                                    g.kappa[l], g.kappa[l + 1]);
             if (VG) {
                 const double2 w = vel_coupling<S>(prev, nbm, nx, nbp, l, rp.inv_r, inv_dr, fld, g.kappa[l],

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <new>
 #include <string>
@@ -109,7 +110,7 @@ struct tdse_ctx {
     int sweep_variant = 0;              // bit 0: two radii per thread, bit 1: XCD-contiguous order,
                                         // bit 2: wave strips of one level (autotuned)
     int fuse_k = 0;                     // Horner terms per fused launch (0: one launch per term)
-    int fuse_kind = 0;                  // fused kernel: 0 LDS rings, 1 wave strips
+    int fuse_kind = 0;                  // fused kernel: 0 LDS rings, 1 wave strips, 2 pair strips
     bool rk4_fused = true;              // RK4: one strip launch per step (else four stage launches)
     int rows_rk4 = 16;
     int rows_fused = 16;
@@ -129,6 +130,7 @@ struct tdse_ctx {
            off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0,
            off_zero = 0, zero_bytes = 0;
     size_t partial_doubles = 0;
+    size_t tile_cap[kNumTileSets] = {};  // tiles each set's workspace region holds
     size_t strip_units_cap = 0;         // most strips any wave-strip tile set can hold
     // pinned staging for the per-step scalars (double buffered)
     double* h_step[2] = {nullptr, nullptr};
@@ -412,6 +414,8 @@ static int states_for(int lmax)
 static int fused_width(int K, int stencil) { return kBlock - 2 * (K - 1) * (stencil == 3 ? 1 : 2); }
 // output radii of one strip tile (kStripWaves strips of 64 - 2 K s)
 static int strip_width(int K, int stencil) { return kStripWaves * (64 - 2 * K * (stencil == 3 ? 1 : 2)); }
+// output radii of one pair-strip tile (two strips of 128 - 2 K s, two waves each)
+static int pair_strip_width(int K, int stencil) { return kPairStrips * (128 - 2 * K * (stencil == 3 ? 1 : 2)); }
 
 // (Re)builds one tile set.  rows = 0 for the population set.  The fused set
 // (K = c->fuse_k terms per launch) uses radially overlapping tiles: tile t
@@ -425,7 +429,9 @@ static void build_tiles(tdse_ctx* c, int set, int rows)
         // RK4 strips are built for its four stages, the sweep strips for one)
         // (the sweep strips are aligned: 4 waves of 64 radii, no overlap)
         const int K = (set == kRk4Tiles) ? 4 : std::max(1, c->fuse_k);
-        const int W = (set == kApplyTiles) ? kBlock : strip_width(K, c->stencil);
+        const int W = (set == kApplyTiles) ? kBlock
+                      : (set == kStripTiles && c->fuse_kind == 2) ? pair_strip_width(K, c->stencil)
+                                                                  : strip_width(K, c->stencil);
         for (int k = 0; k < c->n_inst; ++k) {
             Inst& I = c->inst[k];
             I.tbegin[set] = (int32_t)c->tiles[set].size();
@@ -610,6 +616,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->kappa.resize(lmax_all + 2);
     for (int l = 0; l < lmax_all + 2; ++l)
         c->kappa[l] = (l > 0) ? std::sqrt((double)l * l / (4.0 * l * l - 1.0)) : 0.0;
+
     // Tile sets.  Sweeps: rows per tile from the tuning cache if it has this
     // shape, else chosen so the launch has >= kTargetTiles workgroups.
     // Reductions (Lanczos, copies): up to 16 rows, >= 1024 workgroups.
@@ -701,7 +708,8 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
         if (set == kSweepTiles) cap = (size_t)c->total_cols;
         if (set == kStripTiles || set == kRk4Tiles || set == kApplyTiles) {
             cap = 0;
-            const int W = strip_width(kMaxFused, c->stencil);
+            // the narrowest tiles either strip kernel builds
+            const int W = std::min(strip_width(kMaxFused, c->stencil), pair_strip_width(kMaxFused, c->stencil));
             for (const tdse_grid_desc& g : c->grids) cap += (size_t)((g.n_r + W - 1) / W) * (g.lmax + 1);
             if (set == kStripTiles) c->strip_units_cap = cap * kStripWaves;
         }
@@ -714,6 +722,7 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
             const int W = fused_width(kMaxFused, c->stencil);
             for (const tdse_grid_desc& g : c->grids) cap += (size_t)((g.n_r + W - 1) / W) * (g.lmax + 1);
         }
+        c->tile_cap[set] = cap;
         c->off_tiles[set] = take(sizeof(Tile) * cap);
     }
     c->off_kappa = take(sizeof(double) * c->kappa.size());
@@ -1270,7 +1279,8 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
     void* out = nullptr;
     const int K = (c->gauge != 0) ? 0 : c->fuse_k;   // the fused kernels couple in the length gauge only
     if (K > 0) {
-        const bool strips = c->fuse_kind == 1;
+        const bool strips = c->fuse_kind >= 1;
+        const bool pairs = c->fuse_kind == 2;
         SweepGeom gf = c->geom(strips ? kStripTiles : kFusedTiles);
         if (strips) gf.variant = K;   // the term count the strip tiles were built for
         int which = 0;
@@ -1283,8 +1293,9 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
             hipError_t e;
             {
                 TimedLaunch tl(c, 5);
-                e = strips ? launch_horner_strip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs)
-                           : launch_horner_fused(c->prec, S, terms, gf, in, psi, out, step, first, c->stream);
+                e = pairs ? launch_horner_pstrip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs)
+                    : strips ? launch_horner_strip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs)
+                             : launch_horner_fused(c->prec, S, terms, gf, in, psi, out, step, first, c->stream);
             }
             if (obs && e == hipSuccess) c->obs_main_done = true;
             if (e != hipSuccess) return e;
@@ -1871,6 +1882,7 @@ extern "C" tdse_status tdse_lanczos_dims(tdse_ctx* c, int32_t* host_meff)
 // range of every set: the observables' finish reads the ranges).
 static hipError_t upload_tiles(tdse_ctx* c, int set)
 {
+    if (c->tiles[set].size() > c->tile_cap[set]) return hipErrorInvalidValue;   // never past the region
     hipError_t e = hipMemcpyAsync(c->d_work + c->off_tiles[set], c->tiles[set].data(),
                                   sizeof(Tile) * c->tiles[set].size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
@@ -2032,17 +2044,19 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    // kind 0: LDS-ring kernel, kind 1: wave-strip kernel
+    // kind 0: LDS-ring kernel, kind 1: wave-strip kernel, kind 2: pair strips
     struct Cand { int k, rows, kind; };
     std::vector<Cand> cands = {{0, 0, 0}};
     for (int K = 2; K <= std::min(order, (int)kMaxFused); ++K) {
         if (c->prec != TDSE_FP48)   // the LDS-ring kernel has no 48-bit form
             for (int rows : {8, 16, 32}) cands.push_back({K, rows, 0});
         for (int rows : {8, 16, 32, 64}) cands.push_back({K, rows, 1});
+        for (int rows : {8, 16, 32, 64}) cands.push_back({K, rows, 2});
     }
     double best_ms = 1e300;
     Cand best = {0, keep_rows, keep_kind};
     std::string bad;
+    std::set<std::pair<int, int>> failed;   // (K, kind) with a candidate that missed the reference
     for (const Cand& cd : cands) {
         if (e != hipSuccess) break;
         c->fuse_k = cd.k;
@@ -2069,6 +2083,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
         if (!(rel <= tol)) {
             bad += " K=" + std::to_string(cd.k) + "/rows=" + std::to_string(cd.rows) + "/kind=" +
                    std::to_string(cd.kind) + ": " + std::to_string(rel);
+            failed.insert({cd.k, cd.kind});
             continue;
         }
         // timing: reps steps from the backed-up state
@@ -2105,7 +2120,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     // the faster.  The records go to work vector 3 (free by now), when it
     // holds them.
     const int obs_reps = 8;
-    if (e == hipSuccess && e2 == hipSuccess && c->fuse_k > 0 && c->fuse_kind == 1 &&
+    if (e == hipSuccess && e2 == hipSuccess && c->fuse_k > 0 && c->fuse_kind >= 1 &&
         sizeof(double) * kObsRecord * obs_reps * (size_t)c->n_inst <= c->state_bytes()) {
         tdse_obs* rec = reinterpret_cast<tdse_obs*>(ref);
         const int64_t rec_stride = (int64_t)obs_reps * kObsRecord;
@@ -2118,18 +2133,25 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
             tdse_status su = upload_steps(c, pulses.data(), t0.data(), dt.data(), 0, obs_reps, 1);
             if (su != TDSE_OK) e2 = hipErrorUnknown;
         }
-        // the strip heights the step timing tried, with both modes: the
-        // launch with the sums does one more iteration per tile, which can
-        // move the best height
-        const int chosen_rows = c->rows_fused;
-        int best_rows = chosen_rows;
+        // the strip heights the step timing tried, with both modes, and both
+        // strip kernels: the launch with the sums does one more iteration
+        // per tile, and the sums cost the two kernels differently, which can
+        // move the best height and kernel
+        const int chosen_rows = c->rows_fused, chosen_kind = c->fuse_kind;
+        int best_rows = chosen_rows, best_kind = chosen_kind;
         bool best_fused = true;
         float best_obs_ms = 3.0e38f;
         std::vector<int> heights = {chosen_rows};
         for (int r : {16, 32, 64})
             if (r != chosen_rows) heights.push_back(r);
-        for (int rows : heights) {
+        std::vector<std::pair<int, int>> shapes;   // (kind, rows)
+        for (int kind : {chosen_kind, 3 - chosen_kind})
+            if (kind == chosen_kind || failed.count({c->fuse_k, kind}) == 0)
+                for (int rows : heights) shapes.push_back({kind, rows});
+        for (const auto& sh : shapes) {
             if (e2 != hipSuccess) break;
+            const int rows = sh.second;
+            c->fuse_kind = sh.first;
             c->rows_fused = rows;
             build_tiles(c, kStripTiles, rows);
             e2 = upload_tiles(c, kStripTiles);
@@ -2156,6 +2178,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
                 if (ms_mode[fused] < best_obs_ms) {
                     best_obs_ms = ms_mode[fused];
                     best_rows = rows;
+                    best_kind = sh.first;
                     best_fused = fused != 0;
                 }
             }
@@ -2164,6 +2187,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
         if (o1) (void)hipEventDestroy(o1);
         c->obs_fusion = (e2 == hipSuccess) ? best_fused : true;
         c->rows_fused = (e2 == hipSuccess) ? best_rows : chosen_rows;
+        c->fuse_kind = (e2 == hipSuccess) ? best_kind : chosen_kind;
         build_tiles(c, kFusedTiles, c->rows_fused);
         build_tiles(c, kStripTiles, c->rows_fused);
         if (e2 == hipSuccess) e2 = upload_tiles(c, kFusedTiles);
@@ -2188,8 +2212,8 @@ extern "C" int32_t tdse_taylor_fusion_kind(const tdse_ctx* c) { return c ? c->fu
 extern "C" tdse_status tdse_set_taylor_fusion(tdse_ctx* c, int32_t k, int32_t rows, int32_t kind)
 {
     if (!c) return TDSE_E_INVALID;
-    if (k < 0 || k > kMaxFused || (k > 0 && (rows < 1 || rows > 64)) || kind < 0 || kind > 1)
-        return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: k must be 0..8, rows 1..64, kind 0 or 1");
+    if (k < 0 || k > kMaxFused || (k > 0 && (rows < 1 || rows > 64)) || kind < 0 || kind > 2)
+        return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: k must be 0..8, rows 1..64, kind 0, 1 or 2");
     if (c->prec == TDSE_FP48 && k > 0 && kind == 0)
         return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: the LDS-ring kernel (kind 0) has no 48-bit form");
     if (c->bound) {
@@ -2202,6 +2226,8 @@ extern "C" tdse_status tdse_set_taylor_fusion(tdse_ctx* c, int32_t k, int32_t ro
     c->fuse_kind = kind;
     build_tiles(c, kFusedTiles, c->rows_fused);
     build_tiles(c, kStripTiles, c->rows_fused);
+    if (c->tiles[kFusedTiles].size() > c->tile_cap[kFusedTiles] || c->tiles[kStripTiles].size() > c->tile_cap[kStripTiles])
+        return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: tile table larger than its workspace region");
     if (c->bound) {
         hipError_t e = upload_tiles(c, kFusedTiles);
         if (e == hipSuccess) e = upload_tiles(c, kStripTiles);

@@ -129,6 +129,17 @@ hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const
                                const void* psi, void* out, const double* step, int first_term,
                                hipStream_t st, double* obs_partial = nullptr);
 constexpr int kStripWaves = kBlock / 64;   // strips per strip tile
+// The same K terms on pair strips: lane L holds radii 2L and 2L + 1 of a
+// strip of 128, two waves per strip (levels 1..ceil(K/2) and the rest, the
+// level rows handed over and the psi rows kept in LDS), tiles of kPairStrips
+// strips of 128 - 2 Kt s output radii (g.variant = Kt >= K), 128 threads per
+// strip; same results and aliasing rules as launch_horner_strip; the
+// observables' partial sums in the first kPairStrips units of each tile's
+// four (the others zero).
+constexpr int kPairStrips = 1;   // pair strips per workgroup (two waves each)
+hipError_t launch_horner_pstrip(int prec, int S, int K, const SweepGeom& g, const void* in, const void* psi,
+                                void* out, const double* step, int first_term, hipStream_t st,
+                                double* obs_partial = nullptr);
 // An H sweep (term 0) or one Horner term on the aligned strip tile set of one
 // level (g.variant = 1; tiles of 4 waves of 64 radii from a multiple of 256);
 // same results and aliasing rules as launch_hsweep.

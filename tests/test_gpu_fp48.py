@@ -114,6 +114,8 @@ CASES = [
     ("taylor", 4, (4, 32, 1), True, True),
     ("taylor", 7, (7, 8, 1), True, True),     # one launch of 7 terms (a last launch of 7)
     ("taylor", 8, (5, 16, 1), True, True),    # 5 + 3 terms
+    ("taylor", 8, (8, 16, 2), True, True),    # pair strips, observables in the launch
+    ("taylor", 8, (3, 8, 2), True, False),    # pair strips, 3 + 3 + 2 terms
     ("rk4", 4, None, True, None),             # one strip launch per step
     ("rk4", 4, None, False, None),            # four stage launches
     ("lanczos", 12, None, True, None),

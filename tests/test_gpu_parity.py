@@ -462,7 +462,9 @@ def test_autotune_keeps_results_bitwise(tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("stencil,k,rows,kind", [(5, 8, 4, 0), (5, 4, 16, 0), (3, 5, 3, 0), (3, 8, 32, 0),
                                                  (5, 8, 4, 1), (5, 4, 16, 1), (3, 5, 3, 1), (3, 8, 64, 1),
-                                                 (3, 6, 1, 1), (5, 7, 9, 1)])
+                                                 (3, 6, 1, 1), (5, 7, 9, 1),
+                                                 (5, 8, 4, 2), (5, 4, 16, 2), (3, 5, 3, 2), (3, 8, 64, 2),
+                                                 (3, 6, 1, 2), (5, 7, 9, 2), (3, 3, 2, 2), (5, 2, 5, 2)])
 def test_fused_taylor_bitwise_equal_to_per_term(stencil, k, rows, kind):
     # K Horner terms per launch (either fused kernel) compute every element
     # with the same FP64 expression as one launch per term: identical bits,
@@ -491,7 +493,7 @@ def test_fused_taylor_bitwise_equal_to_per_term(stencil, k, rows, kind):
     assert rel_err(res[1][0], ref) < TOL64
 
 
-@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1, 2])
 def test_fused_taylor_fp32_and_graphs(kind):
     t = lib()
     grid = t.Grid(600, 8, 0.1, 3, t.FP32, 1.0, 5.0)
@@ -531,7 +533,7 @@ def test_autotune_taylor_choice_is_consistent():
     say(f"autotune_taylor: K={k} rows={rows} kind={prop.taylor_fusion_kind}")
     assert np.array_equal(prop.get_state(0), before)           # state restored
     assert k == 0 or 2 <= k <= 8
-    assert prop.taylor_fusion_kind in (0, 1)
+    assert prop.taylor_fusion_kind in (0, 1, 2)
     assert prop.obs_fusion in (True, False)     # the tuner's choice of the observables' summation
     obs_tuned = prop.obs_buffer(12, 1)
     prop.step_taylor(pulse, 5.0, dt, 8, 12, 1, obs_tuned)
@@ -545,7 +547,7 @@ def test_autotune_taylor_choice_is_consistent():
     prop.close()
 
 
-@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1, 2])
 def test_fused_taylor_batch_bitwise(kind):
     # uneven instances in one launch: each fused kernel matches the per-term
     # path bit for bit on every instance (FP64)
@@ -622,8 +624,8 @@ def assert_records_match(a, b, main_bitwise):
         assert np.all(diff <= 1e-13 * scale + 1e-12), (col, float(np.max(diff)), float(np.max(scale)))
 
 
-@pytest.mark.parametrize("prec,stencil", [(0, 5), (1, 3)])
-def test_observables_in_strip_launch_match_pass(prec, stencil):
+@pytest.mark.parametrize("prec,stencil,kind", [(0, 5, 1), (1, 3, 1), (0, 5, 2), (1, 3, 2), (0, 3, 2)])
+def test_observables_in_strip_launch_match_pass(prec, stencil, kind):
     # The main observables (norm, p_ion, dipole, acceleration) summed by the
     # step's last wave-strip launch agree with the observables pass to FP64
     # rounding (another order of the same sums); the populations, the states
@@ -641,11 +643,13 @@ def test_observables_in_strip_launch_match_pass(prec, stencil):
     ng = len(grids)
     nsteps = 12
     say(f"observables in the strip launch vs their own pass, prec {prec}, stencil {stencil}")
-    for K, rows, every, graphs in ((4, 8, 1, False), (3, 4, 3, True), (8, 16, 1, True), (2, 1, 2, False)):
+    # (K = 7 and 5: Taylor-8's last launch has 1 and 3 terms)
+    for K, rows, every, graphs in ((4, 8, 1, False), (3, 4, 3, True), (8, 16, 1, True), (2, 1, 2, False),
+                                   (7, 8, 1, True), (5, 16, 3, False)):
         out = []
         for fused in (True, False):
             prop = t.Propagator(grids, methods=((t.METHOD_TAYLOR, 8),), graphs=graphs)
-            prop.set_taylor_fusion(K, rows, 1)
+            prop.set_taylor_fusion(K, rows, kind)
             prop.set_obs_fusion(fused)
             assert prop.obs_fusion == fused
             dts = [0.5 * t.tdse_taylor_stability_limit(8) / prop.lambda_max_bound(k, 0.1) for k in range(ng)]
@@ -681,7 +685,7 @@ def test_explicit_sweep_shape_bitwise():
         assert np.array_equal(o, out[0])
 
 
-@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1, 2])
 def test_fused_degenerate_shapes(kind):
     # the smallest grids (N = 8, a single row lmax = 0, strips wider than the
     # grid), order 1 and order 2, zero steps: fused == per-term bit for bit,

@@ -256,3 +256,19 @@ def test_absorber_and_flux_need_a_bound_context(tdse):
             assert e.value.code == -8
     finally:
         tdse.tdse_destroy(ctx)
+
+
+@pytest.mark.parametrize("stencil", [3, 5])
+def test_every_fused_shape_fits_its_workspace_region(tdse, stencil):
+    # every fused kernel, term count and strip height builds a tile table
+    # that fits the region the context reserved for it (the narrowest tiles
+    # of any kind, one row each); checked on the host before any upload
+    grids = [tdse.Grid(n, lmax, 0.1, stencil).desc() for n, lmax in ((5001, 7), (130, 0), (777, 33))]
+    ctx = tdse.tdse_init_grid(grids)
+    try:
+        for kind in (0, 1, 2):
+            for k in range(1, 9):
+                for rows in (1, 3, 16, 64):
+                    assert tdse.lib.tdse_set_taylor_fusion(ctx, k, rows, kind) == 0, (kind, k, rows)
+    finally:
+        tdse.tdse_destroy(ctx)
