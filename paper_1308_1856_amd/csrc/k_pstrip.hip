@@ -200,8 +200,15 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
         fprev = Pair{va, vb};
     };
 
+    // Rows outside [0, lmax] of every level are zero (their psi rows and
+    // couplings are), so the checked iterations skip them: at a member's
+    // first and last rows the level pipeline's ramps would otherwise compute
+    // K - k zero rows of level k at each end.
+    auto live = [&](int rr) { return rr >= 0 && rr <= lmax; };
+
     // one iteration (it: this wave's count; CHECK: some levels may not have
-    // reached their first row, and rows past the tile are not stored)
+    // reached their first row or may work on rows outside [0, lmax], and rows
+    // past the tile are not stored)
     auto body = [&](int it, Slot& s, auto check) {
         constexpr bool CHECK = decltype(check)::value;
         const int pit = it - LAG;                // the producer iteration this one plays
@@ -223,7 +230,9 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
             const int wslot = it % R;
             ring_a(wslot) = poa;
             ring_b(wslot) = pob;
-            up = mask(horner(Pair{widen(poa), widen(pob)}, h_row(xc, xm, xp, rho, kq[1], kq[0]), coef[0]));
+            up = zero_pair();
+            if (!CHECK || live(rho))
+                up = mask(horner(Pair{widen(poa), widen(pob)}, h_row(xc, xm, xp, rho, kq[1], kq[0]), coef[0]));
             xm = xc;
             xc = xp;
             if (WRITES && KHI == 1) {
@@ -243,7 +252,7 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
             const int j = k - KLO;               // register index of level k
             const int rk = rho - (k - 1);
             Pair v = zero_pair();
-            if (!CHECK || pit >= 2 * (k - 1)) {
+            if (!CHECK || (pit >= 2 * (k - 1) && live(rk))) {
                 // psi(rk), written by the producer at its iteration pit - (k - 1)
                 const int rslot = (pit - (k - 1) + 2 * R) % R;
                 const Pair pk{widen(ring_a(rslot)), widen(ring_b(rslot))};
@@ -279,13 +288,22 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
 #pragma unroll
         for (int u = 0; u < D; ++u) body(it + u, sl[u], std::true_type{});
     }
-    for (; it + D <= iters; it += D) {
+    // unchecked while every level's row lies in [0, lmax] (level 1 leads:
+    // row rho0 + it - LAG), checked from there to the end
+    const int steady_end = max(warm_trips_end, min(iters, lmax - rho0 + 1 + LAG) / D * D);
+#pragma clang loop unroll(disable)
+    for (; it + D <= steady_end; it += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) body(it + u, sl[u], std::false_type{});
     }
+#pragma clang loop unroll(disable)
+    for (; it + D <= iters; it += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) body(it + u, sl[u], std::true_type{});
+    }
 #pragma unroll
     for (int u = 0; u < D - 1; ++u)
-        if (it + u < iters) body(it + u, sl[u], std::false_type{});
+        if (it + u < iters) body(it + u, sl[u], std::true_type{});
     if (OBS) {
         // the iteration past the last: level K at row l1 for the last pair,
         // checked so that it stores nothing (every wave runs it: one barrier)

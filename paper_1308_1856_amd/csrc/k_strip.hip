@@ -216,7 +216,13 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, ty
         fprev = vs;
     };
 
-    // one iteration; CHECK: some levels may not have reached their first row yet
+    // Rows outside [0, lmax] of every level are zero (their psi rows and
+    // couplings are), so the checked iterations skip them: at a member's
+    // first and last rows the level pipeline's ramps would otherwise compute
+    // K - k zero rows of level k at each end.
+    auto live = [&](int rr) { return rr >= 0 && rr <= lmax; };
+    // one iteration; CHECK: some levels may not have reached their first row
+    // yet, or may work on rows outside [0, lmax]
     auto body = [&](int it, Slot& sl, auto check) {
         constexpr bool CHECK = decltype(check)::value;
         const int rho = rho0 + it;
@@ -240,10 +246,13 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, ty
         pr[0] = po;
 
         // level 1 from the input
-        const double2 h1 = ALIGNED ? h_row_edge(xc, xc1, xc2, xm, xp, rho, kq[1], kq[0])
-                                   : h_row(xc, xm, xp, rho, kq[1], kq[0]);
-        double2 up = APPLY ? h1 : horner_update(widen(pr[0]), h1, coef[0]);
-        if (MASKED) up = pick2(inside, up, zero2());
+        double2 up = zero2();
+        if (!CHECK || live(rho)) {
+            const double2 h1 = ALIGNED ? h_row_edge(xc, xc1, xc2, xm, xp, rho, kq[1], kq[0])
+                                       : h_row(xc, xm, xp, rho, kq[1], kq[0]);
+            up = APPLY ? h1 : horner_update(widen(pr[0]), h1, coef[0]);
+            if (MASKED) up = pick2(inside, up, zero2());
+        }
         // the stored row: in [l0, l1) at every iteration past the warm-up trips
         auto store_row = [&](int rr) { return !CHECK || (rr >= I.l0 && rr < I.l1); };
         if (K == 1 && writes && store_row(rho)) stc(out_i, os, up);
@@ -253,7 +262,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, ty
         for (int k = 2; k <= K; ++k) {
             const int rk = rho - (k - 1);
             double2 v = zero2();
-            if (!CHECK || it >= 2 * (k - 1)) {
+            if (!CHECK || (it >= 2 * (k - 1) && live(rk))) {
                 // level k-1 at rows rk (ra), rk - 1 (rb) and rk + 1 (this iteration)
                 v = horner_update(widen(pr[k - 1]), h_row(ra[k - 2], rb[k - 2], up, rk, kq[k], kq[k - 1]), coef[k - 1]);
                 if (MASKED) v = pick2(inside, v, zero2());
@@ -282,23 +291,32 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, ty
     // trips that hold the warm-up iterations it < 2(K-1) (levels still
     // starting; kept rolled, as the trip count is a constant and the
     // straight-line code of a full unroll would be scheduled into many more
-    // live registers), then the steady trips, then a tail of fewer than D
-    // iterations.  A tile too short to reach the end of the warm-up trips
-    // runs on to it: the extra iterations compute rows past l1 (inputs
-    // outside [0, lmax] read as zero) and store nothing.
+    // live registers), then the steady trips, then checked trips once level
+    // 1 passes lmax, then a tail of fewer than D iterations.  A tile too
+    // short to reach the end of the warm-up trips runs on to it: the extra
+    // iterations compute rows past l1 (inputs outside [0, lmax] read as zero)
+    // and store nothing.
     int it = 0;
 #pragma clang loop unroll(disable)
     for (; it < warm_trips_end; it += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) body(it + u, sl[u], std::true_type{});
     }
-    for (; it + D <= iters; it += D) {
+    // unchecked while every level's row lies in [0, lmax] (level 1 leads:
+    // row rho0 + it), checked from there to the end
+    const int steady_end = max(warm_trips_end, min(iters, lmax - rho0 + 1) / D * D);
+    for (; it + D <= steady_end; it += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) body(it + u, sl[u], std::false_type{});
     }
+#pragma clang loop unroll(disable)
+    for (; it + D <= iters; it += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) body(it + u, sl[u], std::true_type{});
+    }
 #pragma unroll
     for (int u = 0; u < D - 1; ++u)
-        if (it + u < iters) body(it + u, sl[u], std::false_type{});
+        if (it + u < iters) body(it + u, sl[u], std::true_type{});
     if (OBS) {
         // the iteration past the last (slot iters - it < D): level K at row
         // l1 for the last pair, checked so that it stores nothing
