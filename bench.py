@@ -165,7 +165,7 @@ def source_digest(name):
     """sha256 over a kernel source and the device headers it includes."""
     import hashlib
     h = hashlib.sha256()
-    for part in (name, "device_common.hpp", "strip_common.hpp", "tdse_internal.hpp"):
+    for part in (name, "device_common.hpp", "strip_common.hpp", "pstrip_body.hpp", "tdse_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1308_1856_amd", "csrc", part), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

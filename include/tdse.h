@@ -405,21 +405,26 @@ tdse_status tdse_autotune(tdse_ctx* ctx, int32_t* rows_out);
  * independent 64-radius wave strips with the intermediate levels in
  * registers, 8, 16, 32 or 64 rows; kind 2: 128-radius pair strips, two
  * adjacent radii per lane, the psi rows of the levels in an LDS ring, 8, 16,
- * 32 or 64 rows), verifies each candidate's step against
+ * 32 or 64 rows; kind 3: the pair strips in a persistent launch, as many
+ * workgroups as are resident at once taking the tiles from a work queue in
+ * the workspace, most rows first, 16, 32 or 64 rows), verifies each
+ * candidate's step against
  * the one-launch-per-term step (bit for bit in FP64; relative 2-norm
  * difference <= 1e-6 with FP32 storage, where the fused launches keep their
  * intermediates in FP64), and keeps the fastest for later tdse_step_taylor
- * calls.  With the wave-strip kernel chosen it then times 8 steps with a
+ * calls.  With a strip kernel (kind 1..3) chosen it then times 8 steps with a
  * record after each, the main observables summed in the step's last launch
- * and by their own pass (tdse_set_obs_fusion), at the chosen strip height and
- * at 16, 32 and 64 rows (the fastest of four timed passes each), and keeps
- * the fastest pair (when work vector 3 holds
+ * and by their own pass (tdse_set_obs_fusion), for each strip kernel whose
+ * candidates at the chosen K all passed, at the chosen strip height and at
+ * 16, 32 and 64 rows (the fastest of four timed passes each), and keeps the
+ * fastest kernel, height and mode (when work vector 3 holds
  * the 8 records of every instance; else the settings stay).  Needs the TDSE_METHOD_TUNE workspace; the state is restored.
  * *fuse_k_out (0: one launch per term) and *rows_out (may be NULL) receive
  * the choice; tdse_taylor_fusion_kind gives the kernel.  Synchronises. */
 tdse_status tdse_autotune_taylor(tdse_ctx* ctx, int32_t order, int32_t* fuse_k_out, int32_t* rows_out);
 /* Horner terms per fused Taylor launch in use (0: one launch per term), the
- * fused kernel in use (0 LDS rings, 1 wave strips, 2 pair strips), and an explicit choice:
+ * fused kernel in use (0 LDS rings, 1 wave strips, 2 pair strips, 3 pair
+ * strips in a persistent launch), and an explicit choice:
  * k = 0 (one launch per term) or 1..8 terms per fused launch of kernel
  * `kind` on tiles of `rows` rows (1..64); tdse_step_taylor then makes
  * ceil(order/k) launches per step, the last one with the remaining terms.

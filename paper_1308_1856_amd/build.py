@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtdse.so")
 
-SOURCES = ["k_sweep.hip", "k_obs.hip", "k_lanczos.hip", "k_fused.hip", "k_strip.hip", "k_pstrip.hip",
+SOURCES = ["k_sweep.hip", "k_obs.hip", "k_lanczos.hip", "k_fused.hip", "k_strip.hip", "k_pstrip.hip", "k_pstrip_q.hip",
            "tdse_api.cpp", "host_eigen.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

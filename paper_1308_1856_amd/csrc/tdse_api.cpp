@@ -110,7 +110,8 @@ struct tdse_ctx {
     int sweep_variant = 0;              // bit 0: two radii per thread, bit 1: XCD-contiguous order,
                                         // bit 2: wave strips of one level (autotuned)
     int fuse_k = 0;                     // Horner terms per fused launch (0: one launch per term)
-    int fuse_kind = 0;                  // fused kernel: 0 LDS rings, 1 wave strips, 2 pair strips
+    int fuse_kind = 0;                  // fused kernel: 0 LDS rings, 1 wave strips, 2 pair strips,
+                                        // 3 pair strips in a persistent launch over a work queue
     bool rk4_fused = true;              // RK4: one strip launch per step (else four stage launches)
     int rows_rk4 = 16;
     int rows_fused = 16;
@@ -128,8 +129,9 @@ struct tdse_ctx {
     // workspace layout (bytes from d_work)
     size_t off_inst = 0, off_tiles[kNumTileSets] = {0, 0, 0, 0, 0, 0, 0}, off_kappa = 0, off_radial = 0,
            off_step = 0, off_obs_tmp = 0, off_lz = 0, off_partial = 0, off_vecs = 0, fixed_bytes = 0,
-           off_zero = 0, zero_bytes = 0;
+           off_zero = 0, zero_bytes = 0, off_queue = 0, off_perm = 0;
     size_t partial_doubles = 0;
+    std::vector<int32_t> strip_perm;    // strip tiles, longest first (the persistent launch's order)
     size_t tile_cap[kNumTileSets] = {};  // tiles each set's workspace region holds
     size_t strip_units_cap = 0;         // most strips any wave-strip tile set can hold
     // pinned staging for the per-step scalars (double buffered)
@@ -228,6 +230,8 @@ struct tdse_ctx {
     double* d_radial() const { return reinterpret_cast<double*>(d_work + off_radial); }
     LanczosScalars* d_lz() const { return reinterpret_cast<LanczosScalars*>(d_work + off_lz); }
     double* d_jprev() const { return reinterpret_cast<double*>(d_work + off_flux); }
+    unsigned* d_queue() const { return reinterpret_cast<unsigned*>(d_work + off_queue); }
+    int32_t* d_perm() const { return reinterpret_cast<int32_t*>(d_work + off_perm); }
     double* d_yield() const { return d_jprev() + n_inst; }
     char* d_vec(int k) const { return d_work + off_vecs + (size_t)k * state_bytes(); }
     // elements per plane of a state-shaped vector with 48-bit storage (its
@@ -430,7 +434,7 @@ static void build_tiles(tdse_ctx* c, int set, int rows)
         // (the sweep strips are aligned: 4 waves of 64 radii, no overlap)
         const int K = (set == kRk4Tiles) ? 4 : std::max(1, c->fuse_k);
         const int W = (set == kApplyTiles) ? kBlock
-                      : (set == kStripTiles && c->fuse_kind == 2) ? pair_strip_width(K, c->stencil)
+                      : (set == kStripTiles && c->fuse_kind >= 2) ? pair_strip_width(K, c->stencil)
                                                                   : strip_width(K, c->stencil);
         for (int k = 0; k < c->n_inst; ++k) {
             Inst& I = c->inst[k];
@@ -457,6 +461,16 @@ static void build_tiles(tdse_ctx* c, int set, int rows)
                 }
             }
             I.tend[set] = (int32_t)c->tiles[set].size();
+        }
+        if (set == kStripTiles) {
+            // the persistent launch's order: the most rows first (a tile's
+            // time grows with its rows), then the table order
+            const std::vector<Tile>& T = c->tiles[set];
+            c->strip_perm.resize(T.size());
+            for (size_t i = 0; i < T.size(); ++i) c->strip_perm[i] = (int32_t)i;
+            std::stable_sort(c->strip_perm.begin(), c->strip_perm.end(), [&](int32_t a, int32_t b) {
+                return T[a].l1 - T[a].l0 > T[b].l1 - T[b].l0;
+            });
         }
         return;
     }
@@ -737,6 +751,8 @@ extern "C" tdse_status tdse_init_grid(const tdse_grid_desc* grids, int32_t n_ins
     c->off_obs_tmp = take(sizeof(tdse_obs) * n_inst);
     c->off_lz = take(sizeof(LanczosScalars) * n_inst);
     c->off_flux = take(sizeof(double) * 2 * (size_t)n_inst);
+    c->off_queue = take(sizeof(unsigned) * 2);
+    c->off_perm = take(sizeof(int32_t) * c->tile_cap[kStripTiles]);
     // Lanczos dots; the observables pass; or the strips' main partials (two
     // sets, by step parity) and the population tiles
     // (and the Runge-Kutta stages' deviation partials, one per sweep tile:
@@ -839,6 +855,7 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
         {c->off_tiles[kApplyTiles], c->tiles[kApplyTiles].data(), sizeof(Tile) * c->tiles[kApplyTiles].size()},
         {c->off_kappa, c->kappa.data(), sizeof(double) * c->kappa.size()},
         {c->off_radial, c->radial.data(), sizeof(double) * c->radial.size()},
+        {c->off_perm, c->strip_perm.data(), sizeof(int32_t) * c->strip_perm.size()},
     };
     for (const Up& u : ups) {
         hipError_t e = hipMemcpyAsync(c->d_work + u.off, u.src, u.bytes, hipMemcpyHostToDevice, c->stream);
@@ -848,6 +865,9 @@ extern "C" tdse_status tdse_bind(tdse_ctx* c, void* d_state, void* d_work, size_
     if (e != hipSuccess) return c->hip_fail(e, "tdse_bind zero row");
     e = hipMemsetAsync(c->d_work + c->off_flux, 0, sizeof(double) * 2 * (size_t)c->n_inst, c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "tdse_bind flux");
+    // the work queue's counters start at zero (each persistent launch leaves them so)
+    e = hipMemsetAsync(c->d_queue(), 0, sizeof(unsigned) * 2, c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "tdse_bind queue");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return c->hip_fail(e, "tdse_bind sync");
     c->bound = true;
@@ -1280,7 +1300,11 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
     const int K = (c->gauge != 0) ? 0 : c->fuse_k;   // the fused kernels couple in the length gauge only
     if (K > 0) {
         const bool strips = c->fuse_kind >= 1;
-        const bool pairs = c->fuse_kind == 2;
+        const bool pairs = c->fuse_kind >= 2;
+        // pair strips take the tiles most rows first (a persistent launch
+        // from the work queue, else one workgroup per tile in that order)
+        unsigned* queue = (c->fuse_kind == 3) ? c->d_queue() : nullptr;
+        const int32_t* perm = pairs ? c->d_perm() : nullptr;
         SweepGeom gf = c->geom(strips ? kStripTiles : kFusedTiles);
         if (strips) gf.variant = K;   // the term count the strip tiles were built for
         int which = 0;
@@ -1293,7 +1317,8 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
             hipError_t e;
             {
                 TimedLaunch tl(c, 5);
-                e = pairs ? launch_horner_pstrip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs)
+                e = pairs ? launch_horner_pstrip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs,
+                                                 queue, perm)
                     : strips ? launch_horner_strip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs)
                              : launch_horner_fused(c->prec, S, terms, gf, in, psi, out, step, first, c->stream);
             }
@@ -1885,6 +1910,9 @@ static hipError_t upload_tiles(tdse_ctx* c, int set)
     if (c->tiles[set].size() > c->tile_cap[set]) return hipErrorInvalidValue;   // never past the region
     hipError_t e = hipMemcpyAsync(c->d_work + c->off_tiles[set], c->tiles[set].data(),
                                   sizeof(Tile) * c->tiles[set].size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && set == kStripTiles && !c->strip_perm.empty())
+        e = hipMemcpyAsync(c->d_perm(), c->strip_perm.data(), sizeof(int32_t) * c->strip_perm.size(),
+                           hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_work + c->off_inst, c->inst.data(), sizeof(Inst) * c->inst.size(),
                            hipMemcpyHostToDevice, c->stream);
@@ -2044,7 +2072,8 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    // kind 0: LDS-ring kernel, kind 1: wave-strip kernel, kind 2: pair strips
+    // kind 0: LDS-ring kernel, kind 1: wave-strip kernel, kind 2: pair strips,
+    // kind 3: pair strips in a persistent launch
     struct Cand { int k, rows, kind; };
     std::vector<Cand> cands = {{0, 0, 0}};
     for (int K = 2; K <= std::min(order, (int)kMaxFused); ++K) {
@@ -2052,6 +2081,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
             for (int rows : {8, 16, 32}) cands.push_back({K, rows, 0});
         for (int rows : {8, 16, 32, 64}) cands.push_back({K, rows, 1});
         for (int rows : {8, 16, 32, 64}) cands.push_back({K, rows, 2});
+        for (int rows : {16, 32, 64}) cands.push_back({K, rows, 3});
     }
     double best_ms = 1e300;
     Cand best = {0, keep_rows, keep_kind};
@@ -2145,9 +2175,13 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
         for (int r : {16, 32, 64})
             if (r != chosen_rows) heights.push_back(r);
         std::vector<std::pair<int, int>> shapes;   // (kind, rows)
-        for (int kind : {chosen_kind, 3 - chosen_kind})
-            if (kind == chosen_kind || failed.count({c->fuse_k, kind}) == 0)
-                for (int rows : heights) shapes.push_back({kind, rows});
+        for (int kind : {chosen_kind, 1, 2, 3})
+            if (kind == chosen_kind || failed.count({c->fuse_k, kind}) == 0) {
+                bool seen = false;
+                for (const auto& sh : shapes) seen = seen || sh.first == kind;
+                if (!seen)
+                    for (int rows : heights) shapes.push_back({kind, rows});
+            }
         for (const auto& sh : shapes) {
             if (e2 != hipSuccess) break;
             const int rows = sh.second;
@@ -2212,8 +2246,8 @@ extern "C" int32_t tdse_taylor_fusion_kind(const tdse_ctx* c) { return c ? c->fu
 extern "C" tdse_status tdse_set_taylor_fusion(tdse_ctx* c, int32_t k, int32_t rows, int32_t kind)
 {
     if (!c) return TDSE_E_INVALID;
-    if (k < 0 || k > kMaxFused || (k > 0 && (rows < 1 || rows > 64)) || kind < 0 || kind > 2)
-        return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: k must be 0..8, rows 1..64, kind 0, 1 or 2");
+    if (k < 0 || k > kMaxFused || (k > 0 && (rows < 1 || rows > 64)) || kind < 0 || kind > 3)
+        return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: k must be 0..8, rows 1..64, kind 0..3");
     if (c->prec == TDSE_FP48 && k > 0 && kind == 0)
         return c->fail(TDSE_E_INVALID, "tdse_set_taylor_fusion: the LDS-ring kernel (kind 0) has no 48-bit form");
     if (c->bound) {

@@ -137,9 +137,15 @@ constexpr int kStripWaves = kBlock / 64;   // strips per strip tile
 // observables' partial sums in the first kPairStrips units of each tile's
 // four (the others zero).
 constexpr int kPairStrips = 1;   // pair strips per workgroup (two waves each)
+// perm: the tiles in launch order (workgroup b takes tile perm[b]; without
+// it, g.order maps blocks to tiles).  queue (needs perm): a persistent launch
+// of the workgroups resident at once, which take the tiles in the order
+// perm[0..n_tiles) from the counters queue[0..1] (zero before the launch,
+// zero again after it).
 hipError_t launch_horner_pstrip(int prec, int S, int K, const SweepGeom& g, const void* in, const void* psi,
                                 void* out, const double* step, int first_term, hipStream_t st,
-                                double* obs_partial = nullptr);
+                                double* obs_partial = nullptr, unsigned* queue = nullptr,
+                                const int* perm = nullptr);
 // An H sweep (term 0) or one Horner term on the aligned strip tile set of one
 // level (g.variant = 1; tiles of 4 waves of 64 radii from a multiple of 256);
 // same results and aliasing rules as launch_hsweep.

@@ -116,6 +116,7 @@ CASES = [
     ("taylor", 8, (5, 16, 1), True, True),    # 5 + 3 terms
     ("taylor", 8, (8, 16, 2), True, True),    # pair strips, observables in the launch
     ("taylor", 8, (3, 8, 2), True, False),    # pair strips, 3 + 3 + 2 terms
+    ("taylor", 8, (8, 16, 3), True, True),    # pair strips, persistent launch
     ("rk4", 4, None, True, None),             # one strip launch per step
     ("rk4", 4, None, False, None),            # four stage launches
     ("lanczos", 12, None, True, None),

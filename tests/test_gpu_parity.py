@@ -464,7 +464,8 @@ def test_autotune_keeps_results_bitwise(tmp_path, monkeypatch):
                                                  (5, 8, 4, 1), (5, 4, 16, 1), (3, 5, 3, 1), (3, 8, 64, 1),
                                                  (3, 6, 1, 1), (5, 7, 9, 1),
                                                  (5, 8, 4, 2), (5, 4, 16, 2), (3, 5, 3, 2), (3, 8, 64, 2),
-                                                 (3, 6, 1, 2), (5, 7, 9, 2), (3, 3, 2, 2), (5, 2, 5, 2)])
+                                                 (3, 6, 1, 2), (5, 7, 9, 2), (3, 3, 2, 2), (5, 2, 5, 2),
+                                                 (5, 8, 4, 3), (3, 5, 3, 3), (3, 8, 64, 3), (5, 7, 9, 3)])
 def test_fused_taylor_bitwise_equal_to_per_term(stencil, k, rows, kind):
     # K Horner terms per launch (either fused kernel) compute every element
     # with the same FP64 expression as one launch per term: identical bits,
@@ -493,7 +494,7 @@ def test_fused_taylor_bitwise_equal_to_per_term(stencil, k, rows, kind):
     assert rel_err(res[1][0], ref) < TOL64
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
 def test_fused_taylor_fp32_and_graphs(kind):
     t = lib()
     grid = t.Grid(600, 8, 0.1, 3, t.FP32, 1.0, 5.0)
@@ -533,7 +534,7 @@ def test_autotune_taylor_choice_is_consistent():
     say(f"autotune_taylor: K={k} rows={rows} kind={prop.taylor_fusion_kind}")
     assert np.array_equal(prop.get_state(0), before)           # state restored
     assert k == 0 or 2 <= k <= 8
-    assert prop.taylor_fusion_kind in (0, 1, 2)
+    assert prop.taylor_fusion_kind in (0, 1, 2, 3)
     assert prop.obs_fusion in (True, False)     # the tuner's choice of the observables' summation
     obs_tuned = prop.obs_buffer(12, 1)
     prop.step_taylor(pulse, 5.0, dt, 8, 12, 1, obs_tuned)
@@ -547,7 +548,7 @@ def test_autotune_taylor_choice_is_consistent():
     prop.close()
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
 def test_fused_taylor_batch_bitwise(kind):
     # uneven instances in one launch: each fused kernel matches the per-term
     # path bit for bit on every instance (FP64)
@@ -570,6 +571,43 @@ def test_fused_taylor_batch_bitwise(kind):
         prop.close()
     for k in range(3):
         assert np.array_equal(res[0][k], res[1][k]), k
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_persistent_pair_strips_bitwise_vs_one_workgroup_per_tile(graphs):
+    # The persistent launch (workgroups resident at once taking the tiles
+    # from a work queue, most rows first) computes every tile as the launch
+    # with one workgroup per tile does: on an uneven batch over several
+    # chunks of steps, with the observables in the launch and graph replay,
+    # states and records are identical bit for bit.  Two calls in a row check
+    # that each launch leaves the queue reset for the next.
+    t = lib()
+    grids = [t.Grid(n, lmax, 0.1, 3, t.FP64, 1.0, 0.25 * n * 0.1)
+             for n, lmax in ((1500, 12), (333, 3), (2047, 21), (900, 64), (4100, 1))]
+    pulses = [t.Pulse(0.05, 0.3, 2.0, 0.0, 0.0), t.Pulse(0.02, 0.1, 3.0, 0.5, 0.0),
+              t.Pulse(0.08, 0.2, 2.0, -1.0, 0.0), t.Pulse(0.03, 0.25, 2.0, 0.3, 0.0),
+              t.Pulse(0.06, 0.15, 3.0, 0.0, 0.0)]
+    nsteps, m = 300, len(grids)
+    say(f"persistent pair strips (kind 3) vs one workgroup per tile (kind 2), graphs={graphs}")
+    out = []
+    for kind in (2, 3):
+        prop = t.Propagator(grids, methods=((t.METHOD_TAYLOR, 8),), graphs=graphs)
+        y = t.tdse_taylor_stability_limit(8)
+        dts = [0.8 * y / prop.lambda_max_bound(k, abs(p.e0)) for k, p in enumerate(pulses)]
+        prop.set_taylor_fusion(8, 16, kind)
+        for k in range(m):
+            prop.set_state(k, None)
+        recs = []
+        for call in range(2):
+            obs = prop.obs_buffer(nsteps, 1)
+            prop.step_taylor(pulses, [1.0 + call * nsteps * d for d in dts], dts, 8, nsteps, 1, obs)
+            recs.append(obs.cpu().numpy())
+        out.append(([prop.get_state(k) for k in range(m)], recs))
+        prop.close()
+    for k in range(m):
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("obs_every", [1, 2, 3])
@@ -624,7 +662,8 @@ def assert_records_match(a, b, main_bitwise):
         assert np.all(diff <= 1e-13 * scale + 1e-12), (col, float(np.max(diff)), float(np.max(scale)))
 
 
-@pytest.mark.parametrize("prec,stencil,kind", [(0, 5, 1), (1, 3, 1), (0, 5, 2), (1, 3, 2), (0, 3, 2)])
+@pytest.mark.parametrize("prec,stencil,kind", [(0, 5, 1), (1, 3, 1), (0, 5, 2), (1, 3, 2), (0, 3, 2),
+                                               (0, 3, 3), (1, 5, 3)])
 def test_observables_in_strip_launch_match_pass(prec, stencil, kind):
     # The main observables (norm, p_ion, dipole, acceleration) summed by the
     # step's last wave-strip launch agree with the observables pass to FP64
@@ -685,7 +724,7 @@ def test_explicit_sweep_shape_bitwise():
         assert np.array_equal(o, out[0])
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
 def test_fused_degenerate_shapes(kind):
     # the smallest grids (N = 8, a single row lmax = 0, strips wider than the
     # grid), order 1 and order 2, zero steps: fused == per-term bit for bit,

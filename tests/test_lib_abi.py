@@ -266,7 +266,7 @@ def test_every_fused_shape_fits_its_workspace_region(tdse, stencil):
     grids = [tdse.Grid(n, lmax, 0.1, stencil).desc() for n, lmax in ((5001, 7), (130, 0), (777, 33))]
     ctx = tdse.tdse_init_grid(grids)
     try:
-        for kind in (0, 1, 2):
+        for kind in (0, 1, 2, 3):
             for k in range(1, 9):
                 for rows in (1, 3, 16, 64):
                     assert tdse.lib.tdse_set_taylor_fusion(ctx, k, rows, kind) == 0, (kind, k, rows)
