@@ -416,8 +416,9 @@ tdse_status tdse_autotune(tdse_ctx* ctx, int32_t* rows_out);
  * record after each, the main observables summed in the step's last launch
  * and by their own pass (tdse_set_obs_fusion), for each strip kernel whose
  * candidates at the chosen K all passed, at the chosen strip height and at
- * 16, 32 and 64 rows (the fastest of four timed passes each), and keeps the
- * fastest kernel, height and mode (when work vector 3 holds
+ * 16, 32 and 64 rows, and the fastest strip shapes of the two next-fastest
+ * term counts (the fastest of four timed passes each), and keeps the fastest
+ * term count, kernel, height and mode (when work vector 3 holds
  * the 8 records of every instance; else the settings stay).  Needs the TDSE_METHOD_TUNE workspace; the state is restored.
  * *fuse_k_out (0: one launch per term) and *rows_out (may be NULL) receive
  * the choice; tdse_taylor_fusion_kind gives the kernel.  Synchronises. */

@@ -211,6 +211,11 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
     // K - k zero rows of level k at each end.
     auto live = [&](int rr) { return rr >= 0 && rr <= lmax; };
 
+    // The stores are plain (cached) ones: a lane writes the two radii of its
+    // 32-byte pair in two instructions, and the L2 joins the halves of each
+    // line before writing it back; streaming stores wrote the halves out one
+    // by one (a third more HBM writes).
+    //
     // one iteration (it: this wave's count; CHECK: some levels may not have
     // reached their first row or may work on rows outside [0, lmax], and rows
     // past the tile are not stored)
@@ -242,8 +247,8 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
             xc = xp;
             if (WRITES && KHI == 1) {
                 if (store_row(rho)) {
-                    if (P.wa) stc(out_i, os + P.jca, up.a);
-                    if (P.wb) stc(out_i, os + P.jcb, up.b);
+                    if (P.wa) stc_keep(out_i, os + P.jca, up.a);
+                    if (P.wb) stc_keep(out_i, os + P.jcb, up.b);
                 }
                 obs_row(up, rho, check);
             }
@@ -267,8 +272,8 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
             ra[j] = up;
             up = v;
             if (k == K && store_row(rk)) {
-                if (P.wa) stc(out_i, os + P.jca, v.a);
-                if (P.wb) stc(out_i, os + P.jcb, v.b);
+                if (P.wa) stc_keep(out_i, os + P.jca, v.a);
+                if (P.wb) stc_keep(out_i, os + P.jcb, v.b);
             }
             if (k == K) obs_row(v, rk, check);
         }

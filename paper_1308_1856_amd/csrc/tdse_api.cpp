@@ -2087,6 +2087,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
     Cand best = {0, keep_rows, keep_kind};
     std::string bad;
     std::set<std::pair<int, int>> failed;   // (K, kind) with a candidate that missed the reference
+    std::map<int, std::pair<double, Cand>> best_strip;   // per K: the fastest strip candidate (ms, shape)
     for (const Cand& cd : cands) {
         if (e != hipSuccess) break;
         c->fuse_k = cd.k;
@@ -2131,6 +2132,10 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
             best_ms = ms / reps;
             best = cd;
         }
+        if (cd.kind >= 1) {
+            auto it = best_strip.find(cd.k);
+            if (it == best_strip.end() || ms / reps < it->second.first) best_strip[cd.k] = {ms / reps, cd};
+        }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -2167,25 +2172,37 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
         // strip kernels: the launch with the sums does one more iteration
         // per tile, and the sums cost the two kernels differently, which can
         // move the best height and kernel
-        const int chosen_rows = c->rows_fused, chosen_kind = c->fuse_kind;
-        int best_rows = chosen_rows, best_kind = chosen_kind;
+        const int chosen_rows = c->rows_fused, chosen_kind = c->fuse_kind, chosen_k = c->fuse_k;
+        int best_rows = chosen_rows, best_kind = chosen_kind, best_k = chosen_k;
         bool best_fused = true;
         float best_obs_ms = 3.0e38f;
         std::vector<int> heights = {chosen_rows};
         for (int r : {16, 32, 64})
             if (r != chosen_rows) heights.push_back(r);
-        std::vector<std::pair<int, int>> shapes;   // (kind, rows)
+        struct Shape { int k, kind, rows; };
+        std::vector<Shape> shapes;
         for (int kind : {chosen_kind, 1, 2, 3})
-            if (kind == chosen_kind || failed.count({c->fuse_k, kind}) == 0) {
+            if (kind == chosen_kind || failed.count({chosen_k, kind}) == 0) {
                 bool seen = false;
-                for (const auto& sh : shapes) seen = seen || sh.first == kind;
+                for (const Shape& sh : shapes) seen = seen || sh.kind == kind;
                 if (!seen)
-                    for (int rows : heights) shapes.push_back({kind, rows});
+                    for (int rows : heights) shapes.push_back({chosen_k, kind, rows});
             }
-        for (const auto& sh : shapes) {
+        // the best strip shape of the two next-fastest term counts (the
+        // observables in the last launch can reorder close term counts)
+        std::vector<std::pair<double, Cand>> others;
+        for (const auto& kv : best_strip)
+            if (kv.first != chosen_k && failed.count({kv.first, kv.second.second.kind}) == 0)
+                others.push_back(kv.second);
+        std::sort(others.begin(), others.end(),
+                  [](const std::pair<double, Cand>& a, const std::pair<double, Cand>& b) { return a.first < b.first; });
+        for (size_t i = 0; i < others.size() && i < 2; ++i)
+            shapes.push_back({others[i].second.k, others[i].second.kind, others[i].second.rows});
+        for (const Shape& sh : shapes) {
             if (e2 != hipSuccess) break;
-            const int rows = sh.second;
-            c->fuse_kind = sh.first;
+            const int rows = sh.rows;
+            c->fuse_k = sh.k;
+            c->fuse_kind = sh.kind;
             c->rows_fused = rows;
             build_tiles(c, kStripTiles, rows);
             e2 = upload_tiles(c, kStripTiles);
@@ -2212,7 +2229,8 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
                 if (ms_mode[fused] < best_obs_ms) {
                     best_obs_ms = ms_mode[fused];
                     best_rows = rows;
-                    best_kind = sh.first;
+                    best_kind = sh.kind;
+                    best_k = sh.k;
                     best_fused = fused != 0;
                 }
             }
@@ -2222,6 +2240,7 @@ extern "C" tdse_status tdse_autotune_taylor(tdse_ctx* c, int32_t order, int32_t*
         c->obs_fusion = (e2 == hipSuccess) ? best_fused : true;
         c->rows_fused = (e2 == hipSuccess) ? best_rows : chosen_rows;
         c->fuse_kind = (e2 == hipSuccess) ? best_kind : chosen_kind;
+        c->fuse_k = (e2 == hipSuccess) ? best_k : chosen_k;
         build_tiles(c, kFusedTiles, c->rows_fused);
         build_tiles(c, kStripTiles, c->rows_fused);
         if (e2 == hipSuccess) e2 = upload_tiles(c, kFusedTiles);
