@@ -38,12 +38,25 @@
 // not alias `in` or `psi`.
 #pragma once
 #include <algorithm>
+#include <utility>
 
 #include "strip_common.hpp"
 
 namespace tdse {
 
 template <typename T> struct type_tag { using type = T; };
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>), in order.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
 
 // A lane's two radii.
 struct Pair {
@@ -146,6 +159,12 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
     const int iters = max((I.l1 - I.l0) + 2 * K - 2 + KLAG, warm_trips_end);
     const int xhi = min(lmax, rho0 + iters + (OBS ? 1 : 0));
     const int phi = min(lmax, rho0 + iters - 1 + (OBS ? 1 : 0));
+    // A tile from row 0 starts at iteration it0 = K - 1 (rounded down to a
+    // loop trip): before it every level works on rows below 0, which are
+    // zero, so the iterations would only load zero rows and meet at the
+    // barrier.  Both waves skip the same count (their barriers stay paired);
+    // the kept rows of the skipped iterations are the zeros they start with.
+    const int it0 = (I.l0 == 0) ? (K - 1) / D * D : 0;
     auto rowp_x = [&](int rr) -> RowP { return (unsigned)rr <= (unsigned)xhi ? in_i + (int64_t)rr * n : zrow; };
     auto rowp_p = [&](int rr) -> RowP { return (unsigned)rr <= (unsigned)phi ? psi_i + (int64_t)rr * n : zrow; };
 
@@ -155,33 +174,40 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
         C xa, xb, pa, pb;
     };
     Slot sl[D];
-    Pair xm = zero_pair(), xc = zero_pair();
+    // Rows kept from one iteration to the next swap roles with the
+    // iteration's parity instead of being copied: at parity p the centre row
+    // of level 1 is xw[p] and the row below it xw[1 - p], which the new input
+    // row then replaces (the next iteration's centre); likewise lv[p][j] and
+    // lv[1 - p][j] for level j's rows of the level below.  D is even, so every
+    // loop trip starts at parity 0.
+    static_assert(D % 2 == 0, "the row roles alternate over loop trips of D iterations");
+    Pair xw[2] = {zero_pair(), zero_pair()};
     int64_t ox = 0, op = 0;
     if (PRODUCER) {
-        xm = Pair{wa2(rowp_x(rho0 - 1)[P.jca]), wb2(rowp_x(rho0 - 1)[P.jcb])};
-        xc = Pair{wa2(rowp_x(rho0)[P.jca]), wb2(rowp_x(rho0)[P.jcb])};
+        xw[1] = Pair{wa2(rowp_x(rho0 + it0 - 1)[P.jca]), wb2(rowp_x(rho0 + it0 - 1)[P.jcb])};
+        xw[0] = Pair{wa2(rowp_x(rho0 + it0)[P.jca]), wb2(rowp_x(rho0 + it0)[P.jcb])};
 #pragma unroll
         for (int u = 0; u < D; ++u) {
-            const RowP xr = rowp_x(rho0 + 1 + u);
-            const RowP pr = rowp_p(rho0 + u);
+            const RowP xr = rowp_x(rho0 + it0 + 1 + u);
+            const RowP pr = rowp_p(rho0 + it0 + u);
             sl[u] = Slot{xr[P.jca], xr[P.jcb], pr[P.jca], pr[P.jcb]};
         }
-        ox = (int64_t)(rho0 + 1 + D) * n;
-        op = (int64_t)(rho0 + D) * n;
+        ox = (int64_t)(rho0 + it0 + 1 + D) * n;
+        op = (int64_t)(rho0 + it0 + D) * n;
     }
     // for each of this wave's levels, the two older rows of the level below
-    // (a = row r - 1, b = row r - 2 of the level's row r); the producer's
-    // level 1 uses the input rows instead
-    Pair ra[NR], rb[NR];
+    // (the centre row r and the row r - 1 of the level's row r); the
+    // producer's level 1 uses the input rows instead
+    Pair lv[2][NR];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) ra[j] = rb[j] = zero_pair();
+    for (int j = 0; j < NR; ++j) lv[0][j] = lv[1][j] = zero_pair();
     // kappa window: kq[j] = kappa(rho + 1 - j), j = 0..K, rho of the
     // producer iteration played
     double kq[K + 1];
 #pragma unroll
-    for (int j = 0; j <= K; ++j) kq[j] = kap(rho0 - LAG + 1 - j);
-    double kn = kap(rho0 - LAG + 2);
-    int64_t os = (int64_t)(rho0 - LAG - (K - 1)) * n;   // the level-K row's offset
+    for (int j = 0; j <= K; ++j) kq[j] = kap(rho0 + it0 - LAG + 1 - j);
+    double kn = kap(rho0 + it0 - LAG + 2);
+    int64_t os = (int64_t)(rho0 + it0 - LAG - (K - 1)) * n;   // the level-K row's offset
 
     double oacc[kObsMainQ] = {0.0, 0.0, 0.0, 0.0};
     Pair fprev = zero_pair();
@@ -219,8 +245,9 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
     // one iteration (it: this wave's count; CHECK: some levels may not have
     // reached their first row or may work on rows outside [0, lmax], and rows
     // past the tile are not stored)
-    auto body = [&](int it, Slot& s, auto check) {
+    auto body = [&](int it, Slot& s, auto check, auto parity) {
         constexpr bool CHECK = decltype(check)::value;
+        constexpr int PAR = decltype(parity)::value;   // it mod 2
         const int pit = it - LAG;                // the producer iteration this one plays
         const int rho = rho0 + pit;
         auto store_row = [&](int rr) { return !CHECK || (rr >= I.l0 && rr < I.l1); };
@@ -242,9 +269,9 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
             ring_b(wslot) = pob;
             up = zero_pair();
             if (!CHECK || live(rho))
-                up = mask(horner(Pair{widen(poa), widen(pob)}, h_row(xc, xm, xp, rho, kq[1], kq[0]), coef[0]));
-            xm = xc;
-            xc = xp;
+                up = mask(horner(Pair{widen(poa), widen(pob)}, h_row(xw[PAR], xw[1 - PAR], xp, rho, kq[1], kq[0]),
+                                 coef[0]));
+            xw[1 - PAR] = xp;
             if (WRITES && KHI == 1) {
                 if (store_row(rho)) {
                     if (P.wa) stc_keep(out_i, os + P.jca, up.a);
@@ -253,9 +280,13 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
                 obs_row(up, rho, check);
             }
         } else {
-            // the producer's level-K1 row of the iteration before (row rho - (K1 - 1))
+            // the producer's level-K1 row of the iteration before (row rho -
+            // (K1 - 1)); none before the first iteration (a row below 0)
             const int hs = (it + 1) & 1;
-            up = Pair{L.hand[hs * 128 + lane], L.hand[hs * 128 + 64 + lane]};
+            if (CHECK && it == it0)
+                up = zero_pair();
+            else
+                up = Pair{L.hand[hs * 128 + lane], L.hand[hs * 128 + 64 + lane]};
         }
 #pragma unroll
         for (int k = KLO + (PRODUCER ? 1 : 0); k <= KHI; ++k) {
@@ -266,10 +297,9 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
                 // psi(rk), written by the producer at its iteration pit - (k - 1)
                 const int rslot = (pit - (k - 1) + 2 * R) % R;
                 const Pair pk{widen(ring_a(rslot)), widen(ring_b(rslot))};
-                v = mask(horner(pk, h_row(ra[j], rb[j], up, rk, kq[k], kq[k - 1]), coef[k - 1]));
+                v = mask(horner(pk, h_row(lv[PAR][j], lv[1 - PAR][j], up, rk, kq[k], kq[k - 1]), coef[k - 1]));
             }
-            rb[j] = ra[j];
-            ra[j] = up;
+            lv[1 - PAR][j] = up;
             up = v;
             if (k == K && store_row(rk)) {
                 if (P.wa) stc_keep(out_i, os + P.jca, v.a);
@@ -292,28 +322,27 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
         // either wave of the strip goes on
         __syncthreads();
     };
-    int it = 0;
+    // D iterations from ib (a multiple of D), slot u and parity u mod 2 each
+    auto trip = [&](int ib, auto check) {
+        static_for<D>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            body(ib + u, sl[u], check, std::integral_constant<int, u % 2>{});
+        });
+    };
+    int it = it0;
 #pragma clang loop unroll(disable)
-    for (; it < warm_trips_end; it += D) {
-#pragma unroll
-        for (int u = 0; u < D; ++u) body(it + u, sl[u], std::true_type{});
-    }
+    for (; it < warm_trips_end; it += D) trip(it, std::true_type{});
     // unchecked while every level's row lies in [0, lmax] (level 1 leads:
     // row rho0 + it - LAG), checked from there to the end
     const int steady_end = max(warm_trips_end, min(iters, lmax - rho0 + 1 + LAG) / D * D);
 #pragma clang loop unroll(disable)
-    for (; it + D <= steady_end; it += D) {
-#pragma unroll
-        for (int u = 0; u < D; ++u) body(it + u, sl[u], std::false_type{});
-    }
+    for (; it + D <= steady_end; it += D) trip(it, std::false_type{});
 #pragma clang loop unroll(disable)
-    for (; it + D <= iters; it += D) {
-#pragma unroll
-        for (int u = 0; u < D; ++u) body(it + u, sl[u], std::true_type{});
-    }
-#pragma unroll
-    for (int u = 0; u < D - 1; ++u)
-        if (it + u < iters) body(it + u, sl[u], std::true_type{});
+    for (; it + D <= iters; it += D) trip(it, std::true_type{});
+    static_for<D - 1>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        if (it + u < iters) body(it + u, sl[u], std::true_type{}, std::integral_constant<int, u % 2>{});
+    });
     if (OBS) {
         // the iteration past the last: level K at row l1 for the last pair,
         // checked so that it stores nothing (every wave runs it: one barrier)
@@ -321,7 +350,10 @@ __device__ __forceinline__ void pair_loop(const SweepGeom& g, const Tile& I, typ
 #pragma unroll
         for (int u = 1; u < D; ++u)
             if (it + u == iters) last = sl[u];
-        body(iters, last, std::true_type{});
+        if ((iters - it) & 1)
+            body(iters, last, std::true_type{}, std::integral_constant<int, 1>{});
+        else
+            body(iters, last, std::true_type{}, std::integral_constant<int, 0>{});
         if (WRITES) {
 #pragma unroll
             for (int q = 0; q < kObsMainQ; ++q) {
