@@ -134,9 +134,14 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, ty
     };
 
     const int rho0 = I.l0 - K + 1;              // level-1 row at it = 0
+    // A tile of the Horner strips from row 0 starts at iteration it0 = K - 1
+    // (rounded down to a loop trip): before it every level works on rows
+    // below 0, which are zero; the kept rows of the skipped iterations are
+    // the zeros they start with.
+    const int it0 = (!APPLY && !ALIGNED && I.l0 == 0) ? (K - 1) / D * D : 0;
     // input rows rho-1, rho (FP64) of the current iteration
-    double2 xm = widen_lane(rowp(in_i, rho0 - 1)[jc]);
-    double2 xc = widen_lane(rowp(in_i, rho0)[jc]);
+    double2 xm = widen_lane(rowp(in_i, rho0 + it0 - 1)[jc]);
+    double2 xc = widen_lane(rowp(in_i, rho0 + it0)[jc]);
     // ALIGNED: row rho's values beyond the wave ends
     double2 xc1 = zero2(), xc2 = zero2();
     if (ALIGNED) {
@@ -166,8 +171,8 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, ty
     Slot sl[D];
 #pragma unroll
     for (int u = 0; u < D; ++u) {
-        const RowP xr = rowp_x(rho0 + 1 + u);
-        sl[u] = Slot{xr[jc], APPLY ? zero_c<C>() : rowp_p(rho0 + u)[jc], ALIGNED ? xr[edge.e1] : zero_c<C>(),
+        const RowP xr = rowp_x(rho0 + it0 + 1 + u);
+        sl[u] = Slot{xr[jc], APPLY ? zero_c<C>() : rowp_p(rho0 + it0 + u)[jc], ALIGNED ? xr[edge.e1] : zero_c<C>(),
                      ALIGNED && S == 2 ? xr[edge.e2] : zero_c<C>()};
     }
     // psi(rho_k) for level k = 1..K: pr[k-1]
@@ -183,13 +188,13 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, ty
     // value per iteration, loaded an iteration ahead (kn).
     double kq[K + 1];
 #pragma unroll
-    for (int j = 0; j <= K; ++j) kq[j] = kap(rho0 + 1 - j);
-    double kn = kap(rho0 + 2);
+    for (int j = 0; j <= K; ++j) kq[j] = kap(rho0 + it0 + 1 - j);
+    double kn = kap(rho0 + it0 + 2);
     // element offsets of the rows an iteration reloads (input row rho+1+D,
     // psi row rho+D) and stores (level K at rho-(K-1)); each advances by one
     // row per iteration
-    int64_t ox = (int64_t)(rho0 + 1 + D) * n, op = (int64_t)(rho0 + D) * n;
-    int64_t os = (int64_t)(rho0 - (K - 1)) * n + jc;
+    int64_t ox = (int64_t)(rho0 + it0 + 1 + D) * n, op = (int64_t)(rho0 + it0 + D) * n;
+    int64_t os = (int64_t)(rho0 + it0 - (K - 1)) * n + jc;
 
     // OBS: sums per lane over the rows, and the previous level-K row as stored.
     // Level K is zero at the rows below l0 (not yet started), so the pair
@@ -296,7 +301,7 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, ty
     // short to reach the end of the warm-up trips runs on to it: the extra
     // iterations compute rows past l1 (inputs outside [0, lmax] read as zero)
     // and store nothing.
-    int it = 0;
+    int it = it0;
 #pragma clang loop unroll(disable)
     for (; it < warm_trips_end; it += D) {
 #pragma unroll
@@ -336,11 +341,14 @@ __device__ __forceinline__ void strip_loop(const SweepGeom& g, const Tile& I, ty
 template <int S, typename T, int K, bool OBS>
 __global__ void __launch_bounds__(kBlock)
 k_horner_strip(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi, typename Stor<T>::ptr out,
-               const double* __restrict__ step, int first_term, double* __restrict__ obs_partial)
+               const double* __restrict__ step, int first_term, double* __restrict__ obs_partial,
+               const int* __restrict__ perm)
 {
     const int halo = g.variant * S;             // >= K * S: lanes lost per side after K levels
     const int valid = 64 - 2 * halo;            // output radii per wave
-    const Tile I = my_tile(g);
+    // the tile: perm gives the launch order, else g.order maps the block
+    const int t = perm ? perm[blockIdx.x] : my_tile_index(g);
+    const Tile I = g.tiles[t];
     const int n = I.n;
     const int lane = (int)threadIdx.x & 63;
     const int wave = (int)threadIdx.x >> 6;
@@ -367,7 +375,7 @@ k_horner_strip(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr ps
     if (OBS) {
         ob.partial = obs_partial;
         ob.stride = (int64_t)g.n_tiles * kStripWaves;
-        ob.unit = (int64_t)my_tile_index(g) * kStripWaves + wave;
+        ob.unit = (int64_t)t * kStripWaves + wave;
         ob.r = r;
         ob.outer = jc >= I.i_ion;
         ob.lane = lane;
@@ -382,47 +390,48 @@ k_horner_strip(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr ps
 
 template <int S, typename T, int K>
 static hipError_t strip_t(const SweepGeom& g, const void* in, const void* psi, void* out,
-                          const double* step, int first_term, double* obs_partial, hipStream_t st)
+                          const double* step, int first_term, double* obs_partial, const int* perm, hipStream_t st)
 {
     if (obs_partial)
         hipLaunchKernelGGL((k_horner_strip<S, T, K, true>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
                            Stor<T>::cmake(in, g.plane), Stor<T>::cmake(psi, g.plane), Stor<T>::make(out, g.plane),
-                           step, first_term, obs_partial);
+                           step, first_term, obs_partial, perm);
     else
         hipLaunchKernelGGL((k_horner_strip<S, T, K, false>), dim3(g.n_tiles), dim3(kBlock), 0, st, g,
                            Stor<T>::cmake(in, g.plane), Stor<T>::cmake(psi, g.plane), Stor<T>::make(out, g.plane),
-                           step, first_term, obs_partial);
+                           step, first_term, obs_partial, perm);
     return hipGetLastError();
 }
 
 template <int S, typename T>
 static hipError_t strip_k(int K, const SweepGeom& g, const void* in, const void* psi, void* out,
-                          const double* step, int first_term, double* obs_partial, hipStream_t st)
+                          const double* step, int first_term, double* obs_partial, const int* perm,
+                          hipStream_t st)
 {
     switch (K) {
-        case 1: return strip_t<S, T, 1>(g, in, psi, out, step, first_term, obs_partial, st);
-        case 2: return strip_t<S, T, 2>(g, in, psi, out, step, first_term, obs_partial, st);
-        case 3: return strip_t<S, T, 3>(g, in, psi, out, step, first_term, obs_partial, st);
-        case 4: return strip_t<S, T, 4>(g, in, psi, out, step, first_term, obs_partial, st);
-        case 5: return strip_t<S, T, 5>(g, in, psi, out, step, first_term, obs_partial, st);
-        case 6: return strip_t<S, T, 6>(g, in, psi, out, step, first_term, obs_partial, st);
-        case 7: return strip_t<S, T, 7>(g, in, psi, out, step, first_term, obs_partial, st);
-        case 8: return strip_t<S, T, 8>(g, in, psi, out, step, first_term, obs_partial, st);
+        case 1: return strip_t<S, T, 1>(g, in, psi, out, step, first_term, obs_partial, perm, st);
+        case 2: return strip_t<S, T, 2>(g, in, psi, out, step, first_term, obs_partial, perm, st);
+        case 3: return strip_t<S, T, 3>(g, in, psi, out, step, first_term, obs_partial, perm, st);
+        case 4: return strip_t<S, T, 4>(g, in, psi, out, step, first_term, obs_partial, perm, st);
+        case 5: return strip_t<S, T, 5>(g, in, psi, out, step, first_term, obs_partial, perm, st);
+        case 6: return strip_t<S, T, 6>(g, in, psi, out, step, first_term, obs_partial, perm, st);
+        case 7: return strip_t<S, T, 7>(g, in, psi, out, step, first_term, obs_partial, perm, st);
+        case 8: return strip_t<S, T, 8>(g, in, psi, out, step, first_term, obs_partial, perm, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const void* in,
                                const void* psi, void* out, const double* step, int first_term,
-                               hipStream_t st, double* obs_partial)
+                               hipStream_t st, double* obs_partial, const int* perm)
 {
     if (g.gauge != 0) return hipErrorInvalidValue;   // length gauge only
-    if (prec == 0) return S == 1 ? strip_k<1, double>(K, g, in, psi, out, step, first_term, obs_partial, st)
-                                 : strip_k<2, double>(K, g, in, psi, out, step, first_term, obs_partial, st);
-    if (prec == 2) return S == 1 ? strip_k<1, s48>(K, g, in, psi, out, step, first_term, obs_partial, st)
-                                 : strip_k<2, s48>(K, g, in, psi, out, step, first_term, obs_partial, st);
-    return S == 1 ? strip_k<1, float>(K, g, in, psi, out, step, first_term, obs_partial, st)
-                  : strip_k<2, float>(K, g, in, psi, out, step, first_term, obs_partial, st);
+    if (prec == 0) return S == 1 ? strip_k<1, double>(K, g, in, psi, out, step, first_term, obs_partial, perm, st)
+                                 : strip_k<2, double>(K, g, in, psi, out, step, first_term, obs_partial, perm, st);
+    if (prec == 2) return S == 1 ? strip_k<1, s48>(K, g, in, psi, out, step, first_term, obs_partial, perm, st)
+                                 : strip_k<2, s48>(K, g, in, psi, out, step, first_term, obs_partial, perm, st);
+    return S == 1 ? strip_k<1, float>(K, g, in, psi, out, step, first_term, obs_partial, perm, st)
+                  : strip_k<2, float>(K, g, in, psi, out, step, first_term, obs_partial, perm, st);
 }
 
 // The plain H-psi sweep (term 0: out = H(E_mid) in) and single Horner terms

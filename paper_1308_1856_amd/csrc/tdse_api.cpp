@@ -1301,10 +1301,10 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
     if (K > 0) {
         const bool strips = c->fuse_kind >= 1;
         const bool pairs = c->fuse_kind >= 2;
-        // pair strips take the tiles most rows first (a persistent launch
-        // from the work queue, else one workgroup per tile in that order)
+        // strips take the tiles most rows first (a persistent launch from
+        // the work queue, else one workgroup per tile in that order)
         unsigned* queue = (c->fuse_kind == 3) ? c->d_queue() : nullptr;
-        const int32_t* perm = pairs ? c->d_perm() : nullptr;
+        const int32_t* perm = strips ? c->d_perm() : nullptr;
         SweepGeom gf = c->geom(strips ? kStripTiles : kFusedTiles);
         if (strips) gf.variant = K;   // the term count the strip tiles were built for
         int which = 0;
@@ -1319,7 +1319,8 @@ hipError_t taylor_step_launches(tdse_ctx* c, const double* step, int order, void
                 TimedLaunch tl(c, 5);
                 e = pairs ? launch_horner_pstrip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs,
                                                  queue, perm)
-                    : strips ? launch_horner_strip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs)
+                    : strips ? launch_horner_strip(c->prec, S, terms, gf, in, psi, out, step, first, c->stream, obs,
+                                                   perm)
                              : launch_horner_fused(c->prec, S, terms, gf, in, psi, out, step, first, c->stream);
             }
             if (obs && e == hipSuccess) c->obs_main_done = true;

@@ -125,9 +125,11 @@ hipError_t launch_horner_fused(int prec, int S, int K, const SweepGeom& g, const
 // aliasing rules.  With obs_partial, the launch also writes the observables'
 // main partial sums of its output (norm, p_ion, dipole, acceleration), one
 // per strip: obs_partial[q * 4 n_tiles + 4 tile + wave], q < kObsMainQ.
+// perm: the tiles in launch order (workgroup b takes tile perm[b]); without
+// it, g.order maps blocks to tiles.
 hipError_t launch_horner_strip(int prec, int S, int K, const SweepGeom& g, const void* in,
                                const void* psi, void* out, const double* step, int first_term,
-                               hipStream_t st, double* obs_partial = nullptr);
+                               hipStream_t st, double* obs_partial = nullptr, const int* perm = nullptr);
 constexpr int kStripWaves = kBlock / 64;   // strips per strip tile
 // The same K terms on pair strips: lane L holds radii 2L and 2L + 1 of a
 // strip of 128, two waves per strip (levels 1..ceil(K/2) and the rest, the
