@@ -82,6 +82,13 @@ WORKLOADS = {
         PulseSpec(0.0534, 0.057, 2.0), dt=5e-4, dt_nominal=0.05, nsteps=440_000,
         obs_every=100, r_ion=50.0,
         description="FP64 RK4/Taylor-4, 2-cycle sin^2 pulse, 1e14 W/cm^2, w=0.057"),
+    # the same grid and pulse with the Taylor polynomial of order 4 (the same
+    # stability region as RK4), one fused strip launch per step
+    "hydrogen_n2000_l8_fp64_taylor4": Workload(
+        "hydrogen_n2000_l8_fp64_taylor4", 2000, 8, 0.1, 3, "fp64", "taylor", 4,
+        PulseSpec(0.0534, 0.057, 2.0), dt=5e-4, dt_nominal=0.05, nsteps=440_000,
+        obs_every=100, r_ion=50.0,
+        description="FP64 Taylor-4, 2-cycle sin^2 pulse, 1e14 W/cm^2, w=0.057"),
     # single large FP64 instance, Taylor order 8, 5-point
     "hydrogen_n20000_l64_fp64_taylor8": Workload(
         "hydrogen_n20000_l64_fp64_taylor8", 20000, 64, 0.05, 5, "fp64", "taylor", 8,
