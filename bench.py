@@ -22,7 +22,8 @@ Also reported on the same line:
                 the same kernel and shape (null if there is none, or if the
                 kernel source changed since);
   hpsi_sweep    the plain H.psi apply (read psi, write H psi: 2c B per unknown)
-                on the batch, same report;
+                on the batch, same report, at the fastest of the tuned sweep
+                shape and a few strip shapes (APPLY_SHAPES);
   precisions    48-bit and FP32 storage (FP64 arithmetic and reductions): steps
                 per second, speedup over FP64, and a 1000-step window of every
                 member from mid-pulse (a mixed bound / excited / outgoing start)
@@ -79,6 +80,8 @@ def parse():
                     help="RK4 in four stage launches per step (default: one launch per step)")
     ap.add_argument("--autotune", type=int, default=2,
                     help="0: fixed shapes; 1: autotune the sweep tiles; 2: also choose the Taylor fusion")
+    ap.add_argument("--no-apply-search", action="store_true",
+                    help="time the plain H.psi apply on the sweep shape in use only")
     ap.add_argument("--sweep", default=None, metavar="ROWS,VARIANT",
                     help="fixed sweep tile shape instead of the sweep autotuner (profiling runs)")
     ap.add_argument("--fusion", default=None, metavar="K,ROWS,KIND[,OBS]",
@@ -209,26 +212,43 @@ def valu_busy_for(workload, kernel, precision, shape):
     return e.get("valu_busy_pct") if e else None
 
 
+# tile shapes (rows, sweep variant) the plain apply is also timed on: the
+# sweep autotuner times Horner-term sweeps (which also read psi), whose best
+# shape need not be the apply's
+APPLY_SHAPES = ((2, 6), (4, 6), (4, 4), (8, 6))
+
+
 def hpsi_sweep(prop, tdse, torch, U, elem, reps=40):
-    """Mean duration of the plain H.psi apply on the bound grid (HIP events)."""
+    """Mean duration of the plain H.psi apply on the bound grid (HIP events),
+    at the fastest of the tuned sweep shape and APPLY_SHAPES (only the tuned
+    one with --no-apply-search); the tuned shape is restored afterwards."""
     out = prop.new_vector()
     e = 0.01
-    for _ in range(3):
-        prop.apply_H(e, prop.state, out)
-    torch.cuda.synchronize()
-    prop.timing(True)
-    for _ in range(reps):
-        prop.apply_H(e, prop.state, out)
-    launches, kms = prop.timing_read("apply_h")
-    prop.timing(False)
-    torch.cuda.synchronize()
-    us = 1e3 * kms / max(launches, 1)
+    tuned = (prop.tile_rows, prop.sweep_variant)
+    search = ARGS is None or not getattr(ARGS, "no_apply_search", False)
+    best = None
+    for shape in [tuned] + ([s for s in APPLY_SHAPES if s != tuned] if search else []):
+        prop.set_sweep_shape(*shape)
+        for _ in range(3):
+            prop.apply_H(e, prop.state, out)
+        torch.cuda.synchronize()
+        prop.timing(True)
+        for _ in range(reps):
+            prop.apply_H(e, prop.state, out)
+        launches, kms = prop.timing_read("apply_h")
+        prop.timing(False)
+        torch.cuda.synchronize()
+        us = 1e3 * kms / max(launches, 1)
+        if best is None or us < best[0]:
+            best = (us, launches, shape)
+    prop.set_sweep_shape(*tuned)
+    us, launches, shape = best
     bytes_ = 2 * elem * U
     gbs = bytes_ / (us * 1e-6) / 1e9
     return {"bound": "hbm", "kernel": "apply_h", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_, "mean_launch_us": us,
             "launches_timed": launches, "applies_per_s": 1e6 / us,
-            "shape": {"tile_rows": prop.tile_rows, "sweep_variant": prop.sweep_variant}}
+            "shape": {"tile_rows": shape[0], "sweep_variant": shape[1]}}
 
 
 def taylor_bytes_per_launch(elem, U, launches, steps):

@@ -42,6 +42,9 @@ namespace tdse {
 // coefficients are the sweep's (kappa_{lmax+1} multiplies the zero row above
 // lmax in the sweep; zero here gives the same bits).
 constexpr int kStripDepth = 3;   // iterations of row loads in flight per wave (measured: 3 beats 2 and 4)
+// the plain H.psi apply on aligned strips: six rows of loads in flight (on
+// 4-row tiles of the 104M-unknown batch 541 us against 570 us with three)
+constexpr int kApplyDepth = 6;
 
 // The observables' partial sums of the rows a strip writes (OBS below): the
 // wave's sums of norm, p_ion, dipole and acceleration terms go to
@@ -473,11 +476,11 @@ k_sweep_strip(SweepGeom g, typename Stor<T>::cptr in, typename Stor<T>::cptr psi
     const auto psi_i = psi + I.off;
     const auto out_i = out + I.off;
     if (j0 - S >= 0 && j0 + 63 + S < n)   // wave-uniform: every value the wave reads is inside
-        strip_loop<S, T, 1, false, APPLY, true>(g, I, in_i, psi_i, out_i, jc, inside, inside, er, inv_r2, z_over_r,
-                                                coef, edge);
+        strip_loop<S, T, 1, false, APPLY, true, APPLY ? kApplyDepth : kStripDepth>(
+            g, I, in_i, psi_i, out_i, jc, inside, inside, er, inv_r2, z_over_r, coef, edge);
     else
-        strip_loop<S, T, 1, true, APPLY, true>(g, I, in_i, psi_i, out_i, jc, inside, inside, er, inv_r2, z_over_r,
-                                               coef, edge);
+        strip_loop<S, T, 1, true, APPLY, true, APPLY ? kApplyDepth : kStripDepth>(
+            g, I, in_i, psi_i, out_i, jc, inside, inside, er, inv_r2, z_over_r, coef, edge);
 }
 
 template <int S, typename T>
